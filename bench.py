@@ -1,0 +1,145 @@
+"""Benchmark of the EXCMG hot path on one MI355X.
+
+One step = one complete EXCMG solve (Algorithm 1: right-hand sides, direct coarse solves,
+EXP_finite guesses, Bi-CG on every level, EXP_true) of the 512^3-cell second-kind
+manufactured problem (8 seeded sine modes plus an exponential) to the relative residual
+1e-8, with the inputs already in HBM.  Prints one JSON line.
+
+value = Bi-CG GLUPS of the whole job: sum over levels of (unknowns x Bi-CG iterations)
+divided by the wall time of the solve.  The line also carries the time to the 1e-8
+residual, the roofline position of the dominant kernel (measured with device events on the
+library's stream) and the CPU oracle's throughput on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Bi-CG stencil GLUPS & HBM GB/s; time-to-1e-8 residual, FP64 vs mixed"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(arr, N, nl, bc, iters):
+    """The oracle's Bi-CG on the finest level of the same problem, a few iterations."""
+    import numpy as np
+    import oracle
+
+    b = oracle.rhs(N, bc, arr.f, arr.g1, arr.g2)
+    x0 = np.zeros((N - 1) ** 3)
+    t0 = time.perf_counter()
+    _, it, _, _ = oracle.bicg(N, bc, b, x0, 1e-30, maxit=iters)
+    dt = time.perf_counter() - t0
+    nu = (N - 1) ** 3
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": nu * it / dt / 1e9, "unit": "GLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"{it} Bi-CG iterations (plus the initial residual) of the oracle on the "
+                      f"{N}^3-cell finest level of the same problem, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=512, help="finest grid (cells per axis)")
+    ap.add_argument("--levels", type=int, default=8)
+    ap.add_argument("--bc", type=int, default=2)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--config", type=int, default=4, help="seeded problem family (1-4)")
+    ap.add_argument("--cpu-iters", type=int, default=4)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: the solver has no multi-GPU path "
+              "(see DESIGN.md for how it would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1901_05118_amd as ex
+    from manufactured import config_problem, make_arrays
+
+    torch.cuda.set_device(0)
+    N, nl, bc, tol = args.n, args.levels, args.bc, args.tol
+    log(f"generating inputs {N}^3 bc={bc}")
+    arr = make_arrays(config_problem(args.config), N, bc)
+    dev = torch.device("cuda:0")
+    f, g1, g2 = (torch.from_numpy(a).to(dev) for a in (arr.f, arr.g1, arr.g2))
+    u = torch.empty_like(f)
+    ut = torch.empty_like(f)
+    stream = torch.cuda.current_stream()
+    ex.set_stream(stream)
+    ex.setup(N, nl, bc)
+
+    def step():
+        rc, st = ex.solve_ex(N, nl, bc, f, g1, g2, tol, u, ut)
+        if rc != ex.OK:
+            raise RuntimeError(f"solve failed: {rc} {ex.last_error()}")
+        return st
+
+    for w in range(args.warmup):
+        st = step()
+        log(f"warmup {w}: {st.total_ms:.1f} ms, iterations "
+            f"{[l['iterations'] for l in st.levels()]}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for s in range(args.steps):
+        stats.append(step())
+        log(f"step {s}: {stats[-1].total_ms:.1f} ms")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall * 1e3 / args.steps
+    st = stats[-1]
+    levels = st.levels()
+    lups = sum(((lv["n"] - 1) ** 3) * lv["iterations"] for lv in levels)
+    glups = lups / (ms_step * 1e-3) / 1e9
+
+    # accuracy of the last solve against the exact solution (discretisation error)
+    err = (u.view(N + 1, N + 1, N + 1).cpu().numpy() - arr.u)
+    err_t = (ut.view(N + 1, N + 1, N + 1).cpu().numpy() - arr.u)
+    rms = lambda e: float(np.sqrt(np.mean(e * e)))  # noqa: E731
+
+    # roofline of the dominant kernel: Bi-CG sweep A (direction update + pair apply)
+    ms_a, bytes_a = ex.profile_sweep(2, ex.FP64, reps=10)
+    ms_b, bytes_b = ex.profile_sweep(3, ex.FP64, reps=10)
+    ms_c, bytes_c = ex.profile_sweep(4, ex.FP64, reps=10)
+    gbs_a = bytes_a / (ms_a * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(gbs_a, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(gbs_a / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "zmarch<2,InDirection,OutPairApply> (Bi-CG sweep A, FP64)",
+                "ms_per_launch": round(ms_a, 4),
+                "sweep_b_gbs": round(bytes_b / (ms_b * 1e-3) / 1e9, 1),
+                "copy_gbs": round(bytes_c / (ms_c * 1e-3) / 1e9, 1)}
+
+    out = {
+        "metric": METRIC, "value": round(glups, 3), "unit": "GLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"EXCMG {N}^3 cells, bc kind {bc}, seeded family {args.config}, "
+                               f"tol {tol:g}, FP64", "n_finest": N, "n_levels": nl,
+                   "bc_kind": bc, "tol": tol, "precision": "fp64"},
+        "time_to_solution_ms": {"fp64": round(ms_step, 2)},
+        "iterations": [lv["iterations"] for lv in levels],
+        "error_vs_exact": {"u_rms": rms(err), "u_max": float(np.abs(err).max()),
+                           "ut_rms": rms(err_t)},
+        "roofline": roofline,
+    }
+    if not args.no_cpu:
+        log("cpu baseline")
+        out["cpu_baseline"] = cpu_baseline(arr, N, nl, bc, args.cpu_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,175 @@
+/*
+ * excmg.h - C ABI of the MI355X (gfx950) EXCMG solver for the 3D biharmonic equation
+ *
+ *     Delta^2 u = f on (0,1)^3,
+ *     u = g1 and du/dn = g2 on the boundary       (first kind,  bc_kind = 1), or
+ *     u = g1 and d2u/dn2 = g2 on the boundary     (second kind, bc_kind = 2),
+ *
+ * discretised by the 25-point scheme and solved by the extrapolation cascadic multigrid
+ * method (Pan, He & Ni, arXiv:1901.05118: problem statement eqs. bvp, BC, BC2 in Sec. 1;
+ * scheme and boundary treatment in Sec. 2; cascade in Sec. 4.1, Algorithm 1; extrapolation
+ * and interpolation in Sec. 4.2; Bi-CG in Sec. 5, Algorithm 2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  * All arrays are FP64.  A "node array" on a grid of N cells per axis holds (N+1)^3 values,
+ *    node (i,j,k) at x = i/N, y = j/N, z = k/N stored at index (k*(N+1) + j)*(N+1) + i.
+ *    An "interior vector" holds the (N-1)^3 unknowns (nodes 1..N-1 on every axis) in the same
+ *    x-fastest order.
+ *  * g1: read on every boundary node (faces, edges and corners).  g2: read on face-interior
+ *    nodes only; first kind = outward normal derivative, so on the face x = 0 it is -du/dx
+ *    and on x = 1 it is +du/dx; second kind = d2u/dx2 on x faces (likewise y, z).
+ *    f: read on interior nodes only.
+ *  * Pointers may be device (HBM) or host memory; the library detects which with
+ *    hipPointerGetAttributes and stages host arrays through device memory.  The caller owns
+ *    every array it passes; the library keeps no pointer after a call returns.
+ *  * Work is issued on the stream set with excmg_set_stream (default: the null stream) and
+ *    every entry point returns after its results are complete.
+ *  * The library holds one context per process (levels, workspace, cached factors).  Calls
+ *    are not thread-safe.
+ *  * Return codes: EXCMG_OK (0) or a negative code; excmg_last_error() describes the last
+ *    failure.  On EXCMG_ENOCONV the outputs hold the last iterate.
+ *
+ * Levels: a cascade of n_levels grids with N_l = N_0 * 2^l cells, l = 0 .. n_levels-1, where
+ * N_0 = n_finest / 2^(n_levels-1) >= 2 (n_finest must be divisible by 2^(n_levels-1)),
+ * n_levels >= 3.  Levels 0 and 1 are solved directly (DSOLVE); level l >= 2 is the paper's
+ * i = l-1 of L = n_levels-2 and stops at the relative-residual tolerance
+ * eps_i = tol * 10^(i-L).  Coarse-level data are the finest arrays sampled at every
+ * 2^(n_levels-1-l)-th node.
+ */
+#ifndef EXCMG_H
+#define EXCMG_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EXCMG_OK 0
+#define EXCMG_EINVAL (-1)     /* bad size, level count, bc kind, NULL pointer, no context  */
+#define EXCMG_ENOMEM (-2)     /* device allocation failed                                 */
+#define EXCMG_ENOCONV (-3)    /* iteration cap reached before the tolerance               */
+#define EXCMG_EBREAKDOWN (-4) /* Bi-CG denominator zero or non-finite (Algorithm 2)        */
+#define EXCMG_EHIP (-5)       /* a HIP runtime call failed                                */
+
+/* Precision of the Bi-CG vectors and stencil storage. */
+#define EXCMG_FP64 0          /* everything in FP64                                        */
+#define EXCMG_MIXED 1         /* FP32 Bi-CG inside an FP64 iterative-refinement loop       */
+
+#define EXCMG_MAX_LEVELS 16
+
+/* Options of excmg_solve_ex.  Zero-initialise and set what you need. */
+typedef struct excmg_opts {
+    int n_finest;       /* cells per axis on the finest grid                               */
+    int n_levels;       /* number of grids, >= 3                                            */
+    int bc_kind;        /* 1 or 2                                                           */
+    int precision;      /* EXCMG_FP64 or EXCMG_MIXED                                        */
+    double tol;         /* relative-residual tolerance eps of the finest level (> 0)       */
+    int max_iters;      /* Bi-CG iterations per run (0: 100000)                             */
+    int max_runs;       /* Bi-CG runs per level in Algorithm 1's while loop (0: 5)          */
+    double inner_tol;   /* mixed precision: relative tolerance of each FP32 solve (0: 1e-4) */
+    int max_outer;      /* mixed precision: refinement steps per level (0: 60)             */
+} excmg_opts;
+
+/* Per-level record filled by excmg_solve_ex (levels 0 and 1 report iterations = 0). */
+typedef struct excmg_level_stats {
+    int n;              /* cells per axis                                                    */
+    int iterations;     /* Bi-CG iterations (all runs; FP32 inner iterations when mixed)     */
+    int runs;           /* Bi-CG runs (FP64) or refinement steps (mixed)                     */
+    int status;         /* EXCMG_OK / EXCMG_ENOCONV / EXCMG_EBREAKDOWN                        */
+    double eps;         /* tolerance of the level                                             */
+    double rel_residual;/* final true ||b - A x||_2 / ||b||_2                                 */
+    double ms;          /* wall time of the level (device events)                            */
+} excmg_level_stats;
+
+typedef struct excmg_stats {
+    int n_levels;
+    excmg_level_stats level[EXCMG_MAX_LEVELS];
+    double total_ms;    /* whole solve, from entry to outputs written (device events)        */
+} excmg_stats;
+
+/* Use `stream` (a hipStream_t) for all later work; NULL selects the null stream. */
+int excmg_set_stream(void *stream);
+
+/* Build (or rebuild) the context for a cascade: level sizes, device workspace and the
+ * Cholesky factors of the two direct levels.  excmg_solve calls it implicitly. */
+int excmg_setup(int n_finest, int n_levels, int bc_kind);
+
+/* y = A_l x, or A_l^T x when transpose != 0, on level `level` (0 = coarsest) of the current
+ * context: the left-hand side of eq. (method1) with the fictitious points of eqs.
+ * (reflection2)/(reflection4) eliminated for zero boundary data (Sec. 2, eq. sec).  x and y
+ * are interior vectors of (N_l - 1)^3 values.  A_l is exactly symmetric, so both products
+ * use the same kernel.  The coefficients are the paper's integers (A u = h^4 f). */
+int excmg_apply_stencil(int level, int transpose, const double *x, double *y);
+
+/* The same operator on a grid of n cells per axis (n >= 2) without a context: y = A_h x (or
+ * A_h^T x) for interior vectors of (n-1)^3 values and boundary kind bc_kind. */
+int excmg_apply_operator(int n, int bc_kind, int transpose, const double *x, double *y);
+
+/* b = f_h of eq. (sec) on level `level`: h^4 f minus the known boundary terms that the
+ * 25-point scheme and the reflection formulas bring in (Sec. 2).  f, g1, g2 are FINEST-grid
+ * node arrays of the current context (sampled by injection); b is an interior vector. */
+int excmg_rhs(int level, const double *f, const double *g1, const double *g2, double *b);
+
+/* x = A_l^{-1} b by the cached dense Cholesky factor; level must be 0 or 1 (DSOLVE,
+ * Algorithm 1). */
+int excmg_dsolve(int level, const double *b, double *x);
+
+/* One Bi-CG run (Algorithm 2, preconditioner M = I, shadow residual r*_0 = r_0) on level
+ * `level` from the initial guess in x (overwritten by the final iterate): stops when the
+ * recurrence residual satisfies ||r||_2 <= eps ||b||_2 or after max_iters iterations.
+ * Outputs (may be NULL): iterations done and the final recurrence ||r||_2^2. */
+int excmg_bicg(int level, const double *b, double *x, double eps, int max_iters, int *iters,
+               double *rr);
+
+/* Algorithm 1's while loop on one level: Bi-CG runs from x until the TRUE relative residual
+ * ||b - A x||_2 / ||b||_2 <= eps (at most max_runs runs of max_iters iterations).  st may be
+ * NULL. */
+int excmg_level_solve(int level, const double *b, double *x, double eps, int max_iters,
+                      int max_runs, excmg_level_stats *st);
+
+/* w = EXP_finite(u1, u0) (Sec. 4.2.3, Steps 1-5): third-order approximation on the grid of n
+ * cells (n divisible by 4) of the finite-difference solution, from the node arrays u1 (n/2
+ * cells) and u0 (n/4 cells).  w is a node array of n cells.  Needs no context. */
+int excmg_exp_finite(int n, const double *u1, const double *u0, double *w);
+
+/* ut = EXP_true(uh, u2h) (Sec. 4.2.1, eqs. t1 and chenlin): higher-order approximation of the
+ * true solution on the grid of n cells (n even) from the node arrays uh (n cells) and u2h
+ * (n/2 cells).  Needs no context. */
+int excmg_exp_true(int n, const double *uh, const double *u2h, double *ut);
+
+/* Algorithm 1 in FP64: solve and write the finest finite-difference solution u_out (node
+ * array, boundary = g1).  f, g1, g2 are finest-grid node arrays; tol is eps of Algorithm 1. */
+int excmg_solve(int n_finest, int n_levels, int bc_kind, const double *f, const double *g1,
+                const double *g2, double tol, double *u_out);
+
+/* Algorithm 1 with options: opts->precision selects plain FP64 or FP32 Bi-CG inside FP64
+ * iterative refinement (residual, update, extrapolations and Bi-CG scalars stay FP64).
+ * ut_out (may be NULL) receives EXP_true(u_h, u_2h); st (may be NULL) per-level records. */
+int excmg_solve_ex(const excmg_opts *opts, const double *f, const double *g1, const double *g2,
+                   double *u_out, double *ut_out, excmg_stats *st);
+
+/* Measurement helper: launch one of the solver's sweeps `reps` times on the finest level of
+ * the current context (between two device events on the library stream) and report the mean
+ * duration of a launch and the algorithmic HBM bytes it moves (unknowns x vectors read and
+ * written x element size; halos and padding not counted).  Scratch vectors only: no caller
+ * array is touched, and the context's workspace contents are overwritten.
+ *   which 0: y = A x                      (2 vectors)
+ *         1: r = b - A x, r.r partials    (3 vectors)
+ *         2: Bi-CG sweep A: p, p* update + A p, A^T p* + sigma partials (8 vectors)
+ *         3: Bi-CG sweep B: x, r, r* update + rho, r.r partials         (9 vectors)
+ *         4: plain copy y = x             (2 vectors; bandwidth reference)
+ * precision selects FP64 or FP32 vectors (EXCMG_FP64 / EXCMG_MIXED). */
+int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launch,
+                        double *bytes_per_launch);
+
+/* Description of the last error (empty string if none). */
+const char *excmg_last_error(void);
+
+/* Free the context and all device workspace. */
+void excmg_finalize(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EXCMG_H */

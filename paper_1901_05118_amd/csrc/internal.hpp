@@ -1,0 +1,107 @@
+// Internal interfaces between the kernels and the host driver of the EXCMG library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace excmg {
+
+// Geometry of a z-marched stencil launch on an interior grid of n^3 unknowns.
+struct Geom {
+    int n;                          // unknowns per axis (N - 1)
+    int tiles_x, tiles_y, tiles_z;  // 64-wide x tiles, TY-high y tiles, ZC-deep z chunks
+    int zc;
+    int ntiles;
+    double sgn;                     // fictitious-point sign: +1 first kind, -1 second kind
+};
+
+Geom make_geom(int n, int bc, int ty, int zc);
+
+// Device-resident state of one Bi-CG run (Algorithm 2); all scalars FP64.
+struct BicgState {
+    double rho;      // r* . r of the current iterate
+    double sigma;    // p* . A p
+    double alpha;
+    double beta;
+    double rr;       // r . r (recurrence residual)
+    double bb;       // b . b
+    double thr;      // (eps * eps) * bb
+    int iter;        // iterations done in this run
+    int maxit;
+    int status;      // 0 running, 1 converged, -3 iteration cap, -4 breakdown
+    int pad;
+};
+
+constexpr int kRunning = 0, kConverged = 1, kNoConv = -3, kBreakdown = -4;
+
+// ---------------------------------------------------------------- stencil kernels
+
+template <typename T>
+hipError_t stencil_apply(const Geom &g, int ty, const T *x, T *y, hipStream_t st);
+
+// r = b - A x and per-tile Dot2 partials of r.r (one per launched block)
+template <typename T>
+hipError_t stencil_residual(const Geom &g, int ty, const double *b, const T *x, T *r,
+                            Pair *partials, hipStream_t st);
+
+// Sweep A of a Bi-CG iteration: p_new = r + beta p_old, ps_new = rs + beta ps_old (or
+// p_new = r, ps_new = rs when first), q = A p_new, qs = A ps_new, partials of ps_new . q.
+template <typename T>
+hipError_t stencil_pair_direction(const Geom &g, int ty, const T *r, const T *rs,
+                                  const T *p_old, const T *ps_old, const double *beta_dev,
+                                  int first, T *p_new, T *ps_new, T *q, T *qs, Pair *partials,
+                                  const int *status, hipStream_t st);
+
+inline int stencil_blocks(const Geom &g) { return xcd_grid(g.ntiles); }
+
+// ---------------------------------------------------------------- vector kernels
+
+int vec_blocks(long long n);
+
+// x += alpha p; r -= alpha q; rs -= alpha qs; partials of rs.r and r.r
+template <typename T>
+hipError_t bicg_update(long long n, const BicgState *s, T *x, const T *p, T *r, const T *q,
+                       T *rs, const T *qs, Pair *partials, hipStream_t st);
+
+// partials of x.y
+template <typename T>
+hipError_t dot_partials(long long n, const T *x, const T *y, Pair *partials, int nblocks,
+                        hipStream_t st);
+
+template <typename TD, typename TS>
+hipError_t copy_convert(long long n, const TS *src, TD *dst, hipStream_t st);
+
+// finalisation kernels (one workgroup): merge `count` partials
+hipError_t bicg_start(BicgState *s, const Pair *rr_part, int count, double eps, int maxit,
+                      hipStream_t st);   // rr = rho = r.r (r* = r), bb precomputed
+hipError_t bicg_alpha(BicgState *s, const Pair *part, int count, hipStream_t st);
+hipError_t bicg_beta(BicgState *s, const Pair *part, int count, hipStream_t st);
+hipError_t reduce_to(double *out, const Pair *part, int count, int slot, hipStream_t st);
+
+// ---------------------------------------------------------------- level kernels
+
+// b = h^4 f - known terms, from finest-grid node arrays sampled at `stride`
+hipError_t rhs_assemble(int N, int bc, int stride, int Nf, const double *f, const double *g1,
+                        const double *g2, double *b, hipStream_t st);
+
+// node array of N cells: interior from x (interior vector), boundary from g1 (finest
+// node array sampled at stride)
+template <typename T>
+hipError_t to_nodes(int N, int stride, int Nf, const T *x, const double *g1, double *u,
+                    hipStream_t st);
+
+// interior vector from a node array
+hipError_t from_nodes(int N, const double *u, double *x, hipStream_t st);
+
+hipError_t exp_finite(int N, const double *u1, const double *u0, double *v_scratch, double *w,
+                      hipStream_t st);
+hipError_t exp_true(int N, const double *uh, const double *u2h, double *ut, hipStream_t st);
+
+// dense direct solver of the two coarsest levels
+hipError_t dense_assemble(int N, int bc, double *A, hipStream_t st);
+hipError_t dense_cholesky(int n, double *A, int *info, hipStream_t st);
+hipError_t dense_solve(int n, const double *L, const double *b, double *x, double *y,
+                       hipStream_t st);
+
+}  // namespace excmg

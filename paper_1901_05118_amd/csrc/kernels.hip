@@ -1,0 +1,607 @@
+// Streaming, reduction, transfer and direct-solve kernels of the EXCMG library (gfx950).
+//
+// Every kernel here reproduces the arithmetic order its operation is specified with
+// (contraction off, sums left to right as the formulas are written), so results are
+// deterministic and independent of the launch shape.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace excmg {
+
+constexpr int kVecThreads = 256;
+
+int vec_blocks(long long n) {
+    long long b = (n + kVecThreads * 4 - 1) / (kVecThreads * 4);
+    if (b < 1) b = 1;
+    if (b > 4096) b = 4096;
+    return (int)b;
+}
+
+// ------------------------------------------------------------------ Bi-CG updates
+
+// Algorithm 2: x_{k+1} = x_k + alpha p_k, r_{k+1} = r_k - alpha A p_k,
+// r*_{k+1} = r*_k - alpha (p*_k A); partials of r*.r (rho of the next step) and r.r.
+template <typename T>
+__global__ void __launch_bounds__(kVecThreads)
+    k_bicg_update(long long n, const BicgState *s, T *x, const T *p, T *r, const T *q, T *rs,
+                  const T *qs, Pair *partials) {
+    __shared__ Pair sh[2 * (kVecThreads / kWave)];
+    if (s->status != kRunning) return;
+    const double alpha = s->alpha;
+    Pair acc[2] = {{0.0, 0.0}, {0.0, 0.0}};
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        double xi = (double)x[i] + alpha * (double)p[i];
+        double ri = (double)r[i] - alpha * (double)q[i];
+        double si = (double)rs[i] - alpha * (double)qs[i];
+        T xs = (T)xi, rt = (T)ri, st = (T)si;
+        x[i] = xs;
+        r[i] = rt;
+        rs[i] = st;
+        dot2_acc(acc[0], (double)st, (double)rt);
+        dot2_acc(acc[1], (double)rt, (double)rt);
+    }
+    block_merge<2>(acc, sh);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = acc[0];
+        partials[gridDim.x + blockIdx.x] = acc[1];
+    }
+}
+
+template <typename T>
+hipError_t bicg_update(long long n, const BicgState *s, T *x, const T *p, T *r, const T *q,
+                       T *rs, const T *qs, Pair *partials, hipStream_t st) {
+    hipLaunchKernelGGL(k_bicg_update<T>, dim3(vec_blocks(n)), dim3(kVecThreads), 0, st, n, s, x,
+                       p, r, q, rs, qs, partials);
+    return hipGetLastError();
+}
+template hipError_t bicg_update<double>(long long, const BicgState *, double *, const double *,
+                                        double *, const double *, double *, const double *,
+                                        Pair *, hipStream_t);
+template hipError_t bicg_update<float>(long long, const BicgState *, float *, const float *,
+                                       float *, const float *, float *, const float *, Pair *,
+                                       hipStream_t);
+
+template <typename T>
+__global__ void __launch_bounds__(kVecThreads)
+    k_dot(long long n, const T *x, const T *y, Pair *partials) {
+    __shared__ Pair sh[kVecThreads / kWave];
+    Pair acc[1] = {{0.0, 0.0}};
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        dot2_acc(acc[0], (double)x[i], (double)y[i]);
+    block_merge<1>(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
+}
+
+template <typename T>
+hipError_t dot_partials(long long n, const T *x, const T *y, Pair *partials, int nblocks,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_dot<T>, dim3(nblocks), dim3(kVecThreads), 0, st, n, x, y, partials);
+    return hipGetLastError();
+}
+template hipError_t dot_partials<double>(long long, const double *, const double *, Pair *, int,
+                                         hipStream_t);
+template hipError_t dot_partials<float>(long long, const float *, const float *, Pair *, int,
+                                        hipStream_t);
+
+template <typename TD, typename TS>
+__global__ void k_copy_convert(long long n, const TS *src, TD *dst) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        dst[i] = (TD)src[i];
+}
+
+template <typename TD, typename TS>
+hipError_t copy_convert(long long n, const TS *src, TD *dst, hipStream_t st) {
+    hipLaunchKernelGGL((k_copy_convert<TD, TS>), dim3(vec_blocks(n)), dim3(kVecThreads), 0, st, n,
+                       src, dst);
+    return hipGetLastError();
+}
+template hipError_t copy_convert<double, double>(long long, const double *, double *,
+                                                 hipStream_t);
+template hipError_t copy_convert<float, double>(long long, const double *, float *, hipStream_t);
+template hipError_t copy_convert<double, float>(long long, const float *, double *, hipStream_t);
+
+// ------------------------------------------------------------------ finalisation
+
+// Merge `count` pairs (stride apart per value) in a fixed order; result in thread 0.
+template <int NV>
+__device__ void merge_partials(const Pair *part, int count, Pair (&out)[NV], Pair *sh) {
+    for (int q = 0; q < NV; q++) out[q] = Pair{0.0, 0.0};
+    for (int i = threadIdx.x; i < count; i += blockDim.x) {
+#pragma unroll
+        for (int q = 0; q < NV; q++) out[q] = pair_merge(out[q], part[q * count + i]);
+    }
+    block_merge<NV>(out, sh);
+}
+
+__device__ void set_status(BicgState *s) {
+    // the order of the checks follows the loop of Algorithm 2 as run by the oracle
+    if (s->rr <= s->thr) s->status = kConverged;
+    else if (s->iter >= s->maxit) s->status = kNoConv;
+    else if (s->rho == 0.0 || !isfinite(s->rho)) s->status = kBreakdown;
+    else s->status = kRunning;
+}
+
+__global__ void __launch_bounds__(kReduceThreads)
+    k_bicg_start(BicgState *s, const Pair *part, int count, double eps, int maxit) {
+    __shared__ Pair sh[kReduceThreads / kWave];
+    Pair v[1];
+    merge_partials<1>(part, count, v, sh);
+    if (threadIdx.x == 0) {
+        double rr = pair_value(v[0]);
+        s->rr = rr;
+        s->rho = rr;  // r*_0 = r_0
+        s->thr = (eps * eps) * s->bb;
+        s->iter = 0;
+        s->maxit = maxit;
+        s->alpha = 0.0;
+        s->beta = 0.0;
+        s->sigma = 0.0;
+        set_status(s);
+    }
+}
+
+__global__ void __launch_bounds__(kReduceThreads)
+    k_bicg_alpha(BicgState *s, const Pair *part, int count) {
+    __shared__ Pair sh[kReduceThreads / kWave];
+    if (s->status != kRunning) return;
+    Pair v[1];
+    merge_partials<1>(part, count, v, sh);
+    if (threadIdx.x == 0) {
+        double sigma = pair_value(v[0]);
+        s->sigma = sigma;
+        if (sigma == 0.0 || !isfinite(sigma)) s->status = kBreakdown;
+        else s->alpha = s->rho / sigma;
+    }
+}
+
+__global__ void __launch_bounds__(kReduceThreads)
+    k_bicg_beta(BicgState *s, const Pair *part, int count) {
+    __shared__ Pair sh[2 * (kReduceThreads / kWave)];
+    if (s->status != kRunning) return;
+    Pair v[2];
+    merge_partials<2>(part, count, v, sh);
+    if (threadIdx.x == 0) {
+        double rho_new = pair_value(v[0]);
+        s->rr = pair_value(v[1]);
+        s->beta = rho_new / s->rho;
+        s->rho = rho_new;
+        s->iter = s->iter + 1;
+        set_status(s);
+    }
+}
+
+__global__ void __launch_bounds__(kReduceThreads)
+    k_reduce_to(double *out, const Pair *part, int count, int slot) {
+    __shared__ Pair sh[kReduceThreads / kWave];
+    Pair v[1];
+    merge_partials<1>(part, count, v, sh);
+    if (threadIdx.x == 0) out[slot] = pair_value(v[0]);
+}
+
+hipError_t bicg_start(BicgState *s, const Pair *rr_part, int count, double eps, int maxit,
+                      hipStream_t st) {
+    hipLaunchKernelGGL(k_bicg_start, dim3(1), dim3(kReduceThreads), 0, st, s, rr_part, count, eps,
+                       maxit);
+    return hipGetLastError();
+}
+hipError_t bicg_alpha(BicgState *s, const Pair *part, int count, hipStream_t st) {
+    hipLaunchKernelGGL(k_bicg_alpha, dim3(1), dim3(kReduceThreads), 0, st, s, part, count);
+    return hipGetLastError();
+}
+hipError_t bicg_beta(BicgState *s, const Pair *part, int count, hipStream_t st) {
+    hipLaunchKernelGGL(k_bicg_beta, dim3(1), dim3(kReduceThreads), 0, st, s, part, count);
+    return hipGetLastError();
+}
+hipError_t reduce_to(double *out, const Pair *part, int count, int slot, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce_to, dim3(1), dim3(kReduceThreads), 0, st, out, part, count, slot);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ right-hand side
+
+struct Finest {
+    const double *a;
+    int Nf, stride;
+    __device__ __forceinline__ double at(int i, int j, int k) const {
+        const i64 M = (i64)Nf + 1;
+        return a[((i64)k * stride * M + (i64)j * stride) * M + (i64)i * stride];
+    }
+};
+
+// Known value of the 25-point equation at node (i, j, k) of the level (-1..N+1 per axis):
+// interior nodes are unknowns (0 here), boundary nodes are g1, and a fictitious point
+// carries the data part of eq. (reflection2) or (reflection4) with the mirrored unknown
+// set to 0.
+__device__ __forceinline__ double known_value(int i, int j, int k, int N, int bc, double h,
+                                              const Finest &g1, const Finest &g2) {
+    const bool ii = (i >= 1 && i <= N - 1), ji = (j >= 1 && j <= N - 1), ki = (k >= 1 && k <= N - 1);
+    if (ii && ji && ki) return 0.0;
+    const bool ib = (i >= 0 && i <= N), jb = (j >= 0 && j <= N), kb = (k >= 0 && k <= N);
+    if (ib && jb && kb) return g1.at(i, j, k);
+    // fictitious point: exactly one coordinate is -1 or N+1, the others are interior
+    int fi = i, fj = j, fk = k;
+    bool low;
+    if (!ib) { low = (i < 0); fi = low ? 0 : N; }
+    else if (!jb) { low = (j < 0); fj = low ? 0 : N; }
+    else { low = (k < 0); fk = low ? 0 : N; }
+    const double gv = g2.at(fi, fj, fk);
+    const double mirror = 0.0;
+    if (bc == 1) {
+        const double dudx = low ? -gv : gv;
+        return low ? mirror - 2.0 * h * dudx : mirror + 2.0 * h * dudx;
+    }
+    const double u0 = g1.at(fi, fj, fk);
+    return -mirror + 2.0 * u0 + h * h * gv;
+}
+
+__global__ void __launch_bounds__(256)
+    k_rhs(int N, int bc, Finest f, Finest g1, Finest g2, double *b) {
+    const int n = N - 1;
+    const i64 total = (i64)n * n * n;
+    const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int i = (int)(t % n) + 1;
+    const int j = (int)((t / n) % n) + 1;
+    const int k = (int)(t / ((i64)n * n)) + 1;
+    const double h = 1.0 / (double)N;
+    const double h4 = h * h * h * h;
+    const double fv = f.at(i, j, k);
+    const bool deep = (i >= 3 && i <= N - 3 && j >= 3 && j <= N - 3 && k >= 3 && k <= N - 3);
+    if (deep) {  // every neighbour is an unknown: the known part is exactly +0
+        b[t] = h4 * fv - 0.0;
+        return;
+    }
+#define KV(di, dj, dk) known_value(i + (di), j + (dj), k + (dk), N, bc, h, g1, g2)
+    const double c = KV(0, 0, 0);
+    const double S1 = KV(-1, 0, 0) + KV(1, 0, 0) + KV(0, -1, 0) + KV(0, 1, 0) + KV(0, 0, -1) +
+                      KV(0, 0, 1);
+    const double S2 = KV(-2, 0, 0) + KV(2, 0, 0) + KV(0, -2, 0) + KV(0, 2, 0) + KV(0, 0, -2) +
+                      KV(0, 0, 2);
+    const double S3 = KV(-1, -1, 0) + KV(-1, 1, 0) + KV(1, -1, 0) + KV(1, 1, 0) +
+                      KV(-1, 0, -1) + KV(1, 0, -1) + KV(0, -1, -1) + KV(0, 1, -1) +
+                      KV(-1, 0, 1) + KV(1, 0, 1) + KV(0, -1, 1) + KV(0, 1, 1);
+#undef KV
+    const double E = 42.0 * c - 12.0 * S1 + S2 + 2.0 * S3;
+    b[t] = h4 * fv - E;
+}
+
+hipError_t rhs_assemble(int N, int bc, int stride, int Nf, const double *f, const double *g1,
+                        const double *g2, double *b, hipStream_t st) {
+    const i64 total = (i64)(N - 1) * (N - 1) * (N - 1);
+    Finest F{f, Nf, stride}, G1{g1, Nf, stride}, G2{g2, Nf, stride};
+    hipLaunchKernelGGL(k_rhs, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, N, bc, F,
+                       G1, G2, b);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ node arrays
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_to_nodes(int N, Finest g1, const T *x, double *u) {
+    const i64 M = (i64)N + 1;
+    const i64 total = M * M * M;
+    const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int i = (int)(t % M), j = (int)((t / M) % M), k = (int)(t / (M * M));
+    const bool interior = (i >= 1 && i <= N - 1 && j >= 1 && j <= N - 1 && k >= 1 && k <= N - 1);
+    if (interior) {
+        const i64 n = N - 1;
+        u[t] = (double)x[((i64)(k - 1) * n + (j - 1)) * n + (i - 1)];
+    } else {
+        u[t] = g1.at(i, j, k);
+    }
+}
+
+template <typename T>
+hipError_t to_nodes(int N, int stride, int Nf, const T *x, const double *g1, double *u,
+                    hipStream_t st) {
+    const i64 M = (i64)N + 1;
+    Finest G1{g1, Nf, stride};
+    hipLaunchKernelGGL(k_to_nodes<T>, dim3((unsigned)((M * M * M + 255) / 256)), dim3(256), 0, st,
+                       N, G1, x, u);
+    return hipGetLastError();
+}
+template hipError_t to_nodes<double>(int, int, int, const double *, const double *, double *,
+                                     hipStream_t);
+
+__global__ void __launch_bounds__(256) k_from_nodes(int N, const double *u, double *x) {
+    const i64 n = N - 1;
+    const i64 total = n * n * n;
+    const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const i64 i = t % n + 1, j = (t / n) % n + 1, k = t / (n * n) + 1;
+    const i64 M = (i64)N + 1;
+    x[t] = u[(k * M + j) * M + i];
+}
+
+hipError_t from_nodes(int N, const double *u, double *x, hipStream_t st) {
+    const i64 n = N - 1;
+    hipLaunchKernelGGL(k_from_nodes, dim3((unsigned)((n * n * n + 255) / 256)), dim3(256), 0, st,
+                       N, u, x);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ EXP_finite
+
+// Phase 1: the value of every node of Z1 (grid of N1 = N/2 cells), by its place in the
+// interpolation cells of Z0 (N0 = N/4 cells): Step 1 for nodes of Z0, eq. (secfff); Step 2
+// for edge midpoints, eq. (bfsec); Step 3 for face centres, the mean of eq. (bfsec) on the
+// two face diagonals; Step 4 for cell centres, the mean on the four space diagonals.
+struct Z1Grid {
+    const double *u1, *u0;
+    int N1, N0;
+    __device__ __forceinline__ double U1(int a, int b, int c) const {
+        const i64 M = (i64)N1 + 1;
+        return u1[((i64)c * M + b) * M + a];
+    }
+    __device__ __forceinline__ double U0(int a, int b, int c) const {  // even Z1 coordinates
+        const i64 M = (i64)N0 + 1;
+        return u0[((i64)(c / 2) * M + b / 2) * M + a / 2];
+    }
+    // eq. (bfsec) at Z1 node m on the segment from corner e to corner f
+    __device__ __forceinline__ double bfsec(int ma, int mb, int mc, int ea, int eb, int ec,
+                                            int fa, int fb, int fc) const {
+        return U1(ma, mb, mc) +
+               (1.0 / 8.0) * (U1(ea, eb, ec) - U0(ea, eb, ec) + U1(fa, fb, fc) - U0(fa, fb, fc));
+    }
+};
+
+__global__ void __launch_bounds__(256) k_exp_finite_z1(Z1Grid z, double *v) {
+    const i64 M = (i64)z.N1 + 1;
+    const i64 total = M * M * M;
+    const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int a = (int)(t % M), b = (int)((t / M) % M), c = (int)(t / (M * M));
+    const int pa = a & 1, pb = b & 1, pc = c & 1;
+    const int odd = pa + pb + pc;
+    double val;
+    if (odd == 0) {
+        val = (5.0 * z.U1(a, b, c) - z.U0(a, b, c)) / 4.0;
+    } else if (odd == 1) {
+        if (pa) val = z.bfsec(a, b, c, a - 1, b, c, a + 1, b, c);
+        else if (pb) val = z.bfsec(a, b, c, a, b - 1, c, a, b + 1, c);
+        else val = z.bfsec(a, b, c, a, b, c - 1, a, b, c + 1);
+    } else if (odd == 2) {
+        if (!pc) {        // face normal to z: diagonals in x-y
+            val = (z.bfsec(a, b, c, a - 1, b - 1, c, a + 1, b + 1, c) +
+                   z.bfsec(a, b, c, a + 1, b - 1, c, a - 1, b + 1, c)) / 2.0;
+        } else if (!pb) { // face normal to y: diagonals in x-z
+            val = (z.bfsec(a, b, c, a - 1, b, c - 1, a + 1, b, c + 1) +
+                   z.bfsec(a, b, c, a + 1, b, c - 1, a - 1, b, c + 1)) / 2.0;
+        } else {          // face normal to x: diagonals in y-z
+            val = (z.bfsec(a, b, c, a, b - 1, c - 1, a, b + 1, c + 1) +
+                   z.bfsec(a, b, c, a, b + 1, c - 1, a, b - 1, c + 1)) / 2.0;
+        }
+    } else {
+        val = (z.bfsec(a, b, c, a - 1, b - 1, c - 1, a + 1, b + 1, c + 1) +
+               z.bfsec(a, b, c, a + 1, b - 1, c - 1, a - 1, b + 1, c + 1) +
+               z.bfsec(a, b, c, a - 1, b + 1, c - 1, a + 1, b - 1, c + 1) +
+               z.bfsec(a, b, c, a + 1, b + 1, c - 1, a - 1, b - 1, c + 1)) / 4.0;
+    }
+    v[t] = val;
+}
+
+// Phase 2 (Step 5): every node of Z2 (N cells) from the 27 Z1 values of its interpolation
+// cell by tri-quadratic Lagrange interpolation, eqs. (inter)-(iinter).  Along an axis the
+// local position a = 0..4 (in steps of h) has the weights l_0, l_1, l_2 at xi = a/4; even
+// positions select one node with weight 1.  Terms are summed in the node order of the cell
+// (z slowest, x fastest) and zero-weight terms are skipped, which leaves every sum unchanged.
+__constant__ double kLag[5][3] = {{1.0, 0.0, 0.0},
+                                  {0.375, 0.75, -0.125},
+                                  {0.0, 1.0, 0.0},
+                                  {-0.125, 0.75, 0.375},
+                                  {0.0, 0.0, 1.0}};
+
+__global__ void __launch_bounds__(256) k_exp_finite_z2(int N, const double *v, double *w) {
+    const i64 M = (i64)N + 1;
+    const i64 total = M * M * M;
+    const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int i = (int)(t % M), j = (int)((t / M) % M), k = (int)(t / (M * M));
+    const int N1 = N / 2, N0 = N / 4;
+    const i64 M1 = (i64)N1 + 1;
+    if (((i | j | k) & 1) == 0) {
+        w[t] = v[((i64)(k / 2) * M1 + j / 2) * M1 + i / 2];
+        return;
+    }
+    const int cx = min(i / 4, N0 - 1), cy = min(j / 4, N0 - 1), cz = min(k / 4, N0 - 1);
+    const int a = i - 4 * cx, b = j - 4 * cy, c = k - 4 * cz;
+    const int alo = (a & 1) ? 0 : a / 2, ahi = (a & 1) ? 2 : a / 2;
+    const int blo = (b & 1) ? 0 : b / 2, bhi = (b & 1) ? 2 : b / 2;
+    const int clo = (c & 1) ? 0 : c / 2, chi = (c & 1) ? 2 : c / 2;
+    double val = 0.0;
+    for (int ga = clo; ga <= chi; ga++)
+        for (int be = blo; be <= bhi; be++)
+            for (int al = alo; al <= ahi; al++) {
+                const double wgt = kLag[a][al] * kLag[b][be] * kLag[c][ga];
+                val = val + wgt * v[((i64)(2 * cz + ga) * M1 + (2 * cy + be)) * M1 + (2 * cx + al)];
+            }
+    w[t] = val;
+}
+
+hipError_t exp_finite(int N, const double *u1, const double *u0, double *v_scratch, double *w,
+                      hipStream_t st) {
+    Z1Grid z{u1, u0, N / 2, N / 4};
+    const i64 M1 = (i64)N / 2 + 1;
+    hipLaunchKernelGGL(k_exp_finite_z1, dim3((unsigned)((M1 * M1 * M1 + 255) / 256)), dim3(256), 0,
+                       st, z, v_scratch);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const i64 M = (i64)N + 1;
+    hipLaunchKernelGGL(k_exp_finite_z2, dim3((unsigned)((M * M * M + 255) / 256)), dim3(256), 0,
+                       st, N, v_scratch, w);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ EXP_true
+
+// Coarse nodes: eq. (t1); edge midpoints of coarse cells: eq. (chenlin) along the edge; face
+// and cell centres: mean of eq. (chenlin) over the two face diagonals or four space
+// diagonals (the three-dimensional form of Steps 3-4).
+struct TrueGrid {
+    const double *uh, *u2h;
+    int N;
+    __device__ __forceinline__ double H(int i, int j, int k) const {
+        const i64 M = (i64)N + 1;
+        return uh[((i64)k * M + j) * M + i];
+    }
+    __device__ __forceinline__ double C(int i, int j, int k) const {  // even fine coordinates
+        const i64 M = (i64)N / 2 + 1;
+        return u2h[((i64)(k / 2) * M + j / 2) * M + i / 2];
+    }
+    __device__ __forceinline__ double chenlin(double mid, int ei, int ej, int ek, int fi, int fj,
+                                              int fk) const {
+        return mid + (1.0 / 6.0) * (H(ei, ej, ek) - C(ei, ej, ek) + H(fi, fj, fk) - C(fi, fj, fk));
+    }
+};
+
+__global__ void __launch_bounds__(256) k_exp_true(TrueGrid g, double *ut) {
+    const int N = g.N;
+    const i64 M = (i64)N + 1;
+    const i64 total = M * M * M;
+    const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int i = (int)(t % M), j = (int)((t / M) % M), k = (int)(t / (M * M));
+    const int oi = i & 1, oj = j & 1, ok = k & 1;
+    const double mid = g.H(i, j, k);
+    double v;
+    const int odd = oi + oj + ok;
+    if (odd == 0) {
+        v = (4.0 * mid - g.C(i, j, k)) / 3.0;
+    } else if (odd == 1) {
+        if (oi) v = g.chenlin(mid, i - 1, j, k, i + 1, j, k);
+        else if (oj) v = g.chenlin(mid, i, j - 1, k, i, j + 1, k);
+        else v = g.chenlin(mid, i, j, k - 1, i, j, k + 1);
+    } else if (odd == 2) {
+        if (!ok) v = (g.chenlin(mid, i - 1, j - 1, k, i + 1, j + 1, k) +
+                      g.chenlin(mid, i + 1, j - 1, k, i - 1, j + 1, k)) / 2.0;
+        else if (!oj) v = (g.chenlin(mid, i - 1, j, k - 1, i + 1, j, k + 1) +
+                           g.chenlin(mid, i + 1, j, k - 1, i - 1, j, k + 1)) / 2.0;
+        else v = (g.chenlin(mid, i, j - 1, k - 1, i, j + 1, k + 1) +
+                  g.chenlin(mid, i, j + 1, k - 1, i, j - 1, k + 1)) / 2.0;
+    } else {
+        v = (g.chenlin(mid, i - 1, j - 1, k - 1, i + 1, j + 1, k + 1) +
+             g.chenlin(mid, i + 1, j - 1, k - 1, i - 1, j + 1, k + 1) +
+             g.chenlin(mid, i - 1, j + 1, k - 1, i + 1, j - 1, k + 1) +
+             g.chenlin(mid, i + 1, j + 1, k - 1, i - 1, j - 1, k + 1)) / 4.0;
+    }
+    ut[t] = v;
+}
+
+hipError_t exp_true(int N, const double *uh, const double *u2h, double *ut, hipStream_t st) {
+    TrueGrid g{uh, u2h, N};
+    const i64 M = (i64)N + 1;
+    hipLaunchKernelGGL(k_exp_true, dim3((unsigned)((M * M * M + 255) / 256)), dim3(256), 0, st, g,
+                       ut);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ DSOLVE
+
+// Dense A_h of a small level: row r scatters the 25 coefficients of eq. (method1); a term on
+// a fictitious point folds onto the row's own unknown with factor +1 (first kind) or -1
+// (second kind); a term on a boundary node is data.  Entries are small integers, exact in
+// any order.
+__global__ void __launch_bounds__(256) k_dense_assemble(int N, int bc, double *A) {
+    const int n = N - 1;
+    const int nu = n * n * n;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nu) return;
+    double *row = A + (i64)r * nu;
+    for (int c = 0; c < nu; c++) row[c] = 0.0;
+    const int i = r % n + 1, j = (r / n) % n + 1, k = r / (n * n) + 1;
+    const int off[25][3] = {{0, 0, 0},   {-1, 0, 0},  {1, 0, 0},   {0, -1, 0},  {0, 1, 0},
+                            {0, 0, -1},  {0, 0, 1},   {-2, 0, 0},  {2, 0, 0},   {0, -2, 0},
+                            {0, 2, 0},   {0, 0, -2},  {0, 0, 2},   {-1, -1, 0}, {-1, 1, 0},
+                            {1, -1, 0},  {1, 1, 0},   {-1, 0, -1}, {1, 0, -1},  {0, -1, -1},
+                            {0, 1, -1},  {-1, 0, 1},  {1, 0, 1},   {0, -1, 1},  {0, 1, 1}};
+    const double sgn = (bc == 1) ? 1.0 : -1.0;
+    for (int t = 0; t < 25; t++) {
+        const double coef = (t == 0) ? 42.0 : (t <= 6) ? -12.0 : (t <= 12) ? 1.0 : 2.0;
+        int p[3] = {i + off[t][0], j + off[t][1], k + off[t][2]};
+        bool bnd = false, ghost = false;
+        for (int a = 0; a < 3; a++) {
+            if (p[a] == 0 || p[a] == N) bnd = true;
+            if (p[a] == -1) { p[a] = 1; ghost = true; }
+            if (p[a] == N + 1) { p[a] = N - 1; ghost = true; }
+        }
+        if (bnd) continue;
+        const int c = ((p[2] - 1) * n + (p[1] - 1)) * n + (p[0] - 1);
+        row[c] += ghost ? sgn * coef : coef;
+    }
+}
+
+hipError_t dense_assemble(int N, int bc, double *A, hipStream_t st) {
+    const int nu = (N - 1) * (N - 1) * (N - 1);
+    hipLaunchKernelGGL(k_dense_assemble, dim3((nu + 255) / 256), dim3(256), 0, st, N, bc, A);
+    return hipGetLastError();
+}
+
+// Right-looking-free Cholesky A = L L^T in one workgroup, L in the lower triangle of A
+// (row-major).  Column j: the pivot s = A_jj - sum_k L_jk^2 (k ascending) by one lane, then
+// every row i > j in parallel: (A_ij - sum_k L_ik L_jk) / L_jj, k ascending.
+__global__ void __launch_bounds__(1024) k_cholesky(int n, double *A, int *info) {
+    __shared__ double piv;
+    __shared__ int fail;
+    if (threadIdx.x == 0) fail = 0;
+    for (int jj = 0; jj < n; jj++) {
+        if (threadIdx.x == 0) {
+            double s = A[(i64)jj * n + jj];
+            for (int k = 0; k < jj; k++) s -= A[(i64)jj * n + k] * A[(i64)jj * n + k];
+            if (!(s > 0.0)) fail = jj + 1;
+            const double d = sqrt(s);
+            A[(i64)jj * n + jj] = d;
+            piv = d;
+        }
+        __syncthreads();
+        if (fail) break;
+        const double d = piv;
+        for (int i = jj + 1 + threadIdx.x; i < n; i += blockDim.x) {
+            double t = A[(i64)i * n + jj];
+            for (int k = 0; k < jj; k++) t -= A[(i64)i * n + k] * A[(i64)jj * n + k];
+            A[(i64)i * n + jj] = t / d;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *info = fail;
+}
+
+hipError_t dense_cholesky(int n, double *A, int *info, hipStream_t st) {
+    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, st, n, A, info);
+    return hipGetLastError();
+}
+
+// L y = b then L^T x = y.  Forward: column-oriented updates keep every row's subtraction
+// order (k ascending), so the work is spread over the workgroup.  Backward: row i needs
+// x_{i+1} first but subtracts it first, so one lane runs it in order.
+__global__ void __launch_bounds__(1024) k_trisolve(int n, const double *L, const double *b,
+                                                   double *x, double *y) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) y[i] = b[i];
+    __syncthreads();
+    for (int k = 0; k < n; k++) {
+        if (threadIdx.x == 0) y[k] = y[k] / L[(i64)k * n + k];
+        __syncthreads();
+        const double yk = y[k];
+        for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) y[i] -= L[(i64)i * n + k] * yk;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        for (int i = n - 1; i >= 0; i--) {
+            double t = y[i];
+            for (int k = i + 1; k < n; k++) t -= L[(i64)k * n + i] * x[k];
+            x[i] = t / L[(i64)i * n + i];
+        }
+    }
+}
+
+hipError_t dense_solve(int n, const double *L, const double *b, double *x, double *y,
+                       hipStream_t st) {
+    hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(1024), 0, st, n, L, b, x, y);
+    return hipGetLastError();
+}
+
+}  // namespace excmg

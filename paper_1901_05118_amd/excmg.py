@@ -1,0 +1,230 @@
+"""ctypes binding of the C ABI in ``include/excmg.h`` (argument marshalling only).
+
+Array arguments may be torch tensors (device or host) or numpy arrays; they must be
+float64 and contiguous with the size the C function expects.  Device tensors are passed as
+device pointers; host arrays are staged by the library.  Every function raises
+``ExcmgError`` on a negative return code (``bicg``, ``level_solve`` and ``solve_ex`` return
+the code together with their results instead, for the codes that still produce output)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = [
+    "ExcmgError", "OK", "EINVAL", "ENOMEM", "ENOCONV", "EBREAKDOWN", "EHIP", "FP64", "MIXED",
+    "lib_path", "load", "set_stream", "setup", "apply_stencil", "apply_operator", "rhs", "dsolve", "bicg",
+    "level_solve", "exp_finite", "exp_true", "solve", "solve_ex", "profile_sweep",
+    "last_error", "finalize",
+    "LevelStats", "Stats",
+]
+
+OK, EINVAL, ENOMEM, ENOCONV, EBREAKDOWN, EHIP = 0, -1, -2, -3, -4, -5
+FP64, MIXED = 0, 1
+MAX_LEVELS = 16
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+lib_path = os.path.join(_HERE, "libexcmg.so")
+
+
+class ExcmgError(RuntimeError):
+    def __init__(self, fn, code, msg):
+        super().__init__(f"{fn} returned {code}: {msg}")
+        self.code = code
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("n_finest", ctypes.c_int), ("n_levels", ctypes.c_int),
+                ("bc_kind", ctypes.c_int), ("precision", ctypes.c_int),
+                ("tol", ctypes.c_double), ("max_iters", ctypes.c_int),
+                ("max_runs", ctypes.c_int), ("inner_tol", ctypes.c_double),
+                ("max_outer", ctypes.c_int)]
+
+
+class LevelStats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("iterations", ctypes.c_int), ("runs", ctypes.c_int),
+                ("status", ctypes.c_int), ("eps", ctypes.c_double),
+                ("rel_residual", ctypes.c_double), ("ms", ctypes.c_double)]
+
+    def asdict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int), ("level", LevelStats * MAX_LEVELS),
+                ("total_ms", ctypes.c_double)]
+
+    def levels(self):
+        return [self.level[i].asdict() for i in range(self.n_levels)]
+
+
+_lib = None
+
+
+def load():
+    """Load the HIP library.  It must have been built (``__graft_entry__.build()``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(lib_path):
+        raise ImportError(f"{lib_path} is not built; run __graft_entry__.build() first")
+    L = ctypes.CDLL(lib_path)
+    vp, dp, ip = ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)
+    c_int, c_dbl = ctypes.c_int, ctypes.c_double
+    sig = {
+        "excmg_set_stream": (c_int, [vp]),
+        "excmg_setup": (c_int, [c_int, c_int, c_int]),
+        "excmg_apply_stencil": (c_int, [c_int, c_int, dp, dp]),
+        "excmg_apply_operator": (c_int, [c_int, c_int, c_int, dp, dp]),
+        "excmg_rhs": (c_int, [c_int, dp, dp, dp, dp]),
+        "excmg_dsolve": (c_int, [c_int, dp, dp]),
+        "excmg_bicg": (c_int, [c_int, dp, dp, c_dbl, c_int, ip, ctypes.POINTER(c_dbl)]),
+        "excmg_level_solve": (c_int, [c_int, dp, dp, c_dbl, c_int, c_int,
+                                      ctypes.POINTER(LevelStats)]),
+        "excmg_exp_finite": (c_int, [c_int, dp, dp, dp]),
+        "excmg_exp_true": (c_int, [c_int, dp, dp, dp]),
+        "excmg_solve": (c_int, [c_int, c_int, c_int, dp, dp, dp, c_dbl, dp]),
+        "excmg_solve_ex": (c_int, [ctypes.POINTER(Opts), dp, dp, dp, dp, dp,
+                                   ctypes.POINTER(Stats)]),
+        "excmg_profile_sweep": (c_int, [c_int, c_int, c_int, ctypes.POINTER(c_dbl),
+                                        ctypes.POINTER(c_dbl)]),
+        "excmg_last_error": (ctypes.c_char_p, []),
+        "excmg_finalize": (None, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return load().excmg_last_error().decode()
+
+
+def _check(fn, rc):
+    if rc != OK:
+        raise ExcmgError(fn, rc, last_error())
+    return rc
+
+
+def _ptr(a, count=None, name="array"):
+    """Address of a float64 contiguous torch tensor or numpy array (None -> NULL)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        if a.dtype != np.float64 or not a.flags.c_contiguous:
+            raise TypeError(f"{name}: need a contiguous float64 array")
+        n = a.size
+        p = a.ctypes.data
+    else:
+        import torch
+        if not isinstance(a, torch.Tensor):
+            raise TypeError(f"{name}: expected a torch tensor or numpy array")
+        if a.dtype != torch.float64 or not a.is_contiguous():
+            raise TypeError(f"{name}: need a contiguous float64 tensor")
+        n = a.numel()
+        p = a.data_ptr()
+    if count is not None and n != count:
+        raise ValueError(f"{name}: expected {count} values, got {n}")
+    return ctypes.c_void_p(p)
+
+
+def set_stream(stream=None):
+    """Issue later work on ``stream`` (a torch.cuda.Stream, a raw hipStream_t, or None)."""
+    h = None
+    if stream is not None:
+        h = getattr(stream, "cuda_stream", stream)
+    _check("excmg_set_stream", load().excmg_set_stream(ctypes.c_void_p(h) if h else None))
+
+
+def setup(n_finest: int, n_levels: int, bc_kind: int):
+    _check("excmg_setup", load().excmg_setup(n_finest, n_levels, bc_kind))
+
+
+def apply_stencil(level: int, transpose: int, x, y):
+    _check("excmg_apply_stencil", load().excmg_apply_stencil(level, int(transpose), _ptr(x, name="x"),
+                                                             _ptr(y, name="y")))
+
+
+def apply_operator(n: int, bc_kind: int, transpose: int, x, y):
+    _check("excmg_apply_operator", load().excmg_apply_operator(n, bc_kind, int(transpose),
+                                                               _ptr(x, name="x"), _ptr(y, name="y")))
+
+
+def rhs(level: int, f, g1, g2, b):
+    _check("excmg_rhs", load().excmg_rhs(level, _ptr(f, name="f"), _ptr(g1, name="g1"),
+                                         _ptr(g2, name="g2"), _ptr(b, name="b")))
+
+
+def dsolve(level: int, b, x):
+    _check("excmg_dsolve", load().excmg_dsolve(level, _ptr(b, name="b"), _ptr(x, name="x")))
+
+
+def bicg(level: int, b, x, eps: float, max_iters: int = 100000):
+    """One Bi-CG run from x (in place).  Returns (code, iterations, recurrence r.r)."""
+    it = ctypes.c_int(0)
+    rr = ctypes.c_double(0.0)
+    rc = load().excmg_bicg(level, _ptr(b, name="b"), _ptr(x, name="x"), eps, max_iters,
+                           ctypes.byref(it), ctypes.byref(rr))
+    if rc not in (OK, ENOCONV, EBREAKDOWN):
+        _check("excmg_bicg", rc)
+    return rc, it.value, rr.value
+
+
+def level_solve(level: int, b, x, eps: float, max_iters: int = 100000, max_runs: int = 5):
+    """Algorithm 1's loop on one level.  Returns (code, stats dict)."""
+    st = LevelStats()
+    rc = load().excmg_level_solve(level, _ptr(b, name="b"), _ptr(x, name="x"), eps, max_iters,
+                                  max_runs, ctypes.byref(st))
+    if rc not in (OK, ENOCONV, EBREAKDOWN):
+        _check("excmg_level_solve", rc)
+    return rc, st.asdict()
+
+
+def exp_finite(n: int, u1, u0, w):
+    _check("excmg_exp_finite", load().excmg_exp_finite(n, _ptr(u1, name="u1"), _ptr(u0, name="u0"),
+                                                       _ptr(w, name="w")))
+
+
+def exp_true(n: int, uh, u2h, ut):
+    _check("excmg_exp_true", load().excmg_exp_true(n, _ptr(uh, name="uh"), _ptr(u2h, name="u2h"),
+                                                   _ptr(ut, name="ut")))
+
+
+def solve(n_finest: int, n_levels: int, bc_kind: int, f, g1, g2, tol: float, u_out):
+    _check("excmg_solve", load().excmg_solve(n_finest, n_levels, bc_kind, _ptr(f, name="f"),
+                                             _ptr(g1, name="g1"), _ptr(g2, name="g2"), tol,
+                                             _ptr(u_out, name="u_out")))
+
+
+def solve_ex(n_finest: int, n_levels: int, bc_kind: int, f, g1, g2, tol: float, u_out,
+             ut_out=None, precision: int = FP64, max_iters: int = 0, max_runs: int = 0,
+             inner_tol: float = 0.0, max_outer: int = 0):
+    """Algorithm 1 with options.  Returns (code, Stats)."""
+    o = Opts(n_finest, n_levels, bc_kind, precision, tol, max_iters, max_runs, inner_tol,
+             max_outer)
+    st = Stats()
+    rc = load().excmg_solve_ex(ctypes.byref(o), _ptr(f, name="f"), _ptr(g1, name="g1"),
+                               _ptr(g2, name="g2"), _ptr(u_out, name="u_out"),
+                               _ptr(ut_out, name="ut_out"), ctypes.byref(st))
+    if rc not in (OK, ENOCONV, EBREAKDOWN):
+        _check("excmg_solve_ex", rc)
+    return rc, st
+
+
+def profile_sweep(which: int, precision: int = FP64, reps: int = 20):
+    """Mean ms per launch and algorithmic bytes per launch of a solver sweep on the finest
+    level of the current context (see excmg.h)."""
+    ms = ctypes.c_double(0.0)
+    nb = ctypes.c_double(0.0)
+    _check("excmg_profile_sweep", load().excmg_profile_sweep(which, precision, reps,
+                                                             ctypes.byref(ms), ctypes.byref(nb)))
+    return ms.value, nb.value
+
+
+def finalize():
+    if _lib is not None:
+        _lib.excmg_finalize()
