@@ -153,14 +153,25 @@ int excmg_solve_ex(const excmg_opts *opts, const double *f, const double *g1, co
  * duration of a launch and the algorithmic HBM bytes it moves (unknowns x vectors read and
  * written x element size; halos and padding not counted).  Scratch vectors only: no caller
  * array is touched, and the context's workspace contents are overwritten.
- *   which 0: y = A x                      (2 vectors)
- *         1: r = b - A x, r.r partials    (3 vectors)
- *         2: Bi-CG sweep A: p, p* update + A p, A^T p* + sigma partials (8 vectors)
- *         3: Bi-CG sweep B: x, r, r* update + rho, r.r partials         (9 vectors)
- *         4: plain copy y = x             (2 vectors; bandwidth reference)
- * precision selects FP64 or FP32 vectors (EXCMG_FP64 / EXCMG_MIXED). */
+ *   which 0: y = A x                                         FP64 16 B, mixed 8 B
+ *         1: r = b - A x, r.r partials (mixed: FP64 residual of the FP64 iterate, stored
+ *            as FP32 r and r*)                                  FP64 24 B, mixed 24 B
+ *         2: Bi-CG sweep A: p, p* update + A p, A^T p* + sigma  FP64 64 B, mixed 32 B
+ *         3: Bi-CG sweep B: x, r, r* update + rho, r.r (mixed: FP64 x, FP32 rest)
+ *                                                               FP64 72 B, mixed 44 B
+ *         4: plain copy y = x (bandwidth reference)            FP64 16 B, mixed 8 B
+ * (bytes per unknown).  precision selects EXCMG_FP64 or EXCMG_MIXED. */
 int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launch,
                         double *bytes_per_launch);
+
+/* Launch shape of the z-marched stencil kernels on grids of n cells: tiles of 64 x ty
+ * columns marching through chunks of zc planes.  kind 0: the one-array kernels (operator,
+ * residual; ty = 4, 8 or 16); kind 1: Bi-CG sweep A (two arrays; ty = 4 or 8).  ty = 0
+ * restores the built-in rule.  Applies to later launches, including levels of the current
+ * context.  The autotuner uses it; results do not depend on the shape (every output is
+ * computed with the same arithmetic). */
+int excmg_set_shape(int n, int kind, int ty, int zc);
+int excmg_get_shape(int n, int kind, int *ty, int *zc);
 
 /* Description of the last error (empty string if none). */
 const char *excmg_last_error(void);

@@ -131,8 +131,7 @@ struct Level {
     int n = 0;        // unknowns per axis
     long long nu = 0; // unknowns
     long long nodes = 0;
-    int ty = 8;
-    Geom geom{};
+    Geom g1{}, g2{};  // launch shapes: single-array kernels, Bi-CG sweep A
     DBuf b, x, u;     // right-hand side, unknowns, node array (solution or EXP_finite guess)
 };
 
@@ -172,23 +171,38 @@ struct Ctx {
 
 Ctx g_ctx;
 
-// Launch shape per level: 64 x TY tiles, z chunks sized so the launch has enough
-// workgroups to fill 256 CUs.
-void choose_shape(Level &L, int bc) {
-    const int n = L.n;
-    L.ty = (n >= 96) ? 8 : 4;
-    const int tiles_xy = ((n + kWave - 1) / kWave) * ((n + L.ty - 1) / L.ty);
-    int zc = 8;
-    for (int cand : {64, 32, 16, 8}) {
-        int tz = (n + cand - 1) / cand;
-        if ((long long)tiles_xy * tz >= 2048) {
+// Tile shapes chosen by the autotuner (or a caller) per grid size and kernel kind.
+struct ShapeOverride {
+    int N, kind, ty, zc;
+};
+std::vector<ShapeOverride> g_shapes;
+
+// Default launch shape: 64 x TY column tiles, and the longest z chunk that still gives
+// every CU a tile (measured on MI355X: fewer, longer marches beat more, shorter ones,
+// because each chunk re-reads four halo planes).  kind 0: one marched array (apply,
+// residual); kind 1: two marched arrays (Bi-CG sweep A), which holds twice the column state
+// and stays at TY = 8 to keep its registers below 256.
+Geom choose_shape(int N, int bc, int kind) {
+    const int n = N - 1;
+    for (const ShapeOverride &o : g_shapes)
+        if (o.N == N && o.kind == kind) return make_geom(n, bc, o.ty, std::max(1, std::min(o.zc, n)));
+    const int ty = (kind == 0 && n >= 255) ? 16 : (n >= 24 ? 8 : 4);
+    const int tiles_xy = ((n + kWave - 1) / kWave) * ((n + ty - 1) / ty);
+    int zc = 4;
+    for (int cand = 512; cand >= 4; cand >>= 1) {
+        const int tz = (n + cand - 1) / cand;
+        if ((long long)tiles_xy * tz >= 256) {
             zc = cand;
             break;
         }
     }
-    if (zc > n) zc = n;
-    if (zc < 1) zc = 1;
-    L.geom = make_geom(n, bc, L.ty, zc);
+    zc = std::max(1, std::min(zc, n));
+    return make_geom(n, bc, ty, zc);
+}
+
+void choose_shapes(Level &L, int bc) {
+    L.g1 = choose_shape(L.N, bc, 0);
+    L.g2 = choose_shape(L.N, bc, 1);
 }
 
 int check_sizes(int n_finest, int n_levels, int bc) {
@@ -224,7 +238,7 @@ int setup(int n_finest, int n_levels, int bc) {
         L.n = L.N - 1;
         L.nu = (long long)L.n * L.n * L.n;
         L.nodes = (long long)(L.N + 1) * (L.N + 1) * (L.N + 1);
-        choose_shape(L, bc);
+        choose_shapes(L, bc);
         CKR(L.b.ensure(L.nu * 8));
         CKR(L.x.ensure(L.nu * 8));
         CKR(L.u.ensure(L.nodes * 8));
@@ -240,7 +254,7 @@ int setup(int n_finest, int n_levels, int bc) {
     CKR(c.q.ensure(vb));
     CKR(c.qs.ensure(vb));
     int maxblk = 4096 * 2;
-    for (auto &L : c.lv) maxblk = std::max(maxblk, stencil_blocks(L.geom));
+    for (auto &L : c.lv) maxblk = std::max({maxblk, stencil_blocks(L.g1), stencil_blocks(L.g2)});
     CKR(c.part_a.ensure((size_t)maxblk * sizeof(Pair)));
     CKR(c.part_b.ensure((size_t)2 * 4096 * sizeof(Pair)));
     CKR(c.state.ensure(sizeof(BicgState)));
@@ -297,8 +311,8 @@ int read_state(BicgState &s) {
 // r = b - A x on the level, and r.r into scal[slot]
 int true_residual(const Level &L, const double *b, const double *x, double *r, int slot) {
     Ctx &c = g_ctx;
-    CKH(stencil_residual<double>(L.geom, L.ty, b, x, r, c.part_a.as<Pair>(), g_stream));
-    CKH(reduce_to(c.scal.as<double>(), c.part_a.as<Pair>(), stencil_blocks(L.geom), slot,
+    CKH(stencil_residual<double>(L.g1, L.g1.ty, b, x, r, c.part_a.as<Pair>(), g_stream));
+    CKH(reduce_to(c.scal.as<double>(), c.part_a.as<Pair>(), stencil_blocks(L.g1), slot,
                   g_stream));
     return EXCMG_OK;
 }
@@ -322,11 +336,11 @@ int bicg_run(const Level &L, const double *b, double *x, double eps, int maxit, 
     double *q = c.q.as<double>(), *qs = c.qs.as<double>();
     // b.b and r_0 = b - A x_0, r*_0 = r_0
     CKR(device_dot(L.nu, b, b, (double *)&S->bb, 0));
-    CKH(stencil_residual<double>(L.geom, L.ty, b, x, r, c.part_a.as<Pair>(), g_stream));
+    CKH(stencil_residual<double>(L.g1, L.g1.ty, b, x, r, c.part_a.as<Pair>(), g_stream));
     CKH((copy_convert<double, double>(L.nu, r, rs, g_stream)));
-    CKH(bicg_start(S, c.part_a.as<Pair>(), stencil_blocks(L.geom), eps, maxit, g_stream));
+    CKH(bicg_start(S, c.part_a.as<Pair>(), stencil_blocks(L.g1), eps, maxit, g_stream));
     const int K = poll_interval(L.nu);
-    const int nsb = stencil_blocks(L.geom);
+    const int nsb = stencil_blocks(L.g2);
     const int nvb = vec_blocks(L.nu);
     BicgState hs;
     CKR(read_state(hs));
@@ -335,12 +349,13 @@ int bicg_run(const Level &L, const double *b, double *x, double eps, int maxit, 
         for (int t = 0; t < K; t++, j++) {
             const int cur = (int)(j & 1), nxt = cur ^ 1;
             double *pn = c.p[nxt].as<double>(), *psn = c.ps[nxt].as<double>();
-            CKH(stencil_pair_direction<double>(L.geom, L.ty, r, rs, c.p[cur].as<double>(),
+            CKH(stencil_pair_direction<double>(L.g2, L.g2.ty, r, rs, c.p[cur].as<double>(),
                                                c.ps[cur].as<double>(), &S->beta, j == 0 ? 1 : 0,
                                                pn, psn, q, qs, c.part_a.as<Pair>(), &S->status,
                                                g_stream));
             CKH(bicg_alpha(S, c.part_a.as<Pair>(), nsb, g_stream));
-            CKH(bicg_update<double>(L.nu, S, x, pn, r, q, rs, qs, c.part_b.as<Pair>(), g_stream));
+            CKH((bicg_update<double, double>(L.nu, S, x, pn, r, q, rs, qs, c.part_b.as<Pair>(),
+                                             g_stream)));
             CKH(bicg_beta(S, c.part_b.as<Pair>(), nvb, g_stream));
         }
         CKR(read_state(hs));
@@ -395,20 +410,113 @@ int level_solve(const Level &L, const double *b, double *x, double eps, int maxi
     return EXCMG_OK;
 }
 
+// ------------------------------------------------------------------ mixed precision
+
+// One FP32 Bi-CG run for A e = r32 (r32 = r*32 already written by the outer residual), e
+// starting at 0 and accumulated directly into the FP64 iterate u (u + e is the refined
+// solution).  Vectors FP32, scalars and dot products FP64.  Stops at the relative
+// recurrence residual inner_tol.
+int bicg_inner_fp32(const Level &L, double *u, double inner_tol, int maxit, int *iters,
+                    int *status_out) {
+    Ctx &c = g_ctx;
+    BicgState *S = c.state.as<BicgState>();
+    float *r = c.r.as<float>(), *rs = c.rs.as<float>();
+    float *q = c.q.as<float>(), *qs = c.qs.as<float>();
+    const int nvb = vec_blocks(L.nu);
+    CKH(dot_partials<float>(L.nu, r, r, c.part_b.as<Pair>(), nvb, g_stream));
+    CKH(reduce_to((double *)&S->bb, c.part_b.as<Pair>(), nvb, 0, g_stream));
+    CKH(bicg_start(S, c.part_b.as<Pair>(), nvb, inner_tol, maxit, g_stream));
+    const int K = poll_interval(L.nu);
+    const int nsb = stencil_blocks(L.g2);
+    BicgState hs;
+    CKR(read_state(hs));
+    long long j = 0;
+    while (hs.status == kRunning) {
+        for (int t = 0; t < K; t++, j++) {
+            const int cur = (int)(j & 1), nxt = cur ^ 1;
+            float *pn = c.p[nxt].as<float>(), *psn = c.ps[nxt].as<float>();
+            CKH(stencil_pair_direction<float>(L.g2, L.g2.ty, r, rs, c.p[cur].as<float>(),
+                                              c.ps[cur].as<float>(), &S->beta, j == 0 ? 1 : 0,
+                                              pn, psn, q, qs, c.part_a.as<Pair>(), &S->status,
+                                              g_stream));
+            CKH(bicg_alpha(S, c.part_a.as<Pair>(), nsb, g_stream));
+            CKH((bicg_update<double, float>(L.nu, S, u, pn, r, q, rs, qs, c.part_b.as<Pair>(),
+                                            g_stream)));
+            CKH(bicg_beta(S, c.part_b.as<Pair>(), nvb, g_stream));
+        }
+        CKR(read_state(hs));
+    }
+    if (iters) *iters = hs.iter;
+    if (status_out) *status_out = hs.status;
+    return EXCMG_OK;
+}
+
+// Iterative refinement on one level: r = b - A u in FP64 (rounded to FP32 for the inner
+// solve), FP32 Bi-CG correction added to u in FP64, until ||b - A u||_2 <= eps ||b||_2 in
+// FP64.  Stops early (EXCMG_ENOCONV) if an outer step fails to reduce the FP64 residual.
+int level_solve_mixed(const Level &L, const double *b, double *u, double eps, int maxit,
+                      int max_outer, double inner_tol, excmg_level_stats *st) {
+    Ctx &c = g_ctx;
+    double *sc = c.scal.as<double>();
+    CKR(device_dot(L.nu, b, b, sc, 1));
+    const int nrb = stencil_blocks(L.g1);
+    int total = 0, outer = 0, status = EXCMG_OK;
+    double bb = 0.0, rr = 0.0, prev = INFINITY;
+    for (;;) {
+        CKH(stencil_residual_cast(L.g1, L.g1.ty, b, u, c.r.as<float>(), c.rs.as<float>(),
+                                  c.part_a.as<Pair>(), g_stream));
+        CKH(reduce_to(sc, c.part_a.as<Pair>(), nrb, 2, g_stream));
+        CKH(hipMemcpyAsync(c.host_scal, sc, 3 * sizeof(double), hipMemcpyDeviceToHost, g_stream));
+        CKH(hipStreamSynchronize(g_stream));
+        bb = c.host_scal[1];
+        rr = c.host_scal[2];
+        if (rr <= (eps * eps) * bb) break;
+        if (outer >= max_outer || !(rr < prev)) {
+            status = EXCMG_ENOCONV;
+            break;
+        }
+        prev = rr;
+        // no need to solve the correction much more accurately than the outer target
+        double it = std::max(inner_tol, 0.3 * eps * std::sqrt(bb / rr));
+        if (it > 0.5) it = 0.5;
+        int its = 0, bst = 0;
+        CKR(bicg_inner_fp32(L, u, it, maxit, &its, &bst));
+        total += its;
+        outer++;
+        if (bst == kBreakdown) {
+            status = EXCMG_EBREAKDOWN;
+            break;
+        }
+    }
+    if (st) {
+        st->n = L.N;
+        st->iterations = total;
+        st->runs = outer;
+        st->status = status;
+        st->eps = eps;
+        st->rel_residual = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+    }
+    return EXCMG_OK;
+}
+
 double level_tolerance(double tol, int i, int L) {
     double p = 1.0;
     for (int t = 0; t < L - i; t++) p *= 10.0;
     return tol / p;
 }
 
-// Algorithm 1, FP64.  f, g1, g2 are device node arrays of the finest grid.
-int solve_fp64(const excmg_opts &o, const double *f, const double *g1, const double *g2,
-               double *u_out, double *ut_out, excmg_stats *st) {
+// Algorithm 1.  f, g1, g2 are device node arrays of the finest grid.  Bi-CG levels run in
+// FP64 or as FP32 Bi-CG inside FP64 iterative refinement (opts.precision).
+int solve_cascade(const excmg_opts &o, const double *f, const double *g1, const double *g2,
+                  double *u_out, double *ut_out, excmg_stats *st) {
     Ctx &c = g_ctx;
     const int nl = o.n_levels, Nf = o.n_finest;
     const int L = nl - 2;
     const int maxit = o.max_iters > 0 ? o.max_iters : 100000;
     const int max_runs = o.max_runs > 0 ? o.max_runs : 5;
+    const int max_outer = o.max_outer > 0 ? o.max_outer : 60;
+    const double inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-4;
+    const bool mixed = (o.precision == EXCMG_MIXED);
     hipEvent_t ev0, ev1, evl0, evl1;
     CKH(hipEventCreate(&ev0));
     CKH(hipEventCreate(&ev1));
@@ -432,7 +540,12 @@ int solve_fp64(const excmg_opts &o, const double *f, const double *g1, const dou
                            c.vz1.as<double>(), Lv.u.as<double>(), g_stream));
             CKH(from_nodes(Lv.N, Lv.u.as<double>(), Lv.x.as<double>(), g_stream));
             const double eps = level_tolerance(o.tol, l - 1, L);
-            CKR(level_solve(Lv, Lv.b.as<double>(), Lv.x.as<double>(), eps, maxit, max_runs, &ls));
+            if (mixed)
+                CKR(level_solve_mixed(Lv, Lv.b.as<double>(), Lv.x.as<double>(), eps, maxit,
+                                      max_outer, inner_tol, &ls));
+            else
+                CKR(level_solve(Lv, Lv.b.as<double>(), Lv.x.as<double>(), eps, maxit, max_runs,
+                                &ls));
             if (ls.status != EXCMG_OK && worst == EXCMG_OK) worst = ls.status;
         }
         CKH(to_nodes<double>(Lv.N, s, Nf, Lv.x.as<double>(), g1, Lv.u.as<double>(), g_stream));
@@ -488,7 +601,7 @@ int excmg_apply_stencil(int level, int transpose, const double *x, double *y) {
     Arg ax(x, L.nu * 8), ay(y, L.nu * 8);
     CKR(ax.in());
     CKR(ay.out());
-    CKH(stencil_apply<double>(L.geom, L.ty, ax.p<double>(), ay.p<double>(), g_stream));
+    CKH(stencil_apply<double>(L.g1, L.g1.ty, ax.p<double>(), ay.p<double>(), g_stream));
     CKR(ay.back());
     CKH(hipStreamSynchronize(g_stream));
     return EXCMG_OK;
@@ -504,11 +617,11 @@ int excmg_apply_operator(int n, int bc_kind, int transpose, const double *x, dou
     L.N = n;
     L.n = n - 1;
     L.nu = (long long)L.n * L.n * L.n;
-    choose_shape(L, bc_kind);
+    choose_shapes(L, bc_kind);
     Arg ax(x, L.nu * 8), ay(y, L.nu * 8);
     CKR(ax.in());
     CKR(ay.out());
-    CKH(stencil_apply<double>(L.geom, L.ty, ax.p<double>(), ay.p<double>(), g_stream));
+    CKH(stencil_apply<double>(L.g1, L.g1.ty, ax.p<double>(), ay.p<double>(), g_stream));
     CKR(ay.back());
     CKH(hipStreamSynchronize(g_stream));
     return EXCMG_OK;
@@ -635,7 +748,7 @@ int excmg_solve_ex(const excmg_opts *opts, const double *f, const double *g1, co
     const excmg_opts o = *opts;
     if (!f || !g1 || !g2 || !u_out) return fail(EXCMG_EINVAL, "NULL array");
     if (!(o.tol > 0.0)) return fail(EXCMG_EINVAL, "tol must be positive");
-    if (o.precision != EXCMG_FP64)
+    if (o.precision != EXCMG_FP64 && o.precision != EXCMG_MIXED)
         return fail(EXCMG_EINVAL, "precision %d not supported", o.precision);
     CKR(setup(o.n_finest, o.n_levels, o.bc_kind));
     const size_t nb = (size_t)(o.n_finest + 1) * (o.n_finest + 1) * (o.n_finest + 1) * 8;
@@ -646,7 +759,7 @@ int excmg_solve_ex(const excmg_opts *opts, const double *f, const double *g1, co
     CKR(au.out());
     if (ut_out) CKR(at.out());
     if (st) memset(st, 0, sizeof(*st));
-    int rc = solve_fp64(o, af.p<double>(), a1.p<double>(), a2.p<double>(), au.p<double>(),
+    int rc = solve_cascade(o, af.p<double>(), a1.p<double>(), a2.p<double>(), au.p<double>(),
                         ut_out ? at.p<double>() : nullptr, st);
     if (rc != EXCMG_OK && rc != EXCMG_ENOCONV && rc != EXCMG_EBREAKDOWN) return rc;
     CKR(au.back());
@@ -688,28 +801,42 @@ int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launc
     hs.maxit = 1 << 30;
     CKH(hipMemcpyAsync(c.state.p, &hs, sizeof(hs), hipMemcpyHostToDevice, g_stream));
     BicgState *S = c.state.as<BicgState>();
-    const int nvec[5] = {2, 3, 8, 9, 2};
+    // algorithmic bytes per unknown of each sweep
+    const double fp64_bytes[5] = {16, 24, 64, 72, 16};
+    const double mixed_bytes[5] = {8, 24, 32, 44, 8};
     auto launch_once = [&]() -> hipError_t {
         if (precision == EXCMG_FP64) {
             double *r = c.r.as<double>(), *rs = c.rs.as<double>();
             switch (which) {
-                case 0: return stencil_apply<double>(L.geom, L.ty, r, c.q.as<double>(), g_stream);
-                case 1: return stencil_residual<double>(L.geom, L.ty, L.b.as<double>(), r,
+                case 0: return stencil_apply<double>(L.g1, L.g1.ty, r, c.q.as<double>(), g_stream);
+                case 1: return stencil_residual<double>(L.g1, L.g1.ty, L.b.as<double>(), r,
                                                         c.q.as<double>(), c.part_a.as<Pair>(),
                                                         g_stream);
                 case 2: return stencil_pair_direction<double>(
-                            L.geom, L.ty, r, rs, c.p[0].as<double>(), c.ps[0].as<double>(),
+                            L.g2, L.g2.ty, r, rs, c.p[0].as<double>(), c.ps[0].as<double>(),
                             &S->beta, 0, c.p[1].as<double>(), c.ps[1].as<double>(),
                             c.q.as<double>(), c.qs.as<double>(), c.part_a.as<Pair>(), &S->status,
                             g_stream);
-                case 3: return bicg_update<double>(L.nu, S, L.x.as<double>(), c.p[1].as<double>(),
-                                                   r, c.q.as<double>(), rs, c.qs.as<double>(),
-                                                   c.part_b.as<Pair>(), g_stream);
+                case 3: return bicg_update<double, double>(
+                            L.nu, S, L.x.as<double>(), c.p[1].as<double>(), r, c.q.as<double>(),
+                            rs, c.qs.as<double>(), c.part_b.as<Pair>(), g_stream);
                 default: return copy_convert<double, double>(L.nu, r, c.q.as<double>(), g_stream);
             }
         }
-        return fail(EXCMG_EINVAL, "FP32 sweeps are not built yet") ? hipErrorInvalidValue
-                                                                     : hipErrorInvalidValue;
+        float *r = c.r.as<float>(), *rs = c.rs.as<float>();
+        switch (which) {
+            case 0: return stencil_apply<float>(L.g1, L.g1.ty, r, c.q.as<float>(), g_stream);
+            case 1: return stencil_residual_cast(L.g1, L.g1.ty, L.b.as<double>(), L.x.as<double>(),
+                                                 r, rs, c.part_a.as<Pair>(), g_stream);
+            case 2: return stencil_pair_direction<float>(
+                        L.g2, L.g2.ty, r, rs, c.p[0].as<float>(), c.ps[0].as<float>(), &S->beta,
+                        0, c.p[1].as<float>(), c.ps[1].as<float>(), c.q.as<float>(),
+                        c.qs.as<float>(), c.part_a.as<Pair>(), &S->status, g_stream);
+            case 3: return bicg_update<double, float>(L.nu, S, L.x.as<double>(), c.p[1].as<float>(),
+                                                      r, c.q.as<float>(), rs, c.qs.as<float>(),
+                                                      c.part_b.as<Pair>(), g_stream);
+            default: return copy_convert<float, float>(L.nu, r, c.q.as<float>(), g_stream);
+        }
     };
     CKH(launch_once());  // warm-up
     hipEvent_t e0, e1;
@@ -724,7 +851,39 @@ int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launc
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (ms_per_launch) *ms_per_launch = (double)ms / reps;
-    if (bytes_per_launch) *bytes_per_launch = (double)nvec[which] * (double)L.nu * (double)es;
+    if (bytes_per_launch)
+        *bytes_per_launch =
+            (precision == EXCMG_FP64 ? fp64_bytes[which] : mixed_bytes[which]) * (double)L.nu;
+    return EXCMG_OK;
+}
+
+int excmg_set_shape(int n, int kind, int ty, int zc) {
+    g_err[0] = 0;
+    if (n < 2) return fail(EXCMG_EINVAL, "n must be >= 2");
+    if (kind != 0 && kind != 1) return fail(EXCMG_EINVAL, "kind must be 0 or 1");
+    if (ty != 0 && ty != 4 && ty != 8 && ty != 16) return fail(EXCMG_EINVAL, "ty must be 4, 8 or 16");
+    if (kind == 1 && ty == 16) return fail(EXCMG_EINVAL, "sweep A supports ty 4 or 8");
+    if (ty != 0 && zc < 1) return fail(EXCMG_EINVAL, "zc must be >= 1");
+    for (size_t i = 0; i < g_shapes.size(); i++)
+        if (g_shapes[i].N == n && g_shapes[i].kind == kind) {
+            g_shapes.erase(g_shapes.begin() + i);
+            break;
+        }
+    if (ty != 0) g_shapes.push_back(ShapeOverride{n, kind, ty, zc});
+    for (Level &L : g_ctx.lv) {
+        if (L.N != n) continue;
+        choose_shapes(L, g_ctx.bc);
+        const size_t need = (size_t)std::max(stencil_blocks(L.g1), stencil_blocks(L.g2)) * sizeof(Pair);
+        if (need > g_ctx.part_a.bytes) CKR(g_ctx.part_a.ensure(need));
+    }
+    return EXCMG_OK;
+}
+
+int excmg_get_shape(int n, int kind, int *ty, int *zc) {
+    if (n < 2 || (kind != 0 && kind != 1)) return fail(EXCMG_EINVAL, "bad n or kind");
+    Geom g = choose_shape(n, 1, kind);
+    if (ty) *ty = g.ty;
+    if (zc) *zc = g.zc;
     return EXCMG_OK;
 }
 

@@ -10,6 +10,7 @@ namespace excmg {
 // Geometry of a z-marched stencil launch on an interior grid of n^3 unknowns.
 struct Geom {
     int n;                          // unknowns per axis (N - 1)
+    int ty;                         // tile height (4, 8 or 16); tiles are 64 x ty columns
     int tiles_x, tiles_y, tiles_z;  // 64-wide x tiles, TY-high y tiles, ZC-deep z chunks
     int zc;
     int ntiles;
@@ -45,6 +46,11 @@ template <typename T>
 hipError_t stencil_residual(const Geom &g, int ty, const double *b, const T *x, T *r,
                             Pair *partials, hipStream_t st);
 
+// Iterative-refinement residual: r64 = b - A u (FP64), r32 = rs32 = (float) r64, partials of
+// r64.r64
+hipError_t stencil_residual_cast(const Geom &g, int ty, const double *b, const double *u,
+                                 float *r32, float *rs32, Pair *partials, hipStream_t st);
+
 // Sweep A of a Bi-CG iteration: p_new = r + beta p_old, ps_new = rs + beta ps_old (or
 // p_new = r, ps_new = rs when first), q = A p_new, qs = A ps_new, partials of ps_new . q.
 template <typename T>
@@ -59,9 +65,10 @@ inline int stencil_blocks(const Geom &g) { return xcd_grid(g.ntiles); }
 
 int vec_blocks(long long n);
 
-// x += alpha p; r -= alpha q; rs -= alpha qs; partials of rs.r and r.r
-template <typename T>
-hipError_t bicg_update(long long n, const BicgState *s, T *x, const T *p, T *r, const T *q,
+// x += (scale*alpha) p; r -= alpha q; rs -= alpha qs; partials of rs.r and r.r.  x may be
+// held in higher precision than the other vectors (FP64 iterate, FP32 Bi-CG vectors).
+template <typename TX, typename T>
+hipError_t bicg_update(long long n, const BicgState *s, TX *x, const T *p, T *r, const T *q,
                        T *rs, const T *qs, Pair *partials, hipStream_t st);
 
 // partials of x.y

@@ -21,9 +21,11 @@ int vec_blocks(long long n) {
 
 // Algorithm 2: x_{k+1} = x_k + alpha p_k, r_{k+1} = r_k - alpha A p_k,
 // r*_{k+1} = r*_k - alpha (p*_k A); partials of r*.r (rho of the next step) and r.r.
-template <typename T>
+// The iterate x may be FP64 while the Bi-CG vectors are FP32 (iterative refinement updates
+// the FP64 solution directly).
+template <typename TX, typename T>
 __global__ void __launch_bounds__(kVecThreads)
-    k_bicg_update(long long n, const BicgState *s, T *x, const T *p, T *r, const T *q, T *rs,
+    k_bicg_update(long long n, const BicgState *s, TX *x, const T *p, T *r, const T *q, T *rs,
                   const T *qs, Pair *partials) {
     __shared__ Pair sh[2 * (kVecThreads / kWave)];
     if (s->status != kRunning) return;
@@ -34,8 +36,8 @@ __global__ void __launch_bounds__(kVecThreads)
         double xi = (double)x[i] + alpha * (double)p[i];
         double ri = (double)r[i] - alpha * (double)q[i];
         double si = (double)rs[i] - alpha * (double)qs[i];
-        T xs = (T)xi, rt = (T)ri, st = (T)si;
-        x[i] = xs;
+        T rt = (T)ri, st = (T)si;
+        x[i] = (TX)xi;
         r[i] = rt;
         rs[i] = st;
         dot2_acc(acc[0], (double)st, (double)rt);
@@ -48,19 +50,19 @@ __global__ void __launch_bounds__(kVecThreads)
     }
 }
 
-template <typename T>
-hipError_t bicg_update(long long n, const BicgState *s, T *x, const T *p, T *r, const T *q,
+template <typename TX, typename T>
+hipError_t bicg_update(long long n, const BicgState *s, TX *x, const T *p, T *r, const T *q,
                        T *rs, const T *qs, Pair *partials, hipStream_t st) {
-    hipLaunchKernelGGL(k_bicg_update<T>, dim3(vec_blocks(n)), dim3(kVecThreads), 0, st, n, s, x,
-                       p, r, q, rs, qs, partials);
+    hipLaunchKernelGGL((k_bicg_update<TX, T>), dim3(vec_blocks(n)), dim3(kVecThreads), 0, st, n,
+                       s, x, p, r, q, rs, qs, partials);
     return hipGetLastError();
 }
-template hipError_t bicg_update<double>(long long, const BicgState *, double *, const double *,
-                                        double *, const double *, double *, const double *,
-                                        Pair *, hipStream_t);
-template hipError_t bicg_update<float>(long long, const BicgState *, float *, const float *,
-                                       float *, const float *, float *, const float *, Pair *,
-                                       hipStream_t);
+template hipError_t bicg_update<double, double>(long long, const BicgState *, double *,
+                                                const double *, double *, const double *,
+                                                double *, const double *, Pair *, hipStream_t);
+template hipError_t bicg_update<double, float>(long long, const BicgState *, double *,
+                                               const float *, float *, const float *, float *,
+                                               const float *, Pair *, hipStream_t);
 
 template <typename T>
 __global__ void __launch_bounds__(kVecThreads)
@@ -102,6 +104,7 @@ template hipError_t copy_convert<double, double>(long long, const double *, doub
                                                  hipStream_t);
 template hipError_t copy_convert<float, double>(long long, const double *, float *, hipStream_t);
 template hipError_t copy_convert<double, float>(long long, const float *, double *, hipStream_t);
+template hipError_t copy_convert<float, float>(long long, const float *, float *, hipStream_t);
 
 // ------------------------------------------------------------------ finalisation
 

@@ -97,28 +97,37 @@ __device__ __forceinline__ double column_step(Column &s, const double *B, double
     return y;
 }
 
-// Inputs of the marched arrays.  value(a, idx) for interior index idx of array a;
+// Inputs of the marched arrays.  Staging is split in two so that global loads stay in
+// flight while earlier planes are consumed: load() fetches the R raw values of a staged
+// element (into registers, no arithmetic), combine() turns them into the staged value.
 // prepare() runs once per thread before the march.
 template <typename T>
 struct InPlain {            // x itself
+    static constexpr int R = 1;
     const T *x[2];
     __device__ __forceinline__ void prepare() {}
-    __device__ __forceinline__ double value(int a, i64 idx) const { return (double)x[a][idx]; }
+    __device__ __forceinline__ void load(int a, i64 idx, T (&raw)[R]) const { raw[0] = x[a][idx]; }
+    __device__ __forceinline__ double combine(const T (&raw)[R]) const { return (double)raw[0]; }
 };
 
 template <typename T>
 struct InDirection {        // p_new = r + beta p_old (p_new = r on the first iteration)
+    static constexpr int R = 2;
     const T *r[2];
     const T *p[2];
     const double *beta_dev; // beta of Algorithm 2, written by the previous finalisation
     int first;
     double beta;
     __device__ __forceinline__ void prepare() { beta = first ? 0.0 : *beta_dev; }
-    __device__ __forceinline__ double value(int a, i64 idx) const {
-        double rv = (double)r[a][idx];
-        if (first) return rv;
+    __device__ __forceinline__ void load(int a, i64 idx, T (&raw)[R]) const {
+        raw[0] = r[a][idx];
+        raw[1] = p[a][idx];
+    }
+    __device__ __forceinline__ double combine(const T (&raw)[R]) const {
+        const double rv = (double)raw[0];
         // rounded to the storage type, so the operator acts on exactly the stored vector
-        return (double)(T)(rv + beta * (double)p[a][idx]);
+        const double pn = (double)(T)(rv + beta * (double)raw[1]);
+        return first ? rv : pn;
     }
 };
 
@@ -127,7 +136,7 @@ struct InDirection {        // p_new = r + beta p_old (p_new = r on the first it
 //   operator values y and the centre values c of the output plane;
 //   Out::centre(idx, c[NA]) is called for every valid centre of a plane inside the chunk;
 //   Out::finish(block, tile) runs after the march (block-level reductions).
-template <int NA, int TY, class In, class Out>
+template <int NA, int TY, typename T, class In, class Out>
 __global__ void __launch_bounds__(kWave *TY) zmarch(Geom g, In in_arg, Out out) {
     constexpr int TX = kWave;
     constexpr int LS = TX + 4;          // LDS row stride
@@ -158,9 +167,11 @@ __global__ void __launch_bounds__(kWave *TY) zmarch(Geom g, In in_arg, Out out) 
     const int k1 = min(k0 + g.zc, n);
     const i64 plane = (i64)n * n;
 
-    // staging slots of this thread: LDS element e = tid + q*NT
+    // staging slots of this thread: LDS element e = tid + q*NT.  Every slot has a valid
+    // source address (positions outside the grid are clamped and multiplied by 0), so the
+    // loads need no branches and can stay in flight.
     int soff[NL];     // source offset inside a plane (row-major, x fastest)
-    double smul[NL];  // in-plane multiplier (0 = not staged from memory)
+    double smul[NL];  // in-plane multiplier (0 = boundary node, outside, or unused slot)
 #pragma unroll
     for (int q = 0; q < NL; q++) {
         int e = tid + q * NT;
@@ -176,28 +187,29 @@ __global__ void __launch_bounds__(kWave *TY) zmarch(Geom g, In in_arg, Out out) 
         }
     }
 
-    double pre[NL][NA];
-    auto fetch = [&](int m) {
+    constexpr int R = In::R;
+    using Raw = T[NL][NA][R];
+    auto fetch = [&](int m, Raw &raw, double &mz) {
         int sz;
-        double mz = reflect(m, n, g.sgn, sz);
+        mz = reflect(m, n, g.sgn, sz);
 #pragma unroll
         for (int q = 0; q < NL; q++) {
-            double mul = smul[q] * mz;
+            const i64 idx = (i64)sz * plane + soff[q];
 #pragma unroll
-            for (int a = 0; a < NA; a++) {
-                double v = 0.0;
-                if (mul != 0.0) v = mul * in.value(a, (i64)sz * plane + soff[q]);
-                pre[q][a] = v;
-            }
+            for (int a = 0; a < NA; a++) in.load(a, idx, raw[q][a]);
         }
     };
-    auto stash = [&](int b) {
+    auto stash = [&](int b, const Raw &raw, double mz) {
 #pragma unroll
         for (int q = 0; q < NL; q++) {
-            int e = tid + q * NT;
+            const int e = tid + q * NT;
+            const double mul = smul[q] * mz;
             if (e < LE) {
 #pragma unroll
-                for (int a = 0; a < NA; a++) buf[b][a][e] = pre[q][a];
+                for (int a = 0; a < NA; a++) {
+                    const double v = in.combine(raw[q][a]);
+                    buf[b][a][e] = (mul != 0.0) ? mul * v : 0.0;
+                }
             }
         }
     };
@@ -206,15 +218,19 @@ __global__ void __launch_bounds__(kWave *TY) zmarch(Geom g, In in_arg, Out out) 
 #pragma unroll
     for (int a = 0; a < NA; a++) column_init(col[a]);
 
-    const int mbeg = k0 - 2, mend = k1 + 1;   // planes staged: mbeg..mend
-    fetch(mbeg);
-    stash(0);
+    // Planes mbeg..mend are staged; two planes are in flight in registers at any time.
+    const int mbeg = k0 - 2, mend = k1 + 1;
+    Raw rawA, rawB;
+    double mzA, mzB;
+    fetch(mbeg, rawA, mzA);
+    stash(0, rawA, mzA);
+    fetch(min(mbeg + 1, mend), rawA, mzA);
+    fetch(min(mbeg + 2, mend), rawB, mzB);
     __syncthreads();
     int cur = 0;
     const int centre = (ly + 2) * LS + (lx + 2);
-    for (int m = mbeg; m <= mend; m++) {
-        const bool more = (m < mend);
-        if (more) fetch(m + 1);
+    // consume plane m from LDS, stage plane m+1 from `raw`, refill `raw` with plane m+3
+    auto body = [&](int m, Raw &raw, double &mz) {
         double y[NA], c0[NA], cprev[NA];
 #pragma unroll
         for (int a = 0; a < NA; a++) {
@@ -226,9 +242,15 @@ __global__ void __launch_bounds__(kWave *TY) zmarch(Geom g, In in_arg, Out out) 
             const int k = m - 2;
             if (k >= k0 && k < k1) out.emit((i64)k * plane + (i64)iy * n + ix, y, cprev);
         }
-        if (more) stash(cur ^ 1);
+        stash(cur ^ 1, raw, mz);
+        fetch(min(m + 3, mend), raw, mz);
         __syncthreads();
         cur ^= 1;
+    };
+    for (int m = mbeg; m <= mend; m += 2) {
+        body(m, rawA, mzA);
+        if (m + 1 > mend) break;
+        body(m + 1, rawB, mzB);
     }
     out.finish(blockIdx.x, red);
 }
@@ -255,6 +277,30 @@ struct OutResidual {        // r = b - A x, partial of r.r
     __device__ void emit(i64 idx, const double *v, const double *) {
         double rv = b[idx] - v[0];
         r[idx] = (T)rv;
+        dot2_acc(acc, rv, rv);
+    }
+    __device__ void finish(int block, Pair *sh) {
+        Pair v[1] = {acc};
+        block_merge<1>(v, sh);
+        if (threadIdx.x == 0 && threadIdx.y == 0) partials[block] = v[0];
+    }
+};
+
+// Outer residual of iterative refinement: r64 = b - A u in FP64 (u FP64), stored rounded
+// to FP32 twice (the inner Bi-CG's r_0 and r*_0), partial of r64.r64.
+struct OutResidualCast {
+    const double *b;
+    float *r32;
+    float *rs32;
+    Pair *partials;
+    Pair acc;
+    __device__ bool skip() const { return false; }
+    __device__ void centre(i64, const double *) {}
+    __device__ void emit(i64 idx, const double *v, const double *) {
+        const double rv = b[idx] - v[0];
+        const float rf = (float)rv;
+        r32[idx] = rf;
+        rs32[idx] = rf;
         dot2_acc(acc, rv, rv);
     }
     __device__ void finish(int block, Pair *sh) {
@@ -296,6 +342,7 @@ struct OutPairApply {
 Geom make_geom(int n, int bc, int ty, int zc) {
     Geom g;
     g.n = n;
+    g.ty = ty;
     g.tiles_x = (n + kWave - 1) / kWave;
     g.tiles_y = (n + ty - 1) / ty;
     g.zc = zc;
@@ -305,11 +352,11 @@ Geom make_geom(int n, int bc, int ty, int zc) {
     return g;
 }
 
-template <int TY, class In, class Out, int NA>
+template <int TY, typename T, class In, class Out, int NA>
 static hipError_t launch(const Geom &g, const In &in, const Out &out, hipStream_t st) {
     dim3 block(kWave, TY);
-    hipLaunchKernelGGL((zmarch<NA, TY, In, Out>), dim3(xcd_grid(g.ntiles)), block, 0, st, g, in,
-                       out);
+    hipLaunchKernelGGL((zmarch<NA, TY, T, In, Out>), dim3(xcd_grid(g.ntiles)), block, 0, st, g,
+                       in, out);
     return hipGetLastError();
 }
 
@@ -328,7 +375,7 @@ hipError_t stencil_apply(const Geom &g, int ty, const T *x, T *y, hipStream_t st
     in.x[1] = x;
     OutApply<T> out;
     out.y = y;
-    EXCMG_DISPATCH_TY(ty, return (launch<TY, InPlain<T>, OutApply<T>, 1>(g, in, out, st)));
+    EXCMG_DISPATCH_TY(ty, return (launch<TY, T, InPlain<T>, OutApply<T>, 1>(g, in, out, st)));
     return hipSuccess;
 }
 
@@ -343,7 +390,23 @@ hipError_t stencil_residual(const Geom &g, int ty, const double *b, const T *x, 
     out.r = r;
     out.partials = partials;
     out.acc = Pair{0.0, 0.0};
-    EXCMG_DISPATCH_TY(ty, return (launch<TY, InPlain<T>, OutResidual<T>, 1>(g, in, out, st)));
+    EXCMG_DISPATCH_TY(ty, return (launch<TY, T, InPlain<T>, OutResidual<T>, 1>(g, in, out, st)));
+    return hipSuccess;
+}
+
+hipError_t stencil_residual_cast(const Geom &g, int ty, const double *b, const double *u,
+                                 float *r32, float *rs32, Pair *partials, hipStream_t st) {
+    InPlain<double> in;
+    in.x[0] = u;
+    in.x[1] = u;
+    OutResidualCast out;
+    out.b = b;
+    out.r32 = r32;
+    out.rs32 = rs32;
+    out.partials = partials;
+    out.acc = Pair{0.0, 0.0};
+    EXCMG_DISPATCH_TY(ty,
+                      return (launch<TY, double, InPlain<double>, OutResidualCast, 1>(g, in, out, st)));
     return hipSuccess;
 }
 
@@ -369,7 +432,7 @@ hipError_t stencil_pair_direction(const Geom &g, int ty, const T *r, const T *rs
     out.status = status;
     out.acc = Pair{0.0, 0.0};
     EXCMG_DISPATCH_TY(ty,
-                      return (launch<TY, InDirection<T>, OutPairApply<T>, 2>(g, in, out, st)));
+                      return (launch<TY, T, InDirection<T>, OutPairApply<T>, 2>(g, in, out, st)));
     return hipSuccess;
 }
 

@@ -16,6 +16,7 @@ __all__ = [
     "ExcmgError", "OK", "EINVAL", "ENOMEM", "ENOCONV", "EBREAKDOWN", "EHIP", "FP64", "MIXED",
     "lib_path", "load", "set_stream", "setup", "apply_stencil", "apply_operator", "rhs", "dsolve", "bicg",
     "level_solve", "exp_finite", "exp_true", "solve", "solve_ex", "profile_sweep",
+    "set_shape", "get_shape",
     "last_error", "finalize",
     "LevelStats", "Stats",
 ]
@@ -89,6 +90,8 @@ def load():
                                    ctypes.POINTER(Stats)]),
         "excmg_profile_sweep": (c_int, [c_int, c_int, c_int, ctypes.POINTER(c_dbl),
                                         ctypes.POINTER(c_dbl)]),
+        "excmg_set_shape": (c_int, [c_int, c_int, c_int, c_int]),
+        "excmg_get_shape": (c_int, [c_int, c_int, ip, ip]),
         "excmg_last_error": (ctypes.c_char_p, []),
         "excmg_finalize": (None, []),
     }
@@ -223,6 +226,19 @@ def profile_sweep(which: int, precision: int = FP64, reps: int = 20):
     _check("excmg_profile_sweep", load().excmg_profile_sweep(which, precision, reps,
                                                              ctypes.byref(ms), ctypes.byref(nb)))
     return ms.value, nb.value
+
+
+def set_shape(n: int, kind: int, ty: int, zc: int):
+    """Tile shape (64 x ty columns, zc planes per chunk) for grids of n cells; kind 0 = the
+    one-array stencil kernels, 1 = Bi-CG sweep A; ty=0 restores the default."""
+    _check("excmg_set_shape", load().excmg_set_shape(n, kind, ty, zc))
+
+
+def get_shape(n: int, kind: int):
+    ty, zc = ctypes.c_int(0), ctypes.c_int(0)
+    _check("excmg_get_shape", load().excmg_get_shape(n, kind, ctypes.byref(ty),
+                                                     ctypes.byref(zc)))
+    return ty.value, zc.value
 
 
 def finalize():
