@@ -119,18 +119,28 @@ def main():
     glups = head["glups"]
     levels = head["levels"]
 
-    # roofline of the dominant kernel: Bi-CG sweep A (direction update + pair apply)
+    # Roofline of the dominant kernel, Bi-CG sweep A (direction update + pair apply), on the
+    # finest level: one more solve of the headline form with every sweep bracketed by device
+    # events on the library stream; achieved = algorithmic bytes per launch / mean duration.
     prec = ex.MIXED if gate else ex.FP64
-    ms_a, bytes_a = ex.profile_sweep(2, prec, reps=10)
-    ms_b, bytes_b = ex.profile_sweep(3, prec, reps=10)
+    ex.set_timing(True)
+    solve(prec)
+    ms_a, n_a = ex.get_timing(nl - 1, 0)
+    ms_b, n_b = ex.get_timing(nl - 1, 1)
+    ex.set_timing(False)
+    nu = (N - 1) ** 3
+    bytes_a = (32.0 if gate else 64.0) * nu     # read r, r*, p, p*; write p, p*, q, q*
+    bytes_b = (44.0 if gate else 72.0) * nu     # read x, p, r, q, r*, q*; write x, r, r*
+    avg_a, avg_b = ms_a / max(n_a, 1), ms_b / max(n_b, 1)
+    gbs_a = bytes_a / (avg_a * 1e-3) / 1e9
     ms_c, bytes_c = ex.profile_sweep(4, ex.FP64, reps=10)
-    gbs_a = bytes_a / (ms_a * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(gbs_a, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(gbs_a / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": f"zmarch<2,InDirection,OutPairApply> (Bi-CG sweep A, {mode})",
-                "ms_per_launch": round(ms_a, 4),
-                "bytes_per_launch": bytes_a,
-                "sweep_b_gbs": round(bytes_b / (ms_b * 1e-3) / 1e9, 1),
+                "kernel": f"zmarch<2,{'float' if gate else 'double'},InDirection,OutPairApply> "
+                          f"(Bi-CG sweep A, {N}^3 level)",
+                "launches": n_a, "ms_per_launch": round(avg_a, 4), "bytes_per_launch": bytes_a,
+                "sweep_b": {"launches": n_b, "ms_per_launch": round(avg_b, 4),
+                            "gbs": round(bytes_b / (avg_b * 1e-3) / 1e9, 1)},
                 "copy_gbs": round(bytes_c / (ms_c * 1e-3) / 1e9, 1)}
 
     out = {

@@ -164,6 +164,14 @@ int excmg_solve_ex(const excmg_opts *opts, const double *f, const double *g1, co
 int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launch,
                         double *bytes_per_launch);
 
+/* Measurement helper: when on, every Bi-CG sweep launched by later solves is bracketed by
+ * device events on the library stream and its duration is added to a per-level total
+ * (sweep 0 = sweep A: direction update, A p, A^T p*, sigma; sweep 1 = sweep B: x, r, r*
+ * updates, rho, r.r).  Only launches that did work are counted.  Turning it on resets the
+ * totals; excmg_get_timing reads them. */
+int excmg_set_timing(int on);
+int excmg_get_timing(int level, int sweep, double *ms_total, long long *launches);
+
 /* Launch shape of the z-marched stencil kernels on grids of n cells: tiles of 64 x ty
  * columns marching through chunks of zc planes.  kind 0: the one-array kernels (operator,
  * residual; ty = 4, 8 or 16); kind 1: Bi-CG sweep A (two arrays; ty = 4 or 8).  ty = 0

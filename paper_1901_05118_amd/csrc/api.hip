@@ -127,6 +127,7 @@ struct Arg {
 // ------------------------------------------------------------------ context
 
 struct Level {
+    int index = 0;    // level number (0 = coarsest)
     int N = 0;        // cells per axis
     int n = 0;        // unknowns per axis
     long long nu = 0; // unknowns
@@ -170,6 +171,22 @@ struct Ctx {
 };
 
 Ctx g_ctx;
+
+// Optional per-launch timing of the two Bi-CG sweeps (device events on the library stream),
+// accumulated per level: [level][0] sweep A, [level][1] sweep B.
+bool g_timing = false;
+double g_time_ms[EXCMG_MAX_LEVELS][2];
+long long g_time_n[EXCMG_MAX_LEVELS][2];
+std::vector<hipEvent_t> g_events;
+
+int ensure_events(size_t count) {
+    while (g_events.size() < count) {
+        hipEvent_t e;
+        CKH(hipEventCreate(&e));
+        g_events.push_back(e);
+    }
+    return EXCMG_OK;
+}
 
 // Tile shapes chosen by the autotuner (or a caller) per grid size and kernel kind.
 struct ShapeOverride {
@@ -234,6 +251,7 @@ int setup(int n_finest, int n_levels, int bc) {
     c.lv.resize(n_levels);
     for (int l = 0; l < n_levels; l++) {
         Level &L = c.lv[l];
+        L.index = l;
         L.N = N0 << l;
         L.n = L.N - 1;
         L.nu = (long long)L.n * L.n * L.n;
@@ -327,39 +345,67 @@ int poll_interval(long long nu) {
     return (int)k;
 }
 
+// Iterations of Algorithm 2 on level L after bicg_start: the Bi-CG vectors r, r*, p, p*, q, q*
+// have type T, the iterate x type TX.  Sweep A forms p, p* and their products with A (and
+// sigma), sweep B updates x, r, r* (and rho, r.r).  Every kernel returns at once when the
+// run has stopped, so the host launches K iterations between two polls of the state.
+template <typename TX, typename T>
+int bicg_iterate(const Level &L, TX *x, BicgState &hs) {
+    Ctx &c = g_ctx;
+    BicgState *S = c.state.as<BicgState>();
+    T *r = c.r.as<T>(), *rs = c.rs.as<T>(), *q = c.q.as<T>(), *qs = c.qs.as<T>();
+    const int K = poll_interval(L.nu);
+    const int nsb = stencil_blocks(L.g2);
+    const int nvb = vec_blocks(L.nu);
+    if (g_timing) CKR(ensure_events(4 * (size_t)K));
+    long long j = 0;
+    while (hs.status == kRunning) {
+        const int it0 = hs.iter;
+        for (int t = 0; t < K; t++, j++) {
+            const int cur = (int)(j & 1), nxt = cur ^ 1;
+            T *pn = c.p[nxt].as<T>(), *psn = c.ps[nxt].as<T>();
+            if (g_timing) CKH(hipEventRecord(g_events[4 * t], g_stream));
+            CKH(stencil_pair_direction<T>(L.g2, L.g2.ty, r, rs, c.p[cur].as<T>(),
+                                          c.ps[cur].as<T>(), &S->beta, j == 0 ? 1 : 0, pn, psn,
+                                          q, qs, c.part_a.as<Pair>(), &S->status, g_stream));
+            if (g_timing) CKH(hipEventRecord(g_events[4 * t + 1], g_stream));
+            CKH(bicg_alpha(S, c.part_a.as<Pair>(), nsb, g_stream));
+            if (g_timing) CKH(hipEventRecord(g_events[4 * t + 2], g_stream));
+            CKH((bicg_update<TX, T>(L.nu, S, x, pn, r, q, rs, qs, c.part_b.as<Pair>(), g_stream)));
+            if (g_timing) CKH(hipEventRecord(g_events[4 * t + 3], g_stream));
+            CKH(bicg_beta(S, c.part_b.as<Pair>(), nvb, g_stream));
+        }
+        CKR(read_state(hs));
+        if (g_timing && L.index < EXCMG_MAX_LEVELS) {
+            const int active = std::min(K, hs.iter - it0);  // launches that did work
+            for (int t = 0; t < active; t++) {
+                float a = 0.f, b = 0.f;
+                CKH(hipEventElapsedTime(&a, g_events[4 * t], g_events[4 * t + 1]));
+                CKH(hipEventElapsedTime(&b, g_events[4 * t + 2], g_events[4 * t + 3]));
+                g_time_ms[L.index][0] += a;
+                g_time_ms[L.index][1] += b;
+                g_time_n[L.index][0]++;
+                g_time_n[L.index][1]++;
+            }
+        }
+    }
+    return EXCMG_OK;
+}
+
 // One Bi-CG run from x (in place) on level L with right-hand side b.
 int bicg_run(const Level &L, const double *b, double *x, double eps, int maxit, int *iters,
              double *rr_out, int *status_out) {
     Ctx &c = g_ctx;
     BicgState *S = c.state.as<BicgState>();
     double *r = c.r.as<double>(), *rs = c.rs.as<double>();
-    double *q = c.q.as<double>(), *qs = c.qs.as<double>();
     // b.b and r_0 = b - A x_0, r*_0 = r_0
     CKR(device_dot(L.nu, b, b, (double *)&S->bb, 0));
     CKH(stencil_residual<double>(L.g1, L.g1.ty, b, x, r, c.part_a.as<Pair>(), g_stream));
     CKH((copy_convert<double, double>(L.nu, r, rs, g_stream)));
     CKH(bicg_start(S, c.part_a.as<Pair>(), stencil_blocks(L.g1), eps, maxit, g_stream));
-    const int K = poll_interval(L.nu);
-    const int nsb = stencil_blocks(L.g2);
-    const int nvb = vec_blocks(L.nu);
     BicgState hs;
     CKR(read_state(hs));
-    long long j = 0;
-    while (hs.status == kRunning) {
-        for (int t = 0; t < K; t++, j++) {
-            const int cur = (int)(j & 1), nxt = cur ^ 1;
-            double *pn = c.p[nxt].as<double>(), *psn = c.ps[nxt].as<double>();
-            CKH(stencil_pair_direction<double>(L.g2, L.g2.ty, r, rs, c.p[cur].as<double>(),
-                                               c.ps[cur].as<double>(), &S->beta, j == 0 ? 1 : 0,
-                                               pn, psn, q, qs, c.part_a.as<Pair>(), &S->status,
-                                               g_stream));
-            CKH(bicg_alpha(S, c.part_a.as<Pair>(), nsb, g_stream));
-            CKH((bicg_update<double, double>(L.nu, S, x, pn, r, q, rs, qs, c.part_b.as<Pair>(),
-                                             g_stream)));
-            CKH(bicg_beta(S, c.part_b.as<Pair>(), nvb, g_stream));
-        }
-        CKR(read_state(hs));
-    }
+    CKR((bicg_iterate<double, double>(L, x, hs)));
     if (iters) *iters = hs.iter;
     if (rr_out) *rr_out = hs.rr;
     if (status_out) *status_out = hs.status;
@@ -420,32 +466,14 @@ int bicg_inner_fp32(const Level &L, double *u, double inner_tol, int maxit, int 
                     int *status_out) {
     Ctx &c = g_ctx;
     BicgState *S = c.state.as<BicgState>();
-    float *r = c.r.as<float>(), *rs = c.rs.as<float>();
-    float *q = c.q.as<float>(), *qs = c.qs.as<float>();
+    float *r = c.r.as<float>();
     const int nvb = vec_blocks(L.nu);
     CKH(dot_partials<float>(L.nu, r, r, c.part_b.as<Pair>(), nvb, g_stream));
     CKH(reduce_to((double *)&S->bb, c.part_b.as<Pair>(), nvb, 0, g_stream));
     CKH(bicg_start(S, c.part_b.as<Pair>(), nvb, inner_tol, maxit, g_stream));
-    const int K = poll_interval(L.nu);
-    const int nsb = stencil_blocks(L.g2);
     BicgState hs;
     CKR(read_state(hs));
-    long long j = 0;
-    while (hs.status == kRunning) {
-        for (int t = 0; t < K; t++, j++) {
-            const int cur = (int)(j & 1), nxt = cur ^ 1;
-            float *pn = c.p[nxt].as<float>(), *psn = c.ps[nxt].as<float>();
-            CKH(stencil_pair_direction<float>(L.g2, L.g2.ty, r, rs, c.p[cur].as<float>(),
-                                              c.ps[cur].as<float>(), &S->beta, j == 0 ? 1 : 0,
-                                              pn, psn, q, qs, c.part_a.as<Pair>(), &S->status,
-                                              g_stream));
-            CKH(bicg_alpha(S, c.part_a.as<Pair>(), nsb, g_stream));
-            CKH((bicg_update<double, float>(L.nu, S, u, pn, r, q, rs, qs, c.part_b.as<Pair>(),
-                                            g_stream)));
-            CKH(bicg_beta(S, c.part_b.as<Pair>(), nvb, g_stream));
-        }
-        CKR(read_state(hs));
-    }
+    CKR((bicg_iterate<double, float>(L, u, hs)));
     if (iters) *iters = hs.iter;
     if (status_out) *status_out = hs.status;
     return EXCMG_OK;
@@ -854,6 +882,21 @@ int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launc
     if (bytes_per_launch)
         *bytes_per_launch =
             (precision == EXCMG_FP64 ? fp64_bytes[which] : mixed_bytes[which]) * (double)L.nu;
+    return EXCMG_OK;
+}
+
+int excmg_set_timing(int on) {
+    g_timing = (on != 0);
+    memset(g_time_ms, 0, sizeof(g_time_ms));
+    memset(g_time_n, 0, sizeof(g_time_n));
+    return EXCMG_OK;
+}
+
+int excmg_get_timing(int level, int sweep, double *ms_total, long long *launches) {
+    if (level < 0 || level >= EXCMG_MAX_LEVELS || (sweep != 0 && sweep != 1))
+        return fail(EXCMG_EINVAL, "bad level or sweep");
+    if (ms_total) *ms_total = g_time_ms[level][sweep];
+    if (launches) *launches = g_time_n[level][sweep];
     return EXCMG_OK;
 }
 

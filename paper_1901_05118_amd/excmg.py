@@ -16,7 +16,7 @@ __all__ = [
     "ExcmgError", "OK", "EINVAL", "ENOMEM", "ENOCONV", "EBREAKDOWN", "EHIP", "FP64", "MIXED",
     "lib_path", "load", "set_stream", "setup", "apply_stencil", "apply_operator", "rhs", "dsolve", "bicg",
     "level_solve", "exp_finite", "exp_true", "solve", "solve_ex", "profile_sweep",
-    "set_shape", "get_shape",
+    "set_shape", "get_shape", "set_timing", "get_timing",
     "last_error", "finalize",
     "LevelStats", "Stats",
 ]
@@ -90,6 +90,9 @@ def load():
                                    ctypes.POINTER(Stats)]),
         "excmg_profile_sweep": (c_int, [c_int, c_int, c_int, ctypes.POINTER(c_dbl),
                                         ctypes.POINTER(c_dbl)]),
+        "excmg_set_timing": (c_int, [c_int]),
+        "excmg_get_timing": (c_int, [c_int, c_int, ctypes.POINTER(c_dbl),
+                                     ctypes.POINTER(ctypes.c_longlong)]),
         "excmg_set_shape": (c_int, [c_int, c_int, c_int, c_int]),
         "excmg_get_shape": (c_int, [c_int, c_int, ip, ip]),
         "excmg_last_error": (ctypes.c_char_p, []),
@@ -226,6 +229,20 @@ def profile_sweep(which: int, precision: int = FP64, reps: int = 20):
     _check("excmg_profile_sweep", load().excmg_profile_sweep(which, precision, reps,
                                                              ctypes.byref(ms), ctypes.byref(nb)))
     return ms.value, nb.value
+
+
+def set_timing(on: bool):
+    """Bracket every later Bi-CG sweep with device events (and reset the totals)."""
+    _check("excmg_set_timing", load().excmg_set_timing(int(bool(on))))
+
+
+def get_timing(level: int, sweep: int):
+    """(total ms, launches) of sweep 0 (A) or 1 (B) on a level since set_timing(True)."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_longlong(0)
+    _check("excmg_get_timing", load().excmg_get_timing(level, sweep, ctypes.byref(ms),
+                                                       ctypes.byref(n)))
+    return ms.value, n.value
 
 
 def set_shape(n: int, kind: int, ty: int, zc: int):
