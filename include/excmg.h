@@ -68,6 +68,8 @@ typedef struct excmg_opts {
     int max_runs;       /* Bi-CG runs per level in Algorithm 1's while loop (0: 5)          */
     double inner_tol;   /* mixed precision: relative tolerance of each FP32 solve (0: 1e-4) */
     int max_outer;      /* mixed precision: refinement steps per level (0: 60)             */
+    int batch_mode;     /* excmg_solve_batch: 0 = four graph-captured phase launches per    */
+                        /* Bi-CG step, 1 = one persistent work-queue launch per step        */
 } excmg_opts;
 
 /* Per-level record filled by excmg_solve_ex (levels 0 and 1 report iterations = 0). */
@@ -180,6 +182,33 @@ int excmg_get_timing(int level, int sweep, double *ms_total, long long *launches
  * computed with the same arithmetic). */
 int excmg_set_shape(int n, int kind, int ty, int zc);
 int excmg_get_shape(int n, int kind, int *ty, int *zc);
+
+/* One problem of a batch: finest-grid node arrays in the conventions above. */
+typedef struct excmg_problem {
+    int n_finest;
+    int n_levels;
+    int bc_kind;
+    const double *f, *g1, *g2;
+    double *u_out;          /* finest FD solution (node array)                      */
+    double *ut_out;         /* EXP_true solution (node array), may be NULL            */
+} excmg_problem;
+
+/* Algorithm 1 for nprob independent problems (1..256) of possibly different grids, levels
+ * and boundary kinds, advanced together: every Bi-CG iteration of all running systems is
+ * one launch of a persistent work-queue kernel (replayed from a captured hipGraph), while
+ * each problem follows its own cascade, tolerances and stopping decisions exactly as
+ * excmg_solve_ex would.  opts supplies tol, precision and the iteration limits (its
+ * n_finest, n_levels and bc_kind are ignored).  stats, if not NULL, is an array of nprob
+ * records.  Runs on a stream of its own, ordered after the library stream's earlier work. */
+int excmg_solve_batch(int nprob, const excmg_problem *probs, const excmg_opts *opts,
+                      excmg_stats *stats);
+
+/* Autotuner: time the z-marched kernel of `kind` (0: one-array operator, 1: Bi-CG sweep A)
+ * on a grid of n cells for every tile height and z-chunk length it supports, in FP64 or
+ * FP32 (precision), `reps` launches each on scratch vectors, and record the fastest shape
+ * for later launches (as excmg_set_shape).  Outputs (may be NULL): the chosen shape and its
+ * mean ms per launch. */
+int excmg_autotune(int n, int kind, int precision, int reps, int *ty, int *zc, double *ms);
 
 /* Description of the last error (empty string if none). */
 const char *excmg_last_error(void);

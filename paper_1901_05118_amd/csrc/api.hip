@@ -604,6 +604,412 @@ int solve_cascade(const excmg_opts &o, const double *f, const double *g1, const 
     return EXCMG_OK;
 }
 
+
+// ================================================================== batched solves
+
+// Cholesky factors of direct-solve levels, shared by the problems of a batch.
+struct FactorCache {
+    std::vector<std::pair<long long, DBuf>> f;
+    int get(int N, int bc, hipStream_t st, double **out) {
+        const long long key = (long long)N * 4 + bc;
+        for (auto &e : f)
+            if (e.first == key) {
+                *out = e.second.as<double>();
+                return EXCMG_OK;
+            }
+        f.emplace_back(key, DBuf{});
+        DBuf &b = f.back().second;
+        const int n = (N - 1) * (N - 1) * (N - 1);
+        CKR(b.ensure((size_t)n * n * 8));
+        CKH(dense_assemble(N, bc, b.as<double>(), st));
+        DBuf info;
+        CKR(info.ensure(64));
+        CKH(dense_cholesky(n, b.as<double>(), info.as<int>(), st));
+        int h = 0;
+        CKH(hipMemcpyAsync(&h, info.p, sizeof(int), hipMemcpyDeviceToHost, st));
+        CKH(hipStreamSynchronize(st));
+        info.release();
+        if (h != 0) return fail(EXCMG_EBREAKDOWN, "Cholesky pivot %d not positive", h);
+        *out = b.as<double>();
+        return EXCMG_OK;
+    }
+    void release() {
+        for (auto &e : f) e.second.release();
+        f.clear();
+    }
+};
+
+enum { kPhaseCheck = 0, kPhaseRun = 1, kPhaseDone = 2 };
+
+struct BProb {
+    int N = 0, nl = 0, bc = 0, L = 0;
+    std::vector<Level> lv;
+    DBuf r, rs, p[2], ps[2], q, qs, part_a, part_b, ubuf;
+    Arg *af = nullptr, *a1 = nullptr, *a2 = nullptr, *au = nullptr, *at = nullptr;
+    int level = 0, phase = kPhaseCheck;
+    int runs = 0, iters = 0, outer = 0, worst = EXCMG_OK;
+    double eps = 0.0, prev = INFINITY;
+    excmg_stats stats{};
+    ~BProb() {
+        for (auto &l : lv) { l.b.release(); l.x.release(); l.u.release(); }
+        r.release(); rs.release(); p[0].release(); p[1].release(); ps[0].release();
+        ps[1].release(); q.release(); qs.release(); part_a.release(); part_b.release();
+        ubuf.release();
+        delete af; delete a1; delete a2; delete au; delete at;
+    }
+};
+
+struct BatchSolver {
+    bool mixed = false;
+    bool persistent = false;  // one persistent launch per step instead of four phase launches
+    int maxit = 100000, max_runs = 5, max_outer = 60;
+    double tol = 0.0, inner_tol = 1e-4;
+    hipStream_t st = nullptr;
+    std::vector<BProb *> pb;
+    FactorCache fc;
+    DBuf states, runs, items, ctl, scal;
+    BatchRun *h_runs = nullptr;
+    int2 *h_items = nullptr;
+    double *h_scal = nullptr;
+    BicgState *h_states = nullptr;
+    int *h_hdr = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    int grid = 0, steps_per_graph = 8;
+    long long launches = 0;
+
+    ~BatchSolver() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (BProb *b : pb) delete b;
+        states.release(); runs.release(); items.release(); ctl.release(); scal.release();
+        fc.release();
+        if (h_runs) (void)hipHostFree(h_runs);
+        if (h_items) (void)hipHostFree(h_items);
+        if (h_scal) (void)hipHostFree(h_scal);
+        if (h_states) (void)hipHostFree(h_states);
+        if (h_hdr) (void)hipHostFree(h_hdr);
+    }
+
+    BicgState *S(int j) { return states.as<BicgState>() + j; }
+    double *sc(int j) { return scal.as<double>() + 4 * j; }
+
+    int init(int nprob, const excmg_problem *probs, const excmg_opts &o) {
+        mixed = (o.precision == EXCMG_MIXED);
+        persistent = (o.batch_mode == 1);
+        tol = o.tol;
+        maxit = o.max_iters > 0 ? o.max_iters : 100000;
+        max_runs = o.max_runs > 0 ? o.max_runs : 5;
+        max_outer = o.max_outer > 0 ? o.max_outer : 60;
+        inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-4;
+        CKR(states.ensure((size_t)nprob * sizeof(BicgState)));
+        CKR(runs.ensure((size_t)nprob * sizeof(BatchRun)));
+        CKR(ctl.ensure(sizeof(BatchCtl)));
+        CKR(scal.ensure((size_t)nprob * 4 * sizeof(double)));
+        // epoch starts at 1: alpha_epoch[] = 0 must not read as "published" in launch 1
+        CKH(hipMemsetAsync(ctl.p, 0, sizeof(BatchCtl), st));
+        const int one = 1;
+        CKH(hipMemcpyAsync((char *)ctl.p + offsetof(BatchCtl, epoch), &one, sizeof(int),
+                           hipMemcpyHostToDevice, st));
+        CKH(hipHostMalloc((void **)&h_runs, (size_t)nprob * sizeof(BatchRun), hipHostMallocDefault));
+        CKH(hipHostMalloc((void **)&h_scal, (size_t)nprob * 4 * sizeof(double), hipHostMallocDefault));
+        CKH(hipHostMalloc((void **)&h_states, (size_t)nprob * sizeof(BicgState), hipHostMallocDefault));
+        CKH(hipHostMalloc((void **)&h_hdr, (4 + kMaxRuns) * sizeof(int), hipHostMallocDefault));
+        long long max_items = 0;
+        for (int j = 0; j < nprob; j++) {
+            const excmg_problem &P = probs[j];
+            CKR(check_sizes(P.n_finest, P.n_levels, P.bc_kind));
+            if (!P.f || !P.g1 || !P.g2 || !P.u_out) return fail(EXCMG_EINVAL, "problem %d: NULL array", j);
+            BProb *b = new BProb();
+            pb.push_back(b);
+            b->N = P.n_finest;
+            b->nl = P.n_levels;
+            b->bc = P.bc_kind;
+            b->L = P.n_levels - 2;
+            const size_t nb = (size_t)(b->N + 1) * (b->N + 1) * (b->N + 1) * 8;
+            b->af = new Arg(P.f, nb);
+            b->a1 = new Arg(P.g1, nb);
+            b->a2 = new Arg(P.g2, nb);
+            b->au = new Arg(P.u_out, nb);
+            CKR(b->af->in());
+            CKR(b->a1->in());
+            CKR(b->a2->in());
+            CKR(b->au->out());
+            if (P.ut_out) {
+                b->at = new Arg(P.ut_out, nb);
+                CKR(b->at->out());
+            }
+            const int N0 = b->N >> (b->nl - 1);
+            b->lv.resize(b->nl);
+            size_t max_pa = 1, max_pb = 1;
+            for (int l = 0; l < b->nl; l++) {
+                Level &Lv = b->lv[l];
+                Lv.index = l;
+                Lv.N = N0 << l;
+                Lv.n = Lv.N - 1;
+                Lv.nu = (long long)Lv.n * Lv.n * Lv.n;
+                Lv.nodes = (long long)(Lv.N + 1) * (Lv.N + 1) * (Lv.N + 1);
+                Lv.g1 = choose_shape(Lv.N, b->bc, 0);
+                Geom gb = choose_shape(Lv.N, b->bc, 1);
+                Lv.g2 = make_geom(Lv.n, b->bc, kBatchTY, gb.zc);
+                CKR(Lv.b.ensure(Lv.nu * 8));
+                CKR(Lv.x.ensure(Lv.nu * 8));
+                CKR(Lv.u.ensure(Lv.nodes * 8));
+                const long long nch = (Lv.nu + kChunkGraph - 1) / kChunkGraph;
+                max_pa = std::max({max_pa, (size_t)stencil_blocks(Lv.g1), (size_t)Lv.g2.ntiles});
+                max_pb = std::max({max_pb, (size_t)(2 * nch), (size_t)(2 * vec_blocks(Lv.nu))});
+                if (l >= 2) max_items += Lv.g2.ntiles + nch;
+            }
+            const size_t vb = (size_t)b->lv.back().nu * 8;
+            CKR(b->r.ensure(vb)); CKR(b->rs.ensure(vb));
+            CKR(b->p[0].ensure(vb)); CKR(b->p[1].ensure(vb));
+            CKR(b->ps[0].ensure(vb)); CKR(b->ps[1].ensure(vb));
+            CKR(b->q.ensure(vb)); CKR(b->qs.ensure(vb));
+            CKR(b->part_a.ensure(max_pa * sizeof(Pair)));
+            CKR(b->part_b.ensure(max_pb * sizeof(Pair)));
+            const long long m1 = b->N / 2 + 1;
+            CKR(b->ubuf.ensure((size_t)m1 * m1 * m1 * 8));
+            b->stats.n_levels = b->nl;
+        }
+        CKR(items.ensure((size_t)std::max(1LL, max_items) * sizeof(int2)));
+        CKH(hipHostMalloc((void **)&h_items, (size_t)std::max(1LL, max_items) * sizeof(int2),
+                          hipHostMallocDefault));
+        if (mixed) CKH(batch_step_grid<float>(&grid));
+        else CKH(batch_step_grid<double>(&grid));
+        return EXCMG_OK;
+    }
+
+    // Levels 0 and 1 (direct), then the first Bi-CG level's guess.
+    int start(int j) {
+        BProb &b = *pb[j];
+        const double *f = b.af->p<double>(), *g1 = b.a1->p<double>(), *g2 = b.a2->p<double>();
+        for (int l = 0; l < 2; l++) {
+            Level &Lv = b.lv[l];
+            const int s = 1 << (b.nl - 1 - l);
+            CKH(rhs_assemble(Lv.N, b.bc, s, b.N, f, g1, g2, Lv.b.as<double>(), st));
+            double *Lf = nullptr;
+            CKR(fc.get(Lv.N, b.bc, st, &Lf));
+            CKH(dense_solve((int)Lv.nu, Lf, Lv.b.as<double>(), Lv.x.as<double>(),
+                            b.r.as<double>(), st));
+            CKH(to_nodes<double>(Lv.N, s, b.N, Lv.x.as<double>(), g1, Lv.u.as<double>(), st));
+            b.stats.level[l].n = Lv.N;
+        }
+        return enter_level(j, 2);
+    }
+
+    int enter_level(int j, int l) {
+        BProb &b = *pb[j];
+        Level &Lv = b.lv[l];
+        const int s = 1 << (b.nl - 1 - l);
+        CKH(rhs_assemble(Lv.N, b.bc, s, b.N, b.af->p<double>(), b.a1->p<double>(),
+                         b.a2->p<double>(), Lv.b.as<double>(), st));
+        CKH(exp_finite(Lv.N, b.lv[l - 1].u.as<double>(), b.lv[l - 2].u.as<double>(),
+                       b.ubuf.as<double>(), Lv.u.as<double>(), st));
+        CKH(from_nodes(Lv.N, Lv.u.as<double>(), Lv.x.as<double>(), st));
+        // b.b: into the run state (FP64 runs) and the host-visible slot
+        const int nvb = vec_blocks(Lv.nu);
+        CKH(dot_partials<double>(Lv.nu, Lv.b.as<double>(), Lv.b.as<double>(),
+                                 b.part_b.as<Pair>(), nvb, st));
+        CKH(reduce_to(sc(j), b.part_b.as<Pair>(), nvb, 1, st));
+        CKH(reduce_to((double *)&S(j)->bb, b.part_b.as<Pair>(), nvb, 0, st));
+        b.level = l;
+        b.phase = kPhaseCheck;
+        b.runs = b.iters = b.outer = 0;
+        b.prev = INFINITY;
+        b.eps = level_tolerance(tol, l - 1, b.L);
+        return EXCMG_OK;
+    }
+
+    // Launch the true (FP64) residual of the current iterate; r.r lands in slot 2.
+    int launch_check(int j) {
+        BProb &b = *pb[j];
+        Level &Lv = b.lv[b.level];
+        if (mixed)
+            CKH(stencil_residual_cast(Lv.g1, Lv.g1.ty, Lv.b.as<double>(), Lv.x.as<double>(),
+                                      b.r.as<float>(), b.rs.as<float>(), b.part_a.as<Pair>(), st));
+        else
+            CKH(stencil_residual<double>(Lv.g1, Lv.g1.ty, Lv.b.as<double>(), Lv.x.as<double>(),
+                                         b.r.as<double>(), b.part_a.as<Pair>(), st));
+        CKH(reduce_to(sc(j), b.part_a.as<Pair>(), stencil_blocks(Lv.g1), 2, st));
+        return EXCMG_OK;
+    }
+
+    int finish_level(int j, int status, double rr, double bb) {
+        BProb &b = *pb[j];
+        Level &Lv = b.lv[b.level];
+        const int s = 1 << (b.nl - 1 - b.level);
+        excmg_level_stats &ls = b.stats.level[b.level];
+        ls.n = Lv.N;
+        ls.iterations = b.iters;
+        ls.runs = mixed ? b.outer : b.runs;
+        ls.status = status;
+        ls.eps = b.eps;
+        ls.rel_residual = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+        if (status != EXCMG_OK && b.worst == EXCMG_OK) b.worst = status;
+        CKH(to_nodes<double>(Lv.N, s, b.N, Lv.x.as<double>(), b.a1->p<double>(), Lv.u.as<double>(), st));
+        if (b.level == b.nl - 1) {
+            if (b.at) CKH(exp_true(b.N, Lv.u.as<double>(), b.lv[b.nl - 2].u.as<double>(),
+                                   b.at->p<double>(), st));
+            CKH(hipMemcpyAsync(b.au->p<double>(), Lv.u.p, Lv.nodes * 8, hipMemcpyDeviceToDevice, st));
+            b.phase = kPhaseDone;
+            return EXCMG_OK;
+        }
+        return enter_level(j, b.level + 1);
+    }
+
+    // Decide after a check: converged level, give up, or start a (new) Bi-CG run.
+    int decide(int j) {
+        BProb &b = *pb[j];
+        Level &Lv = b.lv[b.level];
+        const double bb = h_scal[4 * j + 1], rr = h_scal[4 * j + 2];
+        const double thr = (b.eps * b.eps) * bb;
+        if (rr <= thr) return finish_level(j, EXCMG_OK, rr, bb);
+        BicgState *Sj = S(j);
+        if (!mixed) {
+            if (b.runs >= max_runs) return finish_level(j, EXCMG_ENOCONV, rr, bb);
+            CKH((copy_convert<double, double>(Lv.nu, b.r.as<double>(), b.rs.as<double>(), st)));
+            CKH(bicg_start(Sj, b.part_a.as<Pair>(), stencil_blocks(Lv.g1), b.eps, maxit, st));
+        } else {
+            if (b.outer >= max_outer || !(rr < b.prev)) return finish_level(j, EXCMG_ENOCONV, rr, bb);
+            b.prev = rr;
+            double it = std::max(inner_tol, 0.3 * b.eps * std::sqrt(bb / rr));
+            if (it > 0.5) it = 0.5;
+            const int nvb = vec_blocks(Lv.nu);
+            CKH(dot_partials<float>(Lv.nu, b.r.as<float>(), b.r.as<float>(), b.part_b.as<Pair>(), nvb, st));
+            CKH(reduce_to((double *)&Sj->bb, b.part_b.as<Pair>(), nvb, 0, st));
+            CKH(bicg_start(Sj, b.part_b.as<Pair>(), nvb, it, maxit, st));
+            b.outer++;
+        }
+        b.phase = kPhaseRun;
+        return EXCMG_OK;
+    }
+
+    // Work list of the running systems: all sweep-A tiles, then all sweep-B chunks.
+    int build_items(int *n_a, int *n_items) {
+        int na = 0;
+        for (size_t j = 0; j < pb.size(); j++) {
+            BProb &b = *pb[j];
+            Level &Lv = b.lv[b.level];
+            BatchRun &R = h_runs[j];
+            R.g = Lv.g2;
+            R.nu = Lv.nu;
+            R.a_count = Lv.g2.ntiles;
+            R.chunk = persistent ? kChunkPersistent : kChunkGraph;
+            R.b_count = (int)((Lv.nu + R.chunk - 1) / R.chunk);
+            R.r = b.r.p; R.rs = b.rs.p;
+            R.p[0] = b.p[0].p; R.p[1] = b.p[1].p; R.ps[0] = b.ps[0].p; R.ps[1] = b.ps[1].p;
+            R.q = b.q.p; R.qs = b.qs.p;
+            R.x = Lv.x.as<double>();
+            R.state = S((int)j);
+            R.part_a = b.part_a.as<Pair>();
+            R.part_b = b.part_b.as<Pair>();
+            if (b.phase != kPhaseRun) continue;
+            for (int t = 0; t < R.a_count; t++) h_items[na++] = make_int2((int)j, t);
+        }
+        int ni = na;
+        for (size_t j = 0; j < pb.size(); j++) {
+            if (pb[j]->phase != kPhaseRun) continue;
+            for (int c = 0; c < h_runs[j].b_count; c++) h_items[ni++] = make_int2((int)j, c);
+        }
+        *n_a = na;
+        *n_items = ni;
+        CKH(hipMemcpyAsync(runs.p, h_runs, pb.size() * sizeof(BatchRun), hipMemcpyHostToDevice, st));
+        CKH(hipMemcpyAsync(items.p, h_items, (size_t)std::max(ni, 1) * sizeof(int2), hipMemcpyHostToDevice, st));
+        // header: n_a, n_items, n_runs, n_active, active[]
+        h_hdr[0] = na;
+        h_hdr[1] = ni;
+        h_hdr[2] = (int)pb.size();
+        int nact = 0;
+        for (size_t j = 0; j < pb.size(); j++)
+            if (pb[j]->phase == kPhaseRun) h_hdr[4 + nact++] = (int)j;
+        h_hdr[3] = nact;
+        CKH(hipMemcpyAsync((char *)ctl.p + offsetof(BatchCtl, n_a), h_hdr,
+                           (4 + kMaxRuns) * sizeof(int), hipMemcpyHostToDevice, st));
+        return EXCMG_OK;
+    }
+
+    int launch_steps() {
+        if (!exec) {
+            CKH(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+            for (int t = 0; t < steps_per_graph; t++) {
+                hipError_t e;
+                if (persistent)
+                    e = mixed ? batch_step<float>(grid, runs.as<BatchRun>(), items.as<int2>(), ctl.as<BatchCtl>(), st)
+                              : batch_step<double>(grid, runs.as<BatchRun>(), items.as<int2>(), ctl.as<BatchCtl>(), st);
+                else
+                    e = mixed ? batch_step_phases<float>(runs.as<BatchRun>(), items.as<int2>(), ctl.as<BatchCtl>(), st)
+                              : batch_step_phases<double>(runs.as<BatchRun>(), items.as<int2>(), ctl.as<BatchCtl>(), st);
+                if (e != hipSuccess) {
+                    hipGraph_t g;
+                    (void)hipStreamEndCapture(st, &g);
+                    return fail(EXCMG_EHIP, "batch step launch: %s", hipGetErrorString(e));
+                }
+            }
+            CKH(hipStreamEndCapture(st, &graph));
+            CKH(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        }
+        CKH(hipGraphLaunch(exec, st));
+        launches += steps_per_graph;
+        return EXCMG_OK;
+    }
+
+    int run() {
+        const int np = (int)pb.size();
+        for (int j = 0; j < np; j++) CKR(start(j));
+        for (;;) {
+            // checks of every system that is between runs
+            bool any_check = false;
+            for (int j = 0; j < np; j++)
+                if (pb[j]->phase == kPhaseCheck) {
+                    CKR(launch_check(j));
+                    any_check = true;
+                }
+            if (any_check) {
+                CKH(hipMemcpyAsync(h_scal, scal.p, (size_t)np * 4 * sizeof(double),
+                                   hipMemcpyDeviceToHost, st));
+                CKH(hipStreamSynchronize(st));
+                for (int j = 0; j < np; j++)
+                    if (pb[j]->phase == kPhaseCheck) CKR(decide(j));
+                continue;  // newly entered levels need their first check
+            }
+            bool running = false;
+            for (int j = 0; j < np; j++) running |= (pb[j]->phase == kPhaseRun);
+            if (!running) break;
+            int na = 0, ni = 0;
+            CKR(build_items(&na, &ni));
+            // advance every running system until one of them stops
+            for (;;) {
+                CKR(launch_steps());
+                CKH(hipMemcpyAsync(h_states, states.p, (size_t)np * sizeof(BicgState),
+                                   hipMemcpyDeviceToHost, st));
+                CKH(hipStreamSynchronize(st));
+                bool changed = false;
+                for (int j = 0; j < np; j++) {
+                    BProb &b = *pb[j];
+                    if (b.phase != kPhaseRun || h_states[j].status == kRunning) continue;
+                    b.iters += h_states[j].iter;
+                    b.runs++;
+                    changed = true;
+                    b.phase = kPhaseCheck;
+                    if (h_states[j].status == kBreakdown) b.worst = EXCMG_EBREAKDOWN;
+                }
+                int err = 0;
+                CKH(hipMemcpyAsync(&err, (char *)ctl.p + offsetof(BatchCtl, error), sizeof(int),
+                                   hipMemcpyDeviceToHost, st));
+                CKH(hipStreamSynchronize(st));
+                if (err) return fail(EXCMG_EHIP, "batched step: a bounded wait expired");
+                if (changed) break;
+            }
+        }
+        for (BProb *b : pb) {
+            CKR(b->au->back());
+            if (b->at) CKR(b->at->back());
+        }
+        CKH(hipStreamSynchronize(st));
+        return EXCMG_OK;
+    }
+};
+
 }  // namespace
 
 // ================================================================== C ABI
@@ -882,6 +1288,135 @@ int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launc
     if (bytes_per_launch)
         *bytes_per_launch =
             (precision == EXCMG_FP64 ? fp64_bytes[which] : mixed_bytes[which]) * (double)L.nu;
+    return EXCMG_OK;
+}
+
+int excmg_solve_batch(int nprob, const excmg_problem *probs, const excmg_opts *opts,
+                      excmg_stats *stats) {
+    g_err[0] = 0;
+    if (nprob < 1 || nprob > kMaxRuns) return fail(EXCMG_EINVAL, "nprob must be in 1..%d", kMaxRuns);
+    if (!probs || !opts) return fail(EXCMG_EINVAL, "NULL problems or options");
+    if (!(opts->tol > 0.0)) return fail(EXCMG_EINVAL, "tol must be positive");
+    if (opts->precision != EXCMG_FP64 && opts->precision != EXCMG_MIXED)
+        return fail(EXCMG_EINVAL, "precision %d not supported", opts->precision);
+    for (int j = 0; j < nprob; j++) CKR(check_sizes(probs[j].n_finest, probs[j].n_levels, probs[j].bc_kind));
+    hipStream_t bs;
+    CKH(hipStreamCreateWithFlags(&bs, hipStreamNonBlocking));
+    hipEvent_t e0, e1, ein;
+    CKH(hipEventCreate(&e0));
+    CKH(hipEventCreate(&e1));
+    CKH(hipEventCreate(&ein));
+    CKH(hipEventRecord(ein, g_stream));
+    CKH(hipStreamWaitEvent(bs, ein, 0));
+    hipStream_t saved = g_stream;
+    g_stream = bs;  // host-array staging of the batch goes through the batch stream
+    int rc;
+    float ms = 0.f;
+    {
+        BatchSolver B;
+        B.st = bs;
+        rc = B.init(nprob, probs, *opts);
+        if (rc == EXCMG_OK) {
+            CKH(hipEventRecord(e0, bs));
+            rc = B.run();
+            CKH(hipEventRecord(e1, bs));
+            CKH(hipEventSynchronize(e1));
+            CKH(hipEventElapsedTime(&ms, e0, e1));
+        }
+        if (rc == EXCMG_OK) {
+            int worst = EXCMG_OK;
+            for (int j = 0; j < nprob; j++) {
+                B.pb[j]->stats.total_ms = ms;
+                if (stats) stats[j] = B.pb[j]->stats;
+                if (B.pb[j]->worst != EXCMG_OK && worst == EXCMG_OK) worst = B.pb[j]->worst;
+            }
+            if (worst != EXCMG_OK) rc = fail(worst, "a level of a batched problem stopped early");
+        }
+        (void)hipStreamSynchronize(bs);
+    }
+    g_stream = saved;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipEventDestroy(ein);
+    (void)hipStreamDestroy(bs);
+    return rc;
+}
+
+int excmg_autotune(int n, int kind, int precision, int reps, int *ty_out, int *zc_out,
+                   double *ms_out) {
+    g_err[0] = 0;
+    if (n < 4 || n > 4096) return fail(EXCMG_EINVAL, "n must be in 4..4096");
+    if (kind != 0 && kind != 1) return fail(EXCMG_EINVAL, "kind must be 0 or 1");
+    if (precision != EXCMG_FP64 && precision != EXCMG_MIXED) return fail(EXCMG_EINVAL, "bad precision");
+    if (reps < 1) reps = 5;
+    const int nn = n - 1;
+    const long long nu = (long long)nn * nn * nn;
+    const size_t es = precision == EXCMG_FP64 ? 8 : 4;
+    DBuf v[8], part, stb;
+    for (auto &b : v) {
+        CKR(b.ensure((size_t)nu * es));
+        CKH(hipMemsetAsync(b.p, 0, (size_t)nu * es, g_stream));
+    }
+    CKR(stb.ensure(sizeof(BicgState)));
+    BicgState hs{};
+    hs.status = kRunning;
+    hs.rho = 1.0;
+    hs.maxit = 1 << 30;
+    CKH(hipMemcpyAsync(stb.p, &hs, sizeof(hs), hipMemcpyHostToDevice, g_stream));
+    BicgState *S = stb.as<BicgState>();
+    std::vector<int> tys = kind == 1 ? std::vector<int>{4, 8} : std::vector<int>{4, 8, 16};
+    double best = INFINITY;
+    int bty = 8, bzc = 8;
+    hipEvent_t e0, e1;
+    CKH(hipEventCreate(&e0));
+    CKH(hipEventCreate(&e1));
+    int rc = EXCMG_OK;
+    for (int ty : tys) {
+        for (int zc = 4; zc <= 512; zc *= 2) {
+            if (zc > nn && zc != 4) break;
+            Geom g = make_geom(nn, 1, ty, std::min(zc, nn));
+            rc = part.ensure((size_t)stencil_blocks(g) * sizeof(Pair));
+            if (rc) break;
+            auto launch = [&]() -> hipError_t {
+                if (kind == 0) {
+                    if (es == 8) return stencil_apply<double>(g, ty, v[0].as<double>(), v[1].as<double>(), g_stream);
+                    return stencil_apply<float>(g, ty, v[0].as<float>(), v[1].as<float>(), g_stream);
+                }
+                if (es == 8)
+                    return stencil_pair_direction<double>(g, ty, v[0].as<double>(), v[1].as<double>(),
+                                                          v[2].as<double>(), v[3].as<double>(), &S->beta, 0,
+                                                          v[4].as<double>(), v[5].as<double>(), v[6].as<double>(),
+                                                          v[7].as<double>(), part.as<Pair>(), &S->status, g_stream);
+                return stencil_pair_direction<float>(g, ty, v[0].as<float>(), v[1].as<float>(),
+                                                     v[2].as<float>(), v[3].as<float>(), &S->beta, 0,
+                                                     v[4].as<float>(), v[5].as<float>(), v[6].as<float>(),
+                                                     v[7].as<float>(), part.as<Pair>(), &S->status, g_stream);
+            };
+            CKH(launch());
+            CKH(hipEventRecord(e0, g_stream));
+            for (int t = 0; t < reps; t++) CKH(launch());
+            CKH(hipEventRecord(e1, g_stream));
+            CKH(hipEventSynchronize(e1));
+            float ms = 0.f;
+            CKH(hipEventElapsedTime(&ms, e0, e1));
+            if (ms / reps < best) {
+                best = ms / reps;
+                bty = ty;
+                bzc = std::min(zc, nn);
+            }
+        }
+        if (rc) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (auto &b : v) b.release();
+    part.release();
+    stb.release();
+    if (rc) return rc;
+    CKR(excmg_set_shape(n, kind, bty, bzc));
+    if (ty_out) *ty_out = bty;
+    if (zc_out) *zc_out = bzc;
+    if (ms_out) *ms_out = best;
     return EXCMG_OK;
 }
 

@@ -111,4 +111,54 @@ hipError_t dense_cholesky(int n, double *A, int *info, hipStream_t st);
 hipError_t dense_solve(int n, const double *L, const double *b, double *x, double *y,
                        hipStream_t st);
 
+// ---------------------------------------------------------------- batched Bi-CG
+
+constexpr int kBatchTY = 8;            // tile height of the batched sweep A
+constexpr int kMaxRuns = 256;          // systems per batch
+constexpr long long kChunkGraph = 16384;      // unknowns per sweep-B item (phase kernels)
+constexpr long long kChunkPersistent = 32768; // unknowns per sweep-B item (persistent kernel)
+
+// One running Bi-CG system of a batch (device-resident table).
+struct BatchRun {
+    Geom g;                 // sweep-A geometry (ty = kBatchTY)
+    long long nu;           // unknowns
+    int a_count, b_count;   // sweep-A tiles, sweep-B chunks
+    long long chunk;        // unknowns per sweep-B chunk
+    void *r, *rs, *p[2], *ps[2], *q, *qs;   // Bi-CG vectors (FP64 or FP32)
+    double *x;              // iterate (FP64)
+    BicgState *state;
+    Pair *part_a;           // a_count partials of sigma
+    Pair *part_b;           // 2 * b_count partials of rho and r.r
+};
+
+// Control block of the persistent step kernel (device).
+struct BatchCtl {
+    int queue;              // next item to claim
+    int exit_count;         // workgroups that left the queue loop
+    int epoch;              // launch number (advanced by the last workgroup out)
+    int error;              // set if a bounded wait expired
+    int n_a;                // items [0, n_a) are sweep-A items
+    int n_items;
+    int n_runs;
+    int n_active;           // running systems (phase kernels)
+    int active[kMaxRuns];   // their indices
+    int a_done[kMaxRuns];
+    int b_done[kMaxRuns];
+    int alpha_epoch[kMaxRuns];
+};
+
+// One Bi-CG iteration of every running system as ONE launch of the persistent work-queue
+// kernel (grid = resident workgroups).
+template <typename T>
+hipError_t batch_step(int grid, const BatchRun *runs, const int2 *items, BatchCtl *ctl,
+                      hipStream_t st);
+template <typename T>
+hipError_t batch_step_grid(int *grid);
+
+// The same iteration as four phase launches (sweep A, alpha, sweep B, beta) over the work
+// list in ctl; grid-stride, no inter-workgroup communication inside a launch.
+template <typename T>
+hipError_t batch_step_phases(const BatchRun *runs, const int2 *items, const BatchCtl *ctl,
+                             hipStream_t st);
+
 }  // namespace excmg

@@ -1,0 +1,347 @@
+// Matrix-free 25-point operator A_h of Sec. 2 on interior vectors, for gfx950: the device code
+// shared by the single-system kernels (stencil.hip) and the batched persistent kernel
+// (batch.hip).
+//
+// Design (one kernel template, several epilogues):
+//  * A workgroup owns a 64 x TY column tile of the (n = N-1)^2 plane and marches through a
+//    chunk of ZC planes in z.  Each plane is staged once in LDS with a 2-wide halo in x and
+//    y (double-buffered, so one barrier per plane); the next plane's global loads are issued
+//    before the current plane is consumed, which hides HBM latency behind the LDS work.
+//  * Every lane keeps the z-direction terms of its column in registers: the centre values
+//    of the last five planes, the four in-plane neighbours of the previous plane and the
+//    partial sums of the three outputs that are still open.  An output on plane k is
+//    complete when plane k+2 arrives.
+//  * The left-hand side of eq. (method1) is summed left to right in the order the paper
+//    prints it, with contraction off:
+//      y = 42 c - 12 S1 + S2 + 2 S3,
+//      S1 = x- + x+ + y- + y+ + z- + z+,   S2 = the same at distance 2,
+//      S3 = (x-y-) + (x-y+) + (x+y-) + (x+y+) + [x-, x+, y-, y+ on plane k-1]
+//           + [x-, x+, y-, y+ on plane k+1].
+//  * Fictitious points (eqs. reflection2 / reflection4 with zero boundary data) are produced
+//    while staging: a halo position one step outside the boundary node holds +x (first kind)
+//    or -x (second kind) of the mirrored interior node, a boundary node holds 0.  The
+//    resulting operator is exactly the paper's A_h, including its boundary rows, with no
+//    per-row branches in the arithmetic.
+//  * Tiles are ordered XCD-aware: each of the 8 XCDs processes a contiguous range of tiles.
+#pragma once
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace excmg {
+
+// Where a staged coordinate comes from: multiplier 1 (interior), sgn (fictitious point,
+// mirrored source) or 0 (boundary node or beyond the grid).
+__device__ __forceinline__ double reflect(int c, int n, double sgn, int &src) {
+    if (c >= 0 && c < n) {
+        src = c;
+        return 1.0;
+    }
+    if (c == -2) {
+        src = 0;
+        return sgn;
+    }
+    if (c == n + 1) {
+        src = n - 1;
+        return sgn;
+    }
+    src = 0;
+    return 0.0;
+}
+
+// Per-column register state of one marched array.
+struct Column {
+    double cm4, cm3, cm2, cm1;   // centre values of planes m-4 .. m-1
+    double np0, np1, np2, np3;   // in-plane neighbours (x-, x+, y-, y+) of plane m-1
+    double a2, a1;               // sum of in-plane neighbours of planes m-2, m-1
+    double b2, b1;               // sum of in-plane distance-2 values of planes m-2, m-1
+    double e2, e1;               // partial S3 of planes m-2, m-1
+};
+
+__device__ __forceinline__ void column_init(Column &s) {
+    s.cm4 = s.cm3 = s.cm2 = s.cm1 = 0.0;
+    s.np0 = s.np1 = s.np2 = s.np3 = 0.0;
+    s.a2 = s.a1 = s.b2 = s.b1 = s.e2 = s.e1 = 0.0;
+}
+
+// Consume plane m from LDS (row stride LS, centre at B) and return the completed output of
+// plane m-2.  `c0` receives the centre value of plane m.
+template <int LS>
+__device__ __forceinline__ double column_step(Column &s, const double *B, double &c0) {
+    const double c = B[0];
+    const double n0 = B[-1], n1 = B[1], n2 = B[-LS], n3 = B[LS];
+    const double s0 = B[-2], s1 = B[2], s2 = B[-2 * LS], s3 = B[2 * LS];
+    const double d0 = B[-1 - LS], d1 = B[-1 + LS], d2 = B[1 - LS], d3 = B[1 + LS];
+    // open output m
+    const double a0 = n0 + n1 + n2 + n3;
+    const double b0 = s0 + s1 + s2 + s3;
+    const double e0 = d0 + d1 + d2 + d3 + s.np0 + s.np1 + s.np2 + s.np3;
+    // output m-1 receives its plane k+1 diagonal terms
+    const double e1 = s.e1 + n0 + n1 + n2 + n3;
+    // output m-2 is complete
+    const double S1 = s.a2 + s.cm3 + s.cm1;
+    const double S2 = s.b2 + s.cm4 + c;
+    const double y = 42.0 * s.cm2 - 12.0 * S1 + S2 + 2.0 * s.e2;
+    // shift
+    s.cm4 = s.cm3;
+    s.cm3 = s.cm2;
+    s.cm2 = s.cm1;
+    s.cm1 = c;
+    s.np0 = n0;
+    s.np1 = n1;
+    s.np2 = n2;
+    s.np3 = n3;
+    s.a2 = s.a1;
+    s.a1 = a0;
+    s.b2 = s.b1;
+    s.b1 = b0;
+    s.e2 = e1;
+    s.e1 = e0;
+    c0 = c;
+    return y;
+}
+
+// Inputs of the marched arrays.  Staging is split in two so that global loads stay in
+// flight while earlier planes are consumed: load() fetches the R raw values of a staged
+// element (into registers, no arithmetic), combine() turns them into the staged value.
+// prepare() runs once per thread before the march.
+template <typename T>
+struct InPlain {            // x itself
+    static constexpr int R = 1;
+    const T *x[2];
+    __device__ __forceinline__ void prepare() {}
+    __device__ __forceinline__ void load(int a, i64 idx, T (&raw)[R]) const { raw[0] = x[a][idx]; }
+    __device__ __forceinline__ double combine(const T (&raw)[R]) const { return (double)raw[0]; }
+};
+
+template <typename T>
+struct InDirection {        // p_new = r + beta p_old (p_new = r on the first iteration)
+    static constexpr int R = 2;
+    const T *r[2];
+    const T *p[2];
+    const double *beta_dev; // beta of Algorithm 2, written by the previous finalisation
+    int first;
+    double beta;
+    __device__ __forceinline__ void prepare() { beta = first ? 0.0 : *beta_dev; }
+    __device__ __forceinline__ void load(int a, i64 idx, T (&raw)[R]) const {
+        raw[0] = r[a][idx];
+        raw[1] = p[a][idx];
+    }
+    __device__ __forceinline__ double combine(const T (&raw)[R]) const {
+        const double rv = (double)raw[0];
+        // rounded to the storage type, so the operator acts on exactly the stored vector
+        const double pn = (double)(T)(rv + beta * (double)raw[1]);
+        return first ? rv : pn;
+    }
+};
+
+// Kernel: NA marched arrays (1 or 2), input policy In, epilogue Out.
+//   Out::emit(lane_state, idx, y[NA], c[NA]) is called for every valid output with the
+//   operator values y and the centre values c of the output plane;
+//   Out::centre(idx, c[NA]) is called for every valid centre of a plane inside the chunk;
+//   Out::finish(block, tile) runs after the march (block-level reductions).
+// March one tile (x-tile, y-tile, z-chunk) of the grid.  `in` must be prepared.  Called by
+// a whole 64 x TY workgroup; contains barriers.
+template <int NA, int TY, typename T, class In, class Out>
+__device__ __forceinline__ void zmarch_tile(const Geom &g, int tile, const In &in, Out &out) {
+    constexpr int TX = kWave;
+    constexpr int LS = TX + 4;          // LDS row stride
+    constexpr int LR = TY + 4;          // LDS rows
+    constexpr int LE = LS * LR;         // elements per plane
+    constexpr int NT = TX * TY;
+    constexpr int NL = (LE + NT - 1) / NT;
+    __shared__ double buf[2][NA][LE];
+    const int n = g.n;
+    const int tx = tile % g.tiles_x;
+    const int ty = (tile / g.tiles_x) % g.tiles_y;
+    const int tz = tile / (g.tiles_x * g.tiles_y);
+    const int lx = threadIdx.x, ly = threadIdx.y;
+    const int tid = ly * TX + lx;
+    const int ix = tx * TX + lx, iy = ty * TY + ly;
+    const bool valid = (ix < n) && (iy < n);
+    const int k0 = tz * g.zc;
+    const int k1 = min(k0 + g.zc, n);
+    const i64 plane = (i64)n * n;
+
+    // staging slots of this thread: LDS element e = tid + q*NT.  Every slot has a valid
+    // source address (positions outside the grid are clamped and multiplied by 0), so the
+    // loads need no branches and can stay in flight.
+    int soff[NL];     // source offset inside a plane (row-major, x fastest)
+    double smul[NL];  // in-plane multiplier (0 = boundary node, outside, or unused slot)
+#pragma unroll
+    for (int q = 0; q < NL; q++) {
+        int e = tid + q * NT;
+        smul[q] = 0.0;
+        soff[q] = 0;
+        if (e < LE) {
+            int row = e / LS, col = e % LS;
+            int sx, sy;
+            double mx = reflect(tx * TX + col - 2, n, g.sgn, sx);
+            double my = reflect(ty * TY + row - 2, n, g.sgn, sy);
+            smul[q] = mx * my;
+            soff[q] = sy * n + sx;
+        }
+    }
+
+    constexpr int R = In::R;
+    using Raw = T[NL][NA][R];
+    auto fetch = [&](int m, Raw &raw, double &mz) {
+        int sz;
+        mz = reflect(m, n, g.sgn, sz);
+#pragma unroll
+        for (int q = 0; q < NL; q++) {
+            const i64 idx = (i64)sz * plane + soff[q];
+#pragma unroll
+            for (int a = 0; a < NA; a++) in.load(a, idx, raw[q][a]);
+        }
+    };
+    auto stash = [&](int b, const Raw &raw, double mz) {
+#pragma unroll
+        for (int q = 0; q < NL; q++) {
+            const int e = tid + q * NT;
+            const double mul = smul[q] * mz;
+            if (e < LE) {
+#pragma unroll
+                for (int a = 0; a < NA; a++) {
+                    const double v = in.combine(raw[q][a]);
+                    buf[b][a][e] = (mul != 0.0) ? mul * v : 0.0;
+                }
+            }
+        }
+    };
+
+    Column col[NA];
+#pragma unroll
+    for (int a = 0; a < NA; a++) column_init(col[a]);
+
+    // Planes mbeg..mend are staged; two planes are in flight in registers at any time.
+    const int mbeg = k0 - 2, mend = k1 + 1;
+    Raw rawA, rawB;
+    double mzA, mzB;
+    fetch(mbeg, rawA, mzA);
+    stash(0, rawA, mzA);
+    fetch(min(mbeg + 1, mend), rawA, mzA);
+    fetch(min(mbeg + 2, mend), rawB, mzB);
+    __syncthreads();
+    int cur = 0;
+    const int centre = (ly + 2) * LS + (lx + 2);
+    // consume plane m from LDS, stage plane m+1 from `raw`, refill `raw` with plane m+3
+    auto body = [&](int m, Raw &raw, double &mz) {
+        double y[NA], c0[NA], cprev[NA];
+#pragma unroll
+        for (int a = 0; a < NA; a++) {
+            cprev[a] = col[a].cm2;   // centre of plane m-2 before the shift
+            y[a] = column_step<LS>(col[a], &buf[cur][a][centre], c0[a]);
+        }
+        if (valid) {
+            if (m >= k0 && m < k1) out.centre((i64)m * plane + (i64)iy * n + ix, c0);
+            const int k = m - 2;
+            if (k >= k0 && k < k1) out.emit((i64)k * plane + (i64)iy * n + ix, y, cprev);
+        }
+        stash(cur ^ 1, raw, mz);
+        fetch(min(m + 3, mend), raw, mz);
+        __syncthreads();
+        cur ^= 1;
+    };
+    for (int m = mbeg; m <= mend; m += 2) {
+        body(m, rawA, mzA);
+        if (m + 1 > mend) break;
+        body(m + 1, rawB, mzB);
+    }
+}
+
+// One workgroup per tile (XCD-aware order), then the epilogue's block-level reduction.
+template <int NA, int TY, typename T, class In, class Out>
+__global__ void __launch_bounds__(kWave *TY) zmarch(Geom g, In in_arg, Out out) {
+    __shared__ Pair red[4 * TY];
+    if (out.skip()) return;
+    In in = in_arg;
+    in.prepare();
+    const int tile = xcd_tile(blockIdx.x, g.ntiles);
+    if (tile < g.ntiles) zmarch_tile<NA, TY, T>(g, tile, in, out);
+    out.finish(blockIdx.x, red);  // padding blocks of the XCD-aware grid contribute zero
+}
+
+// ------------------------------------------------------------------ epilogues
+
+template <typename T>
+struct OutApply {           // y = A x
+    T *y;
+    __device__ bool skip() const { return false; }
+    __device__ void centre(i64, const double *) {}
+    __device__ void emit(i64 idx, const double *v, const double *) { y[idx] = (T)v[0]; }
+    __device__ void finish(int, Pair *) {}
+};
+
+template <typename T>
+struct OutResidual {        // r = b - A x, partial of r.r
+    const double *b;
+    T *r;
+    Pair *partials;
+    Pair acc;
+    __device__ bool skip() const { return false; }
+    __device__ void centre(i64, const double *) {}
+    __device__ void emit(i64 idx, const double *v, const double *) {
+        double rv = b[idx] - v[0];
+        r[idx] = (T)rv;
+        dot2_acc(acc, rv, rv);
+    }
+    __device__ void finish(int block, Pair *sh) {
+        Pair v[1] = {acc};
+        block_merge<1>(v, sh);
+        if (threadIdx.x == 0 && threadIdx.y == 0) partials[block] = v[0];
+    }
+};
+
+// Outer residual of iterative refinement: r64 = b - A u in FP64 (u FP64), stored rounded
+// to FP32 twice (the inner Bi-CG's r_0 and r*_0), partial of r64.r64.
+struct OutResidualCast {
+    const double *b;
+    float *r32;
+    float *rs32;
+    Pair *partials;
+    Pair acc;
+    __device__ bool skip() const { return false; }
+    __device__ void centre(i64, const double *) {}
+    __device__ void emit(i64 idx, const double *v, const double *) {
+        const double rv = b[idx] - v[0];
+        const float rf = (float)rv;
+        r32[idx] = rf;
+        rs32[idx] = rf;
+        dot2_acc(acc, rv, rv);
+    }
+    __device__ void finish(int block, Pair *sh) {
+        Pair v[1] = {acc};
+        block_merge<1>(v, sh);
+        if (threadIdx.x == 0 && threadIdx.y == 0) partials[block] = v[0];
+    }
+};
+
+// Bi-CG sweep A: p_new = r + beta p (staged), q = A p_new, qs = A ps_new, partial of
+// sigma = ps_new . q.  Stores p_new, ps_new (centres) and q, qs.
+template <typename T>
+struct OutPairApply {
+    T *p_new[2];
+    T *q[2];
+    Pair *partials;
+    const int *status;
+    Pair acc;
+    __device__ bool skip() const { return *status != 0; }
+    __device__ void centre(i64 idx, const double *c) {
+        p_new[0][idx] = (T)c[0];
+        p_new[1][idx] = (T)c[1];
+    }
+    __device__ void emit(i64 idx, const double *v, const double *c) {
+        T q0 = (T)v[0], q1 = (T)v[1];
+        q[0][idx] = q0;
+        q[1][idx] = q1;
+        dot2_acc(acc, (double)(T)c[1], (double)q0);
+    }
+    __device__ void finish(int block, Pair *sh) {
+        Pair v[1] = {acc};
+        block_merge<1>(v, sh);
+        if (threadIdx.x == 0 && threadIdx.y == 0) partials[block] = v[0];
+    }
+};
+
+}  // namespace excmg

@@ -16,7 +16,8 @@ __all__ = [
     "ExcmgError", "OK", "EINVAL", "ENOMEM", "ENOCONV", "EBREAKDOWN", "EHIP", "FP64", "MIXED",
     "lib_path", "load", "set_stream", "setup", "apply_stencil", "apply_operator", "rhs", "dsolve", "bicg",
     "level_solve", "exp_finite", "exp_true", "solve", "solve_ex", "profile_sweep",
-    "set_shape", "get_shape", "set_timing", "get_timing",
+    "set_shape", "get_shape", "set_timing", "get_timing", "autotune", "solve_batch",
+    "Problem",
     "last_error", "finalize",
     "LevelStats", "Stats",
 ]
@@ -40,7 +41,7 @@ class Opts(ctypes.Structure):
                 ("bc_kind", ctypes.c_int), ("precision", ctypes.c_int),
                 ("tol", ctypes.c_double), ("max_iters", ctypes.c_int),
                 ("max_runs", ctypes.c_int), ("inner_tol", ctypes.c_double),
-                ("max_outer", ctypes.c_int)]
+                ("max_outer", ctypes.c_int), ("batch_mode", ctypes.c_int)]
 
 
 class LevelStats(ctypes.Structure):
@@ -58,6 +59,12 @@ class Stats(ctypes.Structure):
 
     def levels(self):
         return [self.level[i].asdict() for i in range(self.n_levels)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("n_finest", ctypes.c_int), ("n_levels", ctypes.c_int), ("bc_kind", ctypes.c_int),
+                ("f", ctypes.c_void_p), ("g1", ctypes.c_void_p), ("g2", ctypes.c_void_p),
+                ("u_out", ctypes.c_void_p), ("ut_out", ctypes.c_void_p)]
 
 
 _lib = None
@@ -90,6 +97,9 @@ def load():
                                    ctypes.POINTER(Stats)]),
         "excmg_profile_sweep": (c_int, [c_int, c_int, c_int, ctypes.POINTER(c_dbl),
                                         ctypes.POINTER(c_dbl)]),
+        "excmg_solve_batch": (c_int, [c_int, ctypes.POINTER(Problem), ctypes.POINTER(Opts),
+                                      ctypes.POINTER(Stats)]),
+        "excmg_autotune": (c_int, [c_int, c_int, c_int, c_int, ip, ip, ctypes.POINTER(c_dbl)]),
         "excmg_set_timing": (c_int, [c_int]),
         "excmg_get_timing": (c_int, [c_int, c_int, ctypes.POINTER(c_dbl),
                                      ctypes.POINTER(ctypes.c_longlong)]),
@@ -211,7 +221,7 @@ def solve_ex(n_finest: int, n_levels: int, bc_kind: int, f, g1, g2, tol: float, 
              inner_tol: float = 0.0, max_outer: int = 0):
     """Algorithm 1 with options.  Returns (code, Stats)."""
     o = Opts(n_finest, n_levels, bc_kind, precision, tol, max_iters, max_runs, inner_tol,
-             max_outer)
+             max_outer, 0)
     st = Stats()
     rc = load().excmg_solve_ex(ctypes.byref(o), _ptr(f, name="f"), _ptr(g1, name="g1"),
                                _ptr(g2, name="g2"), _ptr(u_out, name="u_out"),
@@ -229,6 +239,37 @@ def profile_sweep(which: int, precision: int = FP64, reps: int = 20):
     _check("excmg_profile_sweep", load().excmg_profile_sweep(which, precision, reps,
                                                              ctypes.byref(ms), ctypes.byref(nb)))
     return ms.value, nb.value
+
+
+def solve_batch(problems, tol: float, precision: int = FP64, max_iters: int = 0,
+                max_runs: int = 0, inner_tol: float = 0.0, max_outer: int = 0,
+                persistent: bool = False):
+    """Solve independent problems together.  ``problems`` is a list of dicts with keys
+    n_finest, n_levels, bc_kind, f, g1, g2, u_out and optionally ut_out.  Returns
+    (code, list of Stats)."""
+    n = len(problems)
+    arr = (Problem * n)()
+    for i, p in enumerate(problems):
+        arr[i] = Problem(p["n_finest"], p["n_levels"], p["bc_kind"],
+                         _ptr(p["f"], name="f"), _ptr(p["g1"], name="g1"), _ptr(p["g2"], name="g2"),
+                         _ptr(p["u_out"], name="u_out"), _ptr(p.get("ut_out"), name="ut_out"))
+    o = Opts(0, 0, 0, precision, tol, max_iters, max_runs, inner_tol, max_outer,
+             1 if persistent else 0)
+    st = (Stats * n)()
+    rc = load().excmg_solve_batch(n, arr, ctypes.byref(o), st)
+    if rc not in (OK, ENOCONV, EBREAKDOWN):
+        _check("excmg_solve_batch", rc)
+    return rc, list(st)
+
+
+def autotune(n: int, kind: int, precision: int = FP64, reps: int = 5):
+    """Time every tile shape of a stencil kernel on a grid of n cells and keep the fastest.
+    Returns (ty, zc, ms per launch)."""
+    ty, zc = ctypes.c_int(0), ctypes.c_int(0)
+    ms = ctypes.c_double(0.0)
+    _check("excmg_autotune", load().excmg_autotune(n, kind, precision, reps, ctypes.byref(ty),
+                                                   ctypes.byref(zc), ctypes.byref(ms)))
+    return ty.value, zc.value, ms.value
 
 
 def set_timing(on: bool):

@@ -218,3 +218,93 @@ def test_config2_solve(ex):
     print("levels", st.levels(), flush=True)
     assert rel_l2(u, ref.u.ravel()) <= 1e-10
     assert rel_l2(ut, ref.ut.ravel()) <= 1e-10
+
+
+# ------------------------------------------------------------------ batched solves
+
+def _batch_inputs(items):
+    out = []
+    for (N, nl, bc, prob) in items:
+        arr = make_arrays(prob, N, bc)
+        out.append((N, nl, bc, arr, dev(arr.f), dev(arr.g1), dev(arr.g2)))
+    return out
+
+
+BATCH_ITEMS = [(16, 3, 1, 2), (24, 4, 2, 2), (32, 4, 1, 3), (48, 5, 2, 2), (32, 4, 2, 4),
+               (12, 3, 1, 3)]
+
+
+def _batch_problems():
+    return _batch_inputs([(N, nl, bc, config_problem(c)) for (N, nl, bc, c) in BATCH_ITEMS])
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_batch_fp64_matches_single_solves_and_oracle(ex, persistent):
+    data = _batch_problems()
+    probs = []
+    for (N, nl, bc, arr, f, g1, g2) in data:
+        probs.append(dict(n_finest=N, n_levels=nl, bc_kind=bc, f=f, g1=g1, g2=g2,
+                          u_out=torch.empty_like(f), ut_out=torch.empty_like(f)))
+    rc, stats = ex.solve_batch(probs, 1e-9, persistent=persistent)
+    assert rc == ex.OK, ex.last_error()
+    for (N, nl, bc, arr, f, g1, g2), p, st in zip(data, probs, stats):
+        print(f"batch N={N} bc={bc}", [l["iterations"] for l in st.levels()], flush=True)
+        u1 = torch.empty_like(f)
+        rc1, st1 = ex.solve_ex(N, nl, bc, f, g1, g2, 1e-9, u1)
+        assert rc1 == ex.OK
+        assert [l["iterations"] for l in st.levels()] == [l["iterations"] for l in st1.levels()]
+        np.testing.assert_array_equal(host(p["u_out"]), host(u1))
+        ref = O.excmg(N, nl, bc, arr.f, arr.g1, arr.g2, 1e-9)
+        assert rel_l2(host(p["u_out"]), ref.u) <= 1e-10
+        assert rel_l2(host(p["ut_out"]), ref.ut) <= 1e-10
+
+
+def test_batch_mixed_meets_tolerance_and_accuracy(ex):
+    data = _batch_problems()
+    probs = [dict(n_finest=N, n_levels=nl, bc_kind=bc, f=f, g1=g1, g2=g2,
+                  u_out=torch.empty_like(f)) for (N, nl, bc, arr, f, g1, g2) in data]
+    rc, stats = ex.solve_batch(probs, 1e-8, precision=ex.MIXED)
+    assert rc == ex.OK, ex.last_error()
+    for (N, nl, bc, arr, f, g1, g2), p, st in zip(data, probs, stats):
+        u = host(p["u_out"]).reshape((N + 1,) * 3)
+        # the oracle checks the final residual of the GPU's mixed-precision solution
+        b = O.rhs(N, bc, arr.f, arr.g1, arr.g2)
+        r = O.residual(N, bc, b, O.interior(u))
+        assert np.sqrt(O.dot(r, r) / O.dot(b, b)) <= 1e-8
+        ref = O.excmg(N, nl, bc, arr.f, arr.g1, arr.g2, 1e-8)
+        e_mixed = O.norm2(u - arr.u)
+        e_fp64 = O.norm2(ref.u - arr.u)
+        assert abs(e_mixed - e_fp64) <= 0.01 * e_fp64
+        single = torch.empty_like(f)
+        rc1, st1 = ex.solve_ex(N, nl, bc, f, g1, g2, 1e-8, single, precision=ex.MIXED)
+        assert [l["iterations"] for l in st.levels()] == [l["iterations"] for l in st1.levels()]
+        np.testing.assert_array_equal(u.ravel(), host(single).ravel())
+
+
+def test_mixed_solve_config1_meets_tolerance(ex):
+    arr = make_arrays(config_problem(1), 32, 1)
+    f, g1, g2 = dev(arr.f), dev(arr.g1), dev(arr.g2)
+    u = torch.empty_like(f)
+    rc, st = ex.solve_ex(32, 4, 1, f, g1, g2, 1e-10, u, precision=ex.MIXED)
+    assert rc == ex.OK, ex.last_error()
+    ug = host(u).reshape((33,) * 3)
+    b = O.rhs(32, 1, arr.f, arr.g1, arr.g2)
+    r = O.residual(32, 1, b, O.interior(ug))
+    assert np.sqrt(O.dot(r, r) / O.dot(b, b)) <= 1e-10
+    ref = O.excmg(32, 4, 1, arr.f, arr.g1, arr.g2, 1e-10)
+    assert abs(O.norm2(ug - arr.u) - O.norm2(ref.u - arr.u)) <= 0.01 * O.norm2(ref.u - arr.u)
+
+
+def test_autotuned_shape_keeps_results(ex):
+    N, bc = 40, 2
+    ty, zc, ms = ex.autotune(N, 0, ex.FP64, reps=3)
+    assert ty in (4, 8, 16) and 1 <= zc <= N - 1 and ms > 0
+    assert ex.get_shape(N, 0) == (ty, zc)
+    x = np.random.default_rng(8).standard_normal((N - 1) ** 3)
+    y = torch.empty_like(dev(x))
+    ex.apply_operator(N, bc, 0, dev(x), y)
+    np.testing.assert_array_equal(host(y), O.apply(N, bc, x))
+    ty1, zc1, _ = ex.autotune(N, 1, ex.MIXED, reps=3)
+    assert ty1 in (4, 8)
+    ex.set_shape(N, 0, 0, 0)
+    ex.set_shape(N, 1, 0, 0)
