@@ -47,6 +47,46 @@ def cpu_baseline(arr, N, nl, bc, iters):
                       f"{N}^3-cell finest level of the same problem, {dt:.1f} s"}
 
 
+def batch_leg(ex, torch, np):
+    """64 independent problems of 32^3..128^3 cells (mixed boundary kinds), tol 1e-8:
+    batched against one solve after another, FP64 and mixed precision."""
+    from manufactured import batch_problems, make_arrays
+    items = batch_problems(64)
+    dev = torch.device("cuda:0")
+    data = []
+    for it in items:
+        arr = make_arrays(it.problem, it.N, it.bc, with_u=False)
+        f, g1, g2 = (torch.from_numpy(a).to(dev) for a in (arr.f, arr.g1, arr.g2))
+        data.append((it, f, g1, g2, torch.empty_like(f)))
+    res = {"problems": len(items), "unknowns": int(sum((it.N - 1) ** 3 for it in items))}
+    for prec, name in ((ex.FP64, "fp64"), (ex.MIXED, "mixed")):
+        def seq():
+            for (it, f, g1, g2, u) in data:
+                rc, _ = ex.solve_ex(it.N, it.n_levels, it.bc, f, g1, g2, 1e-8, u, precision=prec)
+                if rc != ex.OK:
+                    raise RuntimeError(ex.last_error())
+        probs = [dict(n_finest=it.N, n_levels=it.n_levels, bc_kind=it.bc, f=f, g1=g1, g2=g2,
+                      u_out=u) for (it, f, g1, g2, u) in data]
+
+        def bat():
+            rc, _ = ex.solve_batch(probs, 1e-8, precision=prec)
+            if rc != ex.OK:
+                raise RuntimeError(ex.last_error())
+        times = {}
+        for label, fn in (("sequential", seq), ("batched", bat)):
+            fn()  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            times[label] = (time.perf_counter() - t0) * 1e3
+        log(f"batch {name}: {times}")
+        res[name] = {"sequential_ms": round(times["sequential"], 1),
+                     "batched_ms": round(times["batched"], 1),
+                     "speedup": round(times["sequential"] / times["batched"], 2)}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -59,6 +99,8 @@ def main():
     ap.add_argument("--config", type=int, default=4, help="seeded problem family (1-4)")
     ap.add_argument("--cpu-iters", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch leg")
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the solver has no multi-GPU path "
@@ -81,6 +123,18 @@ def main():
     ut = torch.empty_like(f)
     stream = torch.cuda.current_stream()
     ex.set_stream(stream)
+    tuned = {}
+    if not args.no_autotune:
+        # tile shapes of every grid the runs use, chosen by timing (the project's autotuner)
+        sizes = sorted({N >> k for k in range(nl - 2)} | {32, 48, 64, 96, 128, 24, 12, 16})
+        for n in sizes:
+            for kind in (0, 1):
+                for prec in (ex.FP64, ex.MIXED):
+                    if kind == 0 and prec == ex.MIXED:
+                        continue
+                    ty, zc, ms = ex.autotune(n, kind, prec, reps=3 if n >= 256 else 10)
+                    tuned[f"{n}/{'sweepA' if kind else 'operator'}/{'fp32' if prec else 'fp64'}"] = [ty, zc]
+        log(f"autotuned shapes: {tuned}")
     ex.setup(N, nl, bc)
 
     def solve(prec):
@@ -110,6 +164,22 @@ def main():
     rms = lambda e: float(np.sqrt(np.mean(e * e)))  # noqa: E731
     r64 = timed(ex.FP64, "fp64")
     r32 = timed(ex.MIXED, "mixed")
+    # the CG specialisation of Algorithm 2 (same iterates, one operator product per iteration)
+    cg = {}
+    for prec, name in ((ex.FP64, "fp64"), (ex.MIXED, "mixed")):
+        method_solve = lambda: ex.solve_ex(N, nl, bc, f, g1, g2, tol, u, ut, precision=prec,  # noqa: E731
+                                           method=ex.CG)
+        method_solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s_ in range(args.steps):
+            rc, stc = method_solve()
+        torch.cuda.synchronize()
+        cg[name] = round((time.perf_counter() - t0) * 1e3 / args.steps, 2)
+        same = bool(np.array_equal(u.view(N + 1, N + 1, N + 1).cpu().numpy(),
+                                   (r64 if prec == ex.FP64 else r32)["u"]))
+        cg[name + "_bit_identical_to_bicg"] = same
+        log(f"cg {name}: {cg[name]} ms, identical to Bi-CG: {same}")
     e64 = rms(r64["u"] - arr.u)
     e32 = rms(r32["u"] - arr.u)
     gate = abs(e32 - e64) <= 0.01 * e64
@@ -152,7 +222,8 @@ def main():
                                f"tol {tol:g}, {mode}", "n_finest": N, "n_levels": nl,
                    "bc_kind": bc, "tol": tol, "precision": mode},
         "time_to_solution_ms": {"fp64": round(r64["ms"], 2), "mixed": round(r32["ms"], 2),
-                                "speedup_mixed": round(r64["ms"] / r32["ms"], 3)},
+                                "speedup_mixed": round(r64["ms"] / r32["ms"], 3),
+                                "cg_specialisation": cg},
         "glups": {"fp64": round(r64["glups"], 3), "mixed": round(r32["glups"], 3)},
         "iterations": {"fp64": [lv["iterations"] for lv in r64["levels"]],
                        "mixed": [lv["iterations"] for lv in r32["levels"]]},
@@ -162,6 +233,10 @@ def main():
                            "mixed_gate_1pct": bool(gate)},
         "roofline": roofline,
     }
+    if tuned:
+        out["autotuned_shapes"] = tuned
+    if not args.no_batch:
+        out["batch"] = batch_leg(ex, torch, np)
     if not args.no_cpu:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(arr, N, nl, bc, args.cpu_iters)

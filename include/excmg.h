@@ -55,6 +55,12 @@ extern "C" {
 #define EXCMG_FP64 0          /* everything in FP64                                        */
 #define EXCMG_MIXED 1         /* FP32 Bi-CG inside an FP64 iterative-refinement loop       */
 
+/* Level solver. */
+#define EXCMG_BICG 0          /* Algorithm 2 as printed: both A p and A^T p* every iteration */
+#define EXCMG_CG 1            /* its symmetric specialisation: A_h = A_h^T and r*_0 = r_0 make */
+                              /* the shadow vectors equal to the primal ones, so one product  */
+                              /* and half the vector traffic give bit-identical iterates      */
+
 #define EXCMG_MAX_LEVELS 16
 
 /* Options of excmg_solve_ex.  Zero-initialise and set what you need. */
@@ -70,6 +76,7 @@ typedef struct excmg_opts {
     int max_outer;      /* mixed precision: refinement steps per level (0: 60)             */
     int batch_mode;     /* excmg_solve_batch: 0 = four graph-captured phase launches per    */
                         /* Bi-CG step, 1 = one persistent work-queue launch per step        */
+    int method;         /* EXCMG_BICG (default) or EXCMG_CG (excmg_solve_ex only)           */
 } excmg_opts;
 
 /* Per-level record filled by excmg_solve_ex (levels 0 and 1 report iterations = 0). */
@@ -176,7 +183,8 @@ int excmg_get_timing(int level, int sweep, double *ms_total, long long *launches
 
 /* Launch shape of the z-marched stencil kernels on grids of n cells: tiles of 64 x ty
  * columns marching through chunks of zc planes.  kind 0: the one-array kernels (operator,
- * residual; ty = 4, 8 or 16); kind 1: Bi-CG sweep A (two arrays; ty = 4 or 8).  ty = 0
+ * residual; ty = 4, 8 or 16); kind 1 / 2: Bi-CG sweep A on FP64 / FP32 vectors (two arrays;
+ * ty = 4 or 8).  ty = 0
  * restores the built-in rule.  Applies to later launches, including levels of the current
  * context.  The autotuner uses it; results do not depend on the shape (every output is
  * computed with the same arithmetic). */
@@ -206,7 +214,8 @@ int excmg_solve_batch(int nprob, const excmg_problem *probs, const excmg_opts *o
 /* Autotuner: time the z-marched kernel of `kind` (0: one-array operator, 1: Bi-CG sweep A)
  * on a grid of n cells for every tile height and z-chunk length it supports, in FP64 or
  * FP32 (precision), `reps` launches each on scratch vectors, and record the fastest shape
- * for later launches (as excmg_set_shape).  Outputs (may be NULL): the chosen shape and its
+ * for later launches (as excmg_set_shape; sweep A in FP32 is stored as kind 2).  Outputs (may
+ * be NULL): the chosen shape and its
  * mean ms per launch. */
 int excmg_autotune(int n, int kind, int precision, int reps, int *ty, int *zc, double *ms);
 

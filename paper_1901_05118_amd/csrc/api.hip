@@ -132,7 +132,7 @@ struct Level {
     int n = 0;        // unknowns per axis
     long long nu = 0; // unknowns
     long long nodes = 0;
-    Geom g1{}, g2{};  // launch shapes: single-array kernels, Bi-CG sweep A
+    Geom g1{}, g2{}, g2f{};  // launch shapes: one-array kernels, sweep A FP64, sweep A FP32
     DBuf b, x, u;     // right-hand side, unknowns, node array (solution or EXP_finite guess)
 };
 
@@ -196,9 +196,9 @@ std::vector<ShapeOverride> g_shapes;
 
 // Default launch shape: 64 x TY column tiles, and the longest z chunk that still gives
 // every CU a tile (measured on MI355X: fewer, longer marches beat more, shorter ones,
-// because each chunk re-reads four halo planes).  kind 0: one marched array (apply,
-// residual); kind 1: two marched arrays (Bi-CG sweep A), which holds twice the column state
-// and stays at TY = 8 to keep its registers below 256.
+// because each chunk re-reads four halo planes).  kind 0: one marched array (operator,
+// residual); kind 1 / 2: Bi-CG sweep A on FP64 / FP32 vectors (two marched arrays, twice the
+// column state, TY <= 8 to keep its registers below 256).
 Geom choose_shape(int N, int bc, int kind) {
     const int n = N - 1;
     for (const ShapeOverride &o : g_shapes)
@@ -220,6 +220,7 @@ Geom choose_shape(int N, int bc, int kind) {
 void choose_shapes(Level &L, int bc) {
     L.g1 = choose_shape(L.N, bc, 0);
     L.g2 = choose_shape(L.N, bc, 1);
+    L.g2f = choose_shape(L.N, bc, 2);
 }
 
 int check_sizes(int n_finest, int n_levels, int bc) {
@@ -272,7 +273,8 @@ int setup(int n_finest, int n_levels, int bc) {
     CKR(c.q.ensure(vb));
     CKR(c.qs.ensure(vb));
     int maxblk = 4096 * 2;
-    for (auto &L : c.lv) maxblk = std::max({maxblk, stencil_blocks(L.g1), stencil_blocks(L.g2)});
+    for (auto &L : c.lv)
+        maxblk = std::max({maxblk, stencil_blocks(L.g1), stencil_blocks(L.g2), stencil_blocks(L.g2f)});
     CKR(c.part_a.ensure((size_t)maxblk * sizeof(Pair)));
     CKR(c.part_b.ensure((size_t)2 * 4096 * sizeof(Pair)));
     CKR(c.state.ensure(sizeof(BicgState)));
@@ -349,13 +351,16 @@ int poll_interval(long long nu) {
 // have type T, the iterate x type TX.  Sweep A forms p, p* and their products with A (and
 // sigma), sweep B updates x, r, r* (and rho, r.r).  Every kernel returns at once when the
 // run has stopped, so the host launches K iterations between two polls of the state.
+bool g_cg = false;  // current solve uses the CG specialisation (opts.method)
+
 template <typename TX, typename T>
 int bicg_iterate(const Level &L, TX *x, BicgState &hs) {
     Ctx &c = g_ctx;
     BicgState *S = c.state.as<BicgState>();
     T *r = c.r.as<T>(), *rs = c.rs.as<T>(), *q = c.q.as<T>(), *qs = c.qs.as<T>();
     const int K = poll_interval(L.nu);
-    const int nsb = stencil_blocks(L.g2);
+    const Geom &G = sizeof(T) == 4 ? L.g2f : L.g2;
+    const int nsb = stencil_blocks(G);
     const int nvb = vec_blocks(L.nu);
     if (g_timing) CKR(ensure_events(4 * (size_t)K));
     long long j = 0;
@@ -365,15 +370,25 @@ int bicg_iterate(const Level &L, TX *x, BicgState &hs) {
             const int cur = (int)(j & 1), nxt = cur ^ 1;
             T *pn = c.p[nxt].as<T>(), *psn = c.ps[nxt].as<T>();
             if (g_timing) CKH(hipEventRecord(g_events[4 * t], g_stream));
-            CKH(stencil_pair_direction<T>(L.g2, L.g2.ty, r, rs, c.p[cur].as<T>(),
-                                          c.ps[cur].as<T>(), &S->beta, j == 0 ? 1 : 0, pn, psn,
-                                          q, qs, c.part_a.as<Pair>(), &S->status, g_stream));
+            if (g_cg)
+                CKH(stencil_direction<T>(G, G.ty, r, c.p[cur].as<T>(), &S->beta, j == 0 ? 1 : 0,
+                                         pn, q, c.part_a.as<Pair>(), &S->status, g_stream));
+            else
+                CKH(stencil_pair_direction<T>(G, G.ty, r, rs, c.p[cur].as<T>(),
+                                              c.ps[cur].as<T>(), &S->beta, j == 0 ? 1 : 0, pn,
+                                              psn, q, qs, c.part_a.as<Pair>(), &S->status,
+                                              g_stream));
             if (g_timing) CKH(hipEventRecord(g_events[4 * t + 1], g_stream));
             CKH(bicg_alpha(S, c.part_a.as<Pair>(), nsb, g_stream));
             if (g_timing) CKH(hipEventRecord(g_events[4 * t + 2], g_stream));
-            CKH((bicg_update<TX, T>(L.nu, S, x, pn, r, q, rs, qs, c.part_b.as<Pair>(), g_stream)));
+            if (g_cg)
+                CKH((cg_update<TX, T>(L.nu, S, x, pn, r, q, c.part_b.as<Pair>(), g_stream)));
+            else
+                CKH((bicg_update<TX, T>(L.nu, S, x, pn, r, q, rs, qs, c.part_b.as<Pair>(),
+                                        g_stream)));
             if (g_timing) CKH(hipEventRecord(g_events[4 * t + 3], g_stream));
-            CKH(bicg_beta(S, c.part_b.as<Pair>(), nvb, g_stream));
+            if (g_cg) CKH(cg_beta(S, c.part_b.as<Pair>(), nvb, g_stream));
+            else CKH(bicg_beta(S, c.part_b.as<Pair>(), nvb, g_stream));
         }
         CKR(read_state(hs));
         if (g_timing && L.index < EXCMG_MAX_LEVELS) {
@@ -750,7 +765,7 @@ struct BatchSolver {
                 Lv.nu = (long long)Lv.n * Lv.n * Lv.n;
                 Lv.nodes = (long long)(Lv.N + 1) * (Lv.N + 1) * (Lv.N + 1);
                 Lv.g1 = choose_shape(Lv.N, b->bc, 0);
-                Geom gb = choose_shape(Lv.N, b->bc, 1);
+                Geom gb = choose_shape(Lv.N, b->bc, mixed ? 2 : 1);
                 Lv.g2 = make_geom(Lv.n, b->bc, kBatchTY, gb.zc);
                 CKR(Lv.b.ensure(Lv.nu * 8));
                 CKR(Lv.x.ensure(Lv.nu * 8));
@@ -1109,6 +1124,7 @@ int excmg_bicg(int level, const double *b, double *x, double eps, int max_iters,
     CKR(ax.in());
     int it = 0, status = 0;
     double r2 = 0.0;
+    g_cg = false;
     CKR(bicg_run(L, ab.p<double>(), ax.p<double>(), eps, max_iters, &it, &r2, &status));
     CKR(ax.back());
     CKH(hipStreamSynchronize(g_stream));
@@ -1131,6 +1147,7 @@ int excmg_level_solve(int level, const double *b, double *x, double eps, int max
     CKR(ab.in());
     CKR(ax.in());
     excmg_level_stats ls{};
+    g_cg = false;
     CKR(level_solve(L, ab.p<double>(), ax.p<double>(), eps, max_iters, max_runs, &ls));
     CKR(ax.back());
     CKH(hipStreamSynchronize(g_stream));
@@ -1184,6 +1201,8 @@ int excmg_solve_ex(const excmg_opts *opts, const double *f, const double *g1, co
     if (!(o.tol > 0.0)) return fail(EXCMG_EINVAL, "tol must be positive");
     if (o.precision != EXCMG_FP64 && o.precision != EXCMG_MIXED)
         return fail(EXCMG_EINVAL, "precision %d not supported", o.precision);
+    if (o.method != EXCMG_BICG && o.method != EXCMG_CG)
+        return fail(EXCMG_EINVAL, "method %d not supported", o.method);
     CKR(setup(o.n_finest, o.n_levels, o.bc_kind));
     const size_t nb = (size_t)(o.n_finest + 1) * (o.n_finest + 1) * (o.n_finest + 1) * 8;
     Arg af(f, nb), a1(g1, nb), a2(g2, nb), au(u_out, nb), at(ut_out, nb);
@@ -1193,6 +1212,7 @@ int excmg_solve_ex(const excmg_opts *opts, const double *f, const double *g1, co
     CKR(au.out());
     if (ut_out) CKR(at.out());
     if (st) memset(st, 0, sizeof(*st));
+    g_cg = (o.method == EXCMG_CG);
     int rc = solve_cascade(o, af.p<double>(), a1.p<double>(), a2.p<double>(), au.p<double>(),
                         ut_out ? at.p<double>() : nullptr, st);
     if (rc != EXCMG_OK && rc != EXCMG_ENOCONV && rc != EXCMG_EBREAKDOWN) return rc;
@@ -1263,7 +1283,7 @@ int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launc
             case 1: return stencil_residual_cast(L.g1, L.g1.ty, L.b.as<double>(), L.x.as<double>(),
                                                  r, rs, c.part_a.as<Pair>(), g_stream);
             case 2: return stencil_pair_direction<float>(
-                        L.g2, L.g2.ty, r, rs, c.p[0].as<float>(), c.ps[0].as<float>(), &S->beta,
+                        L.g2f, L.g2f.ty, r, rs, c.p[0].as<float>(), c.ps[0].as<float>(), &S->beta,
                         0, c.p[1].as<float>(), c.ps[1].as<float>(), c.q.as<float>(),
                         c.qs.as<float>(), c.part_a.as<Pair>(), &S->status, g_stream);
             case 3: return bicg_update<double, float>(L.nu, S, L.x.as<double>(), c.p[1].as<float>(),
@@ -1413,7 +1433,7 @@ int excmg_autotune(int n, int kind, int precision, int reps, int *ty_out, int *z
     part.release();
     stb.release();
     if (rc) return rc;
-    CKR(excmg_set_shape(n, kind, bty, bzc));
+    CKR(excmg_set_shape(n, (kind == 1 && es == 4) ? 2 : kind, bty, bzc));
     if (ty_out) *ty_out = bty;
     if (zc_out) *zc_out = bzc;
     if (ms_out) *ms_out = best;
@@ -1438,9 +1458,9 @@ int excmg_get_timing(int level, int sweep, double *ms_total, long long *launches
 int excmg_set_shape(int n, int kind, int ty, int zc) {
     g_err[0] = 0;
     if (n < 2) return fail(EXCMG_EINVAL, "n must be >= 2");
-    if (kind != 0 && kind != 1) return fail(EXCMG_EINVAL, "kind must be 0 or 1");
+    if (kind < 0 || kind > 2) return fail(EXCMG_EINVAL, "kind must be 0, 1 or 2");
     if (ty != 0 && ty != 4 && ty != 8 && ty != 16) return fail(EXCMG_EINVAL, "ty must be 4, 8 or 16");
-    if (kind == 1 && ty == 16) return fail(EXCMG_EINVAL, "sweep A supports ty 4 or 8");
+    if (kind != 0 && ty == 16) return fail(EXCMG_EINVAL, "sweep A supports ty 4 or 8");
     if (ty != 0 && zc < 1) return fail(EXCMG_EINVAL, "zc must be >= 1");
     for (size_t i = 0; i < g_shapes.size(); i++)
         if (g_shapes[i].N == n && g_shapes[i].kind == kind) {
@@ -1451,14 +1471,15 @@ int excmg_set_shape(int n, int kind, int ty, int zc) {
     for (Level &L : g_ctx.lv) {
         if (L.N != n) continue;
         choose_shapes(L, g_ctx.bc);
-        const size_t need = (size_t)std::max(stencil_blocks(L.g1), stencil_blocks(L.g2)) * sizeof(Pair);
+        const size_t need = (size_t)std::max({stencil_blocks(L.g1), stencil_blocks(L.g2),
+                                              stencil_blocks(L.g2f)}) * sizeof(Pair);
         if (need > g_ctx.part_a.bytes) CKR(g_ctx.part_a.ensure(need));
     }
     return EXCMG_OK;
 }
 
 int excmg_get_shape(int n, int kind, int *ty, int *zc) {
-    if (n < 2 || (kind != 0 && kind != 1)) return fail(EXCMG_EINVAL, "bad n or kind");
+    if (n < 2 || kind < 0 || kind > 2) return fail(EXCMG_EINVAL, "bad n or kind");
     Geom g = choose_shape(n, 1, kind);
     if (ty) *ty = g.ty;
     if (zc) *zc = g.zc;

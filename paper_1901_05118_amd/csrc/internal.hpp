@@ -59,6 +59,12 @@ hipError_t stencil_pair_direction(const Geom &g, int ty, const T *r, const T *rs
                                   int first, T *p_new, T *ps_new, T *q, T *qs, Pair *partials,
                                   const int *status, hipStream_t st);
 
+// CG sweep A: p_new = r + beta p_old (p_new = r when first), q = A p_new, partials of p_new . q
+template <typename T>
+hipError_t stencil_direction(const Geom &g, int ty, const T *r, const T *p_old,
+                             const double *beta_dev, int first, T *p_new, T *q, Pair *partials,
+                             const int *status, hipStream_t st);
+
 inline int stencil_blocks(const Geom &g) { return xcd_grid(g.ntiles); }
 
 // ---------------------------------------------------------------- vector kernels
@@ -70,6 +76,12 @@ int vec_blocks(long long n);
 template <typename TX, typename T>
 hipError_t bicg_update(long long n, const BicgState *s, TX *x, const T *p, T *r, const T *q,
                        T *rs, const T *qs, Pair *partials, hipStream_t st);
+
+// CG sweep B: x += alpha p; r -= alpha q; partials of r.r
+template <typename TX, typename T>
+hipError_t cg_update(long long n, const BicgState *s, TX *x, const T *p, T *r, const T *q,
+                     Pair *partials, hipStream_t st);
+hipError_t cg_beta(BicgState *s, const Pair *part, int count, hipStream_t st);
 
 // partials of x.y
 template <typename T>

@@ -64,6 +64,43 @@ template hipError_t bicg_update<double, float>(long long, const BicgState *, dou
                                                const float *, float *, const float *, float *,
                                                const float *, Pair *, hipStream_t);
 
+// CG sweep B: the primal half of the Bi-CG update (the shadow half repeats it bit for bit
+// when r*_0 = r_0), and the partials of r.r, which is also rho of the next iteration.
+template <typename TX, typename T>
+__global__ void __launch_bounds__(kVecThreads)
+    k_cg_update(long long n, const BicgState *s, TX *x, const T *p, T *r, const T *q,
+                Pair *partials) {
+    __shared__ Pair sh[kVecThreads / kWave];
+    if (s->status != kRunning) return;
+    const double alpha = s->alpha;
+    Pair acc[1] = {{0.0, 0.0}};
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        double xi = (double)x[i] + alpha * (double)p[i];
+        double ri = (double)r[i] - alpha * (double)q[i];
+        T rt = (T)ri;
+        x[i] = (TX)xi;
+        r[i] = rt;
+        dot2_acc(acc[0], (double)rt, (double)rt);
+    }
+    block_merge<1>(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
+}
+
+template <typename TX, typename T>
+hipError_t cg_update(long long n, const BicgState *s, TX *x, const T *p, T *r, const T *q,
+                     Pair *partials, hipStream_t st) {
+    hipLaunchKernelGGL((k_cg_update<TX, T>), dim3(vec_blocks(n)), dim3(kVecThreads), 0, st, n, s,
+                       x, p, r, q, partials);
+    return hipGetLastError();
+}
+template hipError_t cg_update<double, double>(long long, const BicgState *, double *,
+                                              const double *, double *, const double *, Pair *,
+                                              hipStream_t);
+template hipError_t cg_update<double, float>(long long, const BicgState *, double *,
+                                             const float *, float *, const float *, Pair *,
+                                             hipStream_t);
+
 template <typename T>
 __global__ void __launch_bounds__(kVecThreads)
     k_dot(long long n, const T *x, const T *y, Pair *partials) {
@@ -174,6 +211,27 @@ __global__ void __launch_bounds__(kReduceThreads)
         s->iter = s->iter + 1;
         set_status(s);
     }
+}
+
+__global__ void __launch_bounds__(kReduceThreads)
+    k_cg_beta(BicgState *s, const Pair *part, int count) {
+    __shared__ Pair sh[kReduceThreads / kWave];
+    if (s->status != kRunning) return;
+    Pair v[1];
+    merge_partials<1>(part, count, v, sh);
+    if (threadIdx.x == 0) {
+        const double rr = pair_value(v[0]);
+        s->rr = rr;
+        s->beta = rr / s->rho;
+        s->rho = rr;
+        s->iter = s->iter + 1;
+        set_status(s);
+    }
+}
+
+hipError_t cg_beta(BicgState *s, const Pair *part, int count, hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(kReduceThreads), 0, st, s, part, count);
+    return hipGetLastError();
 }
 
 __global__ void __launch_bounds__(kReduceThreads)

@@ -109,6 +109,34 @@ template hipError_t stencil_residual<double>(const Geom &, int, const double *, 
                                              double *, Pair *, hipStream_t);
 template hipError_t stencil_residual<float>(const Geom &, int, const double *, const float *,
                                             float *, Pair *, hipStream_t);
+template <typename T>
+hipError_t stencil_direction(const Geom &g, int ty, const T *r, const T *p_old,
+                             const double *beta_dev, int first, T *p_new, T *q, Pair *partials,
+                             const int *status, hipStream_t st) {
+    InDirection<T> in;
+    in.r[0] = r;
+    in.r[1] = r;
+    in.p[0] = p_old;
+    in.p[1] = p_old;
+    in.beta_dev = beta_dev;
+    in.first = first;
+    in.beta = 0.0;
+    OutDirApply<T> out;
+    out.p_new = p_new;
+    out.q = q;
+    out.partials = partials;
+    out.status = status;
+    out.acc = Pair{0.0, 0.0};
+    EXCMG_DISPATCH_TY(ty, return (launch<TY, T, InDirection<T>, OutDirApply<T>, 1>(g, in, out, st)));
+    return hipSuccess;
+}
+template hipError_t stencil_direction<double>(const Geom &, int, const double *, const double *,
+                                              const double *, int, double *, double *, Pair *,
+                                              const int *, hipStream_t);
+template hipError_t stencil_direction<float>(const Geom &, int, const float *, const float *,
+                                             const double *, int, float *, float *, Pair *,
+                                             const int *, hipStream_t);
+
 template hipError_t stencil_pair_direction<double>(const Geom &, int, const double *,
                                                    const double *, const double *,
                                                    const double *, const double *, int,

@@ -66,8 +66,8 @@ __device__ __forceinline__ void column_init(Column &s) {
 
 // Consume plane m from LDS (row stride LS, centre at B) and return the completed output of
 // plane m-2.  `c0` receives the centre value of plane m.
-template <int LS>
-__device__ __forceinline__ double column_step(Column &s, const double *B, double &c0) {
+template <int LS, typename TL>
+__device__ __forceinline__ double column_step(Column &s, const TL *B, double &c0) {
     const double c = B[0];
     const double n0 = B[-1], n1 = B[1], n2 = B[-LS], n3 = B[LS];
     const double s0 = B[-2], s1 = B[2], s2 = B[-2 * LS], s3 = B[2 * LS];
@@ -150,7 +150,9 @@ __device__ __forceinline__ void zmarch_tile(const Geom &g, int tile, const In &i
     constexpr int LE = LS * LR;         // elements per plane
     constexpr int NT = TX * TY;
     constexpr int NL = (LE + NT - 1) / NT;
-    __shared__ double buf[2][NA][LE];
+    // staged values are exactly representable in the storage type T (a stored vector entry
+    // times 0 or +-1), so the planes are kept in LDS as T
+    __shared__ T buf[2][NA][LE];
     const int n = g.n;
     const int tx = tile % g.tiles_x;
     const int ty = (tile / g.tiles_x) % g.tiles_y;
@@ -204,7 +206,7 @@ __device__ __forceinline__ void zmarch_tile(const Geom &g, int tile, const In &i
 #pragma unroll
                 for (int a = 0; a < NA; a++) {
                     const double v = in.combine(raw[q][a]);
-                    buf[b][a][e] = (mul != 0.0) ? mul * v : 0.0;
+                    buf[b][a][e] = (T)((mul != 0.0) ? mul * v : 0.0);
                 }
             }
         }
@@ -231,7 +233,7 @@ __device__ __forceinline__ void zmarch_tile(const Geom &g, int tile, const In &i
 #pragma unroll
         for (int a = 0; a < NA; a++) {
             cprev[a] = col[a].cm2;   // centre of plane m-2 before the shift
-            y[a] = column_step<LS>(col[a], &buf[cur][a][centre], c0[a]);
+            y[a] = column_step<LS, T>(col[a], &buf[cur][a][centre], c0[a]);
         }
         if (valid) {
             if (m >= k0 && m < k1) out.centre((i64)m * plane + (i64)iy * n + ix, c0);
@@ -309,6 +311,30 @@ struct OutResidualCast {
         r32[idx] = rf;
         rs32[idx] = rf;
         dot2_acc(acc, rv, rv);
+    }
+    __device__ void finish(int block, Pair *sh) {
+        Pair v[1] = {acc};
+        block_merge<1>(v, sh);
+        if (threadIdx.x == 0 && threadIdx.y == 0) partials[block] = v[0];
+    }
+};
+
+// CG sweep A (the symmetric specialisation of Bi-CG: with r*_0 = r_0 the shadow sequence equals
+// the primal one): p_new = r + beta p (staged), q = A p_new, partial of p_new . q.  Stores
+// p_new (centres) and q.  Accumulates the same products in the same order as OutPairApply.
+template <typename T>
+struct OutDirApply {
+    T *p_new;
+    T *q;
+    Pair *partials;
+    const int *status;
+    Pair acc;
+    __device__ bool skip() const { return *status != 0; }
+    __device__ void centre(i64 idx, const double *c) { p_new[idx] = (T)c[0]; }
+    __device__ void emit(i64 idx, const double *v, const double *c) {
+        const T q0 = (T)v[0];
+        q[idx] = q0;
+        dot2_acc(acc, (double)(T)c[0], (double)q0);
     }
     __device__ void finish(int block, Pair *sh) {
         Pair v[1] = {acc};

@@ -14,6 +14,7 @@ import numpy as np
 
 __all__ = [
     "ExcmgError", "OK", "EINVAL", "ENOMEM", "ENOCONV", "EBREAKDOWN", "EHIP", "FP64", "MIXED",
+    "BICG", "CG",
     "lib_path", "load", "set_stream", "setup", "apply_stencil", "apply_operator", "rhs", "dsolve", "bicg",
     "level_solve", "exp_finite", "exp_true", "solve", "solve_ex", "profile_sweep",
     "set_shape", "get_shape", "set_timing", "get_timing", "autotune", "solve_batch",
@@ -24,6 +25,7 @@ __all__ = [
 
 OK, EINVAL, ENOMEM, ENOCONV, EBREAKDOWN, EHIP = 0, -1, -2, -3, -4, -5
 FP64, MIXED = 0, 1
+BICG, CG = 0, 1
 MAX_LEVELS = 16
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -41,7 +43,8 @@ class Opts(ctypes.Structure):
                 ("bc_kind", ctypes.c_int), ("precision", ctypes.c_int),
                 ("tol", ctypes.c_double), ("max_iters", ctypes.c_int),
                 ("max_runs", ctypes.c_int), ("inner_tol", ctypes.c_double),
-                ("max_outer", ctypes.c_int), ("batch_mode", ctypes.c_int)]
+                ("max_outer", ctypes.c_int), ("batch_mode", ctypes.c_int),
+                ("method", ctypes.c_int)]
 
 
 class LevelStats(ctypes.Structure):
@@ -218,10 +221,10 @@ def solve(n_finest: int, n_levels: int, bc_kind: int, f, g1, g2, tol: float, u_o
 
 def solve_ex(n_finest: int, n_levels: int, bc_kind: int, f, g1, g2, tol: float, u_out,
              ut_out=None, precision: int = FP64, max_iters: int = 0, max_runs: int = 0,
-             inner_tol: float = 0.0, max_outer: int = 0):
+             inner_tol: float = 0.0, max_outer: int = 0, method: int = BICG):
     """Algorithm 1 with options.  Returns (code, Stats)."""
     o = Opts(n_finest, n_levels, bc_kind, precision, tol, max_iters, max_runs, inner_tol,
-             max_outer, 0)
+             max_outer, 0, method)
     st = Stats()
     rc = load().excmg_solve_ex(ctypes.byref(o), _ptr(f, name="f"), _ptr(g1, name="g1"),
                                _ptr(g2, name="g2"), _ptr(u_out, name="u_out"),
@@ -254,7 +257,7 @@ def solve_batch(problems, tol: float, precision: int = FP64, max_iters: int = 0,
                          _ptr(p["f"], name="f"), _ptr(p["g1"], name="g1"), _ptr(p["g2"], name="g2"),
                          _ptr(p["u_out"], name="u_out"), _ptr(p.get("ut_out"), name="ut_out"))
     o = Opts(0, 0, 0, precision, tol, max_iters, max_runs, inner_tol, max_outer,
-             1 if persistent else 0)
+             1 if persistent else 0, BICG)
     st = (Stats * n)()
     rc = load().excmg_solve_batch(n, arr, ctypes.byref(o), st)
     if rc not in (OK, ENOCONV, EBREAKDOWN):
@@ -288,7 +291,8 @@ def get_timing(level: int, sweep: int):
 
 def set_shape(n: int, kind: int, ty: int, zc: int):
     """Tile shape (64 x ty columns, zc planes per chunk) for grids of n cells; kind 0 = the
-    one-array stencil kernels, 1 = Bi-CG sweep A; ty=0 restores the default."""
+    one-array stencil kernels, 1 / 2 = Bi-CG sweep A in FP64 / FP32; ty=0 restores the
+    default."""
     _check("excmg_set_shape", load().excmg_set_shape(n, kind, ty, zc))
 
 

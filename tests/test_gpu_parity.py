@@ -306,5 +306,25 @@ def test_autotuned_shape_keeps_results(ex):
     np.testing.assert_array_equal(host(y), O.apply(N, bc, x))
     ty1, zc1, _ = ex.autotune(N, 1, ex.MIXED, reps=3)
     assert ty1 in (4, 8)
-    ex.set_shape(N, 0, 0, 0)
-    ex.set_shape(N, 1, 0, 0)
+    assert ex.get_shape(N, 2) == (ty1, zc1)
+    for kind in (0, 1, 2):
+        ex.set_shape(N, kind, 0, 0)
+
+
+# ------------------------------------------------------------------ CG specialisation
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("case", [(32, 4, 1, 1), (48, 5, 2, 2)])
+def test_cg_specialisation_is_bit_identical_to_bicg(ex, prec, case):
+    """With A_h = A_h^T and r*_0 = r_0 the shadow vectors of Algorithm 2 equal the primal
+    ones, so the CG form (one operator product per iteration) reproduces Bi-CG exactly."""
+    N, nl, bc, c = case
+    p = ex.FP64 if prec == "fp64" else ex.MIXED
+    arr = make_arrays(config_problem(c), N, bc)
+    f, g1, g2 = dev(arr.f), dev(arr.g1), dev(arr.g2)
+    u_b, u_c = torch.empty_like(f), torch.empty_like(f)
+    rc1, st1 = ex.solve_ex(N, nl, bc, f, g1, g2, 1e-9, u_b, precision=p, method=ex.BICG)
+    rc2, st2 = ex.solve_ex(N, nl, bc, f, g1, g2, 1e-9, u_c, precision=p, method=ex.CG)
+    assert rc1 == rc2 == ex.OK
+    assert [l["iterations"] for l in st1.levels()] == [l["iterations"] for l in st2.levels()]
+    np.testing.assert_array_equal(host(u_b), host(u_c))
