@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -136,6 +137,8 @@ struct Level {
     DBuf b, x, u;     // right-hand side, unknowns, node array (solution or EXP_finite guess)
 };
 
+void release_graphs();
+
 struct Ctx {
     bool ready = false;
     int n_finest = 0, n_levels = 0, bc = 0;
@@ -151,6 +154,7 @@ struct Ctx {
     BicgState *host_state = nullptr;  // pinned
     double *host_scal = nullptr;      // pinned
     void release() {
+        release_graphs();
         for (auto &L : lv) {
             L.b.release();
             L.x.release();
@@ -351,54 +355,121 @@ int poll_interval(long long nu) {
 // have type T, the iterate x type TX.  Sweep A forms p, p* and their products with A (and
 // sigma), sweep B updates x, r, r* (and rho, r.r).  Every kernel returns at once when the
 // run has stopped, so the host launches K iterations between two polls of the state.
-bool g_cg = false;  // current solve uses the CG specialisation (opts.method)
+bool g_cg = false;          // current solve uses the CG specialisation (opts.method)
+bool g_graphs = false;      // replay iteration windows from captured hipGraphs (solves only)
+hipStream_t g_capture = nullptr;
 
+// Captured windows of K iterations, per level, vector type, method and iterate pointer.
+struct GraphEntry {
+    int level, tsize, cg, K;
+    const void *x;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+std::vector<GraphEntry> g_graph_cache;
+
+void release_graphs() {
+    for (GraphEntry &e : g_graph_cache) {
+        (void)hipGraphExecDestroy(e.exec);
+        (void)hipGraphDestroy(e.graph);
+    }
+    g_graph_cache.clear();
+}
+
+// The four launches of iteration j of a run: sweep A (direction update + products + sigma),
+// alpha, sweep B (updates + rho, r.r), beta.  ev >= 0 brackets the sweeps with timing events.
 template <typename TX, typename T>
-int bicg_iterate(const Level &L, TX *x, BicgState &hs) {
+int launch_iteration(const Level &L, TX *x, long long j, int ev, hipStream_t st) {
     Ctx &c = g_ctx;
     BicgState *S = c.state.as<BicgState>();
     T *r = c.r.as<T>(), *rs = c.rs.as<T>(), *q = c.q.as<T>(), *qs = c.qs.as<T>();
-    const int K = poll_interval(L.nu);
     const Geom &G = sizeof(T) == 4 ? L.g2f : L.g2;
     const int nsb = stencil_blocks(G);
     const int nvb = vec_blocks(L.nu);
+    const int cur = (int)(j & 1), nxt = cur ^ 1;
+    T *pn = c.p[nxt].as<T>(), *psn = c.ps[nxt].as<T>();
+    if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev], st));
+    if (g_cg)
+        CKH(stencil_direction<T>(G, G.ty, r, c.p[cur].as<T>(), &S->beta, j == 0 ? 1 : 0, pn, q,
+                                 c.part_a.as<Pair>(), &S->status, st));
+    else
+        CKH(stencil_pair_direction<T>(G, G.ty, r, rs, c.p[cur].as<T>(), c.ps[cur].as<T>(),
+                                      &S->beta, j == 0 ? 1 : 0, pn, psn, q, qs,
+                                      c.part_a.as<Pair>(), &S->status, st));
+    if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev + 1], st));
+    CKH(bicg_alpha(S, c.part_a.as<Pair>(), nsb, st));
+    if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev + 2], st));
+    if (g_cg)
+        CKH((cg_update<TX, T>(L.nu, S, x, pn, r, q, c.part_b.as<Pair>(), st)));
+    else
+        CKH((bicg_update<TX, T>(L.nu, S, x, pn, r, q, rs, qs, c.part_b.as<Pair>(), st)));
+    if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev + 3], st));
+    if (g_cg) CKH(cg_beta(S, c.part_b.as<Pair>(), nvb, st));
+    else CKH(bicg_beta(S, c.part_b.as<Pair>(), nvb, st));
+    return EXCMG_OK;
+}
+
+// Graph of iterations j = 1..K (K even, so the p / p* buffer parity repeats).
+template <typename TX, typename T>
+int window_graph(const Level &L, TX *x, int K, hipGraphExec_t *out) {
+    for (GraphEntry &e : g_graph_cache)
+        if (e.level == L.index && e.tsize == (int)sizeof(T) && e.cg == (int)g_cg && e.K == K &&
+            e.x == (const void *)x) {
+            *out = e.exec;
+            return EXCMG_OK;
+        }
+    if (!g_capture) CKH(hipStreamCreateWithFlags(&g_capture, hipStreamNonBlocking));
+    CKH(hipStreamBeginCapture(g_capture, hipStreamCaptureModeRelaxed));
+    int rc = EXCMG_OK;
+    for (int t = 0; t < K && rc == EXCMG_OK; t++)
+        rc = launch_iteration<TX, T>(L, x, 1 + t, -1, g_capture);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(g_capture, &graph);
+    if (rc != EXCMG_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    CKH(e);
+    hipGraphExec_t exec = nullptr;
+    CKH(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    g_graph_cache.push_back(GraphEntry{L.index, (int)sizeof(T), (int)g_cg, K, (const void *)x,
+                                       graph, exec});
+    *out = exec;
+    return EXCMG_OK;
+}
+
+// Iterations of Algorithm 2 on level L after bicg_start: the Bi-CG vectors r, r*, p, p*, q, q*
+// have type T, the iterate x type TX.  Every kernel returns at once when the run has stopped,
+// so the host issues K iterations between two polls of the state: directly, or (in solves)
+// as the replay of a captured K-iteration graph after the first iteration.
+template <typename TX, typename T>
+int bicg_iterate(const Level &L, TX *x, BicgState &hs) {
+    int K = poll_interval(L.nu);
+    K += K & 1;
     if (g_timing) CKR(ensure_events(4 * (size_t)K));
+    const bool graphs = g_graphs && !g_timing;
+    hipGraphExec_t exec = nullptr;
+    if (graphs) CKR((window_graph<TX, T>(L, x, K, &exec)));
     long long j = 0;
     while (hs.status == kRunning) {
         const int it0 = hs.iter;
-        for (int t = 0; t < K; t++, j++) {
-            const int cur = (int)(j & 1), nxt = cur ^ 1;
-            T *pn = c.p[nxt].as<T>(), *psn = c.ps[nxt].as<T>();
-            if (g_timing) CKH(hipEventRecord(g_events[4 * t], g_stream));
-            if (g_cg)
-                CKH(stencil_direction<T>(G, G.ty, r, c.p[cur].as<T>(), &S->beta, j == 0 ? 1 : 0,
-                                         pn, q, c.part_a.as<Pair>(), &S->status, g_stream));
-            else
-                CKH(stencil_pair_direction<T>(G, G.ty, r, rs, c.p[cur].as<T>(),
-                                              c.ps[cur].as<T>(), &S->beta, j == 0 ? 1 : 0, pn,
-                                              psn, q, qs, c.part_a.as<Pair>(), &S->status,
-                                              g_stream));
-            if (g_timing) CKH(hipEventRecord(g_events[4 * t + 1], g_stream));
-            CKH(bicg_alpha(S, c.part_a.as<Pair>(), nsb, g_stream));
-            if (g_timing) CKH(hipEventRecord(g_events[4 * t + 2], g_stream));
-            if (g_cg)
-                CKH((cg_update<TX, T>(L.nu, S, x, pn, r, q, c.part_b.as<Pair>(), g_stream)));
-            else
-                CKH((bicg_update<TX, T>(L.nu, S, x, pn, r, q, rs, qs, c.part_b.as<Pair>(),
-                                        g_stream)));
-            if (g_timing) CKH(hipEventRecord(g_events[4 * t + 3], g_stream));
-            if (g_cg) CKH(cg_beta(S, c.part_b.as<Pair>(), nvb, g_stream));
-            else CKH(bicg_beta(S, c.part_b.as<Pair>(), nvb, g_stream));
+        if (graphs) {
+            if (j == 0) CKR((launch_iteration<TX, T>(L, x, 0, -1, g_stream)));
+            CKH(hipGraphLaunch(exec, g_stream));
+            j += (j == 0 ? 1 : 0) + K;
+        } else {
+            for (int t = 0; t < K; t++, j++)
+                CKR((launch_iteration<TX, T>(L, x, j, g_timing ? t : -1, g_stream)));
         }
         CKR(read_state(hs));
         if (g_timing && L.index < EXCMG_MAX_LEVELS) {
             const int active = std::min(K, hs.iter - it0);  // launches that did work
             for (int t = 0; t < active; t++) {
-                float a = 0.f, b = 0.f;
+                float a = 0.f, b2 = 0.f;
                 CKH(hipEventElapsedTime(&a, g_events[4 * t], g_events[4 * t + 1]));
-                CKH(hipEventElapsedTime(&b, g_events[4 * t + 2], g_events[4 * t + 3]));
+                CKH(hipEventElapsedTime(&b2, g_events[4 * t + 2], g_events[4 * t + 3]));
                 g_time_ms[L.index][0] += a;
-                g_time_ms[L.index][1] += b;
+                g_time_ms[L.index][1] += b2;
                 g_time_n[L.index][0]++;
                 g_time_n[L.index][1]++;
             }
@@ -1213,8 +1284,10 @@ int excmg_solve_ex(const excmg_opts *opts, const double *f, const double *g1, co
     if (ut_out) CKR(at.out());
     if (st) memset(st, 0, sizeof(*st));
     g_cg = (o.method == EXCMG_CG);
+    g_graphs = getenv("EXCMG_NO_GRAPHS") == nullptr;
     int rc = solve_cascade(o, af.p<double>(), a1.p<double>(), a2.p<double>(), au.p<double>(),
                         ut_out ? at.p<double>() : nullptr, st);
+    g_graphs = false;
     if (rc != EXCMG_OK && rc != EXCMG_ENOCONV && rc != EXCMG_EBREAKDOWN) return rc;
     CKR(au.back());
     if (ut_out) CKR(at.back());
@@ -1384,7 +1457,8 @@ int excmg_autotune(int n, int kind, int precision, int reps, int *ty_out, int *z
     hs.maxit = 1 << 30;
     CKH(hipMemcpyAsync(stb.p, &hs, sizeof(hs), hipMemcpyHostToDevice, g_stream));
     BicgState *S = stb.as<BicgState>();
-    std::vector<int> tys = kind == 1 ? std::vector<int>{4, 8} : std::vector<int>{4, 8, 16};
+    // FP64 sweep A spills at ty = 16 (1024 threads leave 128 registers per lane)
+    std::vector<int> tys = (kind == 1 && es == 8) ? std::vector<int>{4, 8} : std::vector<int>{4, 8, 16};
     double best = INFINITY;
     int bty = 8, bzc = 8;
     hipEvent_t e0, e1;
@@ -1460,7 +1534,7 @@ int excmg_set_shape(int n, int kind, int ty, int zc) {
     if (n < 2) return fail(EXCMG_EINVAL, "n must be >= 2");
     if (kind < 0 || kind > 2) return fail(EXCMG_EINVAL, "kind must be 0, 1 or 2");
     if (ty != 0 && ty != 4 && ty != 8 && ty != 16) return fail(EXCMG_EINVAL, "ty must be 4, 8 or 16");
-    if (kind != 0 && ty == 16) return fail(EXCMG_EINVAL, "sweep A supports ty 4 or 8");
+    if (kind == 1 && ty == 16) return fail(EXCMG_EINVAL, "FP64 sweep A supports ty 4 or 8");
     if (ty != 0 && zc < 1) return fail(EXCMG_EINVAL, "zc must be >= 1");
     for (size_t i = 0; i < g_shapes.size(); i++)
         if (g_shapes[i].N == n && g_shapes[i].kind == kind) {
@@ -1468,6 +1542,7 @@ int excmg_set_shape(int n, int kind, int ty, int zc) {
             break;
         }
     if (ty != 0) g_shapes.push_back(ShapeOverride{n, kind, ty, zc});
+    release_graphs();  // captured iteration windows hold the old launch shapes
     for (Level &L : g_ctx.lv) {
         if (L.N != n) continue;
         choose_shapes(L, g_ctx.bc);

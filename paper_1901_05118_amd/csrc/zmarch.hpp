@@ -216,19 +216,21 @@ __device__ __forceinline__ void zmarch_tile(const Geom &g, int tile, const In &i
 #pragma unroll
     for (int a = 0; a < NA; a++) column_init(col[a]);
 
-    // Planes mbeg..mend are staged; two planes are in flight in registers at any time.
+    // Planes mbeg..mend are staged; D planes are in flight in registers at any time (measured:
+    // deeper pipelines cost more occupancy than they hide, for FP32 vectors too).
+    constexpr int D = 2;
     const int mbeg = k0 - 2, mend = k1 + 1;
-    Raw rawA, rawB;
-    double mzA, mzB;
-    fetch(mbeg, rawA, mzA);
-    stash(0, rawA, mzA);
-    fetch(min(mbeg + 1, mend), rawA, mzA);
-    fetch(min(mbeg + 2, mend), rawB, mzB);
+    Raw raw[D];
+    double mz[D];
+    fetch(mbeg, raw[0], mz[0]);
+    stash(0, raw[0], mz[0]);
+#pragma unroll
+    for (int k = 0; k < D; k++) fetch(min(mbeg + 1 + k, mend), raw[k], mz[k]);
     __syncthreads();
     int cur = 0;
     const int centre = (ly + 2) * LS + (lx + 2);
-    // consume plane m from LDS, stage plane m+1 from `raw`, refill `raw` with plane m+3
-    auto body = [&](int m, Raw &raw, double &mz) {
+    // consume plane m from LDS, stage plane m+1 from `r`, refill `r` with plane m+1+D
+    auto body = [&](int m, Raw &r, double &z) {
         double y[NA], c0[NA], cprev[NA];
 #pragma unroll
         for (int a = 0; a < NA; a++) {
@@ -240,15 +242,17 @@ __device__ __forceinline__ void zmarch_tile(const Geom &g, int tile, const In &i
             const int k = m - 2;
             if (k >= k0 && k < k1) out.emit((i64)k * plane + (i64)iy * n + ix, y, cprev);
         }
-        stash(cur ^ 1, raw, mz);
-        fetch(min(m + 3, mend), raw, mz);
+        stash(cur ^ 1, r, z);
+        fetch(min(m + 1 + D, mend), r, z);
         __syncthreads();
         cur ^= 1;
     };
-    for (int m = mbeg; m <= mend; m += 2) {
-        body(m, rawA, mzA);
-        if (m + 1 > mend) break;
-        body(m + 1, rawB, mzB);
+    for (int m = mbeg; m <= mend; m += D) {
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+            if (m + k > mend) break;
+            body(m + k, raw[k], mz[k]);
+        }
     }
 }
 
