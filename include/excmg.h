@@ -136,6 +136,11 @@ int excmg_bicg(int level, const double *b, double *x, double eps, int max_iters,
 int excmg_level_solve(int level, const double *b, double *x, double eps, int max_iters,
                       int max_runs, excmg_level_stats *st);
 
+/* Copy the finite-difference solution of level `level` from the last excmg_solve /
+ * excmg_solve_ex on the current context (node array of N_l cells, boundary = g1): the
+ * per-level solutions of Algorithm 1, e.g. to form ||w_h - u_h|| as in the paper's tables. */
+int excmg_get_level_solution(int level, double *u);
+
 /* w = EXP_finite(u1, u0) (Sec. 4.2.3, Steps 1-5): third-order approximation on the grid of n
  * cells (n divisible by 4) of the finite-difference solution, from the node arrays u1 (n/2
  * cells) and u0 (n/4 cells).  w is a node array of n cells.  Needs no context. */

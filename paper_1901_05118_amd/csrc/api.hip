@@ -1227,6 +1227,19 @@ int excmg_level_solve(int level, const double *b, double *x, double eps, int max
     return EXCMG_OK;
 }
 
+int excmg_get_level_solution(int level, double *u) {
+    g_err[0] = 0;
+    CKR(need_ctx(level));
+    if (!u) return fail(EXCMG_EINVAL, "NULL array");
+    const Level &L = g_ctx.lv[level];
+    Arg au(u, L.nodes * 8);
+    CKR(au.out());
+    CKH(hipMemcpyAsync(au.p<double>(), L.u.p, L.nodes * 8, hipMemcpyDeviceToDevice, g_stream));
+    CKR(au.back());
+    CKH(hipStreamSynchronize(g_stream));
+    return EXCMG_OK;
+}
+
 int excmg_exp_finite(int n, const double *u1, const double *u0, double *w) {
     g_err[0] = 0;
     if (n < 4 || n % 4 != 0 || n > 4096) return fail(EXCMG_EINVAL, "n must be a multiple of 4");

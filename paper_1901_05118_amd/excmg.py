@@ -18,6 +18,7 @@ __all__ = [
     "lib_path", "load", "set_stream", "setup", "apply_stencil", "apply_operator", "rhs", "dsolve", "bicg",
     "level_solve", "exp_finite", "exp_true", "solve", "solve_ex", "profile_sweep",
     "set_shape", "get_shape", "set_timing", "get_timing", "autotune", "solve_batch",
+    "get_level_solution",
     "Problem",
     "last_error", "finalize",
     "LevelStats", "Stats",
@@ -94,6 +95,7 @@ def load():
         "excmg_level_solve": (c_int, [c_int, dp, dp, c_dbl, c_int, c_int,
                                       ctypes.POINTER(LevelStats)]),
         "excmg_exp_finite": (c_int, [c_int, dp, dp, dp]),
+        "excmg_get_level_solution": (c_int, [c_int, dp]),
         "excmg_exp_true": (c_int, [c_int, dp, dp, dp]),
         "excmg_solve": (c_int, [c_int, c_int, c_int, dp, dp, dp, c_dbl, dp]),
         "excmg_solve_ex": (c_int, [ctypes.POINTER(Opts), dp, dp, dp, dp, dp,
@@ -201,6 +203,11 @@ def level_solve(level: int, b, x, eps: float, max_iters: int = 100000, max_runs:
     if rc not in (OK, ENOCONV, EBREAKDOWN):
         _check("excmg_level_solve", rc)
     return rc, st.asdict()
+
+
+def get_level_solution(level: int, u):
+    """Node array of level `level` from the last solve on the current context."""
+    _check("excmg_get_level_solution", load().excmg_get_level_solution(level, _ptr(u, name="u")))
 
 
 def exp_finite(n: int, u1, u0, w):

@@ -1,0 +1,102 @@
+"""Failure handling and determinism of the HIP library, forced from the host (no kernel is
+made to fault or hang: every case ends through the library's own status checks)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from manufactured import config_problem, make_arrays, paper_problem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ex():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1901_05118_amd as ex
+    ex.load()
+    yield ex
+    ex.finalize()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _inputs(k=2, N=32, bc=1):
+    arr = make_arrays(config_problem(k), N, bc)
+    return arr, dev(arr.f), dev(arr.g1), dev(arr.g2)
+
+
+def test_nan_forcing_reports_breakdown(ex):
+    arr, f, g1, g2 = _inputs()
+    f[16, 16, 16] = float("nan")
+    u = torch.empty_like(f)
+    rc, st = ex.solve_ex(32, 4, 1, f, g1, g2, 1e-8, u)
+    assert rc == ex.EBREAKDOWN
+    assert any(l["status"] == ex.EBREAKDOWN for l in st.levels())
+
+
+def test_iteration_cap_reports_no_convergence(ex):
+    arr, f, g1, g2 = _inputs()
+    u = torch.empty_like(f)
+    rc, st = ex.solve_ex(32, 4, 1, f, g1, g2, 1e-10, u, max_iters=3, max_runs=2)
+    assert rc == ex.ENOCONV
+    lv = st.levels()
+    assert all(l["iterations"] <= 6 for l in lv[2:])
+    assert np.isfinite(u.cpu().numpy()).all()
+
+
+def test_tolerance_below_the_fp64_floor_stops(ex):
+    """Problem 1 has zero boundary data; at 32^3 its relative-residual floor is ~4e-12, so
+    1e-14 cannot be met: the level stops after max_runs Bi-CG runs instead of looping."""
+    arr = make_arrays(paper_problem(1), 32, 1)
+    f, g1, g2 = dev(arr.f), dev(arr.g1), dev(arr.g2)
+    u = torch.empty_like(f)
+    rc, st = ex.solve_ex(32, 3, 1, f, g1, g2, 1e-14, u, max_runs=3)
+    assert rc == ex.ENOCONV
+    last = st.levels()[-1]
+    assert last["runs"] == 3 and last["rel_residual"] > 1e-14
+    rc, st = ex.solve_ex(32, 3, 1, f, g1, g2, 1e-14, u, precision=ex.MIXED)
+    assert rc == ex.ENOCONV   # refinement stops when an outer step no longer helps
+
+
+def test_solves_are_deterministic(ex):
+    arr, f, g1, g2 = _inputs(3, 48, 2)
+    outs = []
+    for prec in (ex.FP64, ex.FP64, ex.MIXED, ex.MIXED):
+        u = torch.empty_like(f)
+        rc, st = ex.solve_ex(48, 5, 2, f, g1, g2, 1e-9, u, precision=prec)
+        assert rc == ex.OK
+        outs.append(u.cpu().numpy())
+    np.testing.assert_array_equal(outs[0], outs[1])
+    np.testing.assert_array_equal(outs[2], outs[3])
+
+
+def test_host_arrays_through_solve(ex):
+    arr, f, g1, g2 = _inputs(1, 32, 1)
+    u_host = np.empty_like(arr.f)
+    rc, st = ex.solve_ex(32, 4, 1, arr.f, arr.g1, arr.g2, 1e-10, u_host)
+    assert rc == ex.OK
+    u_dev = torch.empty_like(f)
+    ex.solve_ex(32, 4, 1, f, g1, g2, 1e-10, u_dev)
+    np.testing.assert_array_equal(u_host, u_dev.cpu().numpy())
+
+
+def test_level_solutions_form_the_tables_w_column(ex, golden_tables):
+    """||w_h - u_h||_2 of Table 2 at 32^3 from the per-level solutions of one GPU solve."""
+    arr = make_arrays(paper_problem(2), 32, 1)
+    f, g1, g2 = dev(arr.f), dev(arr.g1), dev(arr.g2)
+    u = torch.empty_like(f)
+    rc, st = ex.solve_ex(32, 3, 1, f, g1, g2, 1e-12, u)
+    assert rc == ex.OK
+    u8 = torch.empty((9,) * 3, dtype=torch.float64, device="cuda")
+    u16 = torch.empty((17,) * 3, dtype=torch.float64, device="cuda")
+    ex.get_level_solution(0, u8)
+    ex.get_level_solution(1, u16)
+    w = torch.empty_like(f)
+    ex.exp_finite(32, u16, u8, w)
+    e = w.cpu().numpy() - u.cpu().numpy()
+    assert float(f"{O.norm2(e):.2e}") == golden_tables["problems"]["2"]["w_err2"][0]

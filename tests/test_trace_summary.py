@@ -1,0 +1,34 @@
+"""The profile summariser on small synthetic rocprofv3 outputs (host logic only)."""
+import csv
+import sqlite3
+
+from paper_1901_05118_amd import trace_summary as ts
+
+
+def test_trace_groups_by_grid_and_drops_noop_launches(tmp_path):
+    db = tmp_path / "r.db"
+    con = sqlite3.connect(db)
+    con.execute("create table kernels (name text, duration integer, grid_x integer, "
+                "grid_y integer, grid_z integer)")
+    name = "void excmg::zmarch<2, 8, float>(excmg::Geom, float const*)"
+    rows = [(name, 1000, 512, 8, 1)] * 5 + [(name, 10, 512, 8, 1)] * 2 + [(name, 100, 64, 8, 1)] * 3
+    con.executemany("insert into kernels values (?,?,?,?,?)", rows)
+    con.commit()
+    con.close()
+    md = ts.trace(str(db), "cmd")
+    assert "`zmarch<2, 8, float>`" in md
+    assert "| `zmarch<2, 8, float>` | 10 | 0.01 |" in md
+    # 7 launches on the big grid, 5 active at 1.0 us each
+    assert "| 512x8x1 | 7 | 5 | 1.0 | 1.0 |" in md
+
+
+def test_counters_mean_per_kernel_and_grid(tmp_path):
+    d = tmp_path / "h" / "1"
+    d.mkdir(parents=True)
+    with open(d / "x_counter_collection.csv", "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(["Dispatch_Id", "Grid_Size", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writerow([1, 4096, "void excmg::k_copy<double>(long long)", "FETCH_SIZE", 100.0])
+        w.writerow([2, 4096, "void excmg::k_copy<double>(long long)", "FETCH_SIZE", 300.0])
+    md = ts.counters(str(tmp_path), "cmd")
+    assert "| `k_copy<double>` | 4096 | FETCH_SIZE | 2 | 200 | 100 | 300 |" in md
