@@ -24,10 +24,49 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Bi-CG stencil GLUPS & HBM GB/s; time-to-1e-8 residual, FP64 vs mixed"
 HBM_PEAK_GBS = 8000.0
+# sources of the z-marched stencil kernels: a stored counter measurement of sweep A holds
+# only while these are unchanged
+SWEEP_A_SOURCES = ["paper_1901_05118_amd/csrc/common.hpp",
+                   "paper_1901_05118_amd/csrc/internal.hpp",
+                   "paper_1901_05118_amd/csrc/zmarch.hpp",
+                   "paper_1901_05118_amd/csrc/stencil.hip"]
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def sweep_a_launch(N, ty, zc, fp32):
+    """Name (as the profiler shows it) and launch size in threads of Bi-CG sweep A on the
+    grid of N cells with tiles of 64 x ty columns and zc planes."""
+    n = N - 1
+    tiles = -(-n // 64) * -(-n // ty) * -(-n // zc)
+    tiles = -(-tiles // 8) * 8  # the grid is padded to whole XCD shares
+    t = "float" if fp32 else "double"
+    return f"zmarch<2, {ty}, {t}, InDirection<{t}>, OutPairApply<{t}> >", tiles * 64 * ty
+
+
+def recorded_traffic(kernel, grid):
+    """HBM bytes per launch of (kernel, grid) from the traffic records of the committed
+    counter summaries, provided they were measured on the current kernel sources."""
+    import glob
+    import re
+    from paper_1901_05118_amd.trace_summary import sources_sha256
+    key = f"{kernel}|{grid}"
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as fh:
+            text = fh.read()
+        for m in re.finditer(r"<!-- traffic-record (\{.*?\}) -->", text):
+            rec = json.loads(m.group(1))
+            if key not in rec["bytes_per_launch"]:
+                continue
+            files = [os.path.join(ROOT, f) for f in rec["sources"]]
+            if sorted(rec["sources"]) != sorted(SWEEP_A_SOURCES):
+                continue
+            if all(os.path.exists(f) for f in files) and \
+                    sources_sha256(files) == rec["sources_sha256"]:
+                return rec["bytes_per_launch"][key], os.path.basename(path)
+    return None, None
 
 
 def cpu_baseline(arr, N, nl, bc, iters):
@@ -100,7 +139,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch leg")
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="re-time every tile shape first instead of the built-in tuned table")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the solver has no multi-GPU path "
@@ -124,7 +164,7 @@ def main():
     stream = torch.cuda.current_stream()
     ex.set_stream(stream)
     tuned = {}
-    if not args.no_autotune:
+    if args.autotune:
         # tile shapes of every grid the runs use, chosen by timing (the project's autotuner)
         sizes = sorted({N >> k for k in range(nl - 2)} | {32, 48, 64, 96, 128, 24, 12, 16})
         for n in sizes:
@@ -204,10 +244,15 @@ def main():
     avg_a, avg_b = ms_a / max(n_a, 1), ms_b / max(n_b, 1)
     gbs_a = bytes_a / (avg_a * 1e-3) / 1e9
     ms_c, bytes_c = ex.profile_sweep(4, ex.FP64, reps=10)
+    ty_a, zc_a = ex.get_shape(N, 2 if gate else 1)
+    kname, grid = sweep_a_launch(N, ty_a, zc_a, gate)
+    traffic, traffic_src = recorded_traffic(kname, grid)
     roofline = {"bound": "hbm", "achieved": round(gbs_a, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(gbs_a / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": f"zmarch<2,{'float' if gate else 'double'},InDirection,OutPairApply> "
-                          f"(Bi-CG sweep A, {N}^3 level)",
+                "unit": "GB/s", "frac": round(gbs_a / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else round(traffic),
+                "traffic_source": traffic_src,
+                "kernel": f"{kname} (Bi-CG sweep A, {N}^3 level, tile 64x{ty_a}, "
+                          f"{zc_a} planes, {grid} threads)",
                 "launches": n_a, "ms_per_launch": round(avg_a, 4), "bytes_per_launch": bytes_a,
                 "sweep_b": {"launches": n_b, "ms_per_launch": round(avg_b, 4),
                             "gbs": round(bytes_b / (avg_b * 1e-3) / 1e9, 1)},

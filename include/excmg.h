@@ -190,7 +190,7 @@ int excmg_get_timing(int level, int sweep, double *ms_total, long long *launches
  * columns marching through chunks of zc planes.  kind 0: the one-array kernels (operator,
  * residual; ty = 4, 8 or 16); kind 1 / 2: Bi-CG sweep A on FP64 / FP32 vectors (two arrays;
  * ty = 4 or 8 for FP64, 4, 8 or 16 for FP32).  ty = 0
- * restores the built-in rule.  Applies to later launches, including levels of the current
+ * restores the built-in table (the autotuner's MI355X picks per grid-size band).  Applies to later launches, including levels of the current
  * context.  The autotuner uses it; results do not depend on the shape (every output is
  * computed with the same arithmetic). */
 int excmg_set_shape(int n, int kind, int ty, int zc);

@@ -207,17 +207,19 @@ Geom choose_shape(int N, int bc, int kind) {
     const int n = N - 1;
     for (const ShapeOverride &o : g_shapes)
         if (o.N == N && o.kind == kind) return make_geom(n, bc, o.ty, std::max(1, std::min(o.zc, n)));
-    const int ty = (kind == 0 && n >= 255) ? 16 : (n >= 24 ? 8 : 4);
-    const int tiles_xy = ((n + kWave - 1) / kWave) * ((n + ty - 1) / ty);
-    int zc = 4;
-    for (int cand = 512; cand >= 4; cand >>= 1) {
-        const int tz = (n + cand - 1) / cand;
-        if ((long long)tiles_xy * tz >= 256) {
-            zc = cand;
-            break;
-        }
-    }
-    zc = std::max(1, std::min(zc, n));
+    // Shapes the autotuner picks on MI355X (stable across runs), per grid-size band and
+    // kind {operator/residual, FP64 sweep A, FP32 sweep A}: {ty, zc}.  Grids up to 64^3 are
+    // launch-latency bound and want the most workgroups; larger grids want long z-marches.
+    static const int kTuned[5][3][2] = {
+        {{4, 4}, {4, 4}, {4, 4}},          // N < 96
+        {{4, 8}, {8, 16}, {4, 8}},         // 96 <= N < 128
+        {{16, 8}, {8, 16}, {8, 16}},       // 128 <= N < 256
+        {{8, 32}, {8, 128}, {16, 64}},     // 256 <= N < 512
+        {{8, 128}, {8, 128}, {16, 64}},    // N >= 512
+    };
+    const int band = N < 96 ? 0 : N < 128 ? 1 : N < 256 ? 2 : N < 512 ? 3 : 4;
+    const int ty = kTuned[band][kind][0];
+    const int zc = std::max(1, std::min(kTuned[band][kind][1], n));
     return make_geom(n, bc, ty, zc);
 }
 
