@@ -359,11 +359,14 @@ int poll_interval(long long nu) {
 // run has stopped, so the host launches K iterations between two polls of the state.
 bool g_cg = false;          // current solve uses the CG specialisation (opts.method)
 bool g_graphs = false;      // replay iteration windows from captured hipGraphs (solves only)
+// fold the sigma and rho finalisations into the sweeps (two launches per iteration instead
+// of four); off: separate one-workgroup finalisation kernels
+bool g_fold = getenv("EXCMG_SEPARATE_FINALISE") == nullptr;
 hipStream_t g_capture = nullptr;
 
 // Captured windows of K iterations, per level, vector type, method and iterate pointer.
 struct GraphEntry {
-    int level, tsize, cg, K;
+    int level, tsize, cg, fold, K;
     const void *x;
     hipGraph_t graph;
     hipGraphExec_t exec;
@@ -390,24 +393,46 @@ int launch_iteration(const Level &L, TX *x, long long j, int ev, hipStream_t st)
     const int nvb = vec_blocks(L.nu);
     const int cur = (int)(j & 1), nxt = cur ^ 1;
     T *pn = c.p[nxt].as<T>(), *psn = c.ps[nxt].as<T>();
+    // folded: sweep A merges the previous sweep B's partials (rho, r.r, beta, stopping
+    // checks), sweep B merges sweep A's (sigma, alpha)
+    StepLink la, lb;
+    if (g_fold) {
+        la = StepLink{S, c.part_b.as<Pair>(), nvb, g_cg ? 1 : 2, cur};
+        lb = StepLink{S, c.part_a.as<Pair>(), nsb, 1, cur};
+    }
     if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev], st));
     if (g_cg)
         CKH(stencil_direction<T>(G, G.ty, r, c.p[cur].as<T>(), &S->beta, j == 0 ? 1 : 0, pn, q,
-                                 c.part_a.as<Pair>(), &S->status, st));
+                                 c.part_a.as<Pair>(), &S->status, st, la));
     else
         CKH(stencil_pair_direction<T>(G, G.ty, r, rs, c.p[cur].as<T>(), c.ps[cur].as<T>(),
                                       &S->beta, j == 0 ? 1 : 0, pn, psn, q, qs,
-                                      c.part_a.as<Pair>(), &S->status, st));
+                                      c.part_a.as<Pair>(), &S->status, st, la));
     if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev + 1], st));
-    CKH(bicg_alpha(S, c.part_a.as<Pair>(), nsb, st));
+    if (!g_fold) CKH(bicg_alpha(S, c.part_a.as<Pair>(), nsb, st));
     if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev + 2], st));
     if (g_cg)
-        CKH((cg_update<TX, T>(L.nu, S, x, pn, r, q, c.part_b.as<Pair>(), st)));
+        CKH((cg_update<TX, T>(L.nu, S, x, pn, r, q, c.part_b.as<Pair>(), st, lb)));
     else
-        CKH((bicg_update<TX, T>(L.nu, S, x, pn, r, q, rs, qs, c.part_b.as<Pair>(), st)));
+        CKH((bicg_update<TX, T>(L.nu, S, x, pn, r, q, rs, qs, c.part_b.as<Pair>(), st, lb)));
     if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev + 3], st));
-    if (g_cg) CKH(cg_beta(S, c.part_b.as<Pair>(), nvb, st));
-    else CKH(bicg_beta(S, c.part_b.as<Pair>(), nvb, st));
+    if (!g_fold) {
+        if (g_cg) CKH(cg_beta(S, c.part_b.as<Pair>(), nvb, st));
+        else CKH(bicg_beta(S, c.part_b.as<Pair>(), nvb, st));
+    }
+    return EXCMG_OK;
+}
+
+// Folded steps leave the end-of-iteration checks of iteration j to the next sweep A; before
+// the host reads the state, run them on their own (the next sweep A repeats them with the
+// same result).
+template <typename T>
+int close_window(const Level &L, long long j_next, hipStream_t st) {
+    if (!g_fold) return EXCMG_OK;
+    Ctx &c = g_ctx;
+    const StepLink l{c.state.as<BicgState>(), c.part_b.as<Pair>(), vec_blocks(L.nu), g_cg ? 1 : 2,
+                     (int)(j_next & 1)};
+    CKH(step_check(l, st));
     return EXCMG_OK;
 }
 
@@ -415,8 +440,8 @@ int launch_iteration(const Level &L, TX *x, long long j, int ev, hipStream_t st)
 template <typename TX, typename T>
 int window_graph(const Level &L, TX *x, int K, hipGraphExec_t *out) {
     for (GraphEntry &e : g_graph_cache)
-        if (e.level == L.index && e.tsize == (int)sizeof(T) && e.cg == (int)g_cg && e.K == K &&
-            e.x == (const void *)x) {
+        if (e.level == L.index && e.tsize == (int)sizeof(T) && e.cg == (int)g_cg &&
+            e.fold == (int)g_fold && e.K == K && e.x == (const void *)x) {
             *out = e.exec;
             return EXCMG_OK;
         }
@@ -425,6 +450,7 @@ int window_graph(const Level &L, TX *x, int K, hipGraphExec_t *out) {
     int rc = EXCMG_OK;
     for (int t = 0; t < K && rc == EXCMG_OK; t++)
         rc = launch_iteration<TX, T>(L, x, 1 + t, -1, g_capture);
+    if (rc == EXCMG_OK) rc = close_window<T>(L, K + 1, g_capture);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(g_capture, &graph);
     if (rc != EXCMG_OK) {
@@ -434,8 +460,8 @@ int window_graph(const Level &L, TX *x, int K, hipGraphExec_t *out) {
     CKH(e);
     hipGraphExec_t exec = nullptr;
     CKH(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-    g_graph_cache.push_back(GraphEntry{L.index, (int)sizeof(T), (int)g_cg, K, (const void *)x,
-                                       graph, exec});
+    g_graph_cache.push_back(GraphEntry{L.index, (int)sizeof(T), (int)g_cg, (int)g_fold, K,
+                                       (const void *)x, graph, exec});
     *out = exec;
     return EXCMG_OK;
 }
@@ -462,6 +488,7 @@ int bicg_iterate(const Level &L, TX *x, BicgState &hs) {
         } else {
             for (int t = 0; t < K; t++, j++)
                 CKR((launch_iteration<TX, T>(L, x, j, g_timing ? t : -1, g_stream)));
+            CKR(close_window<T>(L, j, g_stream));
         }
         CKR(read_state(hs));
         if (g_timing && L.index < EXCMG_MAX_LEVELS) {

@@ -32,6 +32,17 @@ struct BicgState {
     int maxit;
     int status;      // 0 running, 1 converged, -3 iteration cap, -4 breakdown
     int pad;
+    double rho_slot[2];  // rho_j in slot j & 1 (steps with folded finalisations)
+};
+
+// A sweep that folds in the finalisation of the preceding sweep (see step.hpp).  state ==
+// nullptr: not folded; the scalars come from the one-workgroup finalisation kernels.
+struct StepLink {
+    BicgState *state = nullptr;
+    const Pair *part = nullptr;  // partials of the preceding sweep
+    int count = 0;               // pairs per value
+    int nv = 1;                  // values: 2 = (r*.r, r.r), 1 = r.r (CG) or sigma
+    int par = 0;                 // parity of the iteration
 };
 
 constexpr int kRunning = 0, kConverged = 1, kNoConv = -3, kBreakdown = -4;
@@ -57,13 +68,13 @@ template <typename T>
 hipError_t stencil_pair_direction(const Geom &g, int ty, const T *r, const T *rs,
                                   const T *p_old, const T *ps_old, const double *beta_dev,
                                   int first, T *p_new, T *ps_new, T *q, T *qs, Pair *partials,
-                                  const int *status, hipStream_t st);
+                                  const int *status, hipStream_t st, StepLink link = StepLink{});
 
 // CG sweep A: p_new = r + beta p_old (p_new = r when first), q = A p_new, partials of p_new . q
 template <typename T>
 hipError_t stencil_direction(const Geom &g, int ty, const T *r, const T *p_old,
                              const double *beta_dev, int first, T *p_new, T *q, Pair *partials,
-                             const int *status, hipStream_t st);
+                             const int *status, hipStream_t st, StepLink link = StepLink{});
 
 inline int stencil_blocks(const Geom &g) { return xcd_grid(g.ntiles); }
 
@@ -75,13 +86,17 @@ int vec_blocks(long long n);
 // held in higher precision than the other vectors (FP64 iterate, FP32 Bi-CG vectors).
 template <typename TX, typename T>
 hipError_t bicg_update(long long n, const BicgState *s, TX *x, const T *p, T *r, const T *q,
-                       T *rs, const T *qs, Pair *partials, hipStream_t st);
+                       T *rs, const T *qs, Pair *partials, hipStream_t st,
+                       StepLink link = StepLink{});
 
 // CG sweep B: x += alpha p; r -= alpha q; partials of r.r
 template <typename TX, typename T>
 hipError_t cg_update(long long n, const BicgState *s, TX *x, const T *p, T *r, const T *q,
-                     Pair *partials, hipStream_t st);
+                     Pair *partials, hipStream_t st, StepLink link = StepLink{});
 hipError_t cg_beta(BicgState *s, const Pair *part, int count, hipStream_t st);
+// the end-of-iteration checks of a folded step as a kernel of its own (one workgroup), run
+// before the host reads the state
+hipError_t step_check(StepLink link, hipStream_t st);
 
 // partials of x.y
 template <typename T>

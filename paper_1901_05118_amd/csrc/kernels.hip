@@ -5,6 +5,7 @@
 // deterministic and independent of the launch shape.
 #include "common.hpp"
 #include "internal.hpp"
+#include "step.hpp"
 
 namespace excmg {
 
@@ -23,13 +24,19 @@ int vec_blocks(long long n) {
 // r*_{k+1} = r*_k - alpha (p*_k A); partials of r*.r (rho of the next step) and r.r.
 // The iterate x may be FP64 while the Bi-CG vectors are FP32 (iterative refinement updates
 // the FP64 solution directly).
+// With a StepLink the kernel first merges sweep A's partials itself (sigma, alpha).
 template <typename TX, typename T>
 __global__ void __launch_bounds__(kVecThreads)
     k_bicg_update(long long n, const BicgState *s, TX *x, const T *p, T *r, const T *q, T *rs,
-                  const T *qs, Pair *partials) {
+                  const T *qs, Pair *partials, StepLink link) {
     __shared__ Pair sh[2 * (kVecThreads / kWave)];
-    if (s->status != kRunning) return;
-    const double alpha = s->alpha;
+    if (!block_running(&s->status)) return;
+    double alpha;
+    if (link.state) {
+        if (!link_alpha(link, alpha, sh)) return;
+    } else {
+        alpha = s->alpha;
+    }
     Pair acc[2] = {{0.0, 0.0}, {0.0, 0.0}};
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
@@ -52,27 +59,33 @@ __global__ void __launch_bounds__(kVecThreads)
 
 template <typename TX, typename T>
 hipError_t bicg_update(long long n, const BicgState *s, TX *x, const T *p, T *r, const T *q,
-                       T *rs, const T *qs, Pair *partials, hipStream_t st) {
+                       T *rs, const T *qs, Pair *partials, hipStream_t st, StepLink link) {
     hipLaunchKernelGGL((k_bicg_update<TX, T>), dim3(vec_blocks(n)), dim3(kVecThreads), 0, st, n,
-                       s, x, p, r, q, rs, qs, partials);
+                       s, x, p, r, q, rs, qs, partials, link);
     return hipGetLastError();
 }
 template hipError_t bicg_update<double, double>(long long, const BicgState *, double *,
                                                 const double *, double *, const double *,
-                                                double *, const double *, Pair *, hipStream_t);
+                                                double *, const double *, Pair *, hipStream_t,
+                                                StepLink);
 template hipError_t bicg_update<double, float>(long long, const BicgState *, double *,
                                                const float *, float *, const float *, float *,
-                                               const float *, Pair *, hipStream_t);
+                                               const float *, Pair *, hipStream_t, StepLink);
 
 // CG sweep B: the primal half of the Bi-CG update (the shadow half repeats it bit for bit
 // when r*_0 = r_0), and the partials of r.r, which is also rho of the next iteration.
 template <typename TX, typename T>
 __global__ void __launch_bounds__(kVecThreads)
     k_cg_update(long long n, const BicgState *s, TX *x, const T *p, T *r, const T *q,
-                Pair *partials) {
+                Pair *partials, StepLink link) {
     __shared__ Pair sh[kVecThreads / kWave];
-    if (s->status != kRunning) return;
-    const double alpha = s->alpha;
+    if (!block_running(&s->status)) return;
+    double alpha;
+    if (link.state) {
+        if (!link_alpha(link, alpha, sh)) return;
+    } else {
+        alpha = s->alpha;
+    }
     Pair acc[1] = {{0.0, 0.0}};
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
@@ -89,17 +102,29 @@ __global__ void __launch_bounds__(kVecThreads)
 
 template <typename TX, typename T>
 hipError_t cg_update(long long n, const BicgState *s, TX *x, const T *p, T *r, const T *q,
-                     Pair *partials, hipStream_t st) {
+                     Pair *partials, hipStream_t st, StepLink link) {
     hipLaunchKernelGGL((k_cg_update<TX, T>), dim3(vec_blocks(n)), dim3(kVecThreads), 0, st, n, s,
-                       x, p, r, q, partials);
+                       x, p, r, q, partials, link);
     return hipGetLastError();
 }
 template hipError_t cg_update<double, double>(long long, const BicgState *, double *,
                                               const double *, double *, const double *, Pair *,
-                                              hipStream_t);
+                                              hipStream_t, StepLink);
 template hipError_t cg_update<double, float>(long long, const BicgState *, double *,
                                              const float *, float *, const float *, Pair *,
-                                             hipStream_t);
+                                             hipStream_t, StepLink);
+
+__global__ void __launch_bounds__(kReduceThreads) k_step_check(StepLink link) {
+    __shared__ Pair sh[2 * (kReduceThreads / kWave)];
+    if (!block_running(&link.state->status)) return;
+    double beta;
+    (void)link_step(link, beta, sh);
+}
+
+hipError_t step_check(StepLink link, hipStream_t st) {
+    hipLaunchKernelGGL(k_step_check, dim3(1), dim3(kReduceThreads), 0, st, link);
+    return hipGetLastError();
+}
 
 template <typename T>
 __global__ void __launch_bounds__(kVecThreads)
@@ -173,6 +198,7 @@ __global__ void __launch_bounds__(kReduceThreads)
         double rr = pair_value(v[0]);
         s->rr = rr;
         s->rho = rr;  // r*_0 = r_0
+        s->rho_slot[0] = rr;
         s->thr = (eps * eps) * s->bb;
         s->iter = 0;
         s->maxit = maxit;

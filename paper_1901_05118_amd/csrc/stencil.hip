@@ -80,8 +80,9 @@ template <typename T>
 hipError_t stencil_pair_direction(const Geom &g, int ty, const T *r, const T *rs,
                                   const T *p_old, const T *ps_old, const double *beta_dev,
                                   int first, T *p_new, T *ps_new, T *q, T *qs, Pair *partials,
-                                  const int *status, hipStream_t st) {
+                                  const int *status, hipStream_t st, StepLink link) {
     InDirection<T> in;
+    in.link = link;
     in.r[0] = r;
     in.r[1] = rs;
     in.p[0] = p_old;
@@ -112,8 +113,9 @@ template hipError_t stencil_residual<float>(const Geom &, int, const double *, c
 template <typename T>
 hipError_t stencil_direction(const Geom &g, int ty, const T *r, const T *p_old,
                              const double *beta_dev, int first, T *p_new, T *q, Pair *partials,
-                             const int *status, hipStream_t st) {
+                             const int *status, hipStream_t st, StepLink link) {
     InDirection<T> in;
+    in.link = link;
     in.r[0] = r;
     in.r[1] = r;
     in.p[0] = p_old;
@@ -132,20 +134,20 @@ hipError_t stencil_direction(const Geom &g, int ty, const T *r, const T *p_old,
 }
 template hipError_t stencil_direction<double>(const Geom &, int, const double *, const double *,
                                               const double *, int, double *, double *, Pair *,
-                                              const int *, hipStream_t);
+                                              const int *, hipStream_t, StepLink);
 template hipError_t stencil_direction<float>(const Geom &, int, const float *, const float *,
                                              const double *, int, float *, float *, Pair *,
-                                             const int *, hipStream_t);
+                                             const int *, hipStream_t, StepLink);
 
 template hipError_t stencil_pair_direction<double>(const Geom &, int, const double *,
                                                    const double *, const double *,
                                                    const double *, const double *, int,
                                                    double *, double *, double *, double *,
-                                                   Pair *, const int *, hipStream_t);
+                                                   Pair *, const int *, hipStream_t, StepLink);
 template hipError_t stencil_pair_direction<float>(const Geom &, int, const float *,
                                                   const float *, const float *, const float *,
                                                   const double *, int, float *, float *,
                                                   float *, float *, Pair *, const int *,
-                                                  hipStream_t);
+                                                  hipStream_t, StepLink);
 
 }  // namespace excmg

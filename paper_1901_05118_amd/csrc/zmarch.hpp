@@ -27,6 +27,7 @@
 
 #include "common.hpp"
 #include "internal.hpp"
+#include "step.hpp"
 
 namespace excmg {
 
@@ -110,6 +111,7 @@ struct InPlain {            // x itself
     static constexpr int R = 1;
     const T *x[2];
     __device__ __forceinline__ void prepare() {}
+    __device__ __forceinline__ bool begin(Pair *) { return true; }
     __device__ __forceinline__ void load(int a, i64 idx, T (&raw)[R]) const { raw[0] = x[a][idx]; }
     __device__ __forceinline__ double combine(const T (&raw)[R]) const { return (double)raw[0]; }
 };
@@ -122,7 +124,16 @@ struct InDirection {        // p_new = r + beta p_old (p_new = r on the first it
     const double *beta_dev; // beta of Algorithm 2, written by the previous finalisation
     int first;
     double beta;
+    StepLink link;          // folded finalisation of the previous sweep B (if link.state)
     __device__ __forceinline__ void prepare() { beta = first ? 0.0 : *beta_dev; }
+    // Called by every thread of the workgroup; returns false when the run has stopped.
+    __device__ __forceinline__ bool begin(Pair *sh) {
+        if (first || link.state == nullptr) {
+            prepare();
+            return true;
+        }
+        return link_step(link, beta, sh);
+    }
     __device__ __forceinline__ void load(int a, i64 idx, T (&raw)[R]) const {
         raw[0] = r[a][idx];
         raw[1] = p[a][idx];
@@ -169,27 +180,28 @@ __device__ __forceinline__ void zmarch_tile(const Geom &g, int tile, const In &i
     // source address (positions outside the grid are clamped and multiplied by 0), so the
     // loads need no branches and can stay in flight.
     int soff[NL];     // source offset inside a plane (row-major, x fastest)
-    double smul[NL];  // in-plane multiplier (0 = boundary node, outside, or unused slot)
+    float smul[NL];   // in-plane multiplier (0 = boundary node, outside, or unused slot),
+                      // exactly 0 or +-1, so single precision holds it in fewer registers
 #pragma unroll
     for (int q = 0; q < NL; q++) {
         int e = tid + q * NT;
-        smul[q] = 0.0;
+        smul[q] = 0.0f;
         soff[q] = 0;
         if (e < LE) {
             int row = e / LS, col = e % LS;
             int sx, sy;
             double mx = reflect(tx * TX + col - 2, n, g.sgn, sx);
             double my = reflect(ty * TY + row - 2, n, g.sgn, sy);
-            smul[q] = mx * my;
+            smul[q] = (float)(mx * my);
             soff[q] = sy * n + sx;
         }
     }
 
     constexpr int R = In::R;
     using Raw = T[NL][NA][R];
-    auto fetch = [&](int m, Raw &raw, double &mz) {
+    auto fetch = [&](int m, Raw &raw, float &mz) {
         int sz;
-        mz = reflect(m, n, g.sgn, sz);
+        mz = (float)reflect(m, n, g.sgn, sz);
 #pragma unroll
         for (int q = 0; q < NL; q++) {
             const i64 idx = (i64)sz * plane + soff[q];
@@ -197,16 +209,16 @@ __device__ __forceinline__ void zmarch_tile(const Geom &g, int tile, const In &i
             for (int a = 0; a < NA; a++) in.load(a, idx, raw[q][a]);
         }
     };
-    auto stash = [&](int b, const Raw &raw, double mz) {
+    auto stash = [&](int b, const Raw &raw, float mz) {
 #pragma unroll
         for (int q = 0; q < NL; q++) {
             const int e = tid + q * NT;
-            const double mul = smul[q] * mz;
+            const float mul = smul[q] * mz;
             if (e < LE) {
 #pragma unroll
                 for (int a = 0; a < NA; a++) {
                     const double v = in.combine(raw[q][a]);
-                    buf[b][a][e] = (T)((mul != 0.0) ? mul * v : 0.0);
+                    buf[b][a][e] = (T)((mul != 0.0f) ? (double)mul * v : 0.0);
                 }
             }
         }
@@ -221,7 +233,7 @@ __device__ __forceinline__ void zmarch_tile(const Geom &g, int tile, const In &i
     constexpr int D = 2;
     const int mbeg = k0 - 2, mend = k1 + 1;
     Raw raw[D];
-    double mz[D];
+    float mz[D];
     fetch(mbeg, raw[0], mz[0]);
     stash(0, raw[0], mz[0]);
 #pragma unroll
@@ -229,8 +241,9 @@ __device__ __forceinline__ void zmarch_tile(const Geom &g, int tile, const In &i
     __syncthreads();
     int cur = 0;
     const int centre = (ly + 2) * LS + (lx + 2);
+    const int col_off = iy * n + ix;    // in-plane offset of this lane's column (n < 2^15)
     // consume plane m from LDS, stage plane m+1 from `r`, refill `r` with plane m+1+D
-    auto body = [&](int m, Raw &r, double &z) {
+    auto body = [&](int m, Raw &r, float &z) {
         double y[NA], c0[NA], cprev[NA];
 #pragma unroll
         for (int a = 0; a < NA; a++) {
@@ -238,9 +251,9 @@ __device__ __forceinline__ void zmarch_tile(const Geom &g, int tile, const In &i
             y[a] = column_step<LS, T>(col[a], &buf[cur][a][centre], c0[a]);
         }
         if (valid) {
-            if (m >= k0 && m < k1) out.centre((i64)m * plane + (i64)iy * n + ix, c0);
+            if (m >= k0 && m < k1) out.centre((i64)m * plane + col_off, c0);
             const int k = m - 2;
-            if (k >= k0 && k < k1) out.emit((i64)k * plane + (i64)iy * n + ix, y, cprev);
+            if (k >= k0 && k < k1) out.emit((i64)k * plane + col_off, y, cprev);
         }
         stash(cur ^ 1, r, z);
         fetch(min(m + 1 + D, mend), r, z);
@@ -260,9 +273,13 @@ __device__ __forceinline__ void zmarch_tile(const Geom &g, int tile, const In &i
 template <int NA, int TY, typename T, class In, class Out>
 __global__ void __launch_bounds__(kWave *TY) zmarch(Geom g, In in_arg, Out out) {
     __shared__ Pair red[4 * TY];
-    if (out.skip()) return;
+    __shared__ int s_skip;
+    // one decision per workgroup (a folded finalisation may publish a new status meanwhile)
+    if (threadIdx.x == 0 && threadIdx.y == 0) s_skip = out.skip() ? 1 : 0;
+    __syncthreads();
+    if (s_skip) return;
     In in = in_arg;
-    in.prepare();
+    if (!in.begin(red)) return;
     const int tile = xcd_tile(blockIdx.x, g.ntiles);
     if (tile < g.ntiles) zmarch_tile<NA, TY, T>(g, tile, in, out);
     out.finish(blockIdx.x, red);  // padding blocks of the XCD-aware grid contribute zero
