@@ -55,6 +55,14 @@ extern "C" {
 #define EXCMG_FP64 0          /* everything in FP64                                        */
 #define EXCMG_MIXED 1         /* FP32 Bi-CG inside an FP64 iterative-refinement loop       */
 
+/* How the mixed path refines (excmg_opts.refine). */
+#define EXCMG_RELIABLE 0      /* one FP32 Bi-CG run per level; whenever its recurrence       */
+                              /* residual has dropped by inner_tol, the FP64 residual         */
+                              /* b - A u replaces it and the run goes on with the same        */
+                              /* search directions (residual replacement)                     */
+#define EXCMG_RESTART 1       /* classic refinement: each step solves A e = r from e = 0 to  */
+                              /* the relative tolerance inner_tol, then u += e               */
+
 /* Level solver. */
 #define EXCMG_BICG 0          /* Algorithm 2 as printed: both A p and A^T p* every iteration */
 #define EXCMG_CG 1            /* its symmetric specialisation: A_h = A_h^T and r*_0 = r_0 make */
@@ -72,18 +80,22 @@ typedef struct excmg_opts {
     double tol;         /* relative-residual tolerance eps of the finest level (> 0)       */
     int max_iters;      /* Bi-CG iterations per run (0: 100000)                             */
     int max_runs;       /* Bi-CG runs per level in Algorithm 1's while loop (0: 5)          */
-    double inner_tol;   /* mixed precision: relative tolerance of each FP32 solve (0: 1e-4) */
+    double inner_tol;   /* mixed precision: residual reduction per refinement step        */
+                        /* (0: 0.1 with EXCMG_RELIABLE, 1e-4 with EXCMG_RESTART)           */
     int max_outer;      /* mixed precision: refinement steps per level (0: 60)             */
     int batch_mode;     /* excmg_solve_batch: 0 = four graph-captured phase launches per    */
                         /* Bi-CG step, 1 = one persistent work-queue launch per step        */
     int method;         /* EXCMG_BICG (default) or EXCMG_CG (excmg_solve_ex only)           */
+    int refine;         /* mixed precision: EXCMG_RELIABLE (default) or EXCMG_RESTART;     */
+                        /* excmg_solve_batch always restarts                                */
 } excmg_opts;
 
 /* Per-level record filled by excmg_solve_ex (levels 0 and 1 report iterations = 0). */
 typedef struct excmg_level_stats {
     int n;              /* cells per axis                                                    */
     int iterations;     /* Bi-CG iterations (all runs; FP32 inner iterations when mixed)     */
-    int runs;           /* Bi-CG runs (FP64) or refinement steps (mixed)                     */
+    int runs;           /* Bi-CG runs (FP64) or refinement steps (mixed: FP64 residual     */
+                        /* replacements, or restarted FP32 solves)                           */
     int status;         /* EXCMG_OK / EXCMG_ENOCONV / EXCMG_EBREAKDOWN                        */
     double eps;         /* tolerance of the level                                             */
     double rel_residual;/* final true ||b - A x||_2 / ||b||_2                                 */

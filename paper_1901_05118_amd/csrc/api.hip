@@ -145,6 +145,7 @@ struct Ctx {
     std::vector<Level> lv;
     // Bi-CG workspace (sized for the finest level)
     DBuf r, rs, p[2], ps[2], q, qs;
+    DBuf ubest;                 // best FP64 iterate of a level solved with residual replacement
     DBuf part_a, part_b;        // Dot2 partials of the two sweeps
     DBuf state;                 // BicgState
     DBuf scal;                  // misc device scalars
@@ -163,7 +164,7 @@ struct Ctx {
         lv.clear();
         r.release(); rs.release();
         p[0].release(); p[1].release(); ps[0].release(); ps[1].release();
-        q.release(); qs.release();
+        q.release(); qs.release(); ubest.release();
         part_a.release(); part_b.release(); state.release(); scal.release();
         chol[0].release(); chol[1].release(); chol_y.release(); info.release(); vz1.release();
         if (host_state) (void)hipHostFree(host_state);
@@ -278,6 +279,7 @@ int setup(int n_finest, int n_levels, int bc) {
     CKR(c.ps[1].ensure(vb));
     CKR(c.q.ensure(vb));
     CKR(c.qs.ensure(vb));
+    CKR(c.ubest.ensure((size_t)F.nu * 8));
     int maxblk = 4096 * 2;
     for (auto &L : c.lv)
         maxblk = std::max({maxblk, stencil_blocks(L.g1), stencil_blocks(L.g2), stencil_blocks(L.g2f)});
@@ -469,22 +471,27 @@ int window_graph(const Level &L, TX *x, int K, hipGraphExec_t *out) {
 // Iterations of Algorithm 2 on level L after bicg_start: the Bi-CG vectors r, r*, p, p*, q, q*
 // have type T, the iterate x type TX.  Every kernel returns at once when the run has stopped,
 // so the host issues K iterations between two polls of the state: directly, or (in solves)
-// as the replay of a captured K-iteration graph after the first iteration.
+// as the replay of a captured K-iteration graph after the first iteration.  j is the index
+// of the next iteration (0 starts the run; a run resumed after its residuals were replaced
+// continues at the j it stopped at, with its search directions).
 template <typename TX, typename T>
-int bicg_iterate(const Level &L, TX *x, BicgState &hs) {
+int bicg_iterate(const Level &L, TX *x, BicgState &hs, long long &j) {
     int K = poll_interval(L.nu);
     K += K & 1;
     if (g_timing) CKR(ensure_events(4 * (size_t)K));
     const bool graphs = g_graphs && !g_timing;
     hipGraphExec_t exec = nullptr;
     if (graphs) CKR((window_graph<TX, T>(L, x, K, &exec)));
-    long long j = 0;
     while (hs.status == kRunning) {
         const int it0 = hs.iter;
         if (graphs) {
-            if (j == 0) CKR((launch_iteration<TX, T>(L, x, 0, -1, g_stream)));
+            // the captured window holds iterations of odd index first
+            if (j == 0 || (j & 1) == 0) {
+                CKR((launch_iteration<TX, T>(L, x, j, -1, g_stream)));
+                j++;
+            }
             CKH(hipGraphLaunch(exec, g_stream));
-            j += (j == 0 ? 1 : 0) + K;
+            j += K;
         } else {
             for (int t = 0; t < K; t++, j++)
                 CKR((launch_iteration<TX, T>(L, x, j, g_timing ? t : -1, g_stream)));
@@ -520,7 +527,8 @@ int bicg_run(const Level &L, const double *b, double *x, double eps, int maxit, 
     CKH(bicg_start(S, c.part_a.as<Pair>(), stencil_blocks(L.g1), eps, maxit, g_stream));
     BicgState hs;
     CKR(read_state(hs));
-    CKR((bicg_iterate<double, double>(L, x, hs)));
+    long long j = 0;
+    CKR((bicg_iterate<double, double>(L, x, hs, j)));
     if (iters) *iters = hs.iter;
     if (rr_out) *rr_out = hs.rr;
     if (status_out) *status_out = hs.status;
@@ -588,7 +596,8 @@ int bicg_inner_fp32(const Level &L, double *u, double inner_tol, int maxit, int 
     CKH(bicg_start(S, c.part_b.as<Pair>(), nvb, inner_tol, maxit, g_stream));
     BicgState hs;
     CKR(read_state(hs));
-    CKR((bicg_iterate<double, float>(L, u, hs)));
+    long long j = 0;
+    CKR((bicg_iterate<double, float>(L, u, hs, j)));
     if (iters) *iters = hs.iter;
     if (status_out) *status_out = hs.status;
     return EXCMG_OK;
@@ -642,6 +651,108 @@ int level_solve_mixed(const Level &L, const double *b, double *u, double eps, in
     return EXCMG_OK;
 }
 
+// Mixed precision with residual replacement (reliable updates).  An FP32 Bi-CG run for
+// A e = r adds its correction directly into the FP64 iterate u (sweep B).  Whenever the
+// run's recurrence residual has fallen by the factor delta since the last replacement (or
+// below half the target), the FP64 residual b - A u replaces r and r* (rounded to FP32),
+// rho is taken from the new vectors and the run goes on with its search directions:
+// unlike restarted refinement, the Krylov space built so far is kept.  The best iterate so
+// far is kept aside: if a stretch of the run made the FP64 residual larger (or a run that
+// has been replaced into breaks down), u goes back to it and a fresh run starts from there
+// (a breakdown of a fresh run is reported).  Stops when ||b - A u||_2 <= eps ||b||_2 in FP64,
+// when two replacements in a row fail to halve the squared residual, or at the caps.
+int level_solve_reliable(const Level &L, const double *b, double *u, double eps, int maxit,
+                         int max_outer, double delta, excmg_level_stats *st) {
+    Ctx &c = g_ctx;
+    BicgState *S = c.state.as<BicgState>();
+    double *sc = c.scal.as<double>(), *ub = c.ubest.as<double>();
+    float *r = c.r.as<float>(), *rs = c.rs.as<float>();
+    const int nrb = stencil_blocks(L.g1), nvb = vec_blocks(L.nu);
+    const size_t ubytes = (size_t)L.nu * 8;
+    CKR(device_dot(L.nu, b, b, sc, 1));
+    // FP64 residual of u (rounded into r and r*), its square norm, and b.b
+    auto true_residual = [&](double &bb, double &rr) -> int {
+        CKH(stencil_residual_cast(L.g1, L.g1.ty, b, u, r, rs, c.part_a.as<Pair>(), g_stream));
+        CKH(reduce_to(sc, c.part_a.as<Pair>(), nrb, 2, g_stream));
+        CKH(hipMemcpyAsync(c.host_scal, sc, 3 * sizeof(double), hipMemcpyDeviceToHost, g_stream));
+        CKH(hipStreamSynchronize(g_stream));
+        bb = c.host_scal[1];
+        rr = c.host_scal[2];
+        return EXCMG_OK;
+    };
+    double bb = 0.0, rr = 0.0;
+    CKR(true_residual(bb, rr));
+    const double target = (eps * eps) * bb;
+    int status = EXCMG_OK, replaced = 0, iters = 0, done = 0, weak = 0;
+    BicgState hs;
+    long long j = 0;
+    int since_start = 0;  // replacements in the current run
+    // fresh run on the current residual: rho_0 = r.r of the FP32 copy
+    auto start_run = [&]() -> int {
+        CKH(dot_partials<float>(L.nu, r, r, c.part_b.as<Pair>(), nvb, g_stream));
+        CKH(reduce_to((double *)&S->bb, c.part_b.as<Pair>(), nvb, 0, g_stream));
+        CKH(bicg_start(S, c.part_b.as<Pair>(), nvb, delta, std::max(1, maxit - done), g_stream));
+        CKH(state_resume(S, std::max((delta * delta) * rr, 0.25 * target), g_stream));
+        CKR(read_state(hs));
+        j = 0;
+        since_start = 0;
+        return EXCMG_OK;
+    };
+    if (!(rr <= target)) {
+        CKH(hipMemcpyAsync(ub, u, ubytes, hipMemcpyDeviceToDevice, g_stream));
+        CKR(start_run());
+        double best = rr;
+        for (;;) {
+            CKR((bicg_iterate<double, float>(L, u, hs, j)));
+            iters = done + hs.iter;
+            const bool broke = (hs.status == kBreakdown);
+            CKR(true_residual(bb, rr));
+            if (rr <= target) break;
+            const bool better = std::isfinite(rr) && rr < best;
+            weak = (better && rr < 0.5 * best) ? 0 : weak + 1;
+            if (better) {
+                best = rr;
+                CKH(hipMemcpyAsync(ub, u, ubytes, hipMemcpyDeviceToDevice, g_stream));
+            } else {
+                // back to the best iterate; r and r* again hold its residual
+                CKH(hipMemcpyAsync(u, ub, ubytes, hipMemcpyDeviceToDevice, g_stream));
+                CKR(true_residual(bb, rr));
+                if (broke && since_start == 0) {
+                    status = EXCMG_EBREAKDOWN;
+                    break;
+                }
+            }
+            if ((!broke && hs.status == kNoConv) || iters >= maxit || replaced >= max_outer ||
+                weak >= 2) {
+                status = EXCMG_ENOCONV;
+                break;
+            }
+            replaced++;
+            if (broke || !better) {
+                done = iters;
+                CKR(start_run());
+                continue;
+            }
+            since_start++;
+            CKH(rho_partials<float>(L.nu, r, rs, c.part_b.as<Pair>(), g_stream));
+            CKH(state_resume(S, std::max((delta * delta) * rr, 0.25 * target), g_stream));
+            CKR(read_state(hs));
+            // the run stopped inside the last window: go on from the iteration it reached
+            // (that index selects the direction buffers and the rho slots)
+            j = hs.iter;
+        }
+    }
+    if (st) {
+        st->n = L.N;
+        st->iterations = iters;
+        st->runs = replaced;
+        st->status = status;
+        st->eps = eps;
+        st->rel_residual = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+    }
+    return EXCMG_OK;
+}
+
 double level_tolerance(double tol, int i, int L) {
     double p = 1.0;
     for (int t = 0; t < L - i; t++) p *= 10.0;
@@ -649,7 +760,7 @@ double level_tolerance(double tol, int i, int L) {
 }
 
 // Algorithm 1.  f, g1, g2 are device node arrays of the finest grid.  Bi-CG levels run in
-// FP64 or as FP32 Bi-CG inside FP64 iterative refinement (opts.precision).
+// FP64 or as FP32 Bi-CG inside FP64 iterative refinement (opts.precision, opts.refine).
 int solve_cascade(const excmg_opts &o, const double *f, const double *g1, const double *g2,
                   double *u_out, double *ut_out, excmg_stats *st) {
     Ctx &c = g_ctx;
@@ -658,7 +769,8 @@ int solve_cascade(const excmg_opts &o, const double *f, const double *g1, const 
     const int maxit = o.max_iters > 0 ? o.max_iters : 100000;
     const int max_runs = o.max_runs > 0 ? o.max_runs : 5;
     const int max_outer = o.max_outer > 0 ? o.max_outer : 60;
-    const double inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-4;
+    const bool reliable = (o.refine == EXCMG_RELIABLE) && g_fold;
+    const double inner_tol = o.inner_tol > 0 ? o.inner_tol : (reliable ? 0.1 : 1e-4);
     const bool mixed = (o.precision == EXCMG_MIXED);
     hipEvent_t ev0, ev1, evl0, evl1;
     CKH(hipEventCreate(&ev0));
@@ -683,7 +795,10 @@ int solve_cascade(const excmg_opts &o, const double *f, const double *g1, const 
                            c.vz1.as<double>(), Lv.u.as<double>(), g_stream));
             CKH(from_nodes(Lv.N, Lv.u.as<double>(), Lv.x.as<double>(), g_stream));
             const double eps = level_tolerance(o.tol, l - 1, L);
-            if (mixed)
+            if (mixed && reliable)
+                CKR(level_solve_reliable(Lv, Lv.b.as<double>(), Lv.x.as<double>(), eps, maxit,
+                                         max_outer, inner_tol, &ls));
+            else if (mixed)
                 CKR(level_solve_mixed(Lv, Lv.b.as<double>(), Lv.x.as<double>(), eps, maxit,
                                       max_outer, inner_tol, &ls));
             else
@@ -1316,6 +1431,8 @@ int excmg_solve_ex(const excmg_opts *opts, const double *f, const double *g1, co
         return fail(EXCMG_EINVAL, "precision %d not supported", o.precision);
     if (o.method != EXCMG_BICG && o.method != EXCMG_CG)
         return fail(EXCMG_EINVAL, "method %d not supported", o.method);
+    if (o.refine != EXCMG_RELIABLE && o.refine != EXCMG_RESTART)
+        return fail(EXCMG_EINVAL, "refine %d not supported", o.refine);
     CKR(setup(o.n_finest, o.n_levels, o.bc_kind));
     const size_t nb = (size_t)(o.n_finest + 1) * (o.n_finest + 1) * (o.n_finest + 1) * 8;
     Arg af(f, nb), a1(g1, nb), a2(g2, nb), au(u_out, nb), at(ut_out, nb);

@@ -97,6 +97,11 @@ hipError_t cg_beta(BicgState *s, const Pair *part, int count, hipStream_t st);
 // the end-of-iteration checks of a folded step as a kernel of its own (one workgroup), run
 // before the host reads the state
 hipError_t step_check(StepLink link, hipStream_t st);
+// partials of rs.r and r.r in the layout of bicg_update's (after a residual replacement)
+template <typename T>
+hipError_t rho_partials(long long n, const T *r, const T *rs, Pair *partials, hipStream_t st);
+// status = running (or iteration cap), thr = new recurrence threshold
+hipError_t state_resume(BicgState *s, double thr, hipStream_t st);
 
 // partials of x.y
 template <typename T>

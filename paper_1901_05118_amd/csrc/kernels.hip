@@ -72,6 +72,7 @@ template hipError_t bicg_update<double, float>(long long, const BicgState *, dou
                                                const float *, float *, const float *, float *,
                                                const float *, Pair *, hipStream_t, StepLink);
 
+
 // CG sweep B: the primal half of the Bi-CG update (the shadow half repeats it bit for bit
 // when r*_0 = r_0), and the partials of r.r, which is also rho of the next iteration.
 template <typename TX, typename T>
@@ -113,6 +114,48 @@ template hipError_t cg_update<double, double>(long long, const BicgState *, doub
 template hipError_t cg_update<double, float>(long long, const BicgState *, double *,
                                              const float *, float *, const float *, Pair *,
                                              hipStream_t, StepLink);
+
+// Partials of r*.r and r.r with the block layout of the Bi-CG update kernels, for a run
+// whose residuals were just replaced (its next sweep A merges them as the rho of the step).
+template <typename T>
+__global__ void __launch_bounds__(kVecThreads)
+    k_rho_partials(long long n, const T *r, const T *rs, Pair *partials) {
+    __shared__ Pair sh[2 * (kVecThreads / kWave)];
+    Pair acc[2] = {{0.0, 0.0}, {0.0, 0.0}};
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        dot2_acc(acc[0], (double)rs[i], (double)r[i]);
+        dot2_acc(acc[1], (double)r[i], (double)r[i]);
+    }
+    block_merge<2>(acc, sh);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = acc[0];
+        partials[gridDim.x + blockIdx.x] = acc[1];
+    }
+}
+
+template <typename T>
+hipError_t rho_partials(long long n, const T *r, const T *rs, Pair *partials, hipStream_t st) {
+    hipLaunchKernelGGL(k_rho_partials<T>, dim3(vec_blocks(n)), dim3(kVecThreads), 0, st, n, r,
+                       rs, partials);
+    return hipGetLastError();
+}
+template hipError_t rho_partials<float>(long long, const float *, const float *, Pair *,
+                                        hipStream_t);
+
+// Let a stopped run go on: running again (unless at its iteration cap), with a new
+// stopping threshold for the recurrence residual.
+__global__ void k_state_resume(BicgState *s, double thr) {
+    if (threadIdx.x == 0) {
+        s->thr = thr;
+        s->status = (s->iter >= s->maxit) ? kNoConv : kRunning;
+    }
+}
+
+hipError_t state_resume(BicgState *s, double thr, hipStream_t st) {
+    hipLaunchKernelGGL(k_state_resume, dim3(1), dim3(kWave), 0, st, s, thr);
+    return hipGetLastError();
+}
 
 __global__ void __launch_bounds__(kReduceThreads) k_step_check(StepLink link) {
     __shared__ Pair sh[2 * (kReduceThreads / kWave)];

@@ -14,7 +14,7 @@ import numpy as np
 
 __all__ = [
     "ExcmgError", "OK", "EINVAL", "ENOMEM", "ENOCONV", "EBREAKDOWN", "EHIP", "FP64", "MIXED",
-    "BICG", "CG",
+    "BICG", "CG", "RELIABLE", "RESTART",
     "lib_path", "load", "set_stream", "setup", "apply_stencil", "apply_operator", "rhs", "dsolve", "bicg",
     "level_solve", "exp_finite", "exp_true", "solve", "solve_ex", "profile_sweep",
     "set_shape", "get_shape", "set_timing", "get_timing", "autotune", "solve_batch",
@@ -27,6 +27,7 @@ __all__ = [
 OK, EINVAL, ENOMEM, ENOCONV, EBREAKDOWN, EHIP = 0, -1, -2, -3, -4, -5
 FP64, MIXED = 0, 1
 BICG, CG = 0, 1
+RELIABLE, RESTART = 0, 1
 MAX_LEVELS = 16
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -45,7 +46,7 @@ class Opts(ctypes.Structure):
                 ("tol", ctypes.c_double), ("max_iters", ctypes.c_int),
                 ("max_runs", ctypes.c_int), ("inner_tol", ctypes.c_double),
                 ("max_outer", ctypes.c_int), ("batch_mode", ctypes.c_int),
-                ("method", ctypes.c_int)]
+                ("method", ctypes.c_int), ("refine", ctypes.c_int)]
 
 
 class LevelStats(ctypes.Structure):
@@ -228,10 +229,11 @@ def solve(n_finest: int, n_levels: int, bc_kind: int, f, g1, g2, tol: float, u_o
 
 def solve_ex(n_finest: int, n_levels: int, bc_kind: int, f, g1, g2, tol: float, u_out,
              ut_out=None, precision: int = FP64, max_iters: int = 0, max_runs: int = 0,
-             inner_tol: float = 0.0, max_outer: int = 0, method: int = BICG):
+             inner_tol: float = 0.0, max_outer: int = 0, method: int = BICG,
+             refine: int = RELIABLE):
     """Algorithm 1 with options.  Returns (code, Stats)."""
     o = Opts(n_finest, n_levels, bc_kind, precision, tol, max_iters, max_runs, inner_tol,
-             max_outer, 0, method)
+             max_outer, 0, method, refine)
     st = Stats()
     rc = load().excmg_solve_ex(ctypes.byref(o), _ptr(f, name="f"), _ptr(g1, name="g1"),
                                _ptr(g2, name="g2"), _ptr(u_out, name="u_out"),
@@ -264,7 +266,7 @@ def solve_batch(problems, tol: float, precision: int = FP64, max_iters: int = 0,
                          _ptr(p["f"], name="f"), _ptr(p["g1"], name="g1"), _ptr(p["g2"], name="g2"),
                          _ptr(p["u_out"], name="u_out"), _ptr(p.get("ut_out"), name="ut_out"))
     o = Opts(0, 0, 0, precision, tol, max_iters, max_runs, inner_tol, max_outer,
-             1 if persistent else 0, BICG)
+             1 if persistent else 0, BICG, RESTART)
     st = (Stats * n)()
     rc = load().excmg_solve_batch(n, arr, ctypes.byref(o), st)
     if rc not in (OK, ENOCONV, EBREAKDOWN):

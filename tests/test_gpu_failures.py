@@ -59,14 +59,17 @@ def test_tolerance_below_the_fp64_floor_stops(ex):
     assert rc == ex.ENOCONV
     last = st.levels()[-1]
     assert last["runs"] == 3 and last["rel_residual"] > 1e-14
-    rc, st = ex.solve_ex(32, 3, 1, f, g1, g2, 1e-14, u, precision=ex.MIXED)
-    assert rc == ex.ENOCONV   # refinement stops when an outer step no longer helps
+    for mode in (ex.RELIABLE, ex.RESTART):
+        # refinement stops when a step no longer reduces the FP64 residual
+        rc, st = ex.solve_ex(32, 3, 1, f, g1, g2, 1e-14, u, precision=ex.MIXED, refine=mode)
+        assert rc == ex.ENOCONV
+        assert st.levels()[-1]["rel_residual"] < 1e-9
 
 
 def test_solves_are_deterministic(ex):
     arr, f, g1, g2 = _inputs(3, 48, 2)
     outs = []
-    for prec in (ex.FP64, ex.FP64, ex.MIXED, ex.MIXED):
+    for prec in (ex.FP64, ex.FP64, ex.MIXED, ex.MIXED):  # mixed: reliable updates
         u = torch.empty_like(f)
         rc, st = ex.solve_ex(48, 5, 2, f, g1, g2, 1e-9, u, precision=prec)
         assert rc == ex.OK

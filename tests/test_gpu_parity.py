@@ -276,22 +276,31 @@ def test_batch_mixed_meets_tolerance_and_accuracy(ex):
         e_fp64 = O.norm2(ref.u - arr.u)
         assert abs(e_mixed - e_fp64) <= 0.01 * e_fp64
         single = torch.empty_like(f)
-        rc1, st1 = ex.solve_ex(N, nl, bc, f, g1, g2, 1e-8, single, precision=ex.MIXED)
+        # the batch path refines by restarted FP32 solves
+        rc1, st1 = ex.solve_ex(N, nl, bc, f, g1, g2, 1e-8, single, precision=ex.MIXED,
+                               refine=ex.RESTART)
         assert [l["iterations"] for l in st.levels()] == [l["iterations"] for l in st1.levels()]
         np.testing.assert_array_equal(u.ravel(), host(single).ravel())
 
 
-def test_mixed_solve_config1_meets_tolerance(ex):
-    arr = make_arrays(config_problem(1), 32, 1)
+@pytest.mark.parametrize("refine", ["reliable", "restart"])
+@pytest.mark.parametrize("case", [(32, 4, 1, 1, 1e-10), (64, 5, 2, 2, 1e-9)])
+def test_mixed_solve_meets_tolerance(ex, refine, case):
+    """Both refinement forms: the oracle's FP64 residual of the returned solution meets the
+    tolerance, and its error against the exact solution is within 1% of the FP64 solve's."""
+    N, nl, bc, c, tol = case
+    arr = make_arrays(config_problem(c), N, bc)
     f, g1, g2 = dev(arr.f), dev(arr.g1), dev(arr.g2)
     u = torch.empty_like(f)
-    rc, st = ex.solve_ex(32, 4, 1, f, g1, g2, 1e-10, u, precision=ex.MIXED)
+    mode = ex.RELIABLE if refine == "reliable" else ex.RESTART
+    rc, st = ex.solve_ex(N, nl, bc, f, g1, g2, tol, u, precision=ex.MIXED, refine=mode)
     assert rc == ex.OK, ex.last_error()
-    ug = host(u).reshape((33,) * 3)
-    b = O.rhs(32, 1, arr.f, arr.g1, arr.g2)
-    r = O.residual(32, 1, b, O.interior(ug))
-    assert np.sqrt(O.dot(r, r) / O.dot(b, b)) <= 1e-10
-    ref = O.excmg(32, 4, 1, arr.f, arr.g1, arr.g2, 1e-10)
+    print(refine, [(l["iterations"], l["runs"]) for l in st.levels()], flush=True)
+    ug = host(u).reshape((N + 1,) * 3)
+    b = O.rhs(N, bc, arr.f, arr.g1, arr.g2)
+    r = O.residual(N, bc, b, O.interior(ug))
+    assert np.sqrt(O.dot(r, r) / O.dot(b, b)) <= tol
+    ref = O.excmg(N, nl, bc, arr.f, arr.g1, arr.g2, tol)
     assert abs(O.norm2(ug - arr.u) - O.norm2(ref.u - arr.u)) <= 0.01 * O.norm2(ref.u - arr.u)
 
 
@@ -313,18 +322,21 @@ def test_autotuned_shape_keeps_results(ex):
 
 # ------------------------------------------------------------------ CG specialisation
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed-restart"])
 @pytest.mark.parametrize("case", [(32, 4, 1, 1), (48, 5, 2, 2)])
 def test_cg_specialisation_is_bit_identical_to_bicg(ex, prec, case):
     """With A_h = A_h^T and r*_0 = r_0 the shadow vectors of Algorithm 2 equal the primal
     ones, so the CG form (one operator product per iteration) reproduces Bi-CG exactly."""
     N, nl, bc, c = case
     p = ex.FP64 if prec == "fp64" else ex.MIXED
+    mode = ex.RESTART if prec == "mixed-restart" else ex.RELIABLE
     arr = make_arrays(config_problem(c), N, bc)
     f, g1, g2 = dev(arr.f), dev(arr.g1), dev(arr.g2)
     u_b, u_c = torch.empty_like(f), torch.empty_like(f)
-    rc1, st1 = ex.solve_ex(N, nl, bc, f, g1, g2, 1e-9, u_b, precision=p, method=ex.BICG)
-    rc2, st2 = ex.solve_ex(N, nl, bc, f, g1, g2, 1e-9, u_c, precision=p, method=ex.CG)
+    rc1, st1 = ex.solve_ex(N, nl, bc, f, g1, g2, 1e-9, u_b, precision=p, method=ex.BICG,
+                           refine=mode)
+    rc2, st2 = ex.solve_ex(N, nl, bc, f, g1, g2, 1e-9, u_c, precision=p, method=ex.CG,
+                           refine=mode)
     assert rc1 == rc2 == ex.OK
     assert [l["iterations"] for l in st1.levels()] == [l["iterations"] for l in st2.levels()]
     np.testing.assert_array_equal(host(u_b), host(u_c))
