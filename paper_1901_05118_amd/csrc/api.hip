@@ -152,8 +152,9 @@ struct Ctx {
     DBuf chol[2], chol_y;       // Cholesky factors of levels 0 and 1, solve scratch
     DBuf info;
     DBuf vz1;                   // EXP_finite Z1 scratch
-    BicgState *host_state = nullptr;  // pinned
+    BicgState *host_state = nullptr;  // pinned; 3 slots (synchronous reads, pipelined polls)
     double *host_scal = nullptr;      // pinned
+    hipEvent_t poll_ev[2] = {nullptr, nullptr};
     void release() {
         release_graphs();
         for (auto &L : lv) {
@@ -168,6 +169,10 @@ struct Ctx {
         part_a.release(); part_b.release(); state.release(); scal.release();
         chol[0].release(); chol[1].release(); chol_y.release(); info.release(); vz1.release();
         if (host_state) (void)hipHostFree(host_state);
+        for (hipEvent_t &e : poll_ev) {
+            if (e) (void)hipEventDestroy(e);
+            e = nullptr;
+        }
         if (host_scal) (void)hipHostFree(host_scal);
         host_state = nullptr;
         host_scal = nullptr;
@@ -290,7 +295,8 @@ int setup(int n_finest, int n_levels, int bc) {
     CKR(c.info.ensure(64));
     const long long nz1 = (long long)(n_finest / 2 + 1) * (n_finest / 2 + 1) * (n_finest / 2 + 1);
     CKR(c.vz1.ensure((size_t)nz1 * 8));
-    CKH(hipHostMalloc((void **)&c.host_state, sizeof(BicgState), hipHostMallocDefault));
+    CKH(hipHostMalloc((void **)&c.host_state, 3 * sizeof(BicgState), hipHostMallocDefault));
+    for (hipEvent_t &e : c.poll_ev) CKH(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     CKH(hipHostMalloc((void **)&c.host_scal, 64 * sizeof(double), hipHostMallocDefault));
     // Cholesky factors of the two direct levels (depend only on the grid and bc kind)
     for (int l = 0; l < 2; l++) {
@@ -482,6 +488,31 @@ int bicg_iterate(const Level &L, TX *x, BicgState &hs, long long &j) {
     const bool graphs = g_graphs && !g_timing;
     hipGraphExec_t exec = nullptr;
     if (graphs) CKR((window_graph<TX, T>(L, x, K, &exec)));
+    if (graphs && K <= 16 && hs.status == kRunning) {
+        // Short windows (large grids): queue window w+1 before reading the state of window
+        // w, so the device never waits for the host.  The window after the one that stopped
+        // the run consists of no-op launches.
+        Ctx &c = g_ctx;
+        if (j == 0 || (j & 1) == 0) {
+            CKR((launch_iteration<TX, T>(L, x, j, -1, g_stream)));
+            j++;
+        }
+        auto queue_window = [&](int slot) -> int {
+            CKH(hipGraphLaunch(exec, g_stream));
+            CKH(hipMemcpyAsync(c.host_state + 1 + slot, c.state.p, sizeof(BicgState),
+                               hipMemcpyDeviceToHost, g_stream));
+            CKH(hipEventRecord(c.poll_ev[slot], g_stream));
+            j += K;
+            return EXCMG_OK;
+        };
+        CKR(queue_window(0));
+        for (int w = 0;; w++) {
+            CKR(queue_window((w + 1) & 1));
+            CKH(hipEventSynchronize(c.poll_ev[w & 1]));
+            if (c.host_state[1 + (w & 1)].status != kRunning) break;
+        }
+        return read_state(hs);
+    }
     while (hs.status == kRunning) {
         const int it0 = hs.iter;
         if (graphs) {
