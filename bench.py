@@ -29,6 +29,7 @@ HBM_PEAK_GBS = 8000.0
 # only while these are unchanged
 SWEEP_A_SOURCES = ["paper_1901_05118_amd/csrc/common.hpp",
                    "paper_1901_05118_amd/csrc/internal.hpp",
+                   "paper_1901_05118_amd/csrc/step.hpp",
                    "paper_1901_05118_amd/csrc/zmarch.hpp",
                    "paper_1901_05118_amd/csrc/stencil.hip"]
 
