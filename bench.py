@@ -25,10 +25,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Bi-CG stencil GLUPS & HBM GB/s; time-to-1e-8 residual, FP64 vs mixed"
 HBM_PEAK_GBS = 8000.0
-# sources of the z-marched stencil kernels: a stored counter measurement of sweep A holds
-# only while these are unchanged
+# sources that define the z-marched stencil kernels: a stored counter measurement of sweep A
+# holds only while these are unchanged
 SWEEP_A_SOURCES = ["paper_1901_05118_amd/csrc/common.hpp",
-                   "paper_1901_05118_amd/csrc/internal.hpp",
                    "paper_1901_05118_amd/csrc/step.hpp",
                    "paper_1901_05118_amd/csrc/zmarch.hpp",
                    "paper_1901_05118_amd/csrc/stencil.hip"]

@@ -398,7 +398,7 @@ int launch_iteration(const Level &L, TX *x, long long j, int ev, hipStream_t st)
     T *r = c.r.as<T>(), *rs = c.rs.as<T>(), *q = c.q.as<T>(), *qs = c.qs.as<T>();
     const Geom &G = sizeof(T) == 4 ? L.g2f : L.g2;
     const int nsb = stencil_blocks(G);
-    const int nvb = vec_blocks(L.nu);
+    const int nvb = update_blocks(L.nu);
     const int cur = (int)(j & 1), nxt = cur ^ 1;
     T *pn = c.p[nxt].as<T>(), *psn = c.ps[nxt].as<T>();
     // folded: sweep A merges the previous sweep B's partials (rho, r.r, beta, stopping
@@ -438,7 +438,7 @@ template <typename T>
 int close_window(const Level &L, long long j_next, hipStream_t st) {
     if (!g_fold) return EXCMG_OK;
     Ctx &c = g_ctx;
-    const StepLink l{c.state.as<BicgState>(), c.part_b.as<Pair>(), vec_blocks(L.nu), g_cg ? 1 : 2,
+    const StepLink l{c.state.as<BicgState>(), c.part_b.as<Pair>(), update_blocks(L.nu), g_cg ? 1 : 2,
                      (int)(j_next & 1)};
     CKH(step_check(l, st));
     return EXCMG_OK;

@@ -81,6 +81,7 @@ inline int stencil_blocks(const Geom &g) { return xcd_grid(g.ntiles); }
 // ---------------------------------------------------------------- vector kernels
 
 int vec_blocks(long long n);
+int update_blocks(long long n);   // workgroups (= partial pairs per value) of the Bi-CG updates
 
 // x += (scale*alpha) p; r -= alpha q; rs -= alpha qs; partials of rs.r and r.r.  x may be
 // held in higher precision than the other vectors (FP64 iterate, FP32 Bi-CG vectors).

@@ -18,6 +18,17 @@ int vec_blocks(long long n) {
     return (int)b;
 }
 
+// Bi-CG updates: fewer, larger workgroups (their partials are merged again by every
+// workgroup of the next sweep A).
+constexpr int kUpdateThreads = 512;
+
+int update_blocks(long long n) {
+    long long b = (n + kUpdateThreads * 4 - 1) / (kUpdateThreads * 4);
+    if (b < 1) b = 1;
+    if (b > 1024) b = 1024;
+    return (int)b;
+}
+
 // ------------------------------------------------------------------ Bi-CG updates
 
 // Algorithm 2: x_{k+1} = x_k + alpha p_k, r_{k+1} = r_k - alpha A p_k,
@@ -26,10 +37,10 @@ int vec_blocks(long long n) {
 // the FP64 solution directly).
 // With a StepLink the kernel first merges sweep A's partials itself (sigma, alpha).
 template <typename TX, typename T>
-__global__ void __launch_bounds__(kVecThreads)
+__global__ void __launch_bounds__(kUpdateThreads)
     k_bicg_update(long long n, const BicgState *s, TX *x, const T *p, T *r, const T *q, T *rs,
                   const T *qs, Pair *partials, StepLink link) {
-    __shared__ Pair sh[2 * (kVecThreads / kWave)];
+    __shared__ Pair sh[2 * (kUpdateThreads / kWave)];
     if (!block_running(&s->status)) return;
     double alpha;
     if (link.state) {
@@ -60,7 +71,7 @@ __global__ void __launch_bounds__(kVecThreads)
 template <typename TX, typename T>
 hipError_t bicg_update(long long n, const BicgState *s, TX *x, const T *p, T *r, const T *q,
                        T *rs, const T *qs, Pair *partials, hipStream_t st, StepLink link) {
-    hipLaunchKernelGGL((k_bicg_update<TX, T>), dim3(vec_blocks(n)), dim3(kVecThreads), 0, st, n,
+    hipLaunchKernelGGL((k_bicg_update<TX, T>), dim3(update_blocks(n)), dim3(kUpdateThreads), 0, st, n,
                        s, x, p, r, q, rs, qs, partials, link);
     return hipGetLastError();
 }
@@ -76,10 +87,10 @@ template hipError_t bicg_update<double, float>(long long, const BicgState *, dou
 // CG sweep B: the primal half of the Bi-CG update (the shadow half repeats it bit for bit
 // when r*_0 = r_0), and the partials of r.r, which is also rho of the next iteration.
 template <typename TX, typename T>
-__global__ void __launch_bounds__(kVecThreads)
+__global__ void __launch_bounds__(kUpdateThreads)
     k_cg_update(long long n, const BicgState *s, TX *x, const T *p, T *r, const T *q,
                 Pair *partials, StepLink link) {
-    __shared__ Pair sh[kVecThreads / kWave];
+    __shared__ Pair sh[kUpdateThreads / kWave];
     if (!block_running(&s->status)) return;
     double alpha;
     if (link.state) {
@@ -104,7 +115,7 @@ __global__ void __launch_bounds__(kVecThreads)
 template <typename TX, typename T>
 hipError_t cg_update(long long n, const BicgState *s, TX *x, const T *p, T *r, const T *q,
                      Pair *partials, hipStream_t st, StepLink link) {
-    hipLaunchKernelGGL((k_cg_update<TX, T>), dim3(vec_blocks(n)), dim3(kVecThreads), 0, st, n, s,
+    hipLaunchKernelGGL((k_cg_update<TX, T>), dim3(update_blocks(n)), dim3(kUpdateThreads), 0, st, n, s,
                        x, p, r, q, partials, link);
     return hipGetLastError();
 }
@@ -118,9 +129,9 @@ template hipError_t cg_update<double, float>(long long, const BicgState *, doubl
 // Partials of r*.r and r.r with the block layout of the Bi-CG update kernels, for a run
 // whose residuals were just replaced (its next sweep A merges them as the rho of the step).
 template <typename T>
-__global__ void __launch_bounds__(kVecThreads)
+__global__ void __launch_bounds__(kUpdateThreads)
     k_rho_partials(long long n, const T *r, const T *rs, Pair *partials) {
-    __shared__ Pair sh[2 * (kVecThreads / kWave)];
+    __shared__ Pair sh[2 * (kUpdateThreads / kWave)];
     Pair acc[2] = {{0.0, 0.0}, {0.0, 0.0}};
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
@@ -136,7 +147,7 @@ __global__ void __launch_bounds__(kVecThreads)
 
 template <typename T>
 hipError_t rho_partials(long long n, const T *r, const T *rs, Pair *partials, hipStream_t st) {
-    hipLaunchKernelGGL(k_rho_partials<T>, dim3(vec_blocks(n)), dim3(kVecThreads), 0, st, n, r,
+    hipLaunchKernelGGL(k_rho_partials<T>, dim3(update_blocks(n)), dim3(kUpdateThreads), 0, st, n, r,
                        rs, partials);
     return hipGetLastError();
 }
