@@ -50,6 +50,9 @@ def lib():
             "oracle_dsolve": (c_int, [c_int, c_int, dp, dp]),
             "oracle_assemble": (c_int, [c_int, c_int, dp]),
             "oracle_bicg": (c_int, [c_int, c_int, dp, dp, dp, c_dbl, c_int, c_int, ip, dp]),
+            "oracle_bicg_ex": (c_int, [c_int, c_int, dp, dp, dp, dp, dp, dp, c_dbl, c_int, c_int,
+                                       ip, dp]),
+            "oracle_diagonal": (c_int, [c_int, c_int, dp]),
             "oracle_level_solve": (c_int, [c_int, c_int, dp, dp, c_dbl, c_int, c_int, c_int,
                                            ip, ip, dp, dp]),
             "oracle_exp_finite": (c_int, [c_int, dp, dp, dp]),
@@ -147,6 +150,34 @@ def assemble(N: int, bc: int) -> np.ndarray:
     A = np.empty((n, n))
     _check("assemble", lib().oracle_assemble(N, bc, _p(A)))
     return A
+
+
+def bicg_ex(N: int, bc: int, b, x0, eps: float, maxit: int = 100000, shadow=None,
+            bstar=None, xstar0=None, mdiag=None, literal_transpose: bool = False):
+    """One run of Algorithm 2 with a diagonal preconditioner M = diag(mdiag) (None: M = I)
+    and a chosen shadow system: r*_0 = shadow, or r*_0 = b* - A^T x*_0 with the dual iterate
+    x* updated alongside (bstar, xstar0).  Returns (x, x* or None, iterations, recurrence
+    r.r, code)."""
+    b = _f64(b).ravel()
+    x = _f64(x0).ravel().copy()
+    sh = None if shadow is None else _f64(shadow).ravel()
+    bs = None if bstar is None else _f64(bstar).ravel()
+    xs = None if xstar0 is None else _f64(xstar0).ravel().copy()
+    md = None if mdiag is None else _f64(mdiag).ravel()
+    it = ctypes.c_int(0)
+    rr = ctypes.c_double(0.0)
+    rc = lib().oracle_bicg_ex(N, bc, _p(b), _p(x), _p(sh), _p(bs), _p(xs), _p(md), eps, maxit,
+                              int(literal_transpose), ctypes.byref(it), ctypes.byref(rr))
+    if rc not in (OK, ENOCONV):
+        raise OracleError("bicg_ex", rc)
+    return x, xs, it.value, rr.value, rc
+
+
+def diagonal(N: int, bc: int) -> np.ndarray:
+    """The diagonal of A_h, read off the operator (the Jacobi preconditioner)."""
+    d = np.empty(n_interior(N))
+    _check("diagonal", lib().oracle_diagonal(N, bc, _p(d)))
+    return d
 
 
 def bicg(N: int, bc: int, b, x0, eps: float, maxit: int = 100000, shadow=None,

@@ -357,23 +357,51 @@ int oracle_assemble(int N, int bc, double *A) {
  * Stops when the recurrence residual satisfies r.r <= (eps*eps)*(b.b), or after maxit
  * iterations (returns -3), or on breakdown (returns -4).  *iters gets the iteration count
  * and *rr_out the final recurrence r.r. */
-int oracle_bicg(int N, int bc, const double *b, double *x, const double *shadow, double eps,
-                int maxit, int literal_t, int *iters, double *rr_out) {
+/* Algorithm 2 (Bi-CG with the preconditioner), real arithmetic.  M is diagonal: mdiag holds
+ * its entries (NULL: M = I), so M^-1 v is v divided entrywise and v^T M^-1 = (M^-T v)^T =
+ * M^-1 v as a column.  The shadow system is either
+ *   - bstar and xstar given: r*_0 = b* - A^T x*_0 and the dual iterate x* is updated in place
+ *     (x*_{k+1} = x*_k + alpha_k p*_k), so that on exit x* approximates the solution of
+ *     A^T x* = b*; or
+ *   - shadow given: r*_0 = shadow (no dual iterate); or
+ *   - neither: r*_0 = r_0.
+ * The products with A^T are formed by scattering the rows of A_h when literal_t, else as
+ * A_h v (A_h is exactly symmetric).  The run stops when the recurrence residual satisfies
+ * ||r_k||_2 <= eps ||b||_2, after maxit iterations (ENOCONV) or on a zero or non-finite
+ * r*.M^-1 r or p*.A p (EBREAKDOWN). */
+int oracle_bicg_ex(int N, int bc, const double *b, double *x, const double *shadow,
+                   const double *bstar, double *xstar, const double *mdiag, double eps,
+                   int maxit, int literal_t, int *iters, double *rr_out) {
     if (N < 2 || (bc != 1 && bc != 2) || !b || !x || maxit < 0) return ORC_EINVAL;
+    if ((bstar == NULL) != (xstar == NULL)) return ORC_EINVAL;
     i64 n = (i64)(N - 1) * (N - 1) * (N - 1);
     double *r = malloc((size_t)n * sizeof(double)), *rs = malloc((size_t)n * sizeof(double));
     double *p = malloc((size_t)n * sizeof(double)), *ps = malloc((size_t)n * sizeof(double));
     double *q = malloc((size_t)n * sizeof(double)), *qs = malloc((size_t)n * sizeof(double));
-    if (!r || !rs || !p || !ps || !q || !qs) {
-        free(r); free(rs); free(p); free(ps); free(q); free(qs);
+    double *z = malloc((size_t)n * sizeof(double)), *zs = malloc((size_t)n * sizeof(double));
+    if (!r || !rs || !p || !ps || !q || !qs || !z || !zs) {
+        free(r); free(rs); free(p); free(ps); free(q); free(qs); free(z); free(zs);
         return ORC_ENOMEM;
     }
     double bb = oracle_dot(n, b, b);
     double thr = (eps * eps) * bb;
     oracle_residual(N, bc, b, x, r); /* r_0 = b - A x_0 */
-    for (i64 t = 0; t < n; t++) rs[t] = shadow ? shadow[t] : r[t];
-    for (i64 t = 0; t < n; t++) { p[t] = r[t]; ps[t] = rs[t]; } /* p_0 = M^-1 r_0 */
-    double rho = oracle_dot(n, rs, r);
+    if (bstar) {                      /* r*_0 = b* - A^T x*_0 */
+        if (literal_t) oracle_apply_transpose(N, bc, xstar, qs);
+        else oracle_apply(N, bc, xstar, qs);
+        for (i64 t = 0; t < n; t++) rs[t] = bstar[t] - qs[t];
+    } else {
+        for (i64 t = 0; t < n; t++) rs[t] = shadow ? shadow[t] : r[t];
+    }
+    /* z = M^-1 r, z* = M^-T r* */
+#define PRECOND()                                                      \
+    for (i64 t = 0; t < n; t++) {                                      \
+        z[t] = mdiag ? r[t] / mdiag[t] : r[t];                         \
+        zs[t] = mdiag ? rs[t] / mdiag[t] : rs[t];                      \
+    }
+    PRECOND();
+    for (i64 t = 0; t < n; t++) { p[t] = z[t]; ps[t] = zs[t]; } /* p_0 = M^-1 r_0 */
+    double rho = oracle_dot(n, rs, z);                             /* r*_0 M^-1 r_0 */
     double rr = oracle_dot(n, r, r);
     int k = 0, rc = ORC_OK;
     while (!(rr <= thr)) {
@@ -388,24 +416,60 @@ int oracle_bicg(int N, int bc, const double *b, double *x, const double *shadow,
 #pragma omp parallel for schedule(static)
         for (i64 t = 0; t < n; t++) {
             x[t] = x[t] + alpha * p[t];
+            if (xstar) xstar[t] = xstar[t] + alpha * ps[t];
             r[t] = r[t] - alpha * q[t];
             rs[t] = rs[t] - alpha * qs[t];
         }
-        double rho_new = oracle_dot(n, rs, r);
+        PRECOND();
+        double rho_new = oracle_dot(n, rs, z);
         rr = oracle_dot(n, r, r);
         double beta = rho_new / rho;
         rho = rho_new;
         k++;
 #pragma omp parallel for schedule(static)
         for (i64 t = 0; t < n; t++) {
-            p[t] = r[t] + beta * p[t];
-            ps[t] = rs[t] + beta * ps[t];
+            p[t] = z[t] + beta * p[t];
+            ps[t] = zs[t] + beta * ps[t];
         }
     }
+#undef PRECOND
     if (iters) *iters = k;
     if (rr_out) *rr_out = rr;
-    free(r); free(rs); free(p); free(ps); free(q); free(qs);
+    free(r); free(rs); free(p); free(ps); free(q); free(qs); free(z); free(zs);
     return rc;
+}
+
+/* Algorithm 2 with M = I and r*_0 = shadow (or r_0). */
+int oracle_bicg(int N, int bc, const double *b, double *x, const double *shadow, double eps,
+                int maxit, int literal_t, int *iters, double *rr_out) {
+    return oracle_bicg_ex(N, bc, b, x, shadow, NULL, NULL, NULL, eps, maxit, literal_t, iters,
+                          rr_out);
+}
+
+/* The diagonal of A_h (the Jacobi choice of M), read off the operator itself: A_h applied
+ * to vectors that are 1 on one residue class of (i mod 5, j mod 5, k mod 5) and 0 elsewhere;
+ * the 25-point stencil reaches 2 points per axis, so no two ones of a class share a row. */
+int oracle_diagonal(int N, int bc, double *d) {
+    if (N < 2 || (bc != 1 && bc != 2) || !d) return ORC_EINVAL;
+    const int n1 = N - 1;
+    i64 n = (i64)n1 * n1 * n1;
+    double *e = malloc((size_t)n * sizeof(double)), *y = malloc((size_t)n * sizeof(double));
+    if (!e || !y) { free(e); free(y); return ORC_ENOMEM; }
+    for (int ck = 0; ck < 5; ck++)
+        for (int cj = 0; cj < 5; cj++)
+            for (int ci = 0; ci < 5; ci++) {
+                for (int k = 0; k < n1; k++)
+                    for (int j = 0; j < n1; j++)
+                        for (int i = 0; i < n1; i++) {
+                            const i64 t = ((i64)k * n1 + j) * n1 + i;
+                            e[t] = (i % 5 == ci && j % 5 == cj && k % 5 == ck) ? 1.0 : 0.0;
+                        }
+                oracle_apply(N, bc, e, y);
+                for (i64 t = 0; t < n; t++)
+                    if (e[t] != 0.0) d[t] = y[t];
+            }
+    free(e); free(y);
+    return ORC_OK;
 }
 
 /* Alg. 1, the while loop of a level: repeat Bi-CG from the current x until the true

@@ -111,3 +111,78 @@ def test_work_units_match_paper_footnotes(golden_tables):
     footnotes."""
     for k, t in golden_tables["problems"].items():
         assert round(O.work_units(t["iters"]), 2) == pytest.approx(t["wu"], abs=0.006), k
+
+
+# ------------------------------------------------------------------ Algorithm 2 variants
+
+@pytest.mark.parametrize("N", [2, 3, 5, 8])
+@pytest.mark.parametrize("bc", [1, 2])
+def test_diagonal_matches_the_assembled_operator(N, bc):
+    """diag(A_h) read off the operator equals that of the Kronecker construction."""
+    np.testing.assert_array_equal(O.diagonal(N, bc), np.diag(_closed_form(N, bc)))
+
+
+@pytest.mark.parametrize("bc", [1, 2])
+@pytest.mark.parametrize("literal", [False, True])
+def test_jacobi_preconditioned_bicg_reaches_direct_solution(bc, literal):
+    N = 8
+    n = (N - 1) ** 3
+    rng = np.random.default_rng(11 + bc)
+    b = rng.standard_normal(n)
+    A = _closed_form(N, bc)
+    x, xs, it, rr, rc = O.bicg_ex(N, bc, b, np.zeros(n), 1e-13, mdiag=O.diagonal(N, bc),
+                                  literal_transpose=literal)
+    assert rc == O.OK and xs is None
+    np.testing.assert_allclose(x, np.linalg.solve(A, b), rtol=0, atol=1e-9 * np.abs(x).max())
+
+
+def test_scalar_preconditioner_gives_the_unpreconditioned_iterates():
+    """M = c I changes p by 1/c and alpha by c: the iterates x_k are those of M = I."""
+    N, bc = 8, 1
+    n = (N - 1) ** 3
+    rng = np.random.default_rng(2)
+    b = rng.standard_normal(n)
+    for k in (1, 3, 7):
+        x1, _, _, _, _ = O.bicg_ex(N, bc, b, np.zeros(n), 1e-30, maxit=k)
+        x2, _, _, _, _ = O.bicg_ex(N, bc, b, np.zeros(n), 1e-30, maxit=k,
+                                   mdiag=np.full(n, 4.0))
+        np.testing.assert_allclose(x2, x1, rtol=1e-12, atol=1e-14 * np.abs(x1).max())
+
+
+@pytest.mark.parametrize("bc", [1, 2])
+def test_dual_iterate_solves_the_transposed_system(bc):
+    """With b* and x*_0 the shadow recurrence is the Bi-CG iteration of A^T x* = b*."""
+    N = 6
+    n = (N - 1) ** 3
+    rng = np.random.default_rng(21 + bc)
+    b, bstar, xs0 = rng.standard_normal(n), rng.standard_normal(n), rng.standard_normal(n)
+    A = _closed_form(N, bc)
+    x, xs, it, rr, rc = O.bicg_ex(N, bc, b, np.zeros(n), 1e-13, bstar=bstar, xstar0=xs0,
+                                  literal_transpose=True)
+    assert rc == O.OK
+    np.testing.assert_allclose(x, np.linalg.solve(A, b), rtol=0, atol=1e-8 * np.abs(x).max())
+    ref = np.linalg.solve(A.T, bstar)
+    np.testing.assert_allclose(xs, ref, rtol=0, atol=1e-6 * np.abs(ref).max())
+
+
+def test_residuals_are_biorthogonal():
+    """r_i . r*_j = 0 for i != j (the defining property of the two Bi-CG sequences), with
+    r_k = b - A x_k and r*_k = b* - A^T x*_k from runs stopped after k steps."""
+    N, bc = 6, 2
+    n = (N - 1) ** 3
+    rng = np.random.default_rng(7)
+    b, bstar = rng.standard_normal(n), rng.standard_normal(n)
+    A = _closed_form(N, bc)
+    rs, rss = [], []
+    for k in range(5):
+        x, xs, *_ = O.bicg_ex(N, bc, b, np.zeros(n), 1e-30, maxit=k, bstar=bstar,
+                              xstar0=np.zeros(n), literal_transpose=True)
+        rs.append(b - A @ x)
+        rss.append(bstar - A.T @ xs)
+    for i in range(5):
+        for j in range(5):
+            c = abs(rs[i] @ rss[j]) / (np.linalg.norm(rs[i]) * np.linalg.norm(rss[j]))
+            if i != j:
+                assert c < 1e-9, (i, j, c)
+            else:
+                assert c > 1e-3
