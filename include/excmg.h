@@ -69,6 +69,10 @@ extern "C" {
                               /* the shadow vectors equal to the primal ones, so one product  */
                               /* and half the vector traffic give bit-identical iterates      */
 
+/* Preconditioner M of Algorithm 2 in solves (excmg_opts.precond). */
+#define EXCMG_PRECOND_NONE 0   /* M = I                                                      */
+#define EXCMG_PRECOND_JACOBI 1 /* M = diag(A_h) (FP64 Bi-CG only)                            */
+
 #define EXCMG_MAX_LEVELS 16
 
 /* Options of excmg_solve_ex.  Zero-initialise and set what you need. */
@@ -88,6 +92,7 @@ typedef struct excmg_opts {
     int method;         /* EXCMG_BICG (default) or EXCMG_CG (excmg_solve_ex only)           */
     int refine;         /* mixed precision: EXCMG_RELIABLE (default) or EXCMG_RESTART;     */
                         /* excmg_solve_batch always restarts                                */
+    int precond;        /* EXCMG_PRECOND_NONE (default) or EXCMG_PRECOND_JACOBI (solve_ex) */
 } excmg_opts;
 
 /* Per-level record filled by excmg_solve_ex (levels 0 and 1 report iterations = 0). */
@@ -134,6 +139,26 @@ int excmg_rhs(int level, const double *f, const double *g1, const double *g2, do
 /* x = A_l^{-1} b by the cached dense Cholesky factor; level must be 0 or 1 (DSOLVE,
  * Algorithm 1). */
 int excmg_dsolve(int level, const double *b, double *x);
+
+/* One run of Algorithm 2 with its options (Sec. 5, Bi-CG with the preconditioner), FP64, on
+ * level `level` from the initial guess in x (overwritten by the final iterate):
+ *   mdiag  the diagonal of a preconditioner M (interior vector, entries > 0; NULL: M = I;
+ *          excmg_diagonal gives diag(A_h), the Jacobi choice);
+ *   bstar, xstar  the shadow system: r*_0 = b* - A^T x*_0, and xstar (in: x*_0, out: the
+ *          dual iterate x*_k = x*_0 + sum alpha_j p*_j, which approximates the solution of
+ *          A^T x* = b*); or
+ *   shadow the shadow residual r*_0 itself (no dual iterate); with neither, r*_0 = r_0.
+ * Stops when the recurrence residual satisfies ||r||_2 <= eps ||b||_2 or after max_iters
+ * iterations.  Outputs (may be NULL): iterations done, final recurrence ||r||_2^2.  Errors:
+ * EXCMG_EINVAL (bstar without xstar or the reverse, shadow together with bstar),
+ * EXCMG_ENOCONV, EXCMG_EBREAKDOWN (r*.M^-1 r or p*.A p zero or not finite). */
+int excmg_bicg_ex(int level, const double *b, double *x, const double *shadow,
+                  const double *bstar, double *xstar, const double *mdiag, double eps,
+                  int max_iters, int *iters, double *rr);
+
+/* diag(A_h) of level `level` of the current context (interior vector): 42 + m for the first
+ * boundary kind, 42 - m for the second, m = number of faces the unknown is next to. */
+int excmg_diagonal(int level, double *d);
 
 /* One Bi-CG run (Algorithm 2, preconditioner M = I, shadow residual r*_0 = r_0) on level
  * `level` from the initial guess in x (overwritten by the final iterate): stops when the

@@ -55,6 +55,8 @@ def lib():
             "oracle_diagonal": (c_int, [c_int, c_int, dp]),
             "oracle_level_solve": (c_int, [c_int, c_int, dp, dp, c_dbl, c_int, c_int, c_int,
                                            ip, ip, dp, dp]),
+            "oracle_level_solve_ex": (c_int, [c_int, c_int, dp, dp, dp, c_dbl, c_int, c_int,
+                                              c_int, ip, ip, dp, dp]),
             "oracle_exp_finite": (c_int, [c_int, dp, dp, dp]),
             "oracle_exp_true": (c_int, [c_int, dp, dp, dp]),
         }
@@ -209,15 +211,17 @@ class LevelResult:
 
 
 def level_solve(N: int, bc: int, b, x0, eps: float, maxit: int = 100000, max_runs: int = 5,
-                literal_transpose: bool = False):
-    """The while loop of Algorithm 1 on one level.  Returns (x, LevelResult)."""
+                literal_transpose: bool = False, mdiag=None):
+    """The while loop of Algorithm 1 on one level (Bi-CG preconditioned by diag(mdiag) if
+    given).  Returns (x, LevelResult)."""
     b = _f64(b).ravel()
     x = _f64(x0).ravel().copy()
+    md = None if mdiag is None else _f64(mdiag).ravel()
     it, runs = ctypes.c_int(0), ctypes.c_int(0)
     rr, bb = ctypes.c_double(0.0), ctypes.c_double(0.0)
-    rc = lib().oracle_level_solve(N, bc, _p(b), _p(x), eps, maxit, max_runs,
-                                  int(literal_transpose), ctypes.byref(it), ctypes.byref(runs),
-                                  ctypes.byref(rr), ctypes.byref(bb))
+    rc = lib().oracle_level_solve_ex(N, bc, _p(b), _p(x), _p(md), eps, maxit, max_runs,
+                                     int(literal_transpose), ctypes.byref(it), ctypes.byref(runs),
+                                     ctypes.byref(rr), ctypes.byref(bb))
     if rc not in (OK, ENOCONV):
         raise OracleError("level_solve", rc)
     return x, LevelResult(N, it.value, runs.value, rr.value, bb.value, eps, rc)
@@ -307,11 +311,12 @@ def level_sizes(n_finest: int, n_levels: int):
 
 def excmg(n_finest: int, n_levels: int, bc: int, f, g1, g2, tol: float, *,
           maxit: int = 100000, max_runs: int = 5, keep_levels: bool = False,
-          literal_transpose: bool = False) -> ExcmgResult:
+          literal_transpose: bool = False, jacobi: bool = False) -> ExcmgResult:
     """Algorithm 1.  f, g1, g2 are node arrays on the finest grid; coarser levels take
     every 2^m-th node (injection).  Levels 0 and 1 use DSOLVE; level l >= 2 is the paper's
     i = l-1 with L = n_levels-2, starts from EXP_finite of the two previous levels and runs
-    Bi-CG until the true relative residual is at most eps_i."""
+    Bi-CG (preconditioned by diag(A_h) with ``jacobi``) until the true relative residual
+    is at most eps_i."""
     sizes = level_sizes(n_finest, n_levels)
     M = n_finest + 1
     f = np.asarray(f, dtype=np.float64).reshape(M, M, M)
@@ -331,7 +336,8 @@ def excmg(n_finest: int, n_levels: int, bc: int, f, g1, g2, tol: float, *,
             w = exp_finite(N, u_prev, u_prev2)
             eps = level_tolerance(tol, l - 1, L)
             x, st = level_solve(N, bc, b, interior(w), eps, maxit=maxit, max_runs=max_runs,
-                                literal_transpose=literal_transpose)
+                                literal_transpose=literal_transpose,
+                                mdiag=diagonal(N, bc) if jacobi else None)
             res.levels.append(st)
         u = to_nodes(N, x, g1l)
         if keep_levels:

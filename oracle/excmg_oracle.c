@@ -476,9 +476,21 @@ int oracle_diagonal(int N, int bc, double *d) {
  * relative residual satisfies ||b - A x||_2 <= eps ||b||_2, at most max_runs Bi-CG runs
  * of at most maxit iterations each.  Outputs: total iterations, Bi-CG runs, final true
  * r.r and b.b. */
+int oracle_level_solve_ex(int N, int bc, const double *b, double *x, const double *mdiag,
+                          double eps, int maxit, int max_runs, int literal_t, int *iters,
+                          int *runs, double *rr_true, double *bb_out);
+
 int oracle_level_solve(int N, int bc, const double *b, double *x, double eps, int maxit,
                        int max_runs, int literal_t, int *iters, int *runs, double *rr_true,
                        double *bb_out) {
+    return oracle_level_solve_ex(N, bc, b, x, NULL, eps, maxit, max_runs, literal_t, iters,
+                                 runs, rr_true, bb_out);
+}
+
+/* The same with Bi-CG preconditioned by M = diag(mdiag) (NULL: M = I). */
+int oracle_level_solve_ex(int N, int bc, const double *b, double *x, const double *mdiag,
+                          double eps, int maxit, int max_runs, int literal_t, int *iters,
+                          int *runs, double *rr_true, double *bb_out) {
     if (N < 2 || (bc != 1 && bc != 2) || !b || !x) return ORC_EINVAL;
     i64 n = (i64)(N - 1) * (N - 1) * (N - 1);
     double *r = malloc((size_t)n * sizeof(double));
@@ -492,7 +504,8 @@ int oracle_level_solve(int N, int bc, const double *b, double *x, double eps, in
         if (nrun >= max_runs) { rc = ORC_ENOCONV; break; }
         int it = 0;
         double rrr = 0.0;
-        int brc = oracle_bicg(N, bc, b, x, NULL, eps, maxit, literal_t, &it, &rrr);
+        int brc = oracle_bicg_ex(N, bc, b, x, NULL, NULL, NULL, mdiag, eps, maxit, literal_t,
+                                 &it, &rrr);
         total += it;
         nrun++;
         oracle_residual(N, bc, b, x, r);

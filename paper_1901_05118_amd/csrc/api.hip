@@ -135,6 +135,7 @@ struct Level {
     long long nodes = 0;
     Geom g1{}, g2{}, g2f{};  // launch shapes: one-array kernels, sweep A FP64, sweep A FP32
     DBuf b, x, u;     // right-hand side, unknowns, node array (solution or EXP_finite guess)
+    DBuf diag;        // diag(A_h), made when a Jacobi-preconditioned solve first needs it
 };
 
 void release_graphs();
@@ -161,6 +162,7 @@ struct Ctx {
             L.b.release();
             L.x.release();
             L.u.release();
+            L.diag.release();
         }
         lv.clear();
         r.release(); rs.release();
@@ -373,9 +375,17 @@ bool g_fold = getenv("EXCMG_SEPARATE_FINALISE") == nullptr;
 hipStream_t g_capture = nullptr;
 
 // Captured windows of K iterations, per level, vector type, method and iterate pointer.
+// Options of Algorithm 2 for the run in progress (FP64 Bi-CG only): the diagonal of a
+// preconditioner M, and the dual iterate x* (updated with the shadow directions).
+struct RunVariant {
+    const double *d = nullptr;
+    double *xs = nullptr;
+};
+RunVariant g_var;
+
 struct GraphEntry {
     int level, tsize, cg, fold, K;
-    const void *x;
+    const void *x, *d, *xs;
     hipGraph_t graph;
     hipGraphExec_t exec;
 };
@@ -409,6 +419,26 @@ int launch_iteration(const Level &L, TX *x, long long j, int ev, hipStream_t st)
         lb = StepLink{S, c.part_a.as<Pair>(), nsb, 1, cur};
     }
     if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev], st));
+    if constexpr (sizeof(T) == 8 && sizeof(TX) == 8) {
+        if (g_var.d || g_var.xs) {  // Algorithm 2 with its options
+            if (g_var.d)
+                CKH(stencil_pair_direction_m(G, G.ty, r, rs, c.p[cur].as<T>(), c.ps[cur].as<T>(),
+                                             g_var.d, &S->beta, j == 0 ? 1 : 0, pn, psn, q, qs,
+                                             c.part_a.as<Pair>(), &S->status, st, la));
+            else
+                CKH(stencil_pair_direction<T>(G, G.ty, r, rs, c.p[cur].as<T>(), c.ps[cur].as<T>(),
+                                              &S->beta, j == 0 ? 1 : 0, pn, psn, q, qs,
+                                              c.part_a.as<Pair>(), &S->status, st, la));
+            if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev + 1], st));
+            if (!g_fold) CKH(bicg_alpha(S, c.part_a.as<Pair>(), nsb, st));
+            if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev + 2], st));
+            CKH(bicg_update_ex(L.nu, S, x, pn, r, q, rs, qs, g_var.d, g_var.xs, psn,
+                               c.part_b.as<Pair>(), st, lb));
+            if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev + 3], st));
+            if (!g_fold) CKH(bicg_beta(S, c.part_b.as<Pair>(), nvb, st));
+            return EXCMG_OK;
+        }
+    }
     if (g_cg)
         CKH(stencil_direction<T>(G, G.ty, r, c.p[cur].as<T>(), &S->beta, j == 0 ? 1 : 0, pn, q,
                                  c.part_a.as<Pair>(), &S->status, st, la));
@@ -449,7 +479,8 @@ template <typename TX, typename T>
 int window_graph(const Level &L, TX *x, int K, hipGraphExec_t *out) {
     for (GraphEntry &e : g_graph_cache)
         if (e.level == L.index && e.tsize == (int)sizeof(T) && e.cg == (int)g_cg &&
-            e.fold == (int)g_fold && e.K == K && e.x == (const void *)x) {
+            e.fold == (int)g_fold && e.K == K && e.x == (const void *)x && e.d == g_var.d &&
+            e.xs == g_var.xs) {
             *out = e.exec;
             return EXCMG_OK;
         }
@@ -469,7 +500,7 @@ int window_graph(const Level &L, TX *x, int K, hipGraphExec_t *out) {
     hipGraphExec_t exec = nullptr;
     CKH(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
     g_graph_cache.push_back(GraphEntry{L.index, (int)sizeof(T), (int)g_cg, (int)g_fold, K,
-                                       (const void *)x, graph, exec});
+                                       (const void *)x, g_var.d, g_var.xs, graph, exec});
     *out = exec;
     return EXCMG_OK;
 }
@@ -546,29 +577,61 @@ int bicg_iterate(const Level &L, TX *x, BicgState &hs, long long &j) {
 }
 
 // One Bi-CG run from x (in place) on level L with right-hand side b.
+// One run of Algorithm 2 from x (in place) on level L with right-hand side b.  Options: d,
+// the diagonal of a preconditioner M (NULL: M = I); the shadow system, either bstar and
+// xstar (r*_0 = b* - A^T x*_0, x* updated in place) or shadow (r*_0 = shadow), else
+// r*_0 = r_0.  A^T is applied as A (A_h is exactly symmetric).
 int bicg_run(const Level &L, const double *b, double *x, double eps, int maxit, int *iters,
-             double *rr_out, int *status_out) {
+             double *rr_out, int *status_out, const double *d = nullptr,
+             const double *shadow = nullptr, const double *bstar = nullptr,
+             double *xstar = nullptr) {
     Ctx &c = g_ctx;
     BicgState *S = c.state.as<BicgState>();
     double *r = c.r.as<double>(), *rs = c.rs.as<double>();
-    // b.b and r_0 = b - A x_0, r*_0 = r_0
+    // b.b and r_0 = b - A x_0
     CKR(device_dot(L.nu, b, b, (double *)&S->bb, 0));
     CKH(stencil_residual<double>(L.g1, L.g1.ty, b, x, r, c.part_a.as<Pair>(), g_stream));
-    CKH((copy_convert<double, double>(L.nu, r, rs, g_stream)));
-    CKH(bicg_start(S, c.part_a.as<Pair>(), stencil_blocks(L.g1), eps, maxit, g_stream));
+    if (!d && !shadow && !bstar) {
+        // r*_0 = r_0 and rho_0 = r_0.r_0
+        CKH((copy_convert<double, double>(L.nu, r, rs, g_stream)));
+        CKH(bicg_start(S, c.part_a.as<Pair>(), stencil_blocks(L.g1), eps, maxit, g_stream));
+    } else {
+        if (bstar)
+            CKH(stencil_residual<double>(L.g1, L.g1.ty, bstar, xstar, rs, c.part_b.as<Pair>(),
+                                         g_stream));
+        else
+            CKH((copy_convert<double, double>(L.nu, shadow ? shadow : r, rs, g_stream)));
+        // rho_0 = r*_0 . M^-1 r_0
+        CKH(rho_partials<double>(L.nu, r, rs, c.part_b.as<Pair>(), g_stream, d));
+        CKH(bicg_start2(S, c.part_b.as<Pair>(), update_blocks(L.nu), eps, maxit, g_stream));
+    }
     BicgState hs;
     CKR(read_state(hs));
     long long j = 0;
-    CKR((bicg_iterate<double, double>(L, x, hs, j)));
+    g_var = RunVariant{d, bstar ? xstar : nullptr};
+    const int rc = bicg_iterate<double, double>(L, x, hs, j);
+    g_var = RunVariant{};
+    CKR(rc);
     if (iters) *iters = hs.iter;
     if (rr_out) *rr_out = hs.rr;
     if (status_out) *status_out = hs.status;
     return EXCMG_OK;
 }
 
+// diag(A_h) of level L (the Jacobi choice of M), made once per context
+const double *level_diagonal(Level &L) {
+    if (!L.diag.p) {
+        if (L.diag.ensure((size_t)L.nu * 8) != EXCMG_OK) return nullptr;
+        if (operator_diagonal(L.n, g_ctx.bc == 1 ? 1.0 : -1.0, L.diag.as<double>(), g_stream) !=
+            hipSuccess)
+            return nullptr;
+    }
+    return L.diag.as<double>();
+}
+
 // Algorithm 1's while loop on one level.
 int level_solve(const Level &L, const double *b, double *x, double eps, int maxit, int max_runs,
-                excmg_level_stats *st) {
+                excmg_level_stats *st, const double *d = nullptr) {
     Ctx &c = g_ctx;
     double *sc = c.scal.as<double>();
     CKR(device_dot(L.nu, b, b, sc, 1));
@@ -586,7 +649,7 @@ int level_solve(const Level &L, const double *b, double *x, double eps, int maxi
         }
         int it = 0, bst = 0;
         double rrr = 0.0;
-        CKR(bicg_run(L, b, x, eps, maxit, &it, &rrr, &bst));
+        CKR(bicg_run(L, b, x, eps, maxit, &it, &rrr, &bst, d));
         total += it;
         runs++;
         CKR(true_residual(L, b, x, c.r.as<double>(), 2));
@@ -801,6 +864,7 @@ int solve_cascade(const excmg_opts &o, const double *f, const double *g1, const 
     const int max_runs = o.max_runs > 0 ? o.max_runs : 5;
     const int max_outer = o.max_outer > 0 ? o.max_outer : 60;
     const bool reliable = (o.refine == EXCMG_RELIABLE) && g_fold;
+    const bool jacobi = (o.precond == EXCMG_PRECOND_JACOBI);
     const double inner_tol = o.inner_tol > 0 ? o.inner_tol : (reliable ? 0.1 : 1e-4);
     const bool mixed = (o.precision == EXCMG_MIXED);
     hipEvent_t ev0, ev1, evl0, evl1;
@@ -834,7 +898,7 @@ int solve_cascade(const excmg_opts &o, const double *f, const double *g1, const 
                                       max_outer, inner_tol, &ls));
             else
                 CKR(level_solve(Lv, Lv.b.as<double>(), Lv.x.as<double>(), eps, maxit, max_runs,
-                                &ls));
+                                &ls, jacobi ? level_diagonal(Lv) : nullptr));
             if (ls.status != EXCMG_OK && worst == EXCMG_OK) worst = ls.status;
         }
         CKH(to_nodes<double>(Lv.N, s, Nf, Lv.x.as<double>(), g1, Lv.u.as<double>(), g_stream));
@@ -1381,6 +1445,58 @@ int excmg_bicg(int level, const double *b, double *x, double eps, int max_iters,
     return EXCMG_OK;
 }
 
+int excmg_bicg_ex(int level, const double *b, double *x, const double *shadow,
+                  const double *bstar, double *xstar, const double *mdiag, double eps,
+                  int max_iters, int *iters, double *rr) {
+    g_err[0] = 0;
+    CKR(need_ctx(level));
+    if (!b || !x) return fail(EXCMG_EINVAL, "NULL array");
+    if ((bstar == nullptr) != (xstar == nullptr))
+        return fail(EXCMG_EINVAL, "bstar and xstar go together");
+    if (bstar && shadow) return fail(EXCMG_EINVAL, "give either shadow or (bstar, xstar)");
+    if (!(eps >= 0.0) || max_iters < 0) return fail(EXCMG_EINVAL, "bad eps or max_iters");
+    Level &L = g_ctx.lv[level];
+    const size_t vb = (size_t)L.nu * 8;
+    Arg ab(b, vb), ax(x, vb), ash(shadow, vb), abs_(bstar, vb), axs(xstar, vb), amd(mdiag, vb);
+    CKR(ab.in());
+    CKR(ax.in());
+    if (shadow) CKR(ash.in());
+    if (bstar) {
+        CKR(abs_.in());
+        CKR(axs.in());
+    }
+    if (mdiag) CKR(amd.in());
+    int it = 0, status = 0;
+    double r2 = 0.0;
+    g_cg = false;
+    CKR(bicg_run(L, ab.p<double>(), ax.p<double>(), eps, max_iters, &it, &r2, &status,
+                 mdiag ? amd.p<double>() : nullptr, shadow ? ash.p<double>() : nullptr,
+                 bstar ? abs_.p<double>() : nullptr, bstar ? axs.p<double>() : nullptr));
+    CKR(ax.back());
+    if (bstar) CKR(axs.back());
+    CKH(hipStreamSynchronize(g_stream));
+    if (iters) *iters = it;
+    if (rr) *rr = r2;
+    if (status == kBreakdown) return fail(EXCMG_EBREAKDOWN, "Bi-CG breakdown");
+    if (status == kNoConv) return fail(EXCMG_ENOCONV, "Bi-CG reached %d iterations", max_iters);
+    return EXCMG_OK;
+}
+
+int excmg_diagonal(int level, double *d) {
+    g_err[0] = 0;
+    CKR(need_ctx(level));
+    if (!d) return fail(EXCMG_EINVAL, "NULL array");
+    Level &L = g_ctx.lv[level];
+    const double *dd = level_diagonal(L);
+    if (!dd) return fail(EXCMG_EHIP, "diagonal of level %d", level);
+    Arg ad(d, (size_t)L.nu * 8);
+    CKR(ad.out());
+    CKH(hipMemcpyAsync(ad.p<double>(), dd, (size_t)L.nu * 8, hipMemcpyDeviceToDevice, g_stream));
+    CKR(ad.back());
+    CKH(hipStreamSynchronize(g_stream));
+    return EXCMG_OK;
+}
+
 int excmg_level_solve(int level, const double *b, double *x, double eps, int max_iters,
                       int max_runs, excmg_level_stats *st) {
     g_err[0] = 0;
@@ -1464,6 +1580,10 @@ int excmg_solve_ex(const excmg_opts *opts, const double *f, const double *g1, co
         return fail(EXCMG_EINVAL, "method %d not supported", o.method);
     if (o.refine != EXCMG_RELIABLE && o.refine != EXCMG_RESTART)
         return fail(EXCMG_EINVAL, "refine %d not supported", o.refine);
+    if (o.precond != EXCMG_PRECOND_NONE && o.precond != EXCMG_PRECOND_JACOBI)
+        return fail(EXCMG_EINVAL, "precond %d not supported", o.precond);
+    if (o.precond == EXCMG_PRECOND_JACOBI && (o.precision != EXCMG_FP64 || o.method != EXCMG_BICG))
+        return fail(EXCMG_EINVAL, "the Jacobi preconditioner runs with FP64 Bi-CG only");
     CKR(setup(o.n_finest, o.n_levels, o.bc_kind));
     const size_t nb = (size_t)(o.n_finest + 1) * (o.n_finest + 1) * (o.n_finest + 1) * 8;
     Arg af(f, nb), a1(g1, nb), a2(g2, nb), au(u_out, nb), at(ut_out, nb);

@@ -70,6 +70,14 @@ hipError_t stencil_pair_direction(const Geom &g, int ty, const T *r, const T *rs
                                   int first, T *p_new, T *ps_new, T *q, T *qs, Pair *partials,
                                   const int *status, hipStream_t st, StepLink link = StepLink{});
 
+// Sweep A with a diagonal preconditioner (entries d): p_new = r / d + beta p_old, likewise
+// for the shadow direction (FP64)
+hipError_t stencil_pair_direction_m(const Geom &g, int ty, const double *r, const double *rs,
+                                   const double *p_old, const double *ps_old, const double *d,
+                                   const double *beta_dev, int first, double *p_new,
+                                   double *ps_new, double *q, double *qs, Pair *partials,
+                                   const int *status, hipStream_t st, StepLink link = StepLink{});
+
 // CG sweep A: p_new = r + beta p_old (p_new = r when first), q = A p_new, partials of p_new . q
 template <typename T>
 hipError_t stencil_direction(const Geom &g, int ty, const T *r, const T *p_old,
@@ -98,9 +106,23 @@ hipError_t cg_beta(BicgState *s, const Pair *part, int count, hipStream_t st);
 // the end-of-iteration checks of a folded step as a kernel of its own (one workgroup), run
 // before the host reads the state
 hipError_t step_check(StepLink link, hipStream_t st);
-// partials of rs.r and r.r in the layout of bicg_update's (after a residual replacement)
+// partials of rs.r and r.r in the layout of bicg_update's (after a residual replacement);
+// with d, of rs.(r / d) and r.r
 template <typename T>
-hipError_t rho_partials(long long n, const T *r, const T *rs, Pair *partials, hipStream_t st);
+hipError_t rho_partials(long long n, const T *r, const T *rs, Pair *partials, hipStream_t st,
+                        const T *d = nullptr);
+// Algorithm 2's sweep B with its options (FP64): d != NULL divides by the diagonal
+// preconditioner in rho' = r*.(M^-1 r); xs != NULL also updates the dual iterate
+// x* += alpha p* (ps)
+hipError_t bicg_update_ex(long long n, const BicgState *s, double *x, const double *p,
+                          double *r, const double *q, double *rs, const double *qs,
+                          const double *d, double *xs, const double *ps, Pair *partials,
+                          hipStream_t st, StepLink link = StepLink{});
+// a run started from 2-valued partials: rho = first value (r*.M^-1 r), r.r = second
+hipError_t bicg_start2(BicgState *s, const Pair *part, int count, double eps, int maxit,
+                       hipStream_t st);
+// diag(A_h) of an n^3-unknown grid: 42 + sgn * (faces the unknown is next to)
+hipError_t operator_diagonal(int n, double sgn, double *d, hipStream_t st);
 // status = running (or iteration cap), thr = new recurrence threshold
 hipError_t state_resume(BicgState *s, double thr, hipStream_t st);
 

@@ -130,12 +130,13 @@ template hipError_t cg_update<double, float>(long long, const BicgState *, doubl
 // whose residuals were just replaced (its next sweep A merges them as the rho of the step).
 template <typename T>
 __global__ void __launch_bounds__(kUpdateThreads)
-    k_rho_partials(long long n, const T *r, const T *rs, Pair *partials) {
+    k_rho_partials(long long n, const T *r, const T *rs, const T *d, Pair *partials) {
     __shared__ Pair sh[2 * (kUpdateThreads / kWave)];
     Pair acc[2] = {{0.0, 0.0}, {0.0, 0.0}};
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        dot2_acc(acc[0], (double)rs[i], (double)r[i]);
+        const double z = d ? (double)r[i] / (double)d[i] : (double)r[i];
+        dot2_acc(acc[0], (double)rs[i], z);
         dot2_acc(acc[1], (double)r[i], (double)r[i]);
     }
     block_merge<2>(acc, sh);
@@ -146,13 +147,88 @@ __global__ void __launch_bounds__(kUpdateThreads)
 }
 
 template <typename T>
-hipError_t rho_partials(long long n, const T *r, const T *rs, Pair *partials, hipStream_t st) {
+hipError_t rho_partials(long long n, const T *r, const T *rs, Pair *partials, hipStream_t st,
+                        const T *d) {
     hipLaunchKernelGGL(k_rho_partials<T>, dim3(update_blocks(n)), dim3(kUpdateThreads), 0, st, n, r,
-                       rs, partials);
+                       rs, d, partials);
     return hipGetLastError();
 }
 template hipError_t rho_partials<float>(long long, const float *, const float *, Pair *,
-                                        hipStream_t);
+                                        hipStream_t, const float *);
+template hipError_t rho_partials<double>(long long, const double *, const double *, Pair *,
+                                         hipStream_t, const double *);
+
+// Sweep B of Algorithm 2 with its options, in the order of the algorithm: x, x*, r, r*
+// updates, then M^-1 r and the partials of r*.(M^-1 r) and r.r.
+template <bool PRE, bool DUAL>
+__global__ void __launch_bounds__(kUpdateThreads)
+    k_bicg_update_ex(long long n, const BicgState *s, double *x, const double *p, double *r,
+                     const double *q, double *rs, const double *qs, const double *d, double *xs,
+                     const double *ps, Pair *partials, StepLink link) {
+    __shared__ Pair sh[2 * (kUpdateThreads / kWave)];
+    if (!block_running(&s->status)) return;
+    double alpha;
+    if (link.state) {
+        if (!link_alpha(link, alpha, sh)) return;
+    } else {
+        alpha = s->alpha;
+    }
+    Pair acc[2] = {{0.0, 0.0}, {0.0, 0.0}};
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double xi = x[i] + alpha * p[i];
+        x[i] = xi;
+        if (DUAL) xs[i] = xs[i] + alpha * ps[i];
+        const double ri = r[i] - alpha * q[i];
+        const double si = rs[i] - alpha * qs[i];
+        r[i] = ri;
+        rs[i] = si;
+        const double z = PRE ? ri / d[i] : ri;
+        dot2_acc(acc[0], si, z);
+        dot2_acc(acc[1], ri, ri);
+    }
+    block_merge<2>(acc, sh);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = acc[0];
+        partials[gridDim.x + blockIdx.x] = acc[1];
+    }
+}
+
+hipError_t bicg_update_ex(long long n, const BicgState *s, double *x, const double *p,
+                          double *r, const double *q, double *rs, const double *qs,
+                          const double *d, double *xs, const double *ps, Pair *partials,
+                          hipStream_t st, StepLink link) {
+    const dim3 grid(update_blocks(n)), block(kUpdateThreads);
+    if (d && xs)
+        hipLaunchKernelGGL((k_bicg_update_ex<true, true>), grid, block, 0, st, n, s, x, p, r, q,
+                           rs, qs, d, xs, ps, partials, link);
+    else if (d)
+        hipLaunchKernelGGL((k_bicg_update_ex<true, false>), grid, block, 0, st, n, s, x, p, r, q,
+                           rs, qs, d, xs, ps, partials, link);
+    else if (xs)
+        hipLaunchKernelGGL((k_bicg_update_ex<false, true>), grid, block, 0, st, n, s, x, p, r, q,
+                           rs, qs, d, xs, ps, partials, link);
+    else
+        hipLaunchKernelGGL((k_bicg_update_ex<false, false>), grid, block, 0, st, n, s, x, p, r, q,
+                           rs, qs, d, xs, ps, partials, link);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(kVecThreads) k_operator_diagonal(int n, double sgn, double *d) {
+    const i64 total = (i64)n * n * n;
+    const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int i = (int)(t % n), j = (int)((t / n) % n), k = (int)(t / ((i64)n * n));
+    const int m = (i == 0) + (i == n - 1) + (j == 0) + (j == n - 1) + (k == 0) + (k == n - 1);
+    d[t] = 42.0 + sgn * (double)m;
+}
+
+hipError_t operator_diagonal(int n, double sgn, double *d, hipStream_t st) {
+    const i64 total = (i64)n * n * n;
+    hipLaunchKernelGGL(k_operator_diagonal, dim3((unsigned)((total + kVecThreads - 1) / kVecThreads)),
+                       dim3(kVecThreads), 0, st, n, sgn, d);
+    return hipGetLastError();
+}
 
 // Let a stopped run go on: running again (unless at its iteration cap), with a new
 // stopping threshold for the recurrence residual.
@@ -261,6 +337,32 @@ __global__ void __launch_bounds__(kReduceThreads)
         s->sigma = 0.0;
         set_status(s);
     }
+}
+
+__global__ void __launch_bounds__(kReduceThreads)
+    k_bicg_start2(BicgState *s, const Pair *part, int count, double eps, int maxit) {
+    __shared__ Pair sh[2 * (kReduceThreads / kWave)];
+    Pair v[2];
+    merge_partials<2>(part, count, v, sh);
+    if (threadIdx.x == 0) {
+        s->rho = pair_value(v[0]);
+        s->rho_slot[0] = s->rho;
+        s->rr = pair_value(v[1]);
+        s->thr = (eps * eps) * s->bb;
+        s->iter = 0;
+        s->maxit = maxit;
+        s->alpha = 0.0;
+        s->beta = 0.0;
+        s->sigma = 0.0;
+        set_status(s);
+    }
+}
+
+hipError_t bicg_start2(BicgState *s, const Pair *part, int count, double eps, int maxit,
+                       hipStream_t st) {
+    hipLaunchKernelGGL(k_bicg_start2, dim3(1), dim3(kReduceThreads), 0, st, s, part, count, eps,
+                       maxit);
+    return hipGetLastError();
 }
 
 __global__ void __launch_bounds__(kReduceThreads)

@@ -103,6 +103,34 @@ hipError_t stencil_pair_direction(const Geom &g, int ty, const T *r, const T *rs
     return hipSuccess;
 }
 
+hipError_t stencil_pair_direction_m(const Geom &g, int ty, const double *r, const double *rs,
+                                   const double *p_old, const double *ps_old, const double *d,
+                                   const double *beta_dev, int first, double *p_new,
+                                   double *ps_new, double *q, double *qs, Pair *partials,
+                                   const int *status, hipStream_t st, StepLink link) {
+    InDirectionM<double> in;
+    in.link = link;
+    in.r[0] = r;
+    in.r[1] = rs;
+    in.p[0] = p_old;
+    in.p[1] = ps_old;
+    in.d = d;
+    in.beta_dev = beta_dev;
+    in.first = first;
+    in.beta = 0.0;
+    OutPairApply<double> out;
+    out.p_new[0] = p_new;
+    out.p_new[1] = ps_new;
+    out.q[0] = q;
+    out.q[1] = qs;
+    out.partials = partials;
+    out.status = status;
+    out.acc = Pair{0.0, 0.0};
+    EXCMG_DISPATCH_TY(ty, return (launch<TY, double, InDirectionM<double>, OutPairApply<double>, 2>(
+                              g, in, out, st)));
+    return hipSuccess;
+}
+
 template hipError_t stencil_apply<double>(const Geom &, int, const double *, double *,
                                           hipStream_t);
 template hipError_t stencil_apply<float>(const Geom &, int, const float *, float *, hipStream_t);

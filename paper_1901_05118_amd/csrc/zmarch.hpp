@@ -146,6 +146,38 @@ struct InDirection {        // p_new = r + beta p_old (p_new = r on the first it
     }
 };
 
+// Preconditioned direction (Algorithm 2 with a diagonal M, entries d): p_new = M^-1 r +
+// beta p_old, p*_new = M^-T r* + beta p*_old (p_new = M^-1 r on the first iteration).
+template <typename T>
+struct InDirectionM {
+    static constexpr int R = 3;
+    const T *r[2];
+    const T *p[2];
+    const T *d;
+    const double *beta_dev;
+    int first;
+    double beta;
+    StepLink link;
+    __device__ __forceinline__ void prepare() { beta = first ? 0.0 : *beta_dev; }
+    __device__ __forceinline__ bool begin(Pair *sh) {
+        if (first || link.state == nullptr) {
+            prepare();
+            return true;
+        }
+        return link_step(link, beta, sh);
+    }
+    __device__ __forceinline__ void load(int a, i64 idx, T (&raw)[R]) const {
+        raw[0] = r[a][idx];
+        raw[1] = p[a][idx];
+        raw[2] = d[idx];
+    }
+    __device__ __forceinline__ double combine(const T (&raw)[R]) const {
+        const double z = (double)raw[0] / (double)raw[2];
+        const double pn = (double)(T)(z + beta * (double)raw[1]);
+        return first ? z : pn;
+    }
+};
+
 // Kernel: NA marched arrays (1 or 2), input policy In, epilogue Out.
 //   Out::emit(lane_state, idx, y[NA], c[NA]) is called for every valid output with the
 //   operator values y and the centre values c of the output plane;

@@ -14,7 +14,7 @@ import numpy as np
 
 __all__ = [
     "ExcmgError", "OK", "EINVAL", "ENOMEM", "ENOCONV", "EBREAKDOWN", "EHIP", "FP64", "MIXED",
-    "BICG", "CG", "RELIABLE", "RESTART",
+    "BICG", "CG", "RELIABLE", "RESTART", "PRECOND_NONE", "PRECOND_JACOBI", "bicg_ex", "diagonal",
     "lib_path", "load", "set_stream", "setup", "apply_stencil", "apply_operator", "rhs", "dsolve", "bicg",
     "level_solve", "exp_finite", "exp_true", "solve", "solve_ex", "profile_sweep",
     "set_shape", "get_shape", "set_timing", "get_timing", "autotune", "solve_batch",
@@ -28,6 +28,7 @@ OK, EINVAL, ENOMEM, ENOCONV, EBREAKDOWN, EHIP = 0, -1, -2, -3, -4, -5
 FP64, MIXED = 0, 1
 BICG, CG = 0, 1
 RELIABLE, RESTART = 0, 1
+PRECOND_NONE, PRECOND_JACOBI = 0, 1
 MAX_LEVELS = 16
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -46,7 +47,7 @@ class Opts(ctypes.Structure):
                 ("tol", ctypes.c_double), ("max_iters", ctypes.c_int),
                 ("max_runs", ctypes.c_int), ("inner_tol", ctypes.c_double),
                 ("max_outer", ctypes.c_int), ("batch_mode", ctypes.c_int),
-                ("method", ctypes.c_int), ("refine", ctypes.c_int)]
+                ("method", ctypes.c_int), ("refine", ctypes.c_int), ("precond", ctypes.c_int)]
 
 
 class LevelStats(ctypes.Structure):
@@ -97,6 +98,9 @@ def load():
                                       ctypes.POINTER(LevelStats)]),
         "excmg_exp_finite": (c_int, [c_int, dp, dp, dp]),
         "excmg_get_level_solution": (c_int, [c_int, dp]),
+        "excmg_bicg_ex": (c_int, [c_int, dp, dp, dp, dp, dp, dp, c_dbl, c_int, ip,
+                                  ctypes.POINTER(c_dbl)]),
+        "excmg_diagonal": (c_int, [c_int, dp]),
         "excmg_exp_true": (c_int, [c_int, dp, dp, dp]),
         "excmg_solve": (c_int, [c_int, c_int, c_int, dp, dp, dp, c_dbl, dp]),
         "excmg_solve_ex": (c_int, [ctypes.POINTER(Opts), dp, dp, dp, dp, dp,
@@ -206,6 +210,26 @@ def level_solve(level: int, b, x, eps: float, max_iters: int = 100000, max_runs:
     return rc, st.asdict()
 
 
+def bicg_ex(level: int, b, x, eps: float, max_iters: int = 100000, shadow=None, bstar=None,
+            xstar=None, mdiag=None):
+    """One run of Algorithm 2 with its options (see excmg_bicg_ex).  x (and xstar) are
+    updated in place.  Returns (code, iterations, recurrence r.r)."""
+    it = ctypes.c_int(0)
+    rr = ctypes.c_double(0.0)
+    rc = load().excmg_bicg_ex(level, _ptr(b, name="b"), _ptr(x, name="x"),
+                              _ptr(shadow, name="shadow"), _ptr(bstar, name="bstar"),
+                              _ptr(xstar, name="xstar"), _ptr(mdiag, name="mdiag"), eps, max_iters,
+                              ctypes.byref(it), ctypes.byref(rr))
+    if rc not in (OK, ENOCONV, EBREAKDOWN):
+        _check("excmg_bicg_ex", rc)
+    return rc, it.value, rr.value
+
+
+def diagonal(level: int, d):
+    """diag(A_h) of a level of the current context into d."""
+    _check("excmg_diagonal", load().excmg_diagonal(level, _ptr(d, name="d")))
+
+
 def get_level_solution(level: int, u):
     """Node array of level `level` from the last solve on the current context."""
     _check("excmg_get_level_solution", load().excmg_get_level_solution(level, _ptr(u, name="u")))
@@ -230,10 +254,10 @@ def solve(n_finest: int, n_levels: int, bc_kind: int, f, g1, g2, tol: float, u_o
 def solve_ex(n_finest: int, n_levels: int, bc_kind: int, f, g1, g2, tol: float, u_out,
              ut_out=None, precision: int = FP64, max_iters: int = 0, max_runs: int = 0,
              inner_tol: float = 0.0, max_outer: int = 0, method: int = BICG,
-             refine: int = RELIABLE):
+             refine: int = RELIABLE, precond: int = PRECOND_NONE):
     """Algorithm 1 with options.  Returns (code, Stats)."""
     o = Opts(n_finest, n_levels, bc_kind, precision, tol, max_iters, max_runs, inner_tol,
-             max_outer, 0, method, refine)
+             max_outer, 0, method, refine, precond)
     st = Stats()
     rc = load().excmg_solve_ex(ctypes.byref(o), _ptr(f, name="f"), _ptr(g1, name="g1"),
                                _ptr(g2, name="g2"), _ptr(u_out, name="u_out"),
@@ -266,7 +290,7 @@ def solve_batch(problems, tol: float, precision: int = FP64, max_iters: int = 0,
                          _ptr(p["f"], name="f"), _ptr(p["g1"], name="g1"), _ptr(p["g2"], name="g2"),
                          _ptr(p["u_out"], name="u_out"), _ptr(p.get("ut_out"), name="ut_out"))
     o = Opts(0, 0, 0, precision, tol, max_iters, max_runs, inner_tol, max_outer,
-             1 if persistent else 0, BICG, RESTART)
+             1 if persistent else 0, BICG, RESTART, PRECOND_NONE)
     st = (Stats * n)()
     rc = load().excmg_solve_batch(n, arr, ctypes.byref(o), st)
     if rc not in (OK, ENOCONV, EBREAKDOWN):

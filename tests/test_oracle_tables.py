@@ -60,3 +60,14 @@ def test_table3_64cube_row_and_orders(golden_tables):
     assert 3.5 < order_t < 4.6
     # the extrapolated solution is far more accurate than u_h
     assert O.norm2(res.ut - arr.u) < 0.05 * O.norm2(e64)
+
+
+def test_jacobi_cascade_reaches_the_same_finite_difference_solution(golden_tables):
+    """Preconditioning changes the path, not the limit: the Jacobi-preconditioned cascade
+    reproduces Table 2's 32^3 row as the plain one does."""
+    arr = make_arrays(paper_problem(2), 32, 1)
+    res = O.excmg(32, 3, 1, arr.f, arr.g1, arr.g2, 1e-12, jacobi=True)
+    assert res.levels[-1].code == O.OK
+    t = golden_tables["problems"]["2"]
+    assert _sig3(O.norm2(res.u - arr.u)) == t["err2"][0]
+    assert _sig3(O.norminf(res.u - arr.u)) == t["errinf"][0]
