@@ -58,6 +58,16 @@ def lib():
             "oracle_level_solve_ex": (c_int, [c_int, c_int, dp, dp, dp, c_dbl, c_int, c_int,
                                               c_int, ip, ip, dp, dp]),
             "oracle_exp_finite": (c_int, [c_int, dp, dp, dp]),
+            "oracle2d_apply": (c_int, [c_int, c_int, dp, dp]),
+            "oracle2d_residual": (c_int, [c_int, c_int, dp, dp, dp]),
+            "oracle2d_rhs": (c_int, [c_int, c_int, dp, dp, dp, dp]),
+            "oracle2d_assemble": (c_int, [c_int, c_int, dp]),
+            "oracle2d_dsolve": (c_int, [c_int, c_int, dp, dp]),
+            "oracle2d_bicg": (c_int, [c_int, c_int, dp, dp, c_dbl, c_int, ip, dp]),
+            "oracle2d_level_solve": (c_int, [c_int, c_int, dp, dp, c_dbl, c_int, c_int, ip, ip,
+                                             dp, dp]),
+            "oracle2d_exp_finite": (c_int, [c_int, dp, dp, dp]),
+            "oracle2d_exp_true": (c_int, [c_int, dp, dp, dp]),
             "oracle_exp_true": (c_int, [c_int, dp, dp, dp]),
         }
         for name, (res, args) in sig.items():
@@ -346,4 +356,129 @@ def excmg(n_finest: int, n_levels: int, bc: int, f, g1, g2, tol: float, *,
         u_prev2, u_prev = u_prev, u
     res.u = u_prev
     res.ut = exp_true(n_finest, u_prev, u_prev2)
+    return res
+
+
+# ------------------------------------------------------------------ 2D (eq. bvp2d)
+
+def n_interior_2d(N: int) -> int:
+    return (N - 1) ** 2
+
+
+def apply_2d(N: int, bc: int, x) -> np.ndarray:
+    """y = A_h x for the 13-point scheme (homogeneous boundary data)."""
+    x = _f64(x).ravel()
+    y = np.empty(n_interior_2d(N))
+    _check("apply_2d", lib().oracle2d_apply(N, bc, _p(x), _p(y)))
+    return y
+
+
+def residual_2d(N: int, bc: int, b, x) -> np.ndarray:
+    b, x = _f64(b).ravel(), _f64(x).ravel()
+    r = np.empty(n_interior_2d(N))
+    _check("residual_2d", lib().oracle2d_residual(N, bc, _p(b), _p(x), _p(r)))
+    return r
+
+
+def rhs_2d(N: int, bc: int, f, g1, g2) -> np.ndarray:
+    f, g1, g2 = _f64(f), _f64(g1), _f64(g2)
+    for a in (f, g1, g2):
+        assert a.size == (N + 1) ** 2
+    b = np.empty(n_interior_2d(N))
+    _check("rhs_2d", lib().oracle2d_rhs(N, bc, _p(f), _p(g1), _p(g2), _p(b)))
+    return b
+
+
+def assemble_2d(N: int, bc: int) -> np.ndarray:
+    n = n_interior_2d(N)
+    A = np.empty((n, n))
+    _check("assemble_2d", lib().oracle2d_assemble(N, bc, _p(A)))
+    return A
+
+
+def dsolve_2d(N: int, bc: int, b) -> np.ndarray:
+    b = _f64(b).ravel()
+    x = np.empty(n_interior_2d(N))
+    _check("dsolve_2d", lib().oracle2d_dsolve(N, bc, _p(b), _p(x)))
+    return x
+
+
+def bicg_2d(N: int, bc: int, b, x0, eps: float, maxit: int = 100000):
+    b = _f64(b).ravel()
+    x = _f64(x0).ravel().copy()
+    it, rr = ctypes.c_int(0), ctypes.c_double(0.0)
+    rc = lib().oracle2d_bicg(N, bc, _p(b), _p(x), eps, maxit, ctypes.byref(it), ctypes.byref(rr))
+    if rc not in (OK, ENOCONV):
+        raise OracleError("bicg_2d", rc)
+    return x, it.value, rr.value, rc
+
+
+def level_solve_2d(N: int, bc: int, b, x0, eps: float, maxit: int = 100000, max_runs: int = 5):
+    b = _f64(b).ravel()
+    x = _f64(x0).ravel().copy()
+    it, runs = ctypes.c_int(0), ctypes.c_int(0)
+    rr, bb = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    rc = lib().oracle2d_level_solve(N, bc, _p(b), _p(x), eps, maxit, max_runs, ctypes.byref(it),
+                                    ctypes.byref(runs), ctypes.byref(rr), ctypes.byref(bb))
+    if rc not in (OK, ENOCONV):
+        raise OracleError("level_solve_2d", rc)
+    return x, LevelResult(N, it.value, runs.value, rr.value, bb.value, eps, rc)
+
+
+def exp_finite_2d(N: int, u1, u0) -> np.ndarray:
+    u1, u0 = _f64(u1).ravel(), _f64(u0).ravel()
+    w = np.empty((N + 1) ** 2)
+    _check("exp_finite_2d", lib().oracle2d_exp_finite(N, _p(u1), _p(u0), _p(w)))
+    return w.reshape(N + 1, N + 1)
+
+
+def exp_true_2d(N: int, uh, u2h) -> np.ndarray:
+    uh, u2h = _f64(uh).ravel(), _f64(u2h).ravel()
+    ut = np.empty((N + 1) ** 2)
+    _check("exp_true_2d", lib().oracle2d_exp_true(N, _p(uh), _p(u2h), _p(ut)))
+    return ut.reshape(N + 1, N + 1)
+
+
+def interior_2d(u) -> np.ndarray:
+    u = np.asarray(u, dtype=np.float64)
+    return np.ascontiguousarray(u[1:-1, 1:-1]).ravel()
+
+
+def to_nodes_2d(N: int, x, g1) -> np.ndarray:
+    u = np.array(np.asarray(g1, dtype=np.float64).reshape(N + 1, N + 1), copy=True)
+    u[1:-1, 1:-1] = np.asarray(x).reshape(N - 1, N - 1)
+    return u
+
+
+def excmg_2d(n_finest: int, n_levels: int, bc: int, f, g1, g2, tol: float, *,
+             maxit: int = 100000, max_runs: int = 5, keep_levels: bool = False) -> ExcmgResult:
+    """Algorithm 1 for the 2D equation: DSOLVE on levels 0 and 1, EXP_finite guesses,
+    Bi-CG level solves to eps_i, EXP_true on the finest grid."""
+    sizes = level_sizes(n_finest, n_levels)
+    M = n_finest + 1
+    f = np.asarray(f, dtype=np.float64).reshape(M, M)
+    g1 = np.asarray(g1, dtype=np.float64).reshape(M, M)
+    g2 = np.asarray(g2, dtype=np.float64).reshape(M, M)
+    L = n_levels - 2
+    res = ExcmgResult(u=None, ut=None)
+    u_prev2 = u_prev = None
+    for l, N in enumerate(sizes):
+        s = 1 << (n_levels - 1 - l)
+        fl, g1l, g2l = f[::s, ::s], g1[::s, ::s], g2[::s, ::s]
+        b = rhs_2d(N, bc, fl, g1l, g2l)
+        w = None
+        if l <= 1:
+            x = dsolve_2d(N, bc, b)
+        else:
+            w = exp_finite_2d(N, u_prev, u_prev2)
+            eps = level_tolerance(tol, l - 1, L)
+            x, st = level_solve_2d(N, bc, b, interior_2d(w), eps, maxit=maxit, max_runs=max_runs)
+            res.levels.append(st)
+        u = to_nodes_2d(N, x, g1l)
+        if keep_levels:
+            res.u_levels.append(u)
+            res.w_levels.append(w)
+        u_prev2, u_prev = u_prev, u
+    res.u = u_prev
+    res.ut = exp_true_2d(n_finest, u_prev, u_prev2)
     return res

@@ -347,16 +347,6 @@ int oracle_assemble(int N, int bc, double *A) {
 
 /* ------------------------------------------------------------- Bi-CG (Alg. 2) */
 
-/* One run of Algorithm 2 with M = I on A_h x = b, starting from x (updated in place).
- * shadow: the initial shadow residual r*_0, or NULL for r*_0 = r_0.  The adjoint iterate
- * x*_k never feeds back into x_k, so it is not formed.
- * literal_t: 1 forms the shadow product p*_k A by the row scatter of oracle_apply_transpose;
- * 0 forms it as A_h p*_k, which is the same vector because A_h equals its transpose entry
- * for entry (the integer coefficients of eq. method1 with the reflected fictitious points;
- * the test suite checks this on assembled matrices).  The two differ only in rounding.
- * Stops when the recurrence residual satisfies r.r <= (eps*eps)*(b.b), or after maxit
- * iterations (returns -3), or on breakdown (returns -4).  *iters gets the iteration count
- * and *rr_out the final recurrence r.r. */
 /* Algorithm 2 (Bi-CG with the preconditioner), real arithmetic.  M is diagonal: mdiag holds
  * its entries (NULL: M = I), so M^-1 v is v divided entrywise and v^T M^-1 = (M^-T v)^T =
  * M^-1 v as a column.  The shadow system is either
@@ -439,7 +429,14 @@ int oracle_bicg_ex(int N, int bc, const double *b, double *x, const double *shad
     return rc;
 }
 
-/* Algorithm 2 with M = I and r*_0 = shadow (or r_0). */
+/* One run of Algorithm 2 with M = I on A_h x = b, starting from x (updated in place).
+ * shadow: the initial shadow residual r*_0, or NULL for r*_0 = r_0; the adjoint iterate is
+ * not formed.  literal_t: 1 forms the shadow product p*_k A by the row scatter of
+ * oracle_apply_transpose; 0 forms it as A_h p*_k, which is the same vector because A_h
+ * equals its transpose entry for entry (the test suite checks this on assembled matrices);
+ * the two differ only in rounding.  Stops when r.r <= (eps*eps)*(b.b), after maxit
+ * iterations (-3) or on breakdown (-4); *iters gets the iteration count and *rr_out the
+ * final recurrence r.r. */
 int oracle_bicg(int N, int bc, const double *b, double *x, const double *shadow, double eps,
                 int maxit, int literal_t, int *iters, double *rr_out) {
     return oracle_bicg_ex(N, bc, b, x, shadow, NULL, NULL, NULL, eps, maxit, literal_t, iters,
