@@ -173,6 +173,27 @@ int excmg_bicg(int level, const double *b, double *x, double eps, int max_iters,
 int excmg_level_solve(int level, const double *b, double *x, double eps, int max_iters,
                       int max_runs, excmg_level_stats *st);
 
+/* ------------------------------------------------------------------------------------
+ * The 2D equation, eq. (bvp2d), through the same pipeline.  The paper writes the equation
+ * and names the 13-point scheme; the scheme here is the square of the 5-point Laplacian
+ * (20 u - 8 * axis neighbours + neighbours at distance 2 + 2 * diagonal neighbours), the
+ * fictitious points come from eqs. (reflection2) / (reflection4) along edge normals, and
+ * EXP_finite / EXP_true are the bi-quadratic and planar forms of Sec. 4.2.  Node arrays are
+ * (N+1)^2 (x fastest), interior vectors (N-1)^2; boundary data as in 3D (g2 on edges).
+ * excmg2d_setup makes the current context two-dimensional: excmg_apply_stencil, excmg_rhs,
+ * excmg_dsolve, excmg_bicg, excmg_bicg_ex, excmg_level_solve, excmg_diagonal and
+ * excmg_get_level_solution then act on its levels.  n_finest <= 16384; the coarsest grid
+ * may have up to 32 cells.
+ * ------------------------------------------------------------------------------------ */
+int excmg2d_setup(int n_finest, int n_levels, int bc_kind);
+/* Algorithm 1 in 2D; options, outputs and return codes as excmg_solve_ex. */
+int excmg2d_solve_ex(const excmg_opts *opts, const double *f, const double *g1, const double *g2,
+                     double *u_out, double *ut_out, excmg_stats *stats);
+/* w = EXP_finite(u1, u0) on the plane of n cells (n a multiple of 4). */
+int excmg2d_exp_finite(int n, const double *u1, const double *u0, double *w);
+/* ut = EXP_true(uh, u2h) on the plane of n cells (n even). */
+int excmg2d_exp_true(int n, const double *uh, const double *u2h, double *ut);
+
 /* Copy the finite-difference solution of level `level` from the last excmg_solve /
  * excmg_solve_ex on the current context (node array of N_l cells, boundary = g1): the
  * per-level solutions of Algorithm 1, e.g. to form ||w_h - u_h|| as in the paper's tables. */

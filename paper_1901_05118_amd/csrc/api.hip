@@ -143,6 +143,7 @@ void release_graphs();
 struct Ctx {
     bool ready = false;
     int n_finest = 0, n_levels = 0, bc = 0;
+    int dim = 3;                // 3: the 3D equation (eq. bvp); 2: the 2D one (eq. bvp2d)
     std::vector<Level> lv;
     // Bi-CG workspace (sized for the finest level)
     DBuf r, rs, p[2], ps[2], q, qs;
@@ -231,37 +232,47 @@ Geom choose_shape(int N, int bc, int kind) {
     return make_geom(n, bc, ty, zc);
 }
 
-void choose_shapes(Level &L, int bc) {
+void choose_shapes(Level &L, int bc, int dim = 3) {
+    if (dim == 2) {  // one pass per tile: more rows per workgroup on large planes
+        const int n = L.N - 1;
+        const int ty = n >= 1024 ? 16 : (n >= 96 ? 8 : 4);
+        L.g1 = L.g2 = L.g2f = make_geom_2d(n, bc, ty);
+        return;
+    }
     L.g1 = choose_shape(L.N, bc, 0);
     L.g2 = choose_shape(L.N, bc, 1);
     L.g2f = choose_shape(L.N, bc, 2);
 }
 
-int check_sizes(int n_finest, int n_levels, int bc) {
+int check_sizes(int n_finest, int n_levels, int bc, int dim = 3) {
     if (bc != 1 && bc != 2) return fail(EXCMG_EINVAL, "bc_kind must be 1 or 2 (got %d)", bc);
     if (n_levels < 3 || n_levels > EXCMG_MAX_LEVELS)
         return fail(EXCMG_EINVAL, "n_levels must be in 3..%d (got %d)", EXCMG_MAX_LEVELS,
                     n_levels);
-    if (n_finest < 8 || n_finest > 2048) return fail(EXCMG_EINVAL, "n_finest out of range");
+    if (n_finest < 8 || n_finest > (dim == 2 ? 16384 : 2048))
+        return fail(EXCMG_EINVAL, "n_finest out of range");
     const int N0 = n_finest >> (n_levels - 1);
     if (N0 < 2 || (N0 << (n_levels - 1)) != n_finest)
         return fail(EXCMG_EINVAL, "n_finest (%d) must be N0 * 2^(n_levels-1) with N0 >= 2",
                     n_finest);
-    if (N0 > 8)
-        return fail(EXCMG_EINVAL, "coarsest grid of %d cells is too large for DSOLVE (max 8)",
-                    N0);
+    const int maxN0 = dim == 2 ? 32 : 8;
+    if (N0 > maxN0)
+        return fail(EXCMG_EINVAL, "coarsest grid of %d cells is too large for DSOLVE (max %d)",
+                    N0, maxN0);
     return EXCMG_OK;
 }
 
-int setup(int n_finest, int n_levels, int bc) {
-    CKR(check_sizes(n_finest, n_levels, bc));
+int setup(int n_finest, int n_levels, int bc, int dim = 3) {
+    CKR(check_sizes(n_finest, n_levels, bc, dim));
     Ctx &c = g_ctx;
-    if (c.ready && c.n_finest == n_finest && c.n_levels == n_levels && c.bc == bc)
+    if (c.ready && c.n_finest == n_finest && c.n_levels == n_levels && c.bc == bc &&
+        c.dim == dim)
         return EXCMG_OK;
     c.release();
     c.n_finest = n_finest;
     c.n_levels = n_levels;
     c.bc = bc;
+    c.dim = dim;
     const int N0 = n_finest >> (n_levels - 1);
     c.lv.resize(n_levels);
     for (int l = 0; l < n_levels; l++) {
@@ -269,9 +280,9 @@ int setup(int n_finest, int n_levels, int bc) {
         L.index = l;
         L.N = N0 << l;
         L.n = L.N - 1;
-        L.nu = (long long)L.n * L.n * L.n;
-        L.nodes = (long long)(L.N + 1) * (L.N + 1) * (L.N + 1);
-        choose_shapes(L, bc);
+        L.nu = (long long)L.n * L.n * (dim == 2 ? 1 : L.n);
+        L.nodes = (long long)(L.N + 1) * (L.N + 1) * (dim == 2 ? 1 : (L.N + 1));
+        choose_shapes(L, bc, dim);
         CKR(L.b.ensure(L.nu * 8));
         CKR(L.x.ensure(L.nu * 8));
         CKR(L.u.ensure(L.nodes * 8));
@@ -295,7 +306,8 @@ int setup(int n_finest, int n_levels, int bc) {
     CKR(c.state.ensure(sizeof(BicgState)));
     CKR(c.scal.ensure(64 * sizeof(double)));
     CKR(c.info.ensure(64));
-    const long long nz1 = (long long)(n_finest / 2 + 1) * (n_finest / 2 + 1) * (n_finest / 2 + 1);
+    const long long nz1 =
+        (long long)(n_finest / 2 + 1) * (n_finest / 2 + 1) * (dim == 2 ? 1 : (n_finest / 2 + 1));
     CKR(c.vz1.ensure((size_t)nz1 * 8));
     CKH(hipHostMalloc((void **)&c.host_state, 3 * sizeof(BicgState), hipHostMallocDefault));
     for (hipEvent_t &e : c.poll_ev) CKH(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -305,7 +317,8 @@ int setup(int n_finest, int n_levels, int bc) {
         Level &L = c.lv[l];
         const int n = (int)L.nu;
         CKR(c.chol[l].ensure((size_t)n * n * 8));
-        CKH(dense_assemble(L.N, bc, c.chol[l].as<double>(), g_stream));
+        if (dim == 2) CKH(dense_assemble_2d(L.N, bc, c.chol[l].as<double>(), g_stream));
+        else CKH(dense_assemble(L.N, bc, c.chol[l].as<double>(), g_stream));
         CKH(dense_cholesky(n, c.chol[l].as<double>(), c.info.as<int>(), g_stream));
         int info = 0;
         CKH(hipMemcpyAsync(&info, c.info.p, sizeof(int), hipMemcpyDeviceToHost, g_stream));
@@ -622,8 +635,8 @@ int bicg_run(const Level &L, const double *b, double *x, double eps, int maxit, 
 const double *level_diagonal(Level &L) {
     if (!L.diag.p) {
         if (L.diag.ensure((size_t)L.nu * 8) != EXCMG_OK) return nullptr;
-        if (operator_diagonal(L.n, g_ctx.bc == 1 ? 1.0 : -1.0, L.diag.as<double>(), g_stream) !=
-            hipSuccess)
+        if (operator_diagonal(L.n, g_ctx.bc == 1 ? 1.0 : -1.0, L.diag.as<double>(), g_stream,
+                              g_ctx.dim) != hipSuccess)
             return nullptr;
     }
     return L.diag.as<double>();
@@ -880,15 +893,22 @@ int solve_cascade(const excmg_opts &o, const double *f, const double *g1, const 
         excmg_level_stats ls{};
         ls.n = Lv.N;
         CKH(hipEventRecord(evl0, g_stream));
-        CKH(rhs_assemble(Lv.N, c.bc, s, Nf, f, g1, g2, Lv.b.as<double>(), g_stream));
+        if (c.dim == 2) CKH(rhs_assemble_2d(Lv.N, c.bc, s, Nf, f, g1, g2, Lv.b.as<double>(), g_stream));
+        else CKH(rhs_assemble(Lv.N, c.bc, s, Nf, f, g1, g2, Lv.b.as<double>(), g_stream));
         if (l <= 1) {
             CKH(dense_solve((int)Lv.nu, c.chol[l].as<double>(), Lv.b.as<double>(),
                             Lv.x.as<double>(), c.chol_y.as<double>(), g_stream));
             ls.status = EXCMG_OK;
         } else {
-            CKH(exp_finite(Lv.N, c.lv[l - 1].u.as<double>(), c.lv[l - 2].u.as<double>(),
-                           c.vz1.as<double>(), Lv.u.as<double>(), g_stream));
-            CKH(from_nodes(Lv.N, Lv.u.as<double>(), Lv.x.as<double>(), g_stream));
+            if (c.dim == 2) {
+                CKH(exp_finite_2d(Lv.N, c.lv[l - 1].u.as<double>(), c.lv[l - 2].u.as<double>(),
+                                  c.vz1.as<double>(), Lv.u.as<double>(), g_stream));
+                CKH(from_nodes_2d(Lv.N, Lv.u.as<double>(), Lv.x.as<double>(), g_stream));
+            } else {
+                CKH(exp_finite(Lv.N, c.lv[l - 1].u.as<double>(), c.lv[l - 2].u.as<double>(),
+                               c.vz1.as<double>(), Lv.u.as<double>(), g_stream));
+                CKH(from_nodes(Lv.N, Lv.u.as<double>(), Lv.x.as<double>(), g_stream));
+            }
             const double eps = level_tolerance(o.tol, l - 1, L);
             if (mixed && reliable)
                 CKR(level_solve_reliable(Lv, Lv.b.as<double>(), Lv.x.as<double>(), eps, maxit,
@@ -901,7 +921,10 @@ int solve_cascade(const excmg_opts &o, const double *f, const double *g1, const 
                                 &ls, jacobi ? level_diagonal(Lv) : nullptr));
             if (ls.status != EXCMG_OK && worst == EXCMG_OK) worst = ls.status;
         }
-        CKH(to_nodes<double>(Lv.N, s, Nf, Lv.x.as<double>(), g1, Lv.u.as<double>(), g_stream));
+        if (c.dim == 2)
+            CKH(to_nodes_2d<double>(Lv.N, s, Nf, Lv.x.as<double>(), g1, Lv.u.as<double>(), g_stream));
+        else
+            CKH(to_nodes<double>(Lv.N, s, Nf, Lv.x.as<double>(), g1, Lv.u.as<double>(), g_stream));
         CKH(hipEventRecord(evl1, g_stream));
         CKH(hipEventSynchronize(evl1));
         float ms = 0.f;
@@ -910,7 +933,12 @@ int solve_cascade(const excmg_opts &o, const double *f, const double *g1, const 
         if (st && l < EXCMG_MAX_LEVELS) st->level[l] = ls;
     }
     const Level &F = c.lv[nl - 1];
-    if (ut_out) CKH(exp_true(Nf, F.u.as<double>(), c.lv[nl - 2].u.as<double>(), ut_out, g_stream));
+    if (ut_out) {
+        if (c.dim == 2)
+            CKH(exp_true_2d(Nf, F.u.as<double>(), c.lv[nl - 2].u.as<double>(), ut_out, g_stream));
+        else
+            CKH(exp_true(Nf, F.u.as<double>(), c.lv[nl - 2].u.as<double>(), ut_out, g_stream));
+    }
     if (u_out) CKH(hipMemcpyAsync(u_out, F.u.p, F.nodes * 8, hipMemcpyDeviceToDevice, g_stream));
     CKH(hipEventRecord(ev1, g_stream));
     CKH(hipEventSynchronize(ev1));
@@ -1392,14 +1420,19 @@ int excmg_rhs(int level, const double *f, const double *g1, const double *g2, do
     if (!f || !g1 || !g2 || !b) return fail(EXCMG_EINVAL, "NULL array");
     const Ctx &c = g_ctx;
     const Level &L = c.lv[level];
-    const size_t nb = (size_t)(c.n_finest + 1) * (c.n_finest + 1) * (c.n_finest + 1) * 8;
+    const size_t nb = (size_t)(c.n_finest + 1) * (c.n_finest + 1) *
+                      (c.dim == 2 ? 1 : (c.n_finest + 1)) * 8;
     Arg af(f, nb), a1(g1, nb), a2(g2, nb), ab(b, L.nu * 8);
     CKR(af.in());
     CKR(a1.in());
     CKR(a2.in());
     CKR(ab.out());
-    CKH(rhs_assemble(L.N, c.bc, 1 << (c.n_levels - 1 - level), c.n_finest, af.p<double>(),
-                     a1.p<double>(), a2.p<double>(), ab.p<double>(), g_stream));
+    if (c.dim == 2)
+        CKH(rhs_assemble_2d(L.N, c.bc, 1 << (c.n_levels - 1 - level), c.n_finest, af.p<double>(),
+                            a1.p<double>(), a2.p<double>(), ab.p<double>(), g_stream));
+    else
+        CKH(rhs_assemble(L.N, c.bc, 1 << (c.n_levels - 1 - level), c.n_finest, af.p<double>(),
+                         a1.p<double>(), a2.p<double>(), ab.p<double>(), g_stream));
     CKR(ab.back());
     CKH(hipStreamSynchronize(g_stream));
     return EXCMG_OK;
@@ -1567,8 +1600,8 @@ int excmg_exp_true(int n, const double *uh, const double *u2h, double *ut) {
     return EXCMG_OK;
 }
 
-int excmg_solve_ex(const excmg_opts *opts, const double *f, const double *g1, const double *g2,
-                   double *u_out, double *ut_out, excmg_stats *st) {
+int solve_ex_dim(const excmg_opts *opts, const double *f, const double *g1, const double *g2,
+                 double *u_out, double *ut_out, excmg_stats *st, int dim) {
     g_err[0] = 0;
     if (!opts) return fail(EXCMG_EINVAL, "NULL options");
     const excmg_opts o = *opts;
@@ -1584,8 +1617,9 @@ int excmg_solve_ex(const excmg_opts *opts, const double *f, const double *g1, co
         return fail(EXCMG_EINVAL, "precond %d not supported", o.precond);
     if (o.precond == EXCMG_PRECOND_JACOBI && (o.precision != EXCMG_FP64 || o.method != EXCMG_BICG))
         return fail(EXCMG_EINVAL, "the Jacobi preconditioner runs with FP64 Bi-CG only");
-    CKR(setup(o.n_finest, o.n_levels, o.bc_kind));
-    const size_t nb = (size_t)(o.n_finest + 1) * (o.n_finest + 1) * (o.n_finest + 1) * 8;
+    CKR(setup(o.n_finest, o.n_levels, o.bc_kind, dim));
+    const size_t nb = (size_t)(o.n_finest + 1) * (o.n_finest + 1) *
+                      (dim == 2 ? 1 : (o.n_finest + 1)) * 8;
     Arg af(f, nb), a1(g1, nb), a2(g2, nb), au(u_out, nb), at(ut_out, nb);
     CKR(af.in());
     CKR(a1.in());
@@ -1603,6 +1637,53 @@ int excmg_solve_ex(const excmg_opts *opts, const double *f, const double *g1, co
     if (ut_out) CKR(at.back());
     CKH(hipStreamSynchronize(g_stream));
     return rc;
+}
+
+int excmg_solve_ex(const excmg_opts *opts, const double *f, const double *g1, const double *g2,
+                   double *u_out, double *ut_out, excmg_stats *st) {
+    return solve_ex_dim(opts, f, g1, g2, u_out, ut_out, st, 3);
+}
+
+int excmg2d_solve_ex(const excmg_opts *opts, const double *f, const double *g1, const double *g2,
+                     double *u_out, double *ut_out, excmg_stats *st) {
+    return solve_ex_dim(opts, f, g1, g2, u_out, ut_out, st, 2);
+}
+
+int excmg2d_setup(int n_finest, int n_levels, int bc_kind) {
+    g_err[0] = 0;
+    return setup(n_finest, n_levels, bc_kind, 2);
+}
+
+int excmg2d_exp_finite(int n, const double *u1, const double *u0, double *w) {
+    g_err[0] = 0;
+    if (n < 4 || n % 4 != 0 || n > 16384) return fail(EXCMG_EINVAL, "n must be a multiple of 4");
+    if (!u1 || !u0 || !w) return fail(EXCMG_EINVAL, "NULL array");
+    const size_t m1 = (size_t)(n / 2 + 1), m0 = (size_t)(n / 4 + 1), m = (size_t)(n + 1);
+    Arg a1(u1, m1 * m1 * 8), a0(u0, m0 * m0 * 8), aw(w, m * m * 8);
+    CKR(a1.in());
+    CKR(a0.in());
+    CKR(aw.out());
+    DBuf v;
+    CKR(v.ensure(m1 * m1 * 8));
+    CKH(exp_finite_2d(n, a1.p<double>(), a0.p<double>(), v.as<double>(), aw.p<double>(), g_stream));
+    CKR(aw.back());
+    CKH(hipStreamSynchronize(g_stream));
+    return EXCMG_OK;
+}
+
+int excmg2d_exp_true(int n, const double *uh, const double *u2h, double *ut) {
+    g_err[0] = 0;
+    if (n < 2 || n % 2 != 0 || n > 16384) return fail(EXCMG_EINVAL, "n must be even");
+    if (!uh || !u2h || !ut) return fail(EXCMG_EINVAL, "NULL array");
+    const size_t m = (size_t)(n + 1), mc = (size_t)(n / 2 + 1);
+    Arg ah(uh, m * m * 8), ac(u2h, mc * mc * 8), at(ut, m * m * 8);
+    CKR(ah.in());
+    CKR(ac.in());
+    CKR(at.out());
+    CKH(exp_true_2d(n, ah.p<double>(), ac.p<double>(), at.p<double>(), g_stream));
+    CKR(at.back());
+    CKH(hipStreamSynchronize(g_stream));
+    return EXCMG_OK;
 }
 
 int excmg_solve(int n_finest, int n_levels, int bc_kind, const double *f, const double *g1,

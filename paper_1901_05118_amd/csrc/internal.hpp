@@ -15,9 +15,11 @@ struct Geom {
     int zc;
     int ntiles;
     double sgn;                     // fictitious-point sign: +1 first kind, -1 second kind
+    int dim = 3;                    // 3: n^3 unknowns (z-marched); 2: n^2 unknowns (one plane)
 };
 
 Geom make_geom(int n, int bc, int ty, int zc);
+Geom make_geom_2d(int n, int bc, int ty);   // the 13-point scheme on an n x n plane
 
 // Device-resident state of one Bi-CG run (Algorithm 2); all scalars FP64.
 struct BicgState {
@@ -121,8 +123,9 @@ hipError_t bicg_update_ex(long long n, const BicgState *s, double *x, const doub
 // a run started from 2-valued partials: rho = first value (r*.M^-1 r), r.r = second
 hipError_t bicg_start2(BicgState *s, const Pair *part, int count, double eps, int maxit,
                        hipStream_t st);
-// diag(A_h) of an n^3-unknown grid: 42 + sgn * (faces the unknown is next to)
-hipError_t operator_diagonal(int n, double sgn, double *d, hipStream_t st);
+// diag(A_h): 42 + sgn * (faces the unknown is next to) on an n^3 grid, or 20 + sgn * (edges)
+// on an n^2 plane (dim 2)
+hipError_t operator_diagonal(int n, double sgn, double *d, hipStream_t st, int dim = 3);
 // status = running (or iteration cap), thr = new recurrence threshold
 hipError_t state_resume(BicgState *s, double thr, hipStream_t st);
 
@@ -162,6 +165,18 @@ hipError_t exp_true(int N, const double *uh, const double *u2h, double *ut, hipS
 
 // dense direct solver of the two coarsest levels
 hipError_t dense_assemble(int N, int bc, double *A, hipStream_t st);
+
+// the same level operations for the 2D equation (node arrays (N+1)^2, interior (N-1)^2)
+hipError_t rhs_assemble_2d(int N, int bc, int stride, int Nf, const double *f, const double *g1,
+                           const double *g2, double *b, hipStream_t st);
+template <typename T>
+hipError_t to_nodes_2d(int N, int stride, int Nf, const T *x, const double *g1, double *u,
+                       hipStream_t st);
+hipError_t from_nodes_2d(int N, const double *u, double *x, hipStream_t st);
+hipError_t exp_finite_2d(int N, const double *u1, const double *u0, double *v_scratch, double *w,
+                         hipStream_t st);
+hipError_t exp_true_2d(int N, const double *uh, const double *u2h, double *ut, hipStream_t st);
+hipError_t dense_assemble_2d(int N, int bc, double *A, hipStream_t st);
 hipError_t dense_cholesky(int n, double *A, int *info, hipStream_t st);
 hipError_t dense_solve(int n, const double *L, const double *b, double *x, double *y,
                        hipStream_t st);

@@ -214,19 +214,21 @@ hipError_t bicg_update_ex(long long n, const BicgState *s, double *x, const doub
     return hipGetLastError();
 }
 
-__global__ void __launch_bounds__(kVecThreads) k_operator_diagonal(int n, double sgn, double *d) {
-    const i64 total = (i64)n * n * n;
+__global__ void __launch_bounds__(kVecThreads)
+    k_operator_diagonal(int n, double sgn, double *d, int dim) {
+    const i64 total = (i64)n * n * (dim == 2 ? 1 : n);
     const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total) return;
-    const int i = (int)(t % n), j = (int)((t / n) % n), k = (int)(t / ((i64)n * n));
-    const int m = (i == 0) + (i == n - 1) + (j == 0) + (j == n - 1) + (k == 0) + (k == n - 1);
-    d[t] = 42.0 + sgn * (double)m;
+    const int i = (int)(t % n), j = (int)((t / n) % n), k = (dim == 2) ? 1 : (int)(t / ((i64)n * n));
+    int m = (i == 0) + (i == n - 1) + (j == 0) + (j == n - 1);
+    if (dim == 3) m += (k == 0) + (k == n - 1);
+    d[t] = (dim == 2 ? 20.0 : 42.0) + sgn * (double)m;
 }
 
-hipError_t operator_diagonal(int n, double sgn, double *d, hipStream_t st) {
-    const i64 total = (i64)n * n * n;
+hipError_t operator_diagonal(int n, double sgn, double *d, hipStream_t st, int dim) {
+    const i64 total = (i64)n * n * (dim == 2 ? 1 : n);
     hipLaunchKernelGGL(k_operator_diagonal, dim3((unsigned)((total + kVecThreads - 1) / kVecThreads)),
-                       dim3(kVecThreads), 0, st, n, sgn, d);
+                       dim3(kVecThreads), 0, st, n, sgn, d, dim);
     return hipGetLastError();
 }
 

@@ -1,4 +1,5 @@
 // Launchers of the z-marched stencil kernels (device code in zmarch.hpp).
+#include "plane2d.hpp"
 #include "zmarch.hpp"
 
 namespace excmg {
@@ -18,11 +19,24 @@ Geom make_geom(int n, int bc, int ty, int zc) {
     return g;
 }
 
+Geom make_geom_2d(int n, int bc, int ty) {
+    Geom g = make_geom(n, bc, ty, 1);
+    g.zc = 1;
+    g.tiles_z = 1;
+    g.ntiles = g.tiles_x * g.tiles_y;
+    g.dim = 2;
+    return g;
+}
+
 template <int TY, typename T, class In, class Out, int NA>
 static hipError_t launch(const Geom &g, const In &in, const Out &out, hipStream_t st) {
     dim3 block(kWave, TY);
-    hipLaunchKernelGGL((zmarch<NA, TY, T, In, Out>), dim3(xcd_grid(g.ntiles)), block, 0, st, g,
-                       in, out);
+    if (g.dim == 2)
+        hipLaunchKernelGGL((plane2d<NA, TY, T, In, Out>), dim3(xcd_grid(g.ntiles)), block, 0, st,
+                           g, in, out);
+    else
+        hipLaunchKernelGGL((zmarch<NA, TY, T, In, Out>), dim3(xcd_grid(g.ntiles)), block, 0, st,
+                           g, in, out);
     return hipGetLastError();
 }
 

@@ -18,7 +18,7 @@ __all__ = [
     "lib_path", "load", "set_stream", "setup", "apply_stencil", "apply_operator", "rhs", "dsolve", "bicg",
     "level_solve", "exp_finite", "exp_true", "solve", "solve_ex", "profile_sweep",
     "set_shape", "get_shape", "set_timing", "get_timing", "autotune", "solve_batch",
-    "get_level_solution",
+    "get_level_solution", "setup_2d", "solve_ex_2d", "exp_finite_2d", "exp_true_2d",
     "Problem",
     "last_error", "finalize",
     "LevelStats", "Stats",
@@ -101,6 +101,11 @@ def load():
         "excmg_bicg_ex": (c_int, [c_int, dp, dp, dp, dp, dp, dp, c_dbl, c_int, ip,
                                   ctypes.POINTER(c_dbl)]),
         "excmg_diagonal": (c_int, [c_int, dp]),
+        "excmg2d_setup": (c_int, [c_int, c_int, c_int]),
+        "excmg2d_solve_ex": (c_int, [ctypes.POINTER(Opts), dp, dp, dp, dp, dp,
+                                     ctypes.POINTER(Stats)]),
+        "excmg2d_exp_finite": (c_int, [c_int, dp, dp, dp]),
+        "excmg2d_exp_true": (c_int, [c_int, dp, dp, dp]),
         "excmg_exp_true": (c_int, [c_int, dp, dp, dp]),
         "excmg_solve": (c_int, [c_int, c_int, c_int, dp, dp, dp, c_dbl, dp]),
         "excmg_solve_ex": (c_int, [ctypes.POINTER(Opts), dp, dp, dp, dp, dp,
@@ -265,6 +270,37 @@ def solve_ex(n_finest: int, n_levels: int, bc_kind: int, f, g1, g2, tol: float, 
     if rc not in (OK, ENOCONV, EBREAKDOWN):
         _check("excmg_solve_ex", rc)
     return rc, st
+
+
+def setup_2d(n_finest: int, n_levels: int, bc_kind: int):
+    """Make the current context the 2D problem (eq. bvp2d) of n_finest^2 cells."""
+    _check("excmg2d_setup", load().excmg2d_setup(n_finest, n_levels, bc_kind))
+
+
+def solve_ex_2d(n_finest: int, n_levels: int, bc_kind: int, f, g1, g2, tol: float, u_out,
+                ut_out=None, precision: int = FP64, max_iters: int = 0, max_runs: int = 0,
+                inner_tol: float = 0.0, max_outer: int = 0, method: int = BICG,
+                refine: int = RELIABLE, precond: int = PRECOND_NONE):
+    """Algorithm 1 for the 2D equation.  Returns (code, Stats)."""
+    o = Opts(n_finest, n_levels, bc_kind, precision, tol, max_iters, max_runs, inner_tol,
+             max_outer, 0, method, refine, precond)
+    st = Stats()
+    rc = load().excmg2d_solve_ex(ctypes.byref(o), _ptr(f, name="f"), _ptr(g1, name="g1"),
+                                 _ptr(g2, name="g2"), _ptr(u_out, name="u_out"),
+                                 _ptr(ut_out, name="ut_out"), ctypes.byref(st))
+    if rc not in (OK, ENOCONV, EBREAKDOWN):
+        _check("excmg2d_solve_ex", rc)
+    return rc, st
+
+
+def exp_finite_2d(n: int, u1, u0, w):
+    _check("excmg2d_exp_finite", load().excmg2d_exp_finite(n, _ptr(u1, name="u1"),
+                                                           _ptr(u0, name="u0"), _ptr(w, name="w")))
+
+
+def exp_true_2d(n: int, uh, u2h, ut):
+    _check("excmg2d_exp_true", load().excmg2d_exp_true(n, _ptr(uh, name="uh"),
+                                                       _ptr(u2h, name="u2h"), _ptr(ut, name="ut")))
 
 
 def profile_sweep(which: int, precision: int = FP64, reps: int = 20):

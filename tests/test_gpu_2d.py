@@ -1,0 +1,133 @@
+"""The 2D equation (eq. bvp2d) through the GPU pipeline against the 2D oracle: every kernel
+and the whole cascade evaluate the same formulas in the same order, so results are compared
+for exact equality (DSOLVE to 1e-14)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from manufactured.twod import family_2d, make_arrays_2d, sine_2d
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+# (N_finest, levels): coarsest grids of 4 to 24 cells, ragged tiles included
+CASES = [(16, 3), (64, 4), (96, 3), (256, 5)]
+
+
+@pytest.fixture(scope="module")
+def ex():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1901_05118_amd as ex
+    ex.load()
+    yield ex
+    ex.finalize()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.mark.parametrize("bc", [1, 2])
+@pytest.mark.parametrize("case", CASES)
+def test_operator_and_rhs_equal_the_oracle(ex, case, bc):
+    N, nl = case
+    ex.setup_2d(N, nl, bc)
+    rng = np.random.default_rng(N + bc)
+    for level in range(nl):
+        Nl = N >> (nl - 1 - level)
+        x = rng.standard_normal((Nl - 1) ** 2)
+        y = torch.empty_like(dev(x))
+        ex.apply_stencil(level, 0, dev(x), y)
+        np.testing.assert_array_equal(host(y), O.apply_2d(Nl, bc, x))
+    arr = make_arrays_2d(family_2d(3), N, bc)
+    b = torch.empty((N - 1) ** 2, dtype=torch.float64, device="cuda")
+    ex.rhs(nl - 1, dev(arr.f), dev(arr.g1), dev(arr.g2), b)
+    np.testing.assert_array_equal(host(b), O.rhs_2d(N, bc, arr.f, arr.g1, arr.g2))
+
+
+@pytest.mark.parametrize("N", [4, 16, 96, 512])
+def test_extrapolations_equal_the_oracle(ex, N):
+    rng = np.random.default_rng(N)
+    u1 = rng.standard_normal((N // 2 + 1,) * 2)
+    u0 = rng.standard_normal((N // 4 + 1,) * 2)
+    w = torch.empty((N + 1,) * 2, dtype=torch.float64, device="cuda")
+    ex.exp_finite_2d(N, dev(u1), dev(u0), w)
+    np.testing.assert_array_equal(host(w), O.exp_finite_2d(N, u1, u0))
+    uh = rng.standard_normal((N + 1,) * 2)
+    ut = torch.empty_like(w)
+    ex.exp_true_2d(N, dev(uh), dev(u1), ut)
+    np.testing.assert_array_equal(host(ut), O.exp_true_2d(N, uh, u1))
+
+
+@pytest.mark.parametrize("bc", [1, 2])
+def test_dsolve_and_bicg_equal_the_oracle(ex, bc):
+    N, nl = 128, 4      # levels of 16, 32, 64, 128 cells
+    ex.setup_2d(N, nl, bc)
+    rng = np.random.default_rng(bc)
+    for level, Nl in ((0, 16), (1, 32)):
+        b = rng.standard_normal((Nl - 1) ** 2)
+        x = torch.empty_like(dev(b))
+        ex.dsolve(level, dev(b), x)
+        ref = O.dsolve_2d(Nl, bc, b)
+        assert np.abs(host(x) - ref).max() <= 1e-13 * np.abs(ref).max()
+    b = rng.standard_normal(127 ** 2)
+    x0 = rng.standard_normal(127 ** 2) * 1e-2
+    x = dev(x0)
+    rc, it, rr = ex.bicg(3, dev(b), x, 1e-12, max_iters=80)
+    xo, ito, rro, rco = O.bicg_2d(128, bc, b, x0, 1e-12, maxit=80)
+    assert it == ito and rr == rro
+    np.testing.assert_array_equal(host(x), xo)
+
+
+@pytest.mark.parametrize("bc", [1, 2])
+@pytest.mark.parametrize("case", [(64, 4), (96, 3), (256, 5)])
+def test_cascade_equals_the_oracle(ex, case, bc):
+    N, nl = case
+    arr = make_arrays_2d(family_2d(11), N, bc)
+    u = torch.empty((N + 1,) * 2, dtype=torch.float64, device="cuda")
+    ut = torch.empty_like(u)
+    rc, st = ex.solve_ex_2d(N, nl, bc, dev(arr.f), dev(arr.g1), dev(arr.g2), 1e-10, u, ut)
+    ref = O.excmg_2d(N, nl, bc, arr.f, arr.g1, arr.g2, 1e-10)
+    assert rc in (ex.OK, ex.ENOCONV)
+    assert [l["status"] for l in st.levels()[2:]] == [s.code for s in ref.levels]
+    assert [l["iterations"] for l in st.levels()[2:]] == [s.iters for s in ref.levels]
+    np.testing.assert_array_equal(host(u), ref.u)
+    np.testing.assert_array_equal(host(ut), ref.ut)
+
+
+@pytest.mark.parametrize("refine", ["reliable", "restart"])
+def test_mixed_cascade_meets_tolerance_and_accuracy(ex, refine):
+    N, nl, bc = 512, 6, 2
+    arr = make_arrays_2d(family_2d(5), N, bc)
+    u = torch.empty((N + 1,) * 2, dtype=torch.float64, device="cuda")
+    mode = ex.RELIABLE if refine == "reliable" else ex.RESTART
+    rc, st = ex.solve_ex_2d(N, nl, bc, dev(arr.f), dev(arr.g1), dev(arr.g2), 1e-9, u,
+                            precision=ex.MIXED, refine=mode)
+    assert rc == ex.OK, ex.last_error()
+    ug = host(u)
+    b = O.rhs_2d(N, bc, arr.f, arr.g1, arr.g2)
+    r = O.residual_2d(N, bc, b, O.interior_2d(ug))
+    assert np.sqrt(O.dot(r, r) / O.dot(b, b)) <= 1e-9
+    u64 = torch.empty_like(u)
+    ex.solve_ex_2d(N, nl, bc, dev(arr.f), dev(arr.g1), dev(arr.g2), 1e-9, u64)
+    e64 = O.norm2(host(u64) - arr.u)
+    assert abs(O.norm2(ug - arr.u) - e64) <= 0.01 * e64
+
+
+def test_cg_specialisation_is_bit_identical_in_2d(ex):
+    N, nl, bc = 256, 5, 1
+    arr = make_arrays_2d(sine_2d(), N, bc)
+    ub = torch.empty((N + 1,) * 2, dtype=torch.float64, device="cuda")
+    uc = torch.empty_like(ub)
+    rc1, st1 = ex.solve_ex_2d(N, nl, bc, dev(arr.f), dev(arr.g1), dev(arr.g2), 1e-10, ub)
+    rc2, st2 = ex.solve_ex_2d(N, nl, bc, dev(arr.f), dev(arr.g1), dev(arr.g2), 1e-10, uc,
+                              method=ex.CG)
+    assert rc1 == rc2 == ex.OK
+    np.testing.assert_array_equal(host(ub), host(uc))
