@@ -87,6 +87,53 @@ def cpu_baseline(arr, N, nl, bc, iters):
                       f"{N}^3-cell finest level of the same problem, {dt:.1f} s"}
 
 
+def plane_leg(ex, torch, np, steps):
+    """The 2D equation (eq. bvp2d) through the same pipeline: 4096^2 cells over 8 levels
+    (direct levels of 32^2 and 64^2 cells), second kind, seeded exponential-plus-sines
+    solution, tol 1e-8, FP64 and mixed."""
+    from manufactured.twod import family_2d, make_arrays_2d
+    N, nl, bc = 4096, 8, 2
+    arr = make_arrays_2d(family_2d(7), N, bc)
+    f, g1, g2 = (torch.from_numpy(a).cuda() for a in (arr.f, arr.g1, arr.g2))
+    u = torch.empty_like(f)
+    res = {"workload": f"2D EXCMG {N}^2 cells, bc kind {bc}, tol 1e-8", "n_finest": N,
+           "n_levels": nl}
+    for prec, name in ((ex.FP64, "fp64"), (ex.MIXED, "mixed")):
+        ex.solve_ex_2d(N, nl, bc, f, g1, g2, 1e-8, u, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            rc, st = ex.solve_ex_2d(N, nl, bc, f, g1, g2, 1e-8, u, precision=prec)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        if rc != ex.OK:
+            raise RuntimeError(f"2D solve failed: {rc} {ex.last_error()}")
+        lv = st.levels()
+        lups = sum(((l["n"] - 1) ** 2) * l["iterations"] for l in lv)
+        e = u.cpu().numpy() - arr.u
+        res[name] = {"ms": round(ms, 2), "glups": round(lups / (ms * 1e-3) / 1e9, 3),
+                     "iterations": [l["iterations"] for l in lv],
+                     "u_rms_error": float(np.sqrt(np.mean(e * e)))}
+        log(f"2d {name}: {res[name]}")
+    return res
+
+
+def jacobi_leg(ex, torch, np, N, nl, bc, tol, f, g1, g2, u, steps):
+    """Algorithm 2 with the Jacobi preconditioner M = diag(A_h) on the same 3D workload."""
+    ex.solve_ex(N, nl, bc, f, g1, g2, tol, u, precond=ex.PRECOND_JACOBI)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rc, st = ex.solve_ex(N, nl, bc, f, g1, g2, tol, u, precond=ex.PRECOND_JACOBI)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    if rc != ex.OK:
+        raise RuntimeError(f"Jacobi solve failed: {rc} {ex.last_error()}")
+    res = {"ms": round(ms, 2), "iterations": [l["iterations"] for l in st.levels()]}
+    log(f"jacobi fp64: {res}")
+    return res
+
+
 def batch_leg(ex, torch, np):
     """64 independent problems of 32^3..128^3 cells (mixed boundary kinds), tol 1e-8:
     batched against one solve after another, FP64 and mixed precision."""
@@ -140,6 +187,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch leg")
+    ap.add_argument("--no-2d", action="store_true", help="skip the 2D (4096^2) leg")
+    ap.add_argument("--no-jacobi", action="store_true", help="skip the Jacobi-preconditioned leg")
     ap.add_argument("--autotune", action="store_true",
                     help="re-time every tile shape first instead of the built-in tuned table")
     args = ap.parse_args()
@@ -285,8 +334,12 @@ def main():
     }
     if tuned:
         out["autotuned_shapes"] = tuned
+    if not args.no_jacobi:
+        out["jacobi_fp64"] = jacobi_leg(ex, torch, np, N, nl, bc, tol, f, g1, g2, u, args.steps)
     if not args.no_batch:
         out["batch"] = batch_leg(ex, torch, np)
+    if not args.no_2d:
+        out["plane_2d"] = plane_leg(ex, torch, np, args.steps)
     if not args.no_cpu:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(arr, N, nl, bc, args.cpu_iters)

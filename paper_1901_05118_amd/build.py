@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libexcmg.so")
-SOURCES = ["stencil.hip", "kernels.hip", "kernels2d.hip", "batch.hip", "api.hip"]
+SOURCES = ["stencil.hip", "kernels.hip", "kernels2d.hip", "direct.hip", "batch.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -151,7 +151,8 @@ struct Ctx {
     DBuf part_a, part_b;        // Dot2 partials of the two sweeps
     DBuf state;                 // BicgState
     DBuf scal;                  // misc device scalars
-    DBuf chol[2], chol_y;       // Cholesky factors of levels 0 and 1, solve scratch
+    DBuf chol[2];               // banded Cholesky factors of levels 0 and 1
+    int chol_w[2] = {0, 0};     // their lower bandwidths
     DBuf info;
     DBuf vz1;                   // EXP_finite Z1 scratch
     BicgState *host_state = nullptr;  // pinned; 3 slots (synchronous reads, pipelined polls)
@@ -170,7 +171,7 @@ struct Ctx {
         p[0].release(); p[1].release(); ps[0].release(); ps[1].release();
         q.release(); qs.release(); ubest.release();
         part_a.release(); part_b.release(); state.release(); scal.release();
-        chol[0].release(); chol[1].release(); chol_y.release(); info.release(); vz1.release();
+        chol[0].release(); chol[1].release(); info.release(); vz1.release();
         if (host_state) (void)hipHostFree(host_state);
         for (hipEvent_t &e : poll_ev) {
             if (e) (void)hipEventDestroy(e);
@@ -262,6 +263,24 @@ int check_sizes(int n_finest, int n_levels, int bc, int dim = 3) {
     return EXCMG_OK;
 }
 
+// Banded Cholesky factor of a direct level into C (nu x (band_width + 1) doubles); info
+// holds at least two ints of device scratch.
+int factor_band(int N, int bc, int dim, double *C, int *info, hipStream_t st) {
+    const int w = band_width(N, dim);
+    const int nu = dim == 2 ? (N - 1) * (N - 1) : (N - 1) * (N - 1) * (N - 1);
+    CKH(hipMemsetAsync(info, 0, 2 * sizeof(int), st));
+    CKH(band_assemble(N, bc, dim, w, C, info + 1, st));
+    CKH(band_cholesky(nu, w, C, info, st));
+    int h[2] = {0, 0};
+    CKH(hipMemcpyAsync(h, info, sizeof(h), hipMemcpyDeviceToHost, st));
+    CKH(hipStreamSynchronize(st));
+    if (h[1] != 0) return fail(EXCMG_EHIP, "operator of %d cells wider than its band", N);
+    if (h[0] != 0)
+        return fail(EXCMG_EBREAKDOWN, "Cholesky pivot %d of the %d-cell level not positive", h[0],
+                    N);
+    return EXCMG_OK;
+}
+
 int setup(int n_finest, int n_levels, int bc, int dim = 3) {
     CKR(check_sizes(n_finest, n_levels, bc, dim));
     Ctx &c = g_ctx;
@@ -315,18 +334,10 @@ int setup(int n_finest, int n_levels, int bc, int dim = 3) {
     // Cholesky factors of the two direct levels (depend only on the grid and bc kind)
     for (int l = 0; l < 2; l++) {
         Level &L = c.lv[l];
-        const int n = (int)L.nu;
-        CKR(c.chol[l].ensure((size_t)n * n * 8));
-        if (dim == 2) CKH(dense_assemble_2d(L.N, bc, c.chol[l].as<double>(), g_stream));
-        else CKH(dense_assemble(L.N, bc, c.chol[l].as<double>(), g_stream));
-        CKH(dense_cholesky(n, c.chol[l].as<double>(), c.info.as<int>(), g_stream));
-        int info = 0;
-        CKH(hipMemcpyAsync(&info, c.info.p, sizeof(int), hipMemcpyDeviceToHost, g_stream));
-        CKH(hipStreamSynchronize(g_stream));
-        if (info != 0)
-            return fail(EXCMG_EBREAKDOWN, "Cholesky pivot %d of level %d not positive", info, l);
+        c.chol_w[l] = band_width(L.N, dim);
+        CKR(c.chol[l].ensure((size_t)L.nu * (c.chol_w[l] + 1) * 8));
+        CKR(factor_band(L.N, bc, dim, c.chol[l].as<double>(), c.info.as<int>(), g_stream));
     }
-    CKR(c.chol_y.ensure((size_t)c.lv[1].nu * 8));
     c.ready = true;
     return EXCMG_OK;
 }
@@ -896,8 +907,8 @@ int solve_cascade(const excmg_opts &o, const double *f, const double *g1, const 
         if (c.dim == 2) CKH(rhs_assemble_2d(Lv.N, c.bc, s, Nf, f, g1, g2, Lv.b.as<double>(), g_stream));
         else CKH(rhs_assemble(Lv.N, c.bc, s, Nf, f, g1, g2, Lv.b.as<double>(), g_stream));
         if (l <= 1) {
-            CKH(dense_solve((int)Lv.nu, c.chol[l].as<double>(), Lv.b.as<double>(),
-                            Lv.x.as<double>(), c.chol_y.as<double>(), g_stream));
+            CKH(band_solve((int)Lv.nu, c.chol_w[l], c.chol[l].as<double>(), Lv.b.as<double>(),
+                           Lv.x.as<double>(), g_stream));
             ls.status = EXCMG_OK;
         } else {
             if (c.dim == 2) {
@@ -972,17 +983,13 @@ struct FactorCache {
             }
         f.emplace_back(key, DBuf{});
         DBuf &b = f.back().second;
-        const int n = (N - 1) * (N - 1) * (N - 1);
-        CKR(b.ensure((size_t)n * n * 8));
-        CKH(dense_assemble(N, bc, b.as<double>(), st));
+        const size_t n = (size_t)(N - 1) * (N - 1) * (N - 1);
+        CKR(b.ensure(n * (band_width(N, 3) + 1) * 8));
         DBuf info;
         CKR(info.ensure(64));
-        CKH(dense_cholesky(n, b.as<double>(), info.as<int>(), st));
-        int h = 0;
-        CKH(hipMemcpyAsync(&h, info.p, sizeof(int), hipMemcpyDeviceToHost, st));
-        CKH(hipStreamSynchronize(st));
+        const int rc = factor_band(N, bc, 3, b.as<double>(), info.as<int>(), st);
         info.release();
-        if (h != 0) return fail(EXCMG_EBREAKDOWN, "Cholesky pivot %d not positive", h);
+        if (rc != EXCMG_OK) return rc;
         *out = b.as<double>();
         return EXCMG_OK;
     }
@@ -1142,8 +1149,8 @@ struct BatchSolver {
             CKH(rhs_assemble(Lv.N, b.bc, s, b.N, f, g1, g2, Lv.b.as<double>(), st));
             double *Lf = nullptr;
             CKR(fc.get(Lv.N, b.bc, st, &Lf));
-            CKH(dense_solve((int)Lv.nu, Lf, Lv.b.as<double>(), Lv.x.as<double>(),
-                            b.r.as<double>(), st));
+            CKH(band_solve((int)Lv.nu, band_width(Lv.N, 3), Lf, Lv.b.as<double>(),
+                           Lv.x.as<double>(), st));
             CKH(to_nodes<double>(Lv.N, s, b.N, Lv.x.as<double>(), g1, Lv.u.as<double>(), st));
             b.stats.level[l].n = Lv.N;
         }
@@ -1448,8 +1455,8 @@ int excmg_dsolve(int level, const double *b, double *x) {
     Arg ab(b, L.nu * 8), ax(x, L.nu * 8);
     CKR(ab.in());
     CKR(ax.out());
-    CKH(dense_solve((int)L.nu, c.chol[level].as<double>(), ab.p<double>(), ax.p<double>(),
-                    c.chol_y.as<double>(), g_stream));
+    CKH(band_solve((int)L.nu, c.chol_w[level], c.chol[level].as<double>(), ab.p<double>(),
+                   ax.p<double>(), g_stream));
     CKR(ax.back());
     CKH(hipStreamSynchronize(g_stream));
     return EXCMG_OK;

@@ -163,8 +163,12 @@ hipError_t exp_finite(int N, const double *u1, const double *u0, double *v_scrat
                       hipStream_t st);
 hipError_t exp_true(int N, const double *uh, const double *u2h, double *ut, hipStream_t st);
 
-// dense direct solver of the two coarsest levels
-hipError_t dense_assemble(int N, int bc, double *A, hipStream_t st);
+// DSOLVE of the two coarsest levels: Cholesky factor in lower-band storage (column c of
+// the matrix at C[c (w+1) + d], d = 0..w, holding entry (c+d, c)), w = band_width(N, dim)
+int band_width(int N, int dim);
+hipError_t band_assemble(int N, int bc, int dim, int w, double *C, int *bad, hipStream_t st);
+hipError_t band_cholesky(int n, int w, double *C, int *info, hipStream_t st);
+hipError_t band_solve(int n, int w, const double *C, const double *b, double *x, hipStream_t st);
 
 // the same level operations for the 2D equation (node arrays (N+1)^2, interior (N-1)^2)
 hipError_t rhs_assemble_2d(int N, int bc, int stride, int Nf, const double *f, const double *g1,
@@ -176,10 +180,6 @@ hipError_t from_nodes_2d(int N, const double *u, double *x, hipStream_t st);
 hipError_t exp_finite_2d(int N, const double *u1, const double *u0, double *v_scratch, double *w,
                          hipStream_t st);
 hipError_t exp_true_2d(int N, const double *uh, const double *u2h, double *ut, hipStream_t st);
-hipError_t dense_assemble_2d(int N, int bc, double *A, hipStream_t st);
-hipError_t dense_cholesky(int n, double *A, int *info, hipStream_t st);
-hipError_t dense_solve(int n, const double *L, const double *b, double *x, double *y,
-                       hipStream_t st);
 
 // ---------------------------------------------------------------- batched Bi-CG
 

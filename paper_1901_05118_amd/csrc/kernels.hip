@@ -745,108 +745,4 @@ hipError_t exp_true(int N, const double *uh, const double *u2h, double *ut, hipS
     return hipGetLastError();
 }
 
-// ------------------------------------------------------------------ DSOLVE
-
-// Dense A_h of a small level: row r scatters the 25 coefficients of eq. (method1); a term on
-// a fictitious point folds onto the row's own unknown with factor +1 (first kind) or -1
-// (second kind); a term on a boundary node is data.  Entries are small integers, exact in
-// any order.
-__global__ void __launch_bounds__(256) k_dense_assemble(int N, int bc, double *A) {
-    const int n = N - 1;
-    const int nu = n * n * n;
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nu) return;
-    double *row = A + (i64)r * nu;
-    for (int c = 0; c < nu; c++) row[c] = 0.0;
-    const int i = r % n + 1, j = (r / n) % n + 1, k = r / (n * n) + 1;
-    const int off[25][3] = {{0, 0, 0},   {-1, 0, 0},  {1, 0, 0},   {0, -1, 0},  {0, 1, 0},
-                            {0, 0, -1},  {0, 0, 1},   {-2, 0, 0},  {2, 0, 0},   {0, -2, 0},
-                            {0, 2, 0},   {0, 0, -2},  {0, 0, 2},   {-1, -1, 0}, {-1, 1, 0},
-                            {1, -1, 0},  {1, 1, 0},   {-1, 0, -1}, {1, 0, -1},  {0, -1, -1},
-                            {0, 1, -1},  {-1, 0, 1},  {1, 0, 1},   {0, -1, 1},  {0, 1, 1}};
-    const double sgn = (bc == 1) ? 1.0 : -1.0;
-    for (int t = 0; t < 25; t++) {
-        const double coef = (t == 0) ? 42.0 : (t <= 6) ? -12.0 : (t <= 12) ? 1.0 : 2.0;
-        int p[3] = {i + off[t][0], j + off[t][1], k + off[t][2]};
-        bool bnd = false, ghost = false;
-        for (int a = 0; a < 3; a++) {
-            if (p[a] == 0 || p[a] == N) bnd = true;
-            if (p[a] == -1) { p[a] = 1; ghost = true; }
-            if (p[a] == N + 1) { p[a] = N - 1; ghost = true; }
-        }
-        if (bnd) continue;
-        const int c = ((p[2] - 1) * n + (p[1] - 1)) * n + (p[0] - 1);
-        row[c] += ghost ? sgn * coef : coef;
-    }
-}
-
-hipError_t dense_assemble(int N, int bc, double *A, hipStream_t st) {
-    const int nu = (N - 1) * (N - 1) * (N - 1);
-    hipLaunchKernelGGL(k_dense_assemble, dim3((nu + 255) / 256), dim3(256), 0, st, N, bc, A);
-    return hipGetLastError();
-}
-
-// Right-looking-free Cholesky A = L L^T in one workgroup, L in the lower triangle of A
-// (row-major).  Column j: the pivot s = A_jj - sum_k L_jk^2 (k ascending) by one lane, then
-// every row i > j in parallel: (A_ij - sum_k L_ik L_jk) / L_jj, k ascending.
-__global__ void __launch_bounds__(1024) k_cholesky(int n, double *A, int *info) {
-    __shared__ double piv;
-    __shared__ int fail;
-    if (threadIdx.x == 0) fail = 0;
-    for (int jj = 0; jj < n; jj++) {
-        if (threadIdx.x == 0) {
-            double s = A[(i64)jj * n + jj];
-            for (int k = 0; k < jj; k++) s -= A[(i64)jj * n + k] * A[(i64)jj * n + k];
-            if (!(s > 0.0)) fail = jj + 1;
-            const double d = sqrt(s);
-            A[(i64)jj * n + jj] = d;
-            piv = d;
-        }
-        __syncthreads();
-        if (fail) break;
-        const double d = piv;
-        for (int i = jj + 1 + threadIdx.x; i < n; i += blockDim.x) {
-            double t = A[(i64)i * n + jj];
-            for (int k = 0; k < jj; k++) t -= A[(i64)i * n + k] * A[(i64)jj * n + k];
-            A[(i64)i * n + jj] = t / d;
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *info = fail;
-}
-
-hipError_t dense_cholesky(int n, double *A, int *info, hipStream_t st) {
-    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, st, n, A, info);
-    return hipGetLastError();
-}
-
-// L y = b then L^T x = y.  Forward: column-oriented updates keep every row's subtraction
-// order (k ascending), so the work is spread over the workgroup.  Backward: row i needs
-// x_{i+1} first but subtracts it first, so one lane runs it in order.
-__global__ void __launch_bounds__(1024) k_trisolve(int n, const double *L, const double *b,
-                                                   double *x, double *y) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) y[i] = b[i];
-    __syncthreads();
-    for (int k = 0; k < n; k++) {
-        if (threadIdx.x == 0) y[k] = y[k] / L[(i64)k * n + k];
-        __syncthreads();
-        const double yk = y[k];
-        for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) y[i] -= L[(i64)i * n + k] * yk;
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        for (int i = n - 1; i >= 0; i--) {
-            double t = y[i];
-            for (int k = i + 1; k < n; k++) t -= L[(i64)k * n + i] * x[k];
-            x[i] = t / L[(i64)i * n + i];
-        }
-    }
-}
-
-hipError_t dense_solve(int n, const double *L, const double *b, double *x, double *y,
-                       hipStream_t st) {
-    hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(1024), 0, st, n, L, b, x, y);
-    return hipGetLastError();
-}
-
 }  // namespace excmg

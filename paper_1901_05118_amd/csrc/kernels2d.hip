@@ -1,6 +1,6 @@
 // Level kernels of the 2D biharmonic equation (eq. bvp2d) through the EXCMG pipeline (gfx950):
 // right-hand side of the 13-point scheme, node/interior transfers, the bi-quadratic
-// EXP_finite, EXP_true and the dense operator of the direct levels.  Node arrays are
+// EXP_finite and EXP_true.  Node arrays are
 // (N+1)^2 (x fastest), interior vectors (N-1)^2.  Every formula is evaluated in the order
 // it is specified in (contraction off), as in the 3D kernels.
 #include "common.hpp"
@@ -173,34 +173,6 @@ __global__ void __launch_bounds__(256)
     ut[t] = v;
 }
 
-// Dense A_h of a small 2D level: row r scatters the 13 coefficients; a term on a fictitious
-// point folds onto the row's own unknown with factor +1 (first kind) or -1 (second kind); a
-// term on a boundary node is data.
-__global__ void __launch_bounds__(256) k_dense_assemble2d(int N, int bc, double *A) {
-    const int n = N - 1;
-    const int nu = n * n;
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nu) return;
-    double *row = A + (i64)r * nu;
-    for (int c = 0; c < nu; c++) row[c] = 0.0;
-    const int i = r % n + 1, j = r / n + 1;
-    const int off[13][2] = {{0, 0},  {-1, 0}, {1, 0},   {0, -1},  {0, 1},  {-2, 0}, {2, 0},
-                            {0, -2}, {0, 2},  {-1, -1}, {-1, 1}, {1, -1}, {1, 1}};
-    const double sgn = (bc == 1) ? 1.0 : -1.0;
-    for (int t = 0; t < 13; t++) {
-        const double coef = (t == 0) ? 20.0 : (t <= 4) ? -8.0 : (t <= 8) ? 1.0 : 2.0;
-        int p[2] = {i + off[t][0], j + off[t][1]};
-        bool bnd = false, ghost = false;
-        for (int a = 0; a < 2; a++) {
-            if (p[a] == 0 || p[a] == N) bnd = true;
-            if (p[a] == -1) { p[a] = 1; ghost = true; }
-            if (p[a] == N + 1) { p[a] = N - 1; ghost = true; }
-        }
-        if (bnd) continue;
-        row[(p[1] - 1) * n + (p[0] - 1)] += ghost ? sgn * coef : coef;
-    }
-}
-
 inline dim3 grid_for(i64 total) { return dim3((unsigned)((total + 255) / 256)); }
 
 }  // namespace
@@ -247,10 +219,5 @@ hipError_t exp_true_2d(int N, const double *uh, const double *u2h, double *ut, h
     return hipGetLastError();
 }
 
-hipError_t dense_assemble_2d(int N, int bc, double *A, hipStream_t st) {
-    const int nu = (N - 1) * (N - 1);
-    hipLaunchKernelGGL(k_dense_assemble2d, grid_for(nu), dim3(256), 0, st, N, bc, A);
-    return hipGetLastError();
-}
 
 }  // namespace excmg

@@ -67,6 +67,18 @@ def test_extrapolations_equal_the_oracle(ex, N):
 
 
 @pytest.mark.parametrize("bc", [1, 2])
+def test_dsolve_at_the_largest_direct_levels(ex, bc):
+    """Coarsest grid of 32 cells: direct levels of 32^2 and 64^2 cells (3969 unknowns)."""
+    ex.setup_2d(256, 4, bc)
+    rng = np.random.default_rng(40 + bc)
+    for level, Nl in ((0, 32), (1, 64)):
+        b = rng.standard_normal((Nl - 1) ** 2)
+        x = torch.empty_like(dev(b))
+        ex.dsolve(level, dev(b), x)
+        np.testing.assert_array_equal(host(x), O.dsolve_2d(Nl, bc, b))
+
+
+@pytest.mark.parametrize("bc", [1, 2])
 def test_dsolve_and_bicg_equal_the_oracle(ex, bc):
     N, nl = 128, 4      # levels of 16, 32, 64, 128 cells
     ex.setup_2d(N, nl, bc)
@@ -76,7 +88,7 @@ def test_dsolve_and_bicg_equal_the_oracle(ex, bc):
         x = torch.empty_like(dev(b))
         ex.dsolve(level, dev(b), x)
         ref = O.dsolve_2d(Nl, bc, b)
-        assert np.abs(host(x) - ref).max() <= 1e-13 * np.abs(ref).max()
+        np.testing.assert_array_equal(host(x), ref)
     b = rng.standard_normal(127 ** 2)
     x0 = rng.standard_normal(127 ** 2) * 1e-2
     x = dev(x0)

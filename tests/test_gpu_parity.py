@@ -133,7 +133,8 @@ def test_dsolve_matches_oracle(ex, N0, bc):
         x = torch.empty_like(dev(b))
         ex.dsolve(level, dev(b), x)
         ref = O.dsolve(N, bc, b)
-        np.testing.assert_allclose(host(x), ref, rtol=0, atol=1e-14 * np.abs(ref).max())
+        # the banded factor skips only exact zeros of the dense elimination: same bits
+        np.testing.assert_array_equal(host(x), ref)
 
 
 @pytest.mark.parametrize("bc", [1, 2])
