@@ -129,7 +129,8 @@ def jacobi_leg(ex, torch, np, N, nl, bc, tol, f, g1, g2, u, steps):
     ms = (time.perf_counter() - t0) * 1e3 / steps
     if rc != ex.OK:
         raise RuntimeError(f"Jacobi solve failed: {rc} {ex.last_error()}")
-    res = {"ms": round(ms, 2), "iterations": [l["iterations"] for l in st.levels()]}
+    res = {"ms": round(ms, 2), "iterations": [l["iterations"] for l in st.levels()],
+           "runs": [l["runs"] for l in st.levels()]}
     log(f"jacobi fp64: {res}")
     return res
 
@@ -326,6 +327,8 @@ def main():
         "iterations": {"fp64": [lv["iterations"] for lv in r64["levels"]],
                        "mixed": [lv["iterations"] for lv in r32["levels"]],
                        "mixed_restarted_refinement": [lv["iterations"] for lv in r32r["levels"]]},
+        "runs": {"fp64": [lv["runs"] for lv in r64["levels"]],
+                 "mixed": [lv["runs"] for lv in r32["levels"]]},
         "error_vs_exact": {"fp64_u_rms": e64, "mixed_u_rms": e32,
                            "fp64_ut_rms": rms(r64["ut"] - arr.u),
                            "mixed_vs_fp64_max": float(np.abs(r32["u"] - r64["u"]).max()),

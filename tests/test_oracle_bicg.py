@@ -186,3 +186,32 @@ def test_residuals_are_biorthogonal():
                 assert c < 1e-9, (i, j, c)
             else:
                 assert c > 1e-3
+
+
+def test_preconditioned_residuals_are_biorthogonal_in_the_inverse_metric():
+    """With a diagonal M the two residual sequences are biorthogonal in the M^-1 inner
+    product: r_i . M^-1 r*_j = 0 for i != j.  A strongly varying M separates this from the
+    M inner product, which would vanish instead if M were applied where M^-1 belongs."""
+    N, bc = 6, 2
+    n = (N - 1) ** 3
+    rng = np.random.default_rng(17)
+    b, bstar = rng.standard_normal(n), rng.standard_normal(n)
+    m = rng.uniform(1.0, 10.0, n)
+    A = _closed_form(N, bc)
+    rs, rss = [], []
+    for k in range(5):
+        x, xs, *_ = O.bicg_ex(N, bc, b, np.zeros(n), 1e-30, maxit=k, bstar=bstar,
+                              xstar0=np.zeros(n), mdiag=m, literal_transpose=True)
+        rs.append(b - A @ x)
+        rss.append(bstar - A.T @ xs)
+
+    def cos(u, v, w):
+        return abs(u @ (w * v)) / np.sqrt((u @ (w * u)) * (v @ (w * v)))
+
+    worst_wrong = 0.0
+    for i in range(5):
+        for j in range(5):
+            if i != j:
+                assert cos(rs[i], rss[j], 1.0 / m) < 1e-9, (i, j)
+                worst_wrong = max(worst_wrong, cos(rs[i], rss[j], m))
+    assert worst_wrong > 1e-3
