@@ -8,9 +8,10 @@
 //    y (double-buffered, so one barrier per plane); the next plane's global loads are issued
 //    before the current plane is consumed, which hides HBM latency behind the LDS work.
 //  * Every lane keeps the z-direction terms of its column in registers: the centre values
-//    of the last five planes, the four in-plane neighbours of the previous plane and the
-//    partial sums of the three outputs that are still open.  An output on plane k is
-//    complete when plane k+2 arrives.
+//    of the last two planes, the four in-plane neighbours of the previous plane and the
+//    partial sums of the two outputs that are still open, each term added as soon as its
+//    plane is consumed (a two-deep pipeline, so an unroll by two renames it for free).  An
+//    output on plane k is complete when plane k+2 arrives.
 //  * The left-hand side of eq. (method1) is summed left to right in the order the paper
 //    prints it, with contraction off:
 //      y = 42 c - 12 S1 + S2 + 2 S3,
@@ -50,19 +51,21 @@ __device__ __forceinline__ double reflect(int c, int n, double sgn, int &src) {
     return 0.0;
 }
 
-// Per-column register state of one marched array.
+// Per-column register state of one marched array.  Each term of an output is added as
+// soon as its plane has been consumed, in the order of eq. (method1); the state is a
+// two-deep pipeline: output k = m-2 (completed by plane m) and output j = m-1.
 struct Column {
-    double cm4, cm3, cm2, cm1;   // centre values of planes m-4 .. m-1
+    double c1, c2;               // centre values of planes m-1, m-2
     double np0, np1, np2, np3;   // in-plane neighbours (x-, x+, y-, y+) of plane m-1
-    double a2, a1;               // sum of in-plane neighbours of planes m-2, m-1
-    double b2, b1;               // sum of in-plane distance-2 values of planes m-2, m-1
-    double e2, e1;               // partial S3 of planes m-2, m-1
+    double s1k, s1j;             // S1 of output k (complete); of output j (without z+)
+    double s2k, s2j;             // S2 of outputs k and j without their z+2 term
+    double ek, ej;               // S3 of output k (complete); of output j (without plane j+1)
 };
 
 __device__ __forceinline__ void column_init(Column &s) {
-    s.cm4 = s.cm3 = s.cm2 = s.cm1 = 0.0;
+    s.c1 = s.c2 = 0.0;
     s.np0 = s.np1 = s.np2 = s.np3 = 0.0;
-    s.a2 = s.a1 = s.b2 = s.b1 = s.e2 = s.e1 = 0.0;
+    s.s1k = s.s1j = s.s2k = s.s2j = s.ek = s.ej = 0.0;
 }
 
 // Consume plane m from LDS (row stride LS, centre at B) and return the completed output of
@@ -71,33 +74,29 @@ template <int LS, typename TL>
 __device__ __forceinline__ double column_step(Column &s, const TL *B, double &c0) {
     const double c = B[0];
     const double n0 = B[-1], n1 = B[1], n2 = B[-LS], n3 = B[LS];
-    const double s0 = B[-2], s1 = B[2], s2 = B[-2 * LS], s3 = B[2 * LS];
+    const double f0 = B[-2], f1 = B[2], f2 = B[-2 * LS], f3 = B[2 * LS];
     const double d0 = B[-1 - LS], d1 = B[-1 + LS], d2 = B[1 - LS], d3 = B[1 + LS];
-    // open output m
+    // output m-2 is complete once its S2 has this plane's centre (z+2)
+    const double y = 42.0 * s.c2 - 12.0 * s.s1k + (s.s2k + c) + 2.0 * s.ek;
+    // output m-1 receives z+ (S1) and its plane k+1 terms (S3)
+    const double s1 = s.s1j + c;
+    const double e1 = s.ej + n0 + n1 + n2 + n3;
+    // output m opens with the terms of planes m, m-1 and m-2 that are already known
     const double a0 = n0 + n1 + n2 + n3;
-    const double b0 = s0 + s1 + s2 + s3;
+    const double b0 = f0 + f1 + f2 + f3;
     const double e0 = d0 + d1 + d2 + d3 + s.np0 + s.np1 + s.np2 + s.np3;
-    // output m-1 receives its plane k+1 diagonal terms
-    const double e1 = s.e1 + n0 + n1 + n2 + n3;
-    // output m-2 is complete
-    const double S1 = s.a2 + s.cm3 + s.cm1;
-    const double S2 = s.b2 + s.cm4 + c;
-    const double y = 42.0 * s.cm2 - 12.0 * S1 + S2 + 2.0 * s.e2;
-    // shift
-    s.cm4 = s.cm3;
-    s.cm3 = s.cm2;
-    s.cm2 = s.cm1;
-    s.cm1 = c;
+    s.s1k = s1;
+    s.s1j = a0 + s.c1;
+    s.s2k = s.s2j;
+    s.s2j = b0 + s.c2;
+    s.ek = e1;
+    s.ej = e0;
+    s.c2 = s.c1;
+    s.c1 = c;
     s.np0 = n0;
     s.np1 = n1;
     s.np2 = n2;
     s.np3 = n3;
-    s.a2 = s.a1;
-    s.a1 = a0;
-    s.b2 = s.b1;
-    s.b1 = b0;
-    s.e2 = e1;
-    s.e1 = e0;
     c0 = c;
     return y;
 }
@@ -279,7 +278,7 @@ __device__ __forceinline__ void zmarch_tile(const Geom &g, int tile, const In &i
         double y[NA], c0[NA], cprev[NA];
 #pragma unroll
         for (int a = 0; a < NA; a++) {
-            cprev[a] = col[a].cm2;   // centre of plane m-2 before the shift
+            cprev[a] = col[a].c2;    // centre of plane m-2 before the shift
             y[a] = column_step<LS, T>(col[a], &buf[cur][a][centre], c0[a]);
         }
         if (valid) {
