@@ -93,6 +93,9 @@ typedef struct excmg_opts {
     int refine;         /* mixed precision: EXCMG_RELIABLE (default) or EXCMG_RESTART;     */
                         /* excmg_solve_batch always restarts                                */
     int precond;        /* EXCMG_PRECOND_NONE (default) or EXCMG_PRECOND_JACOBI (solve_ex) */
+    int fp32_min_unknowns; /* mixed precision with EXCMG_RELIABLE: levels with fewer        */
+                        /* unknowns run FP64 Bi-CG (launch-latency bound, so FP32 vectors    */
+                        /* gain nothing there); 0: 262144 (2^18), 1: FP32 on every level    */
 } excmg_opts;
 
 /* Per-level record filled by excmg_solve_ex (levels 0 and 1 report iterations = 0). */

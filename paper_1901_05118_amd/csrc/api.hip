@@ -281,6 +281,10 @@ int factor_band(int N, int bc, int dim, double *C, int *info, hipStream_t st) {
     return EXCMG_OK;
 }
 
+int setup_levels(int n_finest, int n_levels, int bc, int dim);
+
+// Make the context the given hierarchy (kept if it already is).  A failed set-up (for
+// instance device memory exhausted) frees whatever it had allocated.
 int setup(int n_finest, int n_levels, int bc, int dim = 3) {
     CKR(check_sizes(n_finest, n_levels, bc, dim));
     Ctx &c = g_ctx;
@@ -288,6 +292,13 @@ int setup(int n_finest, int n_levels, int bc, int dim = 3) {
         c.dim == dim)
         return EXCMG_OK;
     c.release();
+    const int rc = setup_levels(n_finest, n_levels, bc, dim);
+    if (rc != EXCMG_OK) c.release();
+    return rc;
+}
+
+int setup_levels(int n_finest, int n_levels, int bc, int dim) {
+    Ctx &c = g_ctx;
     c.n_finest = n_finest;
     c.n_levels = n_levels;
     c.bc = bc;
@@ -921,10 +932,14 @@ int solve_cascade(const excmg_opts &o, const double *f, const double *g1, const 
                 CKH(from_nodes(Lv.N, Lv.u.as<double>(), Lv.x.as<double>(), g_stream));
             }
             const double eps = level_tolerance(o.tol, l - 1, L);
-            if (mixed && reliable)
+            // with residual replacement, small levels run FP64 Bi-CG: they are bound by launch
+            // latency, so FP32 vectors save nothing and the replacements cost extra
+            const long long fp32_min = o.fp32_min_unknowns > 0 ? o.fp32_min_unknowns : (1LL << 18);
+            const bool lmixed = mixed && (!reliable || Lv.nu >= fp32_min);
+            if (lmixed && reliable)
                 CKR(level_solve_reliable(Lv, Lv.b.as<double>(), Lv.x.as<double>(), eps, maxit,
                                          max_outer, inner_tol, &ls));
-            else if (mixed)
+            else if (lmixed)
                 CKR(level_solve_mixed(Lv, Lv.b.as<double>(), Lv.x.as<double>(), eps, maxit,
                                       max_outer, inner_tol, &ls));
             else
@@ -1622,6 +1637,8 @@ int solve_ex_dim(const excmg_opts *opts, const double *f, const double *g1, cons
         return fail(EXCMG_EINVAL, "refine %d not supported", o.refine);
     if (o.precond != EXCMG_PRECOND_NONE && o.precond != EXCMG_PRECOND_JACOBI)
         return fail(EXCMG_EINVAL, "precond %d not supported", o.precond);
+    if (o.fp32_min_unknowns < 0)
+        return fail(EXCMG_EINVAL, "fp32_min_unknowns must be >= 0");
     if (o.precond == EXCMG_PRECOND_JACOBI && (o.precision != EXCMG_FP64 || o.method != EXCMG_BICG))
         return fail(EXCMG_EINVAL, "the Jacobi preconditioner runs with FP64 Bi-CG only");
     CKR(setup(o.n_finest, o.n_levels, o.bc_kind, dim));

@@ -47,7 +47,8 @@ class Opts(ctypes.Structure):
                 ("tol", ctypes.c_double), ("max_iters", ctypes.c_int),
                 ("max_runs", ctypes.c_int), ("inner_tol", ctypes.c_double),
                 ("max_outer", ctypes.c_int), ("batch_mode", ctypes.c_int),
-                ("method", ctypes.c_int), ("refine", ctypes.c_int), ("precond", ctypes.c_int)]
+                ("method", ctypes.c_int), ("refine", ctypes.c_int), ("precond", ctypes.c_int),
+                ("fp32_min_unknowns", ctypes.c_int)]
 
 
 class LevelStats(ctypes.Structure):
@@ -259,10 +260,10 @@ def solve(n_finest: int, n_levels: int, bc_kind: int, f, g1, g2, tol: float, u_o
 def solve_ex(n_finest: int, n_levels: int, bc_kind: int, f, g1, g2, tol: float, u_out,
              ut_out=None, precision: int = FP64, max_iters: int = 0, max_runs: int = 0,
              inner_tol: float = 0.0, max_outer: int = 0, method: int = BICG,
-             refine: int = RELIABLE, precond: int = PRECOND_NONE):
+             refine: int = RELIABLE, precond: int = PRECOND_NONE, fp32_min_unknowns: int = 0):
     """Algorithm 1 with options.  Returns (code, Stats)."""
     o = Opts(n_finest, n_levels, bc_kind, precision, tol, max_iters, max_runs, inner_tol,
-             max_outer, 0, method, refine, precond)
+             max_outer, 0, method, refine, precond, fp32_min_unknowns)
     st = Stats()
     rc = load().excmg_solve_ex(ctypes.byref(o), _ptr(f, name="f"), _ptr(g1, name="g1"),
                                _ptr(g2, name="g2"), _ptr(u_out, name="u_out"),
@@ -280,10 +281,11 @@ def setup_2d(n_finest: int, n_levels: int, bc_kind: int):
 def solve_ex_2d(n_finest: int, n_levels: int, bc_kind: int, f, g1, g2, tol: float, u_out,
                 ut_out=None, precision: int = FP64, max_iters: int = 0, max_runs: int = 0,
                 inner_tol: float = 0.0, max_outer: int = 0, method: int = BICG,
-                refine: int = RELIABLE, precond: int = PRECOND_NONE):
+                refine: int = RELIABLE, precond: int = PRECOND_NONE,
+                fp32_min_unknowns: int = 0):
     """Algorithm 1 for the 2D equation.  Returns (code, Stats)."""
     o = Opts(n_finest, n_levels, bc_kind, precision, tol, max_iters, max_runs, inner_tol,
-             max_outer, 0, method, refine, precond)
+             max_outer, 0, method, refine, precond, fp32_min_unknowns)
     st = Stats()
     rc = load().excmg2d_solve_ex(ctypes.byref(o), _ptr(f, name="f"), _ptr(g1, name="g1"),
                                  _ptr(g2, name="g2"), _ptr(u_out, name="u_out"),
@@ -326,7 +328,7 @@ def solve_batch(problems, tol: float, precision: int = FP64, max_iters: int = 0,
                          _ptr(p["f"], name="f"), _ptr(p["g1"], name="g1"), _ptr(p["g2"], name="g2"),
                          _ptr(p["u_out"], name="u_out"), _ptr(p.get("ut_out"), name="ut_out"))
     o = Opts(0, 0, 0, precision, tol, max_iters, max_runs, inner_tol, max_outer,
-             1 if persistent else 0, BICG, RESTART, PRECOND_NONE)
+             1 if persistent else 0, BICG, RESTART, PRECOND_NONE, 0)
     st = (Stats * n)()
     rc = load().excmg_solve_batch(n, arr, ctypes.byref(o), st)
     if rc not in (OK, ENOCONV, EBREAKDOWN):

@@ -120,8 +120,9 @@ def test_mixed_cascade_meets_tolerance_and_accuracy(ex, refine):
     arr = make_arrays_2d(family_2d(5), N, bc)
     u = torch.empty((N + 1,) * 2, dtype=torch.float64, device="cuda")
     mode = ex.RELIABLE if refine == "reliable" else ex.RESTART
+    # FP32 Bi-CG on every level (by default levels under 2^18 unknowns run FP64)
     rc, st = ex.solve_ex_2d(N, nl, bc, dev(arr.f), dev(arr.g1), dev(arr.g2), 1e-9, u,
-                            precision=ex.MIXED, refine=mode)
+                            precision=ex.MIXED, refine=mode, fp32_min_unknowns=1)
     assert rc == ex.OK, ex.last_error()
     ug = host(u)
     b = O.rhs_2d(N, bc, arr.f, arr.g1, arr.g2)

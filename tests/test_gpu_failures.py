@@ -61,7 +61,8 @@ def test_tolerance_below_the_fp64_floor_stops(ex):
     assert last["runs"] == 3 and last["rel_residual"] > 1e-14
     for mode in (ex.RELIABLE, ex.RESTART):
         # refinement stops when a step no longer reduces the FP64 residual
-        rc, st = ex.solve_ex(32, 3, 1, f, g1, g2, 1e-14, u, precision=ex.MIXED, refine=mode)
+        rc, st = ex.solve_ex(32, 3, 1, f, g1, g2, 1e-14, u, precision=ex.MIXED, refine=mode,
+                             fp32_min_unknowns=1)
         assert rc == ex.ENOCONV
         assert st.levels()[-1]["rel_residual"] < 1e-9
 
@@ -71,7 +72,7 @@ def test_solves_are_deterministic(ex):
     outs = []
     for prec in (ex.FP64, ex.FP64, ex.MIXED, ex.MIXED):  # mixed: reliable updates
         u = torch.empty_like(f)
-        rc, st = ex.solve_ex(48, 5, 2, f, g1, g2, 1e-9, u, precision=prec)
+        rc, st = ex.solve_ex(48, 5, 2, f, g1, g2, 1e-9, u, precision=prec, fp32_min_unknowns=1)
         assert rc == ex.OK
         outs.append(u.cpu().numpy())
     np.testing.assert_array_equal(outs[0], outs[1])
@@ -103,3 +104,20 @@ def test_level_solutions_form_the_tables_w_column(ex, golden_tables):
     ex.exp_finite(32, u16, u8, w)
     e = w.cpu().numpy() - u.cpu().numpy()
     assert float(f"{O.norm2(e):.2e}") == golden_tables["problems"]["2"]["w_err2"][0]
+
+
+def test_hierarchy_beyond_device_memory_is_refused_and_released(ex):
+    """2048^3 cells (nine vectors of 68.6 GB each) does not fit in HBM: set-up reports
+    ENOMEM, frees what it had allocated, and a later solve equals one made before it."""
+    arr, f, g1, g2 = _inputs()
+    u0 = torch.empty_like(f)
+    assert ex.solve_ex(32, 4, 1, f, g1, g2, 1e-8, u0)[0] == ex.OK
+    free0, _ = torch.cuda.mem_get_info()
+    rc = ex.load().excmg_setup(2048, 9, 1)
+    assert rc == ex.ENOMEM
+    assert "allocation" in ex.last_error()
+    free1, _ = torch.cuda.mem_get_info()
+    assert free1 >= free0 - (1 << 30)
+    u1 = torch.empty_like(f)
+    assert ex.solve_ex(32, 4, 1, f, g1, g2, 1e-8, u1)[0] == ex.OK
+    assert torch.equal(u0, u1)

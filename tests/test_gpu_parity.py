@@ -294,7 +294,8 @@ def test_mixed_solve_meets_tolerance(ex, refine, case):
     f, g1, g2 = dev(arr.f), dev(arr.g1), dev(arr.g2)
     u = torch.empty_like(f)
     mode = ex.RELIABLE if refine == "reliable" else ex.RESTART
-    rc, st = ex.solve_ex(N, nl, bc, f, g1, g2, tol, u, precision=ex.MIXED, refine=mode)
+    rc, st = ex.solve_ex(N, nl, bc, f, g1, g2, tol, u, precision=ex.MIXED, refine=mode,
+                         fp32_min_unknowns=1)
     assert rc == ex.OK, ex.last_error()
     print(refine, [(l["iterations"], l["runs"]) for l in st.levels()], flush=True)
     ug = host(u).reshape((N + 1,) * 3)
@@ -303,6 +304,38 @@ def test_mixed_solve_meets_tolerance(ex, refine, case):
     assert np.sqrt(O.dot(r, r) / O.dot(b, b)) <= tol
     ref = O.excmg(N, nl, bc, arr.f, arr.g1, arr.g2, tol)
     assert abs(O.norm2(ug - arr.u) - O.norm2(ref.u - arr.u)) <= 0.01 * O.norm2(ref.u - arr.u)
+
+
+def test_mixed_default_runs_small_levels_in_fp64(ex):
+    """Residual replacement keeps levels under 2^18 unknowns in FP64: those levels equal
+    the FP64 solve's bit for bit, the 128^3 level runs FP32 with replacements, and the
+    threshold can be moved (1: FP32 everywhere)."""
+    N, nl, bc = 128, 5, 2          # levels of 8, 16, 32, 64 (250047 unknowns), 128 cells
+    arr = make_arrays(config_problem(2), N, bc)
+    f, g1, g2 = dev(arr.f), dev(arr.g1), dev(arr.g2)
+    sols = {}
+    for name, kw in (("fp64", dict()), ("mixed", dict(precision=ex.MIXED)),
+                     ("fp32all", dict(precision=ex.MIXED, fp32_min_unknowns=1))):
+        u = torch.empty_like(f)
+        rc, st = ex.solve_ex(N, nl, bc, f, g1, g2, 1e-9, u, **kw)
+        assert rc == ex.OK, ex.last_error()
+        levels = []
+        for lv in range(nl):
+            n = N >> (nl - 1 - lv)
+            w = torch.empty((n + 1) ** 3, dtype=torch.float64, device="cuda")
+            ex.get_level_solution(lv, w)
+            levels.append(host(w))
+        sols[name] = (st.levels(), levels)
+    (s64, l64), (smx, lmx), (s32, l32) = sols["fp64"], sols["mixed"], sols["fp32all"]
+    for lv in range(nl - 1):
+        np.testing.assert_array_equal(lmx[lv], l64[lv])
+        assert smx[lv]["iterations"] == s64[lv]["iterations"]
+    assert smx[-1]["runs"] > 1                       # FP32 with residual replacements
+    assert s32[3]["runs"] > 1                        # the 64^3 level too when asked
+    assert not np.array_equal(l32[3], l64[3])
+    with pytest.raises(ex.ExcmgError):
+        ex.solve_ex(N, nl, bc, f, g1, g2, 1e-9, torch.empty_like(f), precision=ex.MIXED,
+                    fp32_min_unknowns=-1)
 
 
 def test_autotuned_shape_keeps_results(ex):
@@ -335,9 +368,9 @@ def test_cg_specialisation_is_bit_identical_to_bicg(ex, prec, case):
     f, g1, g2 = dev(arr.f), dev(arr.g1), dev(arr.g2)
     u_b, u_c = torch.empty_like(f), torch.empty_like(f)
     rc1, st1 = ex.solve_ex(N, nl, bc, f, g1, g2, 1e-9, u_b, precision=p, method=ex.BICG,
-                           refine=mode)
+                           refine=mode, fp32_min_unknowns=1)
     rc2, st2 = ex.solve_ex(N, nl, bc, f, g1, g2, 1e-9, u_c, precision=p, method=ex.CG,
-                           refine=mode)
+                           refine=mode, fp32_min_unknowns=1)
     assert rc1 == rc2 == ex.OK
     assert [l["iterations"] for l in st1.levels()] == [l["iterations"] for l in st2.levels()]
     np.testing.assert_array_equal(host(u_b), host(u_c))
