@@ -41,6 +41,20 @@ __global__ void __launch_bounds__(kUpdateThreads)
     k_bicg_update(long long n, const BicgState *s, TX *x, const T *p, T *r, const T *q, T *rs,
                   const T *qs, Pair *partials, StepLink link) {
     __shared__ Pair sh[2 * (kUpdateThreads / kWave)];
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    const long long i0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    // this thread's first element is requested before the status and the scalars, whose
+    // loads and merge would otherwise be waited for first (launch latency on small grids)
+    TX x0 = 0;
+    T p0 = 0, r0 = 0, q0 = 0, s0 = 0, t0 = 0;
+    if (i0 < n) {
+        x0 = x[i0];
+        p0 = p[i0];
+        r0 = r[i0];
+        q0 = q[i0];
+        s0 = rs[i0];
+        t0 = qs[i0];
+    }
     if (!block_running(&s->status)) return;
     double alpha;
     if (link.state) {
@@ -49,11 +63,18 @@ __global__ void __launch_bounds__(kUpdateThreads)
         alpha = s->alpha;
     }
     Pair acc[2] = {{0.0, 0.0}, {0.0, 0.0}};
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        double xi = (double)x[i] + alpha * (double)p[i];
-        double ri = (double)r[i] - alpha * (double)q[i];
-        double si = (double)rs[i] - alpha * (double)qs[i];
+    for (long long i = i0; i < n; i += stride) {
+        if (i != i0) {
+            x0 = x[i];
+            p0 = p[i];
+            r0 = r[i];
+            q0 = q[i];
+            s0 = rs[i];
+            t0 = qs[i];
+        }
+        double xi = (double)x0 + alpha * (double)p0;
+        double ri = (double)r0 - alpha * (double)q0;
+        double si = (double)s0 - alpha * (double)t0;
         T rt = (T)ri, st = (T)si;
         x[i] = (TX)xi;
         r[i] = rt;
@@ -91,6 +112,17 @@ __global__ void __launch_bounds__(kUpdateThreads)
     k_cg_update(long long n, const BicgState *s, TX *x, const T *p, T *r, const T *q,
                 Pair *partials, StepLink link) {
     __shared__ Pair sh[kUpdateThreads / kWave];
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    const long long i0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    // first element requested before the status and the scalars (see k_bicg_update)
+    TX x0 = 0;
+    T p0 = 0, r0 = 0, q0 = 0;
+    if (i0 < n) {
+        x0 = x[i0];
+        p0 = p[i0];
+        r0 = r[i0];
+        q0 = q[i0];
+    }
     if (!block_running(&s->status)) return;
     double alpha;
     if (link.state) {
@@ -99,10 +131,15 @@ __global__ void __launch_bounds__(kUpdateThreads)
         alpha = s->alpha;
     }
     Pair acc[1] = {{0.0, 0.0}};
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        double xi = (double)x[i] + alpha * (double)p[i];
-        double ri = (double)r[i] - alpha * (double)q[i];
+    for (long long i = i0; i < n; i += stride) {
+        if (i != i0) {
+            x0 = x[i];
+            p0 = p[i];
+            r0 = r[i];
+            q0 = q[i];
+        }
+        double xi = (double)x0 + alpha * (double)p0;
+        double ri = (double)r0 - alpha * (double)q0;
         T rt = (T)ri;
         x[i] = (TX)xi;
         r[i] = rt;

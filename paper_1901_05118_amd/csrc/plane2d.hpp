@@ -14,8 +14,11 @@
 
 namespace excmg {
 
-template <int NA, int TY, typename T, class In, class Out>
-__device__ __forceinline__ void plane_tile(const Geom &g, int tile, const In &in, Out &out) {
+// One tile; `begin()` prepares `in` after the tile's loads have been issued (see
+// zmarch_tile).  Returns false (nothing written) when begin() ends the run.
+template <int NA, int TY, typename T, class In, class Out, class Begin>
+__device__ __forceinline__ bool plane_tile(const Geom &g, int tile, const In &in, Out &out,
+                                           Begin begin) {
     constexpr int TX = kWave;
     constexpr int LS = TX + 4;
     constexpr int LR = TY + 4;
@@ -30,22 +33,31 @@ __device__ __forceinline__ void plane_tile(const Geom &g, int tile, const In &in
     const int lx = threadIdx.x, ly = threadIdx.y;
     const int tid = ly * TX + lx;
     const int ix = tx * TX + lx, iy = ty * TY + ly;
+    // every staged element is requested first (positions outside the grid read a valid
+    // clamped element and are multiplied by 0)
+    T raw[NL][NA][R];
+    double mul[NL];
+#pragma unroll
+    for (int q = 0; q < NL; q++) {
+        const int e = min(tid + q * NT, LE - 1);
+        const int row = e / LS, col = e % LS;
+        int sx, sy;
+        const double mx = reflect(tx * TX + col - 2, n, g.sgn, sx);
+        const double my = reflect(ty * TY + row - 2, n, g.sgn, sy);
+        mul[q] = mx * my;
+        const i64 idx = (i64)sy * n + sx;
+#pragma unroll
+        for (int a = 0; a < NA; a++) in.load(a, idx, raw[q][a]);
+    }
+    if (!begin()) return false;
 #pragma unroll
     for (int q = 0; q < NL; q++) {
         const int e = tid + q * NT;
         if (e < LE) {
-            const int row = e / LS, col = e % LS;
-            int sx, sy;
-            const double mx = reflect(tx * TX + col - 2, n, g.sgn, sx);
-            const double my = reflect(ty * TY + row - 2, n, g.sgn, sy);
-            const double mul = mx * my;
-            const i64 idx = (i64)sy * n + sx;
 #pragma unroll
             for (int a = 0; a < NA; a++) {
-                T raw[R];
-                in.load(a, idx, raw);
-                const double v = in.combine(raw);
-                buf[a][e] = (T)((mul != 0.0) ? mul * v : 0.0);
+                const double v = in.combine(raw[q][a]);
+                buf[a][e] = (T)((mul[q] != 0.0) ? mul[q] * v : 0.0);
             }
         }
     }
@@ -68,19 +80,23 @@ __device__ __forceinline__ void plane_tile(const Geom &g, int tile, const In &in
         out.centre(idx, c0);
         out.emit(idx, y, c0);
     }
+    return true;
 }
 
 template <int NA, int TY, typename T, class In, class Out>
 __global__ void __launch_bounds__(kWave *TY) plane2d(Geom g, In in_arg, Out out) {
     __shared__ Pair red[4 * TY];
     __shared__ int s_skip;
-    if (threadIdx.x == 0 && threadIdx.y == 0) s_skip = out.skip() ? 1 : 0;
-    __syncthreads();
-    if (s_skip) return;
     In in = in_arg;
-    if (!in.begin(red)) return;
+    auto start = [&]() {    // status, then scalars, once the tile's loads are in flight
+        if (threadIdx.x == 0 && threadIdx.y == 0) s_skip = out.skip() ? 1 : 0;
+        __syncthreads();
+        if (s_skip) return false;
+        return in.begin(red);
+    };
     const int tile = xcd_tile(blockIdx.x, g.ntiles);
-    if (tile < g.ntiles) plane_tile<NA, TY, T>(g, tile, in, out);
+    const bool go = tile < g.ntiles ? plane_tile<NA, TY, T>(g, tile, in, out, start) : start();
+    if (!go) return;
     __syncthreads();
     out.finish(blockIdx.x, red);
 }

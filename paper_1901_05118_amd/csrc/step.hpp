@@ -65,6 +65,10 @@ __device__ void merge_fixed(const Pair *part, int count, Pair (&out)[NV], Pair *
 // the loop (residual, iteration cap, breakdown), beta_{j-1} = rho_j / rho_{j-1}.  Returns
 // true while the run goes on.
 __device__ __forceinline__ bool link_step(const StepLink &L, double &beta, Pair *sh) {
+    BicgState *s = L.state;
+    // state fields of the previous launches, requested before the merge waits on memory
+    const double thr = s->thr, rho_old = s->rho_slot[L.par ^ 1];
+    const int iter = s->iter, maxit = s->maxit;
     Pair v[2];
     if (L.nv == 2) {
         merge_fixed<2>(L.part, L.count, v, sh);
@@ -74,15 +78,14 @@ __device__ __forceinline__ bool link_step(const StepLink &L, double &beta, Pair 
         v[0] = w[0];
         v[1] = w[0];
     }
-    BicgState *s = L.state;
     const double rho_new = pair_value(v[0]);
     const double rr = pair_value(v[1]);
     int st;
-    if (rr <= s->thr) st = kConverged;
-    else if (s->iter >= s->maxit) st = kNoConv;
+    if (rr <= thr) st = kConverged;
+    else if (iter >= maxit) st = kNoConv;
     else if (rho_new == 0.0 || !isfinite(rho_new)) st = kBreakdown;
     else st = kRunning;
-    beta = wave_uniform(rho_new / s->rho_slot[L.par ^ 1]);
+    beta = wave_uniform(rho_new / rho_old);
     if (blockIdx.x == 0 && block_tid() == 0) {
         s->rr = rr;
         s->beta = beta;
@@ -96,12 +99,13 @@ __device__ __forceinline__ bool link_step(const StepLink &L, double &beta, Pair 
 // Start of sweep B of iteration j: sigma from the partials of sweep A, alpha_j =
 // rho_j / sigma.  Counts the iteration.  Returns false on breakdown.
 __device__ __forceinline__ bool link_alpha(const StepLink &L, double &alpha, Pair *sh) {
+    BicgState *s = L.state;
+    const double rho = s->rho_slot[L.par];   // requested before the merge waits on memory
     Pair v[1];
     merge_fixed<1>(L.part, L.count, v, sh);
-    BicgState *s = L.state;
     const double sigma = pair_value(v[0]);
     const bool bad = (sigma == 0.0 || !isfinite(sigma));
-    alpha = wave_uniform(bad ? 0.0 : s->rho_slot[L.par] / sigma);
+    alpha = wave_uniform(bad ? 0.0 : rho / sigma);
     if (blockIdx.x == 0 && block_tid() == 0) {
         s->sigma = sigma;
         if (bad) {

@@ -182,10 +182,19 @@ struct InDirectionM {
 //   operator values y and the centre values c of the output plane;
 //   Out::centre(idx, c[NA]) is called for every valid centre of a plane inside the chunk;
 //   Out::finish(block, tile) runs after the march (block-level reductions).
-// March one tile (x-tile, y-tile, z-chunk) of the grid.  `in` must be prepared.  Called by
-// a whole 64 x TY workgroup; contains barriers.
-template <int NA, int TY, typename T, class In, class Out>
-__device__ __forceinline__ void zmarch_tile(const Geom &g, int tile, const In &in, Out &out) {
+// No step before the march: `in` is already prepared.
+struct NoBegin {
+    __device__ bool operator()() const { return true; }
+};
+
+// March one tile (x-tile, y-tile, z-chunk) of the grid.  Called by a whole 64 x TY
+// workgroup; contains barriers.  `begin()` prepares `in` (its scalars, e.g. beta from the
+// partials of the previous sweep); it is called after the first planes have been requested,
+// so that their loads and the scalars' merge overlap.  Returns false (nothing written) when
+// begin() ends the run.
+template <int NA, int TY, typename T, class In, class Out, class Begin = NoBegin>
+__device__ __forceinline__ bool zmarch_tile(const Geom &g, int tile, const In &in, Out &out,
+                                            Begin begin = Begin{}) {
     constexpr int TX = kWave;
     constexpr int LS = TX + 4;          // LDS row stride
     constexpr int LR = TY + 4;          // LDS rows
@@ -263,12 +272,13 @@ __device__ __forceinline__ void zmarch_tile(const Geom &g, int tile, const In &i
     // deeper pipelines cost more occupancy than they hide, for FP32 vectors too).
     constexpr int D = 2;
     const int mbeg = k0 - 2, mend = k1 + 1;
-    Raw raw[D];
-    float mz[D];
-    fetch(mbeg, raw[0], mz[0]);
-    stash(0, raw[0], mz[0]);
+    Raw raw[D], raw0;
+    float mz[D], mz0;
+    fetch(mbeg, raw0, mz0);
 #pragma unroll
     for (int k = 0; k < D; k++) fetch(min(mbeg + 1 + k, mend), raw[k], mz[k]);
+    if (!begin()) return false;
+    stash(0, raw0, mz0);
     __syncthreads();
     int cur = 0;
     const int centre = (ly + 2) * LS + (lx + 2);
@@ -298,6 +308,7 @@ __device__ __forceinline__ void zmarch_tile(const Geom &g, int tile, const In &i
             body(m + k, raw[k], mz[k]);
         }
     }
+    return true;
 }
 
 // One workgroup per tile (XCD-aware order), then the epilogue's block-level reduction.
@@ -305,14 +316,18 @@ template <int NA, int TY, typename T, class In, class Out>
 __global__ void __launch_bounds__(kWave *TY) zmarch(Geom g, In in_arg, Out out) {
     __shared__ Pair red[4 * TY];
     __shared__ int s_skip;
-    // one decision per workgroup (a folded finalisation may publish a new status meanwhile)
-    if (threadIdx.x == 0 && threadIdx.y == 0) s_skip = out.skip() ? 1 : 0;
-    __syncthreads();
-    if (s_skip) return;
     In in = in_arg;
-    if (!in.begin(red)) return;
+    // after the tile's first loads are in flight: the status (one decision per workgroup, as
+    // a folded finalisation may publish a new status meanwhile), then the scalars
+    auto start = [&]() {
+        if (threadIdx.x == 0 && threadIdx.y == 0) s_skip = out.skip() ? 1 : 0;
+        __syncthreads();
+        if (s_skip) return false;
+        return in.begin(red);
+    };
     const int tile = xcd_tile(blockIdx.x, g.ntiles);
-    if (tile < g.ntiles) zmarch_tile<NA, TY, T>(g, tile, in, out);
+    const bool go = tile < g.ntiles ? zmarch_tile<NA, TY, T>(g, tile, in, out, start) : start();
+    if (!go) return;
     out.finish(blockIdx.x, red);  // padding blocks of the XCD-aware grid contribute zero
 }
 
