@@ -194,8 +194,9 @@ def main():
                     help="re-time every tile shape first instead of the built-in tuned table")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: the solver has no multi-GPU path "
-              "(see DESIGN.md for how it would shard)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the solver has no multi-GPU path (one "
+              "problem would shard into z-slabs with two-plane halo exchanges and all-reduced "
+              "dot products; a batch would split by problem)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

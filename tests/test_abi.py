@@ -24,7 +24,7 @@ def lib():
     return ex.load()
 
 
-def test_header_declares_the_north_star_calls():
+def test_header_declares_the_solver_entry_points():
     names = _declared()
     for required in ("excmg_solve", "excmg_apply_stencil", "excmg_setup", "excmg_finalize",
                      "excmg_last_error", "excmg_exp_finite", "excmg_exp_true", "excmg_rhs",
