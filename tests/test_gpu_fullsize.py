@@ -1,0 +1,85 @@
+"""Parity at the benchmark's full size (512^3 cells, second kind, the benchmark's problem and
+launch shapes): the operator element by element, the first Bi-CG iterations of the finest
+level bit for bit against the oracle, and the benchmark's solves through properties that
+hold at any size (the oracle's FP64 residual of the returned solution, the discretisation
+error against the exact solution)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from manufactured import config_problem, make_arrays
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+N, NL, BC = 512, 8, 2
+NU = (N - 1) ** 3
+
+
+@pytest.fixture(scope="module")
+def ex():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1901_05118_amd as ex
+    ex.load()
+    yield ex
+    ex.finalize()
+
+
+@pytest.fixture(scope="module")
+def problem():
+    print("generating the 512^3 problem", flush=True)
+    arr = make_arrays(config_problem(4), N, BC)
+    b = O.rhs(N, BC, arr.f, arr.g1, arr.g2)
+    return arr, b
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def test_operator_at_full_size(ex):
+    print("operator 512^3", flush=True)
+    x = np.random.default_rng(512).standard_normal(NU)
+    y = torch.empty(NU, dtype=torch.float64, device="cuda")
+    ex.apply_operator(N, BC, 0, dev(x), y)
+    np.testing.assert_array_equal(host(y), O.apply(N, BC, x))
+
+
+def test_first_bicg_iterations_at_full_size(ex, problem):
+    """Two iterations of Algorithm 2 on the 512^3 level of the benchmark's hierarchy: the
+    FP64 sweeps in their tuned launch shapes give the oracle's iterate bit for bit."""
+    print("bicg 512^3", flush=True)
+    arr, b = problem
+    ex.setup(N, NL, BC)
+    x = torch.zeros(NU, dtype=torch.float64, device="cuda")
+    rc, it, rr = ex.bicg(NL - 1, dev(b), x, 1e-30, max_iters=2)
+    xo, ito, rro, rco = O.bicg(N, BC, b, np.zeros(NU), 1e-30, maxit=2)
+    assert it == ito == 2 and rr == rro
+    np.testing.assert_array_equal(host(x), xo)
+
+
+def test_benchmark_solves_meet_tolerance(ex, problem):
+    """The benchmark's solves: for both precisions the oracle's FP64 residual of the returned
+    solution meets 1e-8 (the exact solution's own residual is 1.6e-8: the tolerance sits at
+    the discretisation floor), and the mixed solve's RMS error against the exact solution is
+    the FP64 solve's within 1%."""
+    arr, b = problem
+    f, g1, g2 = dev(arr.f), dev(arr.g1), dev(arr.g2)
+    errs = {}
+    for name, p in (("fp64", ex.FP64), ("mixed", ex.MIXED)):
+        print(f"solve 512^3 {name}", flush=True)
+        u = torch.empty_like(f)
+        rc, st = ex.solve_ex(N, NL, BC, f, g1, g2, 1e-8, u, precision=p)
+        assert rc == ex.OK, ex.last_error()
+        ug = host(u).reshape((N + 1,) * 3)
+        del u
+        r = O.residual(N, BC, b, O.interior(ug))
+        assert np.sqrt(O.dot(r, r) / O.dot(b, b)) <= 1e-8
+        errs[name] = O.norm2(ug - arr.u)
+    assert abs(errs["mixed"] - errs["fp64"]) <= 0.01 * errs["fp64"]
