@@ -39,12 +39,14 @@ def log(msg):
 
 def sweep_a_launch(N, ty, zc, fp32):
     """Name (as the profiler shows it) and launch size in threads of Bi-CG sweep A on the
-    grid of N cells with tiles of 64 x ty columns and zc planes."""
+    grid of N cells with tiles of 64 x ty columns and zc planes.  In the mixed solve, sweep A
+    on such grids also applies the previous iteration's update of the FP64 iterate."""
     n = N - 1
     tiles = -(-n // 64) * -(-n // ty) * -(-n // zc)
     tiles = -(-tiles // 8) * 8  # the grid is padded to whole XCD shares
     t = "float" if fp32 else "double"
-    return f"zmarch<2, {ty}, {t}, InDirection<{t}>, OutPairApply<{t}> >", tiles * 64 * ty
+    out = "OutPairApplyX" if fp32 else "OutPairApply"
+    return f"zmarch<2, {ty}, {t}, InDirection<{t}>, {out}<{t}> >", tiles * 64 * ty
 
 
 def recorded_traffic(kernel, grid):
@@ -288,13 +290,18 @@ def main():
     # events on the library stream; achieved = algorithmic bytes per launch / mean duration.
     prec = ex.MIXED if gate else ex.FP64
     ex.set_timing(True)
-    solve(prec)
+    st_t = solve(prec)
+    if [lv["iterations"] for lv in st_t.levels()] != [lv["iterations"] for lv in levels]:
+        raise RuntimeError("the event-timed solve took other iterations than the timed one")
     ms_a, n_a = ex.get_timing(nl - 1, 0)
     ms_b, n_b = ex.get_timing(nl - 1, 1)
     ex.set_timing(False)
     nu = (N - 1) ** 3
-    bytes_a = (32.0 if gate else 64.0) * nu     # read r, r*, p, p*; write p, p*, q, q*
-    bytes_b = (44.0 if gate else 72.0) * nu     # read x, p, r, q, r*, q*; write x, r, r*
+    # FP64: sweep A reads r, r*, p, p* and writes p, p*, q, q*; sweep B reads x, p, r, q, r*,
+    # q* and writes x, r, r*.  Mixed: sweep A also applies x += alpha p of the previous
+    # iteration (x read and written in FP64), sweep B streams r, q, r*, q* and writes r, r*.
+    bytes_a = (48.0 if gate else 64.0) * nu
+    bytes_b = (24.0 if gate else 72.0) * nu
     avg_a, avg_b = ms_a / max(n_a, 1), ms_b / max(n_b, 1)
     gbs_a = bytes_a / (avg_a * 1e-3) / 1e9
     ms_c, bytes_c = ex.profile_sweep(4, ex.FP64, reps=10)

@@ -235,7 +235,11 @@ int excmg_solve_ex(const excmg_opts *opts, const double *f, const double *g1, co
  *         3: Bi-CG sweep B: x, r, r* update + rho, r.r (mixed: FP64 x, FP32 rest)
  *                                                               FP64 72 B, mixed 44 B
  *         4: plain copy y = x (bandwidth reference)            FP64 16 B, mixed 8 B
- * (bytes per unknown).  precision selects EXCMG_FP64 or EXCMG_MIXED. */
+ *         5: sweep A also applying the previous iteration's x += alpha p (the form a
+ *            mixed-precision solve runs on grids of 64^3 and up)        mixed 48 B
+ *         6: sweep B without x (its partner)                              mixed 24 B
+ * (bytes per unknown).  precision selects EXCMG_FP64 or EXCMG_MIXED (sweeps 5 and 6: mixed,
+ * 3D contexts only). */
 int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launch,
                         double *bytes_per_launch);
 

@@ -407,6 +407,9 @@ bool g_graphs = false;      // replay iteration windows from captured hipGraphs 
 // fold the sigma and rho finalisations into the sweeps (two launches per iteration instead
 // of four); off: separate one-workgroup finalisation kernels
 bool g_fold = getenv("EXCMG_SEPARATE_FINALISE") == nullptr;
+// mixed-precision Bi-CG on large grids: x's update moves from sweep B to the next sweep A
+// (off: the update stays in sweep B; results are the same bit for bit)
+bool g_defer = getenv("EXCMG_NO_DEFERRED_UPDATE") == nullptr;
 hipStream_t g_capture = nullptr;
 
 // Captured windows of K iterations, per level, vector type, method and iterate pointer.
@@ -419,7 +422,7 @@ struct RunVariant {
 RunVariant g_var;
 
 struct GraphEntry {
-    int level, tsize, cg, fold, K;
+    int level, tsize, cg, fold, K, defer;
     const void *x, *d, *xs;
     hipGraph_t graph;
     hipGraphExec_t exec;
@@ -437,7 +440,11 @@ void release_graphs() {
 // The four launches of iteration j of a run: sweep A (direction update + products + sigma),
 // alpha, sweep B (updates + rho, r.r), beta.  ev >= 0 brackets the sweeps with timing events.
 template <typename TX, typename T>
-int launch_iteration(const Level &L, TX *x, long long j, int ev, hipStream_t st) {
+// defer: 0 = sweep B updates x; 1 = x's update is left to the next sweep A (deferred), this
+// sweep A has none pending (first launch of a run or of a resumed run); 2 = deferred, and
+// this sweep A applies the pending update of iteration j-1.  Deferral: FP32 vectors, FP64
+// iterate, Bi-CG with folded finalisations and no options.
+int launch_iteration(const Level &L, TX *x, long long j, int ev, hipStream_t st, int defer = 0) {
     Ctx &c = g_ctx;
     BicgState *S = c.state.as<BicgState>();
     T *r = c.r.as<T>(), *rs = c.rs.as<T>(), *q = c.q.as<T>(), *qs = c.qs.as<T>();
@@ -474,7 +481,15 @@ int launch_iteration(const Level &L, TX *x, long long j, int ev, hipStream_t st)
             return EXCMG_OK;
         }
     }
-    if (g_cg)
+    if (defer == 2) {
+        la.defer = 1;
+        if constexpr (sizeof(T) == 4 && sizeof(TX) == 8)
+            CKH(stencil_pair_direction_x(G, G.ty, r, rs, c.p[cur].as<T>(), c.ps[cur].as<T>(),
+                                         &S->beta, pn, psn, q, qs, c.part_a.as<Pair>(),
+                                         &S->status, x, &S->alpha, st, la));
+        else
+            return fail(EXCMG_EINVAL, "deferred update needs FP32 vectors and an FP64 iterate");
+    } else if (g_cg)
         CKH(stencil_direction<T>(G, G.ty, r, c.p[cur].as<T>(), &S->beta, j == 0 ? 1 : 0, pn, q,
                                  c.part_a.as<Pair>(), &S->status, st, la));
     else
@@ -487,7 +502,8 @@ int launch_iteration(const Level &L, TX *x, long long j, int ev, hipStream_t st)
     if (g_cg)
         CKH((cg_update<TX, T>(L.nu, S, x, pn, r, q, c.part_b.as<Pair>(), st, lb)));
     else
-        CKH((bicg_update<TX, T>(L.nu, S, x, pn, r, q, rs, qs, c.part_b.as<Pair>(), st, lb)));
+        CKH((bicg_update<TX, T>(L.nu, S, defer ? nullptr : x, pn, r, q, rs, qs,
+                                c.part_b.as<Pair>(), st, lb)));
     if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev + 3], st));
     if (!g_fold) {
         if (g_cg) CKH(cg_beta(S, c.part_b.as<Pair>(), nvb, st));
@@ -499,23 +515,25 @@ int launch_iteration(const Level &L, TX *x, long long j, int ev, hipStream_t st)
 // Folded steps leave the end-of-iteration checks of iteration j to the next sweep A; before
 // the host reads the state, run them on their own (the next sweep A repeats them with the
 // same result).
+// With a deferred update pending the check only publishes its decision (poll_status): the
+// next sweep A stops the run after applying the update.
 template <typename T>
-int close_window(const Level &L, long long j_next, hipStream_t st) {
+int close_window(const Level &L, long long j_next, hipStream_t st, int defer = 0) {
     if (!g_fold) return EXCMG_OK;
     Ctx &c = g_ctx;
     const StepLink l{c.state.as<BicgState>(), c.part_b.as<Pair>(), update_blocks(L.nu), g_cg ? 1 : 2,
-                     (int)(j_next & 1)};
+                     (int)(j_next & 1), defer ? 1 : 0};
     CKH(step_check(l, st));
     return EXCMG_OK;
 }
 
 // Graph of iterations j = 1..K (K even, so the p / p* buffer parity repeats).
 template <typename TX, typename T>
-int window_graph(const Level &L, TX *x, int K, hipGraphExec_t *out) {
+int window_graph(const Level &L, TX *x, int K, hipGraphExec_t *out, int defer = 0) {
     for (GraphEntry &e : g_graph_cache)
         if (e.level == L.index && e.tsize == (int)sizeof(T) && e.cg == (int)g_cg &&
-            e.fold == (int)g_fold && e.K == K && e.x == (const void *)x && e.d == g_var.d &&
-            e.xs == g_var.xs) {
+            e.fold == (int)g_fold && e.K == K && e.defer == defer && e.x == (const void *)x &&
+            e.d == g_var.d && e.xs == g_var.xs) {
             *out = e.exec;
             return EXCMG_OK;
         }
@@ -523,8 +541,8 @@ int window_graph(const Level &L, TX *x, int K, hipGraphExec_t *out) {
     CKH(hipStreamBeginCapture(g_capture, hipStreamCaptureModeRelaxed));
     int rc = EXCMG_OK;
     for (int t = 0; t < K && rc == EXCMG_OK; t++)
-        rc = launch_iteration<TX, T>(L, x, 1 + t, -1, g_capture);
-    if (rc == EXCMG_OK) rc = close_window<T>(L, K + 1, g_capture);
+        rc = launch_iteration<TX, T>(L, x, 1 + t, -1, g_capture, defer ? 2 : 0);
+    if (rc == EXCMG_OK) rc = close_window<T>(L, K + 1, g_capture, defer);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(g_capture, &graph);
     if (rc != EXCMG_OK) {
@@ -534,7 +552,7 @@ int window_graph(const Level &L, TX *x, int K, hipGraphExec_t *out) {
     CKH(e);
     hipGraphExec_t exec = nullptr;
     CKH(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-    g_graph_cache.push_back(GraphEntry{L.index, (int)sizeof(T), (int)g_cg, (int)g_fold, K,
+    g_graph_cache.push_back(GraphEntry{L.index, (int)sizeof(T), (int)g_cg, (int)g_fold, K, defer,
                                        (const void *)x, g_var.d, g_var.xs, graph, exec});
     *out = exec;
     return EXCMG_OK;
@@ -552,14 +570,28 @@ int bicg_iterate(const Level &L, TX *x, BicgState &hs, long long &j) {
     K += K & 1;
     if (g_timing) CKR(ensure_events(4 * (size_t)K));
     const bool graphs = g_graphs && !g_timing;
+    // x += alpha p deferred to the next sweep A (large grids, FP32 vectors, plain Bi-CG):
+    // sweep B then streams r, q, r*, q* only
+    const int defer = ((graphs || g_timing) && K <= 16 && g_defer && sizeof(T) == 4 &&
+                       sizeof(TX) == 8 && !g_cg && g_fold && !g_var.d && !g_var.xs &&
+                       g_ctx.dim == 3) ? 1 : 0;
     hipGraphExec_t exec = nullptr;
-    if (graphs) CKR((window_graph<TX, T>(L, x, K, &exec)));
+    if (graphs) CKR((window_graph<TX, T>(L, x, K, &exec, defer)));
     if (graphs && K <= 16 && hs.status == kRunning) {
         // Short windows (large grids): queue window w+1 before reading the state of window
         // w, so the device never waits for the host.  The window after the one that stopped
-        // the run consists of no-op launches.
+        // the run consists of no-op launches (with a deferred update, its first sweep A
+        // applies the update and stops the run).
         Ctx &c = g_ctx;
-        if (j == 0 || (j & 1) == 0) {
+        if (defer) {
+            // the first sweep A of a run, or of a resumed run, has no update pending
+            CKR((launch_iteration<TX, T>(L, x, j, -1, g_stream, 1)));
+            j++;
+            if ((j & 1) == 0) {   // the captured window starts at an odd iteration
+                CKR((launch_iteration<TX, T>(L, x, j, -1, g_stream, 2)));
+                j++;
+            }
+        } else if (j == 0 || (j & 1) == 0) {
             CKR((launch_iteration<TX, T>(L, x, j, -1, g_stream)));
             j++;
         }
@@ -575,10 +607,13 @@ int bicg_iterate(const Level &L, TX *x, BicgState &hs, long long &j) {
         for (int w = 0;; w++) {
             CKR(queue_window((w + 1) & 1));
             CKH(hipEventSynchronize(c.poll_ev[w & 1]));
-            if (c.host_state[1 + (w & 1)].status != kRunning) break;
+            if (c.host_state[1 + (w & 1)].poll_status != kRunning) break;
         }
-        return read_state(hs);
+        CKR(read_state(hs));
+        if (hs.status == kStopping) hs.status = hs.poll_status;  // (a sweep B always follows)
+        return EXCMG_OK;
     }
+    bool seg_first = true;
     while (hs.status == kRunning) {
         const int it0 = hs.iter;
         if (graphs) {
@@ -590,11 +625,22 @@ int bicg_iterate(const Level &L, TX *x, BicgState &hs, long long &j) {
             CKH(hipGraphLaunch(exec, g_stream));
             j += K;
         } else {
-            for (int t = 0; t < K; t++, j++)
-                CKR((launch_iteration<TX, T>(L, x, j, g_timing ? t : -1, g_stream)));
-            CKR(close_window<T>(L, j, g_stream));
+            for (int t = 0; t < K; t++, j++) {
+                // with a deferred update, the first sweep A of the call has none pending
+                const int dm = defer ? (seg_first ? 1 : 2) : 0;
+                seg_first = false;
+                CKR((launch_iteration<TX, T>(L, x, j, g_timing ? t : -1, g_stream, dm)));
+            }
+            CKR(close_window<T>(L, j, g_stream, defer));
         }
         CKR(read_state(hs));
+        if (defer && hs.status == kRunning && hs.poll_status != kRunning) {
+            // the closing check found the stop: one more sweep A applies the owed update
+            CKR((launch_iteration<TX, T>(L, x, j, -1, g_stream, 2)));
+            j++;
+            CKR(read_state(hs));
+        }
+        if (hs.status == kStopping) hs.status = hs.poll_status;
         if (g_timing && L.index < EXCMG_MAX_LEVELS) {
             const int active = std::min(K, hs.iter - it0);  // launches that did work
             for (int t = 0; t < active; t++) {
@@ -1726,9 +1772,11 @@ int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launc
                         double *bytes_per_launch) {
     g_err[0] = 0;
     if (!g_ctx.ready) return fail(EXCMG_EINVAL, "no context: call excmg_setup first");
-    if (which < 0 || which > 4 || reps < 1) return fail(EXCMG_EINVAL, "bad sweep or reps");
+    if (which < 0 || which > 6 || reps < 1) return fail(EXCMG_EINVAL, "bad sweep or reps");
     if (precision != EXCMG_FP64 && precision != EXCMG_MIXED)
         return fail(EXCMG_EINVAL, "bad precision");
+    if (which >= 5 && (precision != EXCMG_MIXED || g_ctx.dim != 3))
+        return fail(EXCMG_EINVAL, "sweeps 5 and 6 are the mixed-precision 3D ones");
     Ctx &c = g_ctx;
     const Level &L = c.lv.back();
     const size_t es = precision == EXCMG_FP64 ? 8 : 4;
@@ -1744,8 +1792,8 @@ int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launc
     CKH(hipMemcpyAsync(c.state.p, &hs, sizeof(hs), hipMemcpyHostToDevice, g_stream));
     BicgState *S = c.state.as<BicgState>();
     // algorithmic bytes per unknown of each sweep
-    const double fp64_bytes[5] = {16, 24, 64, 72, 16};
-    const double mixed_bytes[5] = {8, 24, 32, 44, 8};
+    const double fp64_bytes[7] = {16, 24, 64, 72, 16, 0, 0};
+    const double mixed_bytes[7] = {8, 24, 32, 44, 8, 48, 24};
     auto launch_once = [&]() -> hipError_t {
         if (precision == EXCMG_FP64) {
             double *r = c.r.as<double>(), *rs = c.rs.as<double>();
@@ -1776,6 +1824,14 @@ int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launc
                         c.qs.as<float>(), c.part_a.as<Pair>(), &S->status, g_stream);
             case 3: return bicg_update<double, float>(L.nu, S, L.x.as<double>(), c.p[1].as<float>(),
                                                       r, c.q.as<float>(), rs, c.qs.as<float>(),
+                                                      c.part_b.as<Pair>(), g_stream);
+            case 5: return stencil_pair_direction_x(
+                        L.g2f, L.g2f.ty, r, rs, c.p[0].as<float>(), c.ps[0].as<float>(), &S->beta,
+                        c.p[1].as<float>(), c.ps[1].as<float>(), c.q.as<float>(),
+                        c.qs.as<float>(), c.part_a.as<Pair>(), &S->status, L.x.as<double>(),
+                        &S->alpha, g_stream, StepLink{});
+            case 6: return bicg_update<double, float>(L.nu, S, nullptr, c.p[1].as<float>(), r,
+                                                      c.q.as<float>(), rs, c.qs.as<float>(),
                                                       c.part_b.as<Pair>(), g_stream);
             default: return copy_convert<float, float>(L.nu, r, c.q.as<float>(), g_stream);
         }

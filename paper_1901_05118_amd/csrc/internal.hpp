@@ -33,7 +33,8 @@ struct BicgState {
     int iter;        // iterations done in this run
     int maxit;
     int status;      // 0 running, 1 converged, -3 iteration cap, -4 breakdown
-    int pad;
+    int poll_status; // the status as the host polls it: a window's closing check writes only
+                     // this one when the run's last update is still pending (see step.hpp)
     double rho_slot[2];  // rho_j in slot j & 1 (steps with folded finalisations)
 };
 
@@ -45,9 +46,14 @@ struct StepLink {
     int count = 0;               // pairs per value
     int nv = 1;                  // values: 2 = (r*.r, r.r), 1 = r.r (CG) or sigma
     int par = 0;                 // parity of the iteration
+    int poll_only = 0;           // end-of-window check: publish the decision for the host only
+    int defer = 0;               // sweep A owing the iterate's update of the previous iteration
 };
 
-constexpr int kRunning = 0, kConverged = 1, kNoConv = -3, kBreakdown = -4;
+// kStopping: the sweep A that stops a run while owing the iterate's update publishes this
+// transient status, so its workgroups that start after the decision still apply their part
+// of the update; the sweep B that follows replaces it by the final status (poll_status).
+constexpr int kRunning = 0, kConverged = 1, kStopping = 2, kNoConv = -3, kBreakdown = -4;
 
 // ---------------------------------------------------------------- stencil kernels
 
@@ -74,6 +80,11 @@ hipError_t stencil_pair_direction(const Geom &g, int ty, const T *r, const T *rs
 
 // Sweep A with a diagonal preconditioner (entries d): p_new = r / d + beta p_old, likewise
 // for the shadow direction (FP64)
+hipError_t stencil_pair_direction_x(const Geom &g, int ty, const float *r, const float *rs,
+                                   const float *p_old, const float *ps_old, const double *beta_dev,
+                                   float *p_new, float *ps_new, float *q, float *qs,
+                                   Pair *partials, const int *status, double *x,
+                                   const double *alpha_dev, hipStream_t st, StepLink link);
 hipError_t stencil_pair_direction_m(const Geom &g, int ty, const double *r, const double *rs,
                                    const double *p_old, const double *ps_old, const double *d,
                                    const double *beta_dev, int first, double *p_new,

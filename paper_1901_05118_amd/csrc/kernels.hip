@@ -47,15 +47,24 @@ __global__ void __launch_bounds__(kUpdateThreads)
     // loads and merge would otherwise be waited for first (launch latency on small grids)
     TX x0 = 0;
     T p0 = 0, r0 = 0, q0 = 0, s0 = 0, t0 = 0;
+    const bool upd_x = (x != nullptr);   // else the next sweep A applies x += alpha p
     if (i0 < n) {
-        x0 = x[i0];
-        p0 = p[i0];
+        if (upd_x) {
+            x0 = x[i0];
+            p0 = p[i0];
+        }
         r0 = r[i0];
         q0 = q[i0];
         s0 = rs[i0];
         t0 = qs[i0];
     }
-    if (!block_running(&s->status)) return;
+    if (!block_running(&s->status)) {
+        // after a sweep A that stopped the run owing the iterate's update: the final status
+        BicgState *w = link.state;   // deferred updates run with folded finalisations
+        if (!upd_x && w && blockIdx.x == 0 && threadIdx.x == 0 && w->status == kStopping)
+            w->status = w->poll_status;
+        return;
+    }
     double alpha;
     if (link.state) {
         if (!link_alpha(link, alpha, sh)) return;
@@ -65,18 +74,19 @@ __global__ void __launch_bounds__(kUpdateThreads)
     Pair acc[2] = {{0.0, 0.0}, {0.0, 0.0}};
     for (long long i = i0; i < n; i += stride) {
         if (i != i0) {
-            x0 = x[i];
-            p0 = p[i];
+            if (upd_x) {
+                x0 = x[i];
+                p0 = p[i];
+            }
             r0 = r[i];
             q0 = q[i];
             s0 = rs[i];
             t0 = qs[i];
         }
-        double xi = (double)x0 + alpha * (double)p0;
         double ri = (double)r0 - alpha * (double)q0;
         double si = (double)s0 - alpha * (double)t0;
         T rt = (T)ri, st = (T)si;
-        x[i] = (TX)xi;
+        if (upd_x) x[i] = (TX)((double)x0 + alpha * (double)p0);
         r[i] = rt;
         rs[i] = st;
         dot2_acc(acc[0], (double)st, (double)rt);
@@ -275,6 +285,7 @@ __global__ void k_state_resume(BicgState *s, double thr) {
     if (threadIdx.x == 0) {
         s->thr = thr;
         s->status = (s->iter >= s->maxit) ? kNoConv : kRunning;
+        s->poll_status = s->status;
     }
 }
 
@@ -356,6 +367,7 @@ __device__ void set_status(BicgState *s) {
     else if (s->iter >= s->maxit) s->status = kNoConv;
     else if (s->rho == 0.0 || !isfinite(s->rho)) s->status = kBreakdown;
     else s->status = kRunning;
+    s->poll_status = s->status;
 }
 
 __global__ void __launch_bounds__(kReduceThreads)
@@ -413,7 +425,7 @@ __global__ void __launch_bounds__(kReduceThreads)
     if (threadIdx.x == 0) {
         double sigma = pair_value(v[0]);
         s->sigma = sigma;
-        if (sigma == 0.0 || !isfinite(sigma)) s->status = kBreakdown;
+        if (sigma == 0.0 || !isfinite(sigma)) s->status = s->poll_status = kBreakdown;
         else s->alpha = s->rho / sigma;
     }
 }

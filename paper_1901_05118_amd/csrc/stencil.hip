@@ -117,6 +117,58 @@ hipError_t stencil_pair_direction(const Geom &g, int ty, const T *r, const T *rs
     return hipSuccess;
 }
 
+// Sweep A applying the previous iteration's update of the FP64 iterate (3D grids; see
+// OutPairApplyX).
+hipError_t stencil_pair_direction_x(const Geom &g, int ty, const float *r, const float *rs,
+                                   const float *p_old, const float *ps_old, const double *beta_dev,
+                                   float *p_new, float *ps_new, float *q, float *qs,
+                                   Pair *partials, const int *status, double *x,
+                                   const double *alpha_dev, hipStream_t st, StepLink link) {
+    if (g.dim != 3) return hipErrorInvalidValue;
+    InDirection<float> in;
+    in.link = link;
+    in.r[0] = r;
+    in.r[1] = rs;
+    in.p[0] = p_old;
+    in.p[1] = ps_old;
+    in.beta_dev = beta_dev;
+    in.first = 0;
+    in.beta = 0.0;
+    OutPairApplyX<float> out;
+    out.p_new[0] = p_new;
+    out.p_new[1] = ps_new;
+    out.q[0] = q;
+    out.q[1] = qs;
+    out.partials = partials;
+    out.status = status;
+    out.acc = Pair{0.0, 0.0};
+    out.x = x;
+    out.pold = p_old;
+    out.alpha_dev = alpha_dev;
+    out.alpha = 0.0;
+    dim3 block(kWave, 1);
+    switch (ty) {
+        case 4:
+            block.y = 4;
+            hipLaunchKernelGGL((zmarch<2, 4, float, InDirection<float>, OutPairApplyX<float>>),
+                               dim3(xcd_grid(g.ntiles)), block, 0, st, g, in, out);
+            break;
+        case 8:
+            block.y = 8;
+            hipLaunchKernelGGL((zmarch<2, 8, float, InDirection<float>, OutPairApplyX<float>>),
+                               dim3(xcd_grid(g.ntiles)), block, 0, st, g, in, out);
+            break;
+        case 16:
+            block.y = 16;
+            hipLaunchKernelGGL((zmarch<2, 16, float, InDirection<float>, OutPairApplyX<float>>),
+                               dim3(xcd_grid(g.ntiles)), block, 0, st, g, in, out);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t stencil_pair_direction_m(const Geom &g, int ty, const double *r, const double *rs,
                                    const double *p_old, const double *ps_old, const double *d,
                                    const double *beta_dev, int first, double *p_new,

@@ -91,7 +91,10 @@ __device__ __forceinline__ bool link_step(const StepLink &L, double &beta, Pair 
         s->beta = beta;
         s->rho = rho_new;
         s->rho_slot[L.par] = rho_new;
-        s->status = st;
+        s->poll_status = st;
+        // a poll-only check leaves the run going: the next sweep A takes the same decision
+        // and applies the iterate's pending update before it stops
+        if (!L.poll_only) s->status = (L.defer && st != kRunning) ? kStopping : st;
     }
     return st == kRunning;
 }
@@ -110,6 +113,7 @@ __device__ __forceinline__ bool link_alpha(const StepLink &L, double &alpha, Pai
         s->sigma = sigma;
         if (bad) {
             s->status = kBreakdown;
+            s->poll_status = kBreakdown;
         } else {
             s->alpha = alpha;
             s->iter = s->iter + 1;

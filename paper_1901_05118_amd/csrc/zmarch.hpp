@@ -26,6 +26,8 @@
 //  * Tiles are ordered XCD-aware: each of the 8 XCDs processes a contiguous range of tiles.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "internal.hpp"
 #include "step.hpp"
@@ -182,6 +184,22 @@ struct InDirectionM {
 //   operator values y and the centre values c of the output plane;
 //   Out::centre(idx, c[NA]) is called for every valid centre of a plane inside the chunk;
 //   Out::finish(block, tile) runs after the march (block-level reductions).
+// Epilogues that request per-output data ahead (Out::Pre, Out::pre(idx)): the values of an
+// output are requested when its own plane is consumed and handed to emit() two planes later,
+// when the output is complete.
+template <class O, class = void>
+struct HasPre : std::false_type {};
+template <class O>
+struct HasPre<O, std::void_t<typename O::Pre>> : std::true_type {};
+template <class O, bool = HasPre<O>::value>
+struct PreOf {
+    struct type {};
+};
+template <class O>
+struct PreOf<O, true> {
+    using type = typename O::Pre;
+};
+
 // No step before the march: `in` is already prepared.
 struct NoBegin {
     __device__ bool operator()() const { return true; }
@@ -283,8 +301,11 @@ __device__ __forceinline__ bool zmarch_tile(const Geom &g, int tile, const In &i
     int cur = 0;
     const int centre = (ly + 2) * LS + (lx + 2);
     const int col_off = iy * n + ix;    // in-plane offset of this lane's column (n < 2^15)
+    constexpr bool kPre = HasPre<Out>::value;
+    using PreT = typename PreOf<Out>::type;
+    PreT pre[D];             // per-output data of planes m-2 (slot m % D), requested at plane m
     // consume plane m from LDS, stage plane m+1 from `r`, refill `r` with plane m+1+D
-    auto body = [&](int m, Raw &r, float &z) {
+    auto body = [&](int m, Raw &r, float &z, PreT &pm) {
         double y[NA], c0[NA], cprev[NA];
 #pragma unroll
         for (int a = 0; a < NA; a++) {
@@ -294,7 +315,13 @@ __device__ __forceinline__ bool zmarch_tile(const Geom &g, int tile, const In &i
         if (valid) {
             if (m >= k0 && m < k1) out.centre((i64)m * plane + col_off, c0);
             const int k = m - 2;
-            if (k >= k0 && k < k1) out.emit((i64)k * plane + col_off, y, cprev);
+            if (k >= k0 && k < k1) {
+                if constexpr (kPre) out.emit((i64)k * plane + col_off, y, cprev, pm);
+                else out.emit((i64)k * plane + col_off, y, cprev);
+            }
+            if constexpr (kPre) {
+                if (m >= k0 && m < k1) pm = out.pre((i64)m * plane + col_off);
+            }
         }
         stash(cur ^ 1, r, z);
         fetch(min(m + 1 + D, mend), r, z);
@@ -305,10 +332,26 @@ __device__ __forceinline__ bool zmarch_tile(const Geom &g, int tile, const In &i
 #pragma unroll
         for (int k = 0; k < D; k++) {
             if (m + k > mend) break;
-            body(m + k, raw[k], mz[k]);
+            body(m + k, raw[k], mz[k], pre[k]);
         }
     }
     return true;
+}
+
+// The outputs of one tile without the march: Out::finish_output(idx) for each (used when a
+// run stops at the start of a sweep whose epilogue still owes work on its outputs).
+template <int TY, class Out>
+__device__ __forceinline__ void zmarch_tile_outputs(const Geom &g, int tile, Out &out) {
+    const int n = g.n;
+    const int tx = tile % g.tiles_x;
+    const int ty = (tile / g.tiles_x) % g.tiles_y;
+    const int tz = tile / (g.tiles_x * g.tiles_y);
+    const int ix = tx * kWave + threadIdx.x, iy = ty * TY + threadIdx.y;
+    if (ix >= n || iy >= n) return;
+    const int k0 = tz * g.zc, k1 = min(k0 + g.zc, n);
+    const i64 plane = (i64)n * n;
+    const i64 col = (i64)iy * n + ix;
+    for (int k = k0; k < k1; k++) out.finish_output((i64)k * plane + col);
 }
 
 // One workgroup per tile (XCD-aware order), then the epilogue's block-level reduction.
@@ -317,17 +360,33 @@ __global__ void __launch_bounds__(kWave *TY) zmarch(Geom g, In in_arg, Out out) 
     __shared__ Pair red[4 * TY];
     __shared__ int s_skip;
     In in = in_arg;
+    if constexpr (HasPre<Out>::value) out.prepare();
+    bool stops = false;      // the run stops at the start of this launch
     // after the tile's first loads are in flight: the status (one decision per workgroup, as
     // a folded finalisation may publish a new status meanwhile), then the scalars
     auto start = [&]() {
-        if (threadIdx.x == 0 && threadIdx.y == 0) s_skip = out.skip() ? 1 : 0;
+        if (threadIdx.x == 0 && threadIdx.y == 0) {
+            if constexpr (HasPre<Out>::value) s_skip = out.gate();
+            else s_skip = out.skip() ? 1 : 0;
+        }
         __syncthreads();
+        if (s_skip == 2) {     // the run stops in this launch (decided by another workgroup)
+            stops = true;
+            return false;
+        }
         if (s_skip) return false;
-        return in.begin(red);
+        const bool run = in.begin(red);
+        stops = !run;
+        return run;
     };
     const int tile = xcd_tile(blockIdx.x, g.ntiles);
     const bool go = tile < g.ntiles ? zmarch_tile<NA, TY, T>(g, tile, in, out, start) : start();
-    if (!go) return;
+    if (!go) {
+        if constexpr (HasPre<Out>::value) {
+            if (stops && tile < g.ntiles) zmarch_tile_outputs<TY>(g, tile, out);
+        }
+        return;
+    }
     out.finish(blockIdx.x, red);  // padding blocks of the XCD-aware grid contribute zero
 }
 
@@ -435,6 +494,36 @@ struct OutPairApply {
         block_merge<1>(v, sh);
         if (threadIdx.x == 0 && threadIdx.y == 0) partials[block] = v[0];
     }
+};
+
+// Sweep A that also applies the previous iteration's update of the iterate, x += alpha p
+// (alpha and p of iteration j-1, which sweep B then leaves to it): the streams of x and p
+// move from the update sweep into this one, where p is read anyway.  The arithmetic is the
+// update sweep's.  x and p of an output are requested when its plane is consumed.  When
+// the run stops at the start of the launch, the update is applied on its own.
+template <typename T>
+struct OutPairApplyX : OutPairApply<T> {
+    double *x;
+    const T *pold;               // p of iteration j-1 (the direction sweep A reads)
+    const double *alpha_dev;     // alpha of iteration j-1
+    double alpha;
+    struct Pre {
+        double x;
+        T p;
+    };
+    __device__ void prepare() { alpha = wave_uniform(*alpha_dev); }
+    // 0: running; 2: the run stops in this launch (a workgroup already decided it); 1: stopped
+    // before this launch (nothing owed)
+    __device__ int gate() const {
+        const int s = *this->status;
+        return s == kRunning ? 0 : (s == kStopping ? 2 : 1);
+    }
+    __device__ Pre pre(i64 idx) const { return Pre{x[idx], pold[idx]}; }
+    __device__ void emit(i64 idx, const double *v, const double *c, const Pre &pr) {
+        x[idx] = pr.x + alpha * (double)pr.p;
+        OutPairApply<T>::emit(idx, v, c);
+    }
+    __device__ void finish_output(i64 idx) { x[idx] = x[idx] + alpha * (double)pold[idx]; }
 };
 
 }  // namespace excmg

@@ -8,7 +8,8 @@ warm-up launch) through ``excmg_profile_sweep``, followed by the same number of 
 copies of one finest-level vector: a kernel of known traffic (16 bytes per unknown) against
 which HBM byte counters are calibrated.  Sweeps: 0 operator apply, 1 residual, 2 sweep A
 (direction update and the pair of operator products), 3 sweep B (x, r, r* updates with the
-next rho), 4 copy.  Prints one line per sweep: mean ms per launch, algorithmic bytes per
+next rho), 4 copy, 5 sweep A applying the previous iteration's x update and 6 the sweep B
+that then leaves x alone (the pair a mixed-precision solve runs on grids of 64^3 and up).  Prints one line per sweep: mean ms per launch, algorithmic bytes per
 launch and the rate.  Uses no torch: every launch comes from the library.
 """
 import argparse

@@ -356,6 +356,48 @@ def test_autotuned_shape_keeps_results(ex):
 
 # ------------------------------------------------------------------ CG specialisation
 
+def test_deferred_update_keeps_bicg_equal_to_cg(ex):
+    """On grids of 64^3 and up the mixed Bi-CG moves x += alpha p from sweep B into the next
+    sweep A (same arithmetic, applied one launch later, and on its own when a run stops);
+    the CG form keeps it in its update sweep.  Both must give the same iterates bit for bit,
+    through residual replacements and window ends."""
+    N, nl, bc = 128, 6, 2
+    arr = make_arrays(config_problem(2), N, bc)
+    f, g1, g2 = dev(arr.f), dev(arr.g1), dev(arr.g2)
+    u_b, u_c = torch.empty_like(f), torch.empty_like(f)
+    rc1, st1 = ex.solve_ex(N, nl, bc, f, g1, g2, 1e-9, u_b, precision=ex.MIXED, method=ex.BICG,
+                           fp32_min_unknowns=1)
+    rc2, st2 = ex.solve_ex(N, nl, bc, f, g1, g2, 1e-9, u_c, precision=ex.MIXED, method=ex.CG,
+                           fp32_min_unknowns=1)
+    assert rc1 == rc2 == ex.OK
+    assert [(l["iterations"], l["runs"]) for l in st1.levels()] == \
+        [(l["iterations"], l["runs"]) for l in st2.levels()]
+    assert st1.levels()[-1]["runs"] > 1
+    np.testing.assert_array_equal(host(u_b), host(u_c))
+
+def test_event_timed_solve_equals_the_graph_solve(ex):
+    """With per-sweep timing on, a solve runs its iterations launch by launch (no captured
+    graphs), the deferred update of the mixed form included; it must give the same
+    iterates, and the timings must count every sweep that did work."""
+    N, nl, bc = 128, 6, 2
+    arr = make_arrays(config_problem(2), N, bc)
+    f, g1, g2 = dev(arr.f), dev(arr.g1), dev(arr.g2)
+    outs, its = [], []
+    for timing in (False, True):
+        ex.set_timing(timing)
+        u = torch.empty_like(f)
+        rc, st = ex.solve_ex(N, nl, bc, f, g1, g2, 1e-9, u, precision=ex.MIXED,
+                             fp32_min_unknowns=1)
+        assert rc == ex.OK, ex.last_error()
+        outs.append(host(u))
+        its.append([(l["iterations"], l["runs"]) for l in st.levels()])
+    ms_a, n_a = ex.get_timing(nl - 1, 0)
+    ms_b, n_b = ex.get_timing(nl - 1, 1)
+    ex.set_timing(False)
+    assert its[0] == its[1]
+    np.testing.assert_array_equal(outs[0], outs[1])
+    assert n_a == n_b == its[1][-1][0] and ms_a > 0 and ms_b > 0
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed-restart"])
 @pytest.mark.parametrize("case", [(32, 4, 1, 1), (48, 5, 2, 2)])
 def test_cg_specialisation_is_bit_identical_to_bicg(ex, prec, case):
