@@ -246,8 +246,10 @@ int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launc
 /* Measurement helper: when on, every Bi-CG sweep launched by later solves is bracketed by
  * device events on the library stream and its duration is added to a per-level total
  * (sweep 0 = sweep A: direction update, A p, A^T p*, sigma; sweep 1 = sweep B: x, r, r*
- * updates, rho, r.r).  Only launches that did work are counted.  Turning it on resets the
- * totals; excmg_get_timing reads them. */
+ * updates, rho, r.r; sweep 2 = sweep A that also applies the previous iteration's x update,
+ * which mixed-precision solves use on grids of 64^3 and up, their sweep B then leaving x
+ * alone).  Only launches that did work are counted.  Turning it on resets the totals;
+ * excmg_get_timing reads them. */
 int excmg_set_timing(int on);
 int excmg_get_timing(int level, int sweep, double *ms_total, long long *launches);
 

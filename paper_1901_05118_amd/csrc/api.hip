@@ -189,8 +189,8 @@ Ctx g_ctx;
 // Optional per-launch timing of the two Bi-CG sweeps (device events on the library stream),
 // accumulated per level: [level][0] sweep A, [level][1] sweep B.
 bool g_timing = false;
-double g_time_ms[EXCMG_MAX_LEVELS][2];
-long long g_time_n[EXCMG_MAX_LEVELS][2];
+double g_time_ms[EXCMG_MAX_LEVELS][3];   // [0] sweep A, [1] sweep B, [2] sweep A with the
+long long g_time_n[EXCMG_MAX_LEVELS][3];  // deferred update of the iterate
 std::vector<hipEvent_t> g_events;
 
 int ensure_events(size_t count) {
@@ -624,7 +624,10 @@ int bicg_iterate(const Level &L, TX *x, BicgState &hs, long long &j) {
             }
             CKH(hipGraphLaunch(exec, g_stream));
             j += K;
-        } else {
+        }
+        int plain_first = 0;   // timed window starting with a sweep A that owes no update
+        if (!graphs) {
+            plain_first = (defer && seg_first) ? 1 : 0;
             for (int t = 0; t < K; t++, j++) {
                 // with a deferred update, the first sweep A of the call has none pending
                 const int dm = defer ? (seg_first ? 1 : 2) : 0;
@@ -647,9 +650,10 @@ int bicg_iterate(const Level &L, TX *x, BicgState &hs, long long &j) {
                 float a = 0.f, b2 = 0.f;
                 CKH(hipEventElapsedTime(&a, g_events[4 * t], g_events[4 * t + 1]));
                 CKH(hipEventElapsedTime(&b2, g_events[4 * t + 2], g_events[4 * t + 3]));
-                g_time_ms[L.index][0] += a;
+                const int ka = (defer && !(t == 0 && plain_first)) ? 2 : 0;
+                g_time_ms[L.index][ka] += a;
                 g_time_ms[L.index][1] += b2;
-                g_time_n[L.index][0]++;
+                g_time_n[L.index][ka]++;
                 g_time_n[L.index][1]++;
             }
         }
@@ -1993,7 +1997,7 @@ int excmg_set_timing(int on) {
 }
 
 int excmg_get_timing(int level, int sweep, double *ms_total, long long *launches) {
-    if (level < 0 || level >= EXCMG_MAX_LEVELS || (sweep != 0 && sweep != 1))
+    if (level < 0 || level >= EXCMG_MAX_LEVELS || sweep < 0 || sweep > 2)
         return fail(EXCMG_EINVAL, "bad level or sweep");
     if (ms_total) *ms_total = g_time_ms[level][sweep];
     if (launches) *launches = g_time_n[level][sweep];

@@ -352,7 +352,8 @@ def set_timing(on: bool):
 
 
 def get_timing(level: int, sweep: int):
-    """(total ms, launches) of sweep 0 (A) or 1 (B) on a level since set_timing(True)."""
+    """(total ms, launches) of sweep 0 (A), 1 (B) or 2 (A with the deferred x update) on a
+    level since set_timing(True)."""
     ms = ctypes.c_double(0.0)
     n = ctypes.c_longlong(0)
     _check("excmg_get_timing", load().excmg_get_timing(level, sweep, ctypes.byref(ms),

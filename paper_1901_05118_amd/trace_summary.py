@@ -9,8 +9,9 @@
 ``kernels`` view) and prints the kernels by total time, then, for the Bi-CG sweeps, the
 launches grouped by launch grid: the grid tells the levels apart, since every level of the
 hierarchy runs the same kernels.  Inside a polling window a converged run issues launches
-that return at once; a launch counts as active when it lasts at least half the median of
-its group, and the active mean is the per-launch cost of the sweep on that level.
+that return at once, and a sweep that stops a run may do only part of its work; a launch
+counts as active (a full sweep) when it lasts at least half the longest launch of its
+group, and the active mean is the per-launch cost of the sweep on that level.
 
 ``counters`` reads the ``*counter_collection.csv`` files of ``rocprofv3 --pmc ... -f csv``
 below DIR and prints, per kernel and launch grid, the mean of each counter per dispatch.
@@ -41,7 +42,7 @@ def short_name(n: str) -> str:
 
 def _grid_rows(durations):
     med = statistics.median(durations)
-    act = [v for v in durations if v >= 0.5 * med]
+    act = [v for v in durations if v >= 0.5 * max(durations)]
     return len(durations), len(act), sum(act) / len(act), med
 
 
@@ -59,7 +60,7 @@ def trace(db_path: str, cmd: str, top: int = 16, sweeps: int = 4) -> str:
                    f"{100 * s / total:.1f}% |")
     out += ["", f"Total kernel time: {total / 1e6:.1f} ms", "",
             "Launches per grid (x*y*z threads) of the busiest kernels; 'active' = lasting at "
-            "least half the group's median.", "",
+            "least half the group's longest launch (full sweeps).", "",
             "| kernel | grid | calls | active | mean active us | median us |",
             "|---|---|---:|---:|---:|---:|"]
     for n, *_ in rows[:sweeps]:

@@ -391,12 +391,14 @@ def test_event_timed_solve_equals_the_graph_solve(ex):
         assert rc == ex.OK, ex.last_error()
         outs.append(host(u))
         its.append([(l["iterations"], l["runs"]) for l in st.levels()])
-    ms_a, n_a = ex.get_timing(nl - 1, 0)
+    ms_a, n_a = ex.get_timing(nl - 1, 0)   # sweeps A owing no update (first of each run)
     ms_b, n_b = ex.get_timing(nl - 1, 1)
+    ms_x, n_x = ex.get_timing(nl - 1, 2)   # sweeps A applying the deferred update
     ex.set_timing(False)
     assert its[0] == its[1]
     np.testing.assert_array_equal(outs[0], outs[1])
-    assert n_a == n_b == its[1][-1][0] and ms_a > 0 and ms_b > 0
+    assert n_a + n_x == n_b == its[1][-1][0]
+    assert n_x > n_a > 0 and ms_x > 0 and ms_b > 0
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed-restart"])
 @pytest.mark.parametrize("case", [(32, 4, 1, 1), (48, 5, 2, 2)])

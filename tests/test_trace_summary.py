@@ -23,6 +23,23 @@ def test_trace_groups_by_grid_and_drops_noop_launches(tmp_path):
     assert "| 512x8x1 | 7 | 5 | 1.0 | 1.0 |" in md
 
 
+
+def test_trace_active_means_full_sweeps_only(tmp_path):
+    """Three populations on one grid: no-op launches, sweeps that stop a run after a partial
+    pass, full sweeps; only the full ones are active, even when they are not the majority."""
+    db = tmp_path / "r.db"
+    con = sqlite3.connect(db)
+    con.execute("create table kernels (name text, duration integer, grid_x integer, "
+                "grid_y integer, grid_z integer)")
+    name = "void excmg::zmarch<2, 16, float>(excmg::Geom, float const*)"
+    rows = ([(name, 20, 512, 16, 1)] * 40 + [(name, 560, 512, 16, 1)] * 12
+            + [(name, 1720, 512, 16, 1)] * 45)
+    con.executemany("insert into kernels values (?,?,?,?,?)", rows)
+    con.commit()
+    con.close()
+    md = ts.trace(str(db), "cmd")
+    assert "| 512x16x1 | 97 | 45 | 1.7 |" in md
+
 def test_counters_mean_per_kernel_and_grid(tmp_path):
     d = tmp_path / "h" / "1"
     d.mkdir(parents=True)
