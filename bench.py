@@ -319,6 +319,11 @@ def main():
                 "launches": n_a, "ms_per_launch": round(avg_a, 4), "bytes_per_launch": bytes_a,
                 "sweep_b": {"launches": n_b, "ms_per_launch": round(avg_b, 4),
                             "gbs": round(bytes_b / (avg_b * 1e-3) / 1e9, 1)},
+                # one Bi-CG iteration (both sweeps): 76 (mixed) or 136 (FP64) bytes per unknown
+                "iteration": {"ms": round(avg_a + avg_b, 4),
+                              "gbs": round((bytes_a + bytes_b) / ((avg_a + avg_b) * 1e-3) / 1e9, 1),
+                              "frac": round((bytes_a + bytes_b) / ((avg_a + avg_b) * 1e-3) / 1e9
+                                            / HBM_PEAK_GBS, 4)},
                 "copy_gbs": round(bytes_c / (ms_c * 1e-3) / 1e9, 1)}
 
     out = {
