@@ -96,6 +96,13 @@ typedef struct excmg_opts {
     int fp32_min_unknowns; /* mixed precision with EXCMG_RELIABLE: levels with fewer        */
                         /* unknowns run FP64 Bi-CG (launch-latency bound, so FP32 vectors    */
                         /* gain nothing there); 0: 262144 (2^18), 1: FP32 on every level    */
+    int row_pad;        /* mixed precision, 3D: 1 stores the rows of the FP32 Bi-CG vectors */
+                        /* (and of the FP64 iterate and right-hand side they are solved     */
+                        /* with) on a 128-byte multiple plus 128 bytes, so no cache line is */
+                        /* split between two stencil tiles; the level's b and u are copied  */
+                        /* in and out.  0 (default): contiguous rows.  Same results bit for */
+                        /* bit; padded rows speed up the Bi-CG stencil sweep on large grids */
+                        /* and slow the vector updates, about even for the whole solve      */
 } excmg_opts;
 
 /* Per-level record filled by excmg_solve_ex (levels 0 and 1 report iterations = 0). */

@@ -134,8 +134,17 @@ struct Level {
     long long nu = 0; // unknowns
     long long nodes = 0;
     Geom g1{}, g2{}, g2f{};  // launch shapes: one-array kernels, sweep A FP64, sweep A FP32
+    // Rows of the FP32 Bi-CG vectors (and of the FP64 iterate and right-hand side they are
+    // solved with): ld elements apart, nflat elements of storage; g1p is g1 on that layout
+    // (g2f always is).  ld = n: contiguous, as every other vector of the level.  The vector
+    // kernels walk the nu unknowns in the contiguous order whatever the layout, so results
+    // do not depend on it.
+    int ld = 0;
+    long long nflat = 0;
+    Geom g1p{};
     DBuf b, x, u;     // right-hand side, unknowns, node array (solution or EXP_finite guess)
     DBuf diag;        // diag(A_h), made when a Jacobi-preconditioned solve first needs it
+    Rows rows() const { return ld == n ? Rows{} : Rows{n, ld}; }
 };
 
 void release_graphs();
@@ -148,6 +157,7 @@ struct Ctx {
     // Bi-CG workspace (sized for the finest level)
     DBuf r, rs, p[2], ps[2], q, qs;
     DBuf ubest;                 // best FP64 iterate of a level solved with residual replacement
+    DBuf xp, bp;                // FP64 iterate and right-hand side of a level with padded rows
     DBuf part_a, part_b;        // Dot2 partials of the two sweeps
     DBuf state;                 // BicgState
     DBuf scal;                  // misc device scalars
@@ -169,7 +179,7 @@ struct Ctx {
         lv.clear();
         r.release(); rs.release();
         p[0].release(); p[1].release(); ps[0].release(); ps[1].release();
-        q.release(); qs.release(); ubest.release();
+        q.release(); qs.release(); ubest.release(); xp.release(); bp.release();
         part_a.release(); part_b.release(); state.release(); scal.release();
         chol[0].release(); chol[1].release(); info.release(); vz1.release();
         if (host_state) (void)hipHostFree(host_state);
@@ -233,16 +243,32 @@ Geom choose_shape(int N, int bc, int kind) {
     return make_geom(n, bc, ty, zc);
 }
 
+// Row stride of padded vectors: a multiple of 32 elements (every row starts on a 128-byte
+// line in FP32 and FP64) plus one more line, which keeps the stride off powers of two
+// (rows a power of two apart fall into the same cache sets).
+int padded_ld(int n) { return (n + 31) / 32 * 32 + 32; }
+
+void set_rows(Level &L, int ld, int dim) {
+    if (dim == 2) ld = L.n;
+    L.ld = ld;
+    L.nflat = dim == 2 ? L.nu : (long long)L.n * L.n * ld;
+    L.g1p = with_rows(L.g1, ld);
+    L.g2f = with_rows(L.g2f, ld);
+}
+
+int level_ld(int n, int row_pad) { return row_pad > 0 ? padded_ld(n) : n; }
+
 void choose_shapes(Level &L, int bc, int dim = 3) {
     if (dim == 2) {  // one pass per tile: more rows per workgroup on large planes
         const int n = L.N - 1;
         const int ty = n >= 1024 ? 16 : (n >= 96 ? 8 : 4);
         L.g1 = L.g2 = L.g2f = make_geom_2d(n, bc, ty);
-        return;
+    } else {
+        L.g1 = choose_shape(L.N, bc, 0);
+        L.g2 = choose_shape(L.N, bc, 1);
+        L.g2f = choose_shape(L.N, bc, 2);
     }
-    L.g1 = choose_shape(L.N, bc, 0);
-    L.g2 = choose_shape(L.N, bc, 1);
-    L.g2f = choose_shape(L.N, bc, 2);
+    set_rows(L, L.ld > 0 ? L.ld : L.n, dim);
 }
 
 int check_sizes(int n_finest, int n_levels, int bc, int dim = 3) {
@@ -312,13 +338,19 @@ int setup_levels(int n_finest, int n_levels, int bc, int dim) {
         L.n = L.N - 1;
         L.nu = (long long)L.n * L.n * (dim == 2 ? 1 : L.n);
         L.nodes = (long long)(L.N + 1) * (L.N + 1) * (dim == 2 ? 1 : (L.N + 1));
+        L.ld = 0;
         choose_shapes(L, bc, dim);
         CKR(L.b.ensure(L.nu * 8));
         CKR(L.x.ensure(L.nu * 8));
         CKR(L.u.ensure(L.nodes * 8));
     }
     const Level &F = c.lv.back();
-    const size_t vb = (size_t)F.nu * 8;
+    // FP32 vectors with padded rows (row_pad) fit in the FP64 vectors' room, except on
+    // grids of under 64 unknowns per axis
+    long long flat = F.nu;
+    if (dim == 3)
+        for (const Level &L : c.lv) flat = std::max(flat, (long long)L.n * L.n * padded_ld(L.n));
+    const size_t vb = std::max((size_t)F.nu * 8, (size_t)flat * 4);
     CKR(c.r.ensure(vb));
     CKR(c.rs.ensure(vb));
     CKR(c.p[0].ensure(vb));
@@ -362,10 +394,11 @@ int need_ctx(int level) {
 
 // ------------------------------------------------------------------ reductions
 
-int device_dot(long long n, const double *x, const double *y, double *out_dev, int slot) {
+int device_dot(long long n, const double *x, const double *y, double *out_dev, int slot,
+               Rows rows = Rows{}) {
     Ctx &c = g_ctx;
     const int nb = vec_blocks(n);
-    CKH(dot_partials<double>(n, x, y, c.part_b.as<Pair>(), nb, g_stream));
+    CKH(dot_partials<double>(n, x, y, c.part_b.as<Pair>(), nb, g_stream, rows));
     CKH(reduce_to(out_dev, c.part_b.as<Pair>(), nb, slot, g_stream));
     return EXCMG_OK;
 }
@@ -422,7 +455,7 @@ struct RunVariant {
 RunVariant g_var;
 
 struct GraphEntry {
-    int level, tsize, cg, fold, K, defer;
+    int level, tsize, cg, fold, K, defer, ld;
     const void *x, *d, *xs;
     hipGraph_t graph;
     hipGraphExec_t exec;
@@ -449,6 +482,8 @@ int launch_iteration(const Level &L, TX *x, long long j, int ev, hipStream_t st,
     BicgState *S = c.state.as<BicgState>();
     T *r = c.r.as<T>(), *rs = c.rs.as<T>(), *q = c.q.as<T>(), *qs = c.qs.as<T>();
     const Geom &G = sizeof(T) == 4 ? L.g2f : L.g2;
+    // FP32 vectors (and the iterate solved with them) have the level's row layout
+    const Rows rows = sizeof(T) == 4 ? L.rows() : Rows{};
     const int nsb = stencil_blocks(G);
     const int nvb = update_blocks(L.nu);
     const int cur = (int)(j & 1), nxt = cur ^ 1;
@@ -500,10 +535,10 @@ int launch_iteration(const Level &L, TX *x, long long j, int ev, hipStream_t st,
     if (!g_fold) CKH(bicg_alpha(S, c.part_a.as<Pair>(), nsb, st));
     if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev + 2], st));
     if (g_cg)
-        CKH((cg_update<TX, T>(L.nu, S, x, pn, r, q, c.part_b.as<Pair>(), st, lb)));
+        CKH((cg_update<TX, T>(L.nu, S, x, pn, r, q, c.part_b.as<Pair>(), st, lb, rows)));
     else
         CKH((bicg_update<TX, T>(L.nu, S, defer ? nullptr : x, pn, r, q, rs, qs,
-                                c.part_b.as<Pair>(), st, lb)));
+                                c.part_b.as<Pair>(), st, lb, rows)));
     if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev + 3], st));
     if (!g_fold) {
         if (g_cg) CKH(cg_beta(S, c.part_b.as<Pair>(), nvb, st));
@@ -532,7 +567,8 @@ template <typename TX, typename T>
 int window_graph(const Level &L, TX *x, int K, hipGraphExec_t *out, int defer = 0) {
     for (GraphEntry &e : g_graph_cache)
         if (e.level == L.index && e.tsize == (int)sizeof(T) && e.cg == (int)g_cg &&
-            e.fold == (int)g_fold && e.K == K && e.defer == defer && e.x == (const void *)x &&
+            e.fold == (int)g_fold && e.K == K && e.defer == defer && e.ld == L.ld &&
+            e.x == (const void *)x &&
             e.d == g_var.d && e.xs == g_var.xs) {
             *out = e.exec;
             return EXCMG_OK;
@@ -553,7 +589,7 @@ int window_graph(const Level &L, TX *x, int K, hipGraphExec_t *out, int defer = 
     hipGraphExec_t exec = nullptr;
     CKH(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
     g_graph_cache.push_back(GraphEntry{L.index, (int)sizeof(T), (int)g_cg, (int)g_fold, K, defer,
-                                       (const void *)x, g_var.d, g_var.xs, graph, exec});
+                                       L.ld, (const void *)x, g_var.d, g_var.xs, graph, exec});
     *out = exec;
     return EXCMG_OK;
 }
@@ -770,7 +806,7 @@ int bicg_inner_fp32(const Level &L, double *u, double inner_tol, int maxit, int 
     BicgState *S = c.state.as<BicgState>();
     float *r = c.r.as<float>();
     const int nvb = vec_blocks(L.nu);
-    CKH(dot_partials<float>(L.nu, r, r, c.part_b.as<Pair>(), nvb, g_stream));
+    CKH(dot_partials<float>(L.nu, r, r, c.part_b.as<Pair>(), nvb, g_stream, L.rows()));
     CKH(reduce_to((double *)&S->bb, c.part_b.as<Pair>(), nvb, 0, g_stream));
     CKH(bicg_start(S, c.part_b.as<Pair>(), nvb, inner_tol, maxit, g_stream));
     BicgState hs;
@@ -782,19 +818,34 @@ int bicg_inner_fp32(const Level &L, double *u, double inner_tol, int maxit, int 
     return EXCMG_OK;
 }
 
+// The mixed-precision solvers work on the level's row layout (L.ld): b and u are padded
+// into the context's copies first when the rows are padded, and u is copied back after.
+template <class Solve>
+int with_level_rows(const Level &L, const double *b, double *u, Solve solve) {
+    if (L.ld == L.n) return solve(b, u);
+    Ctx &c = g_ctx;
+    double *bp = c.bp.as<double>(), *xp = c.xp.as<double>();
+    CKH(pad_rows(L.n, L.ld, b, bp, g_stream));
+    CKH(pad_rows(L.n, L.ld, u, xp, g_stream));
+    CKR(solve(bp, xp));
+    CKH(unpad_rows(L.n, L.ld, xp, u, g_stream));
+    return EXCMG_OK;
+}
+
 // Iterative refinement on one level: r = b - A u in FP64 (rounded to FP32 for the inner
 // solve), FP32 Bi-CG correction added to u in FP64, until ||b - A u||_2 <= eps ||b||_2 in
 // FP64.  Stops early (EXCMG_ENOCONV) if an outer step fails to reduce the FP64 residual.
+// b and u have the level's row layout.
 int level_solve_mixed(const Level &L, const double *b, double *u, double eps, int maxit,
                       int max_outer, double inner_tol, excmg_level_stats *st) {
     Ctx &c = g_ctx;
     double *sc = c.scal.as<double>();
-    CKR(device_dot(L.nu, b, b, sc, 1));
-    const int nrb = stencil_blocks(L.g1);
+    CKR(device_dot(L.nu, b, b, sc, 1, L.rows()));
+    const int nrb = stencil_blocks(L.g1p);
     int total = 0, outer = 0, status = EXCMG_OK;
     double bb = 0.0, rr = 0.0, prev = INFINITY;
     for (;;) {
-        CKH(stencil_residual_cast(L.g1, L.g1.ty, b, u, c.r.as<float>(), c.rs.as<float>(),
+        CKH(stencil_residual_cast(L.g1p, L.g1p.ty, b, u, c.r.as<float>(), c.rs.as<float>(),
                                   c.part_a.as<Pair>(), g_stream));
         CKH(reduce_to(sc, c.part_a.as<Pair>(), nrb, 2, g_stream));
         CKH(hipMemcpyAsync(c.host_scal, sc, 3 * sizeof(double), hipMemcpyDeviceToHost, g_stream));
@@ -840,18 +891,20 @@ int level_solve_mixed(const Level &L, const double *b, double *u, double eps, in
 // has been replaced into breaks down), u goes back to it and a fresh run starts from there
 // (a breakdown of a fresh run is reported).  Stops when ||b - A u||_2 <= eps ||b||_2 in FP64,
 // when two replacements in a row fail to halve the squared residual, or at the caps.
+// b and u have the level's row layout.
 int level_solve_reliable(const Level &L, const double *b, double *u, double eps, int maxit,
                          int max_outer, double delta, excmg_level_stats *st) {
     Ctx &c = g_ctx;
     BicgState *S = c.state.as<BicgState>();
     double *sc = c.scal.as<double>(), *ub = c.ubest.as<double>();
     float *r = c.r.as<float>(), *rs = c.rs.as<float>();
-    const int nrb = stencil_blocks(L.g1), nvb = vec_blocks(L.nu);
-    const size_t ubytes = (size_t)L.nu * 8;
-    CKR(device_dot(L.nu, b, b, sc, 1));
+    const Rows rows = L.rows();
+    const int nrb = stencil_blocks(L.g1p), nvb = vec_blocks(L.nu);
+    const size_t ubytes = (size_t)L.nflat * 8;
+    CKR(device_dot(L.nu, b, b, sc, 1, rows));
     // FP64 residual of u (rounded into r and r*), its square norm, and b.b
     auto true_residual = [&](double &bb, double &rr) -> int {
-        CKH(stencil_residual_cast(L.g1, L.g1.ty, b, u, r, rs, c.part_a.as<Pair>(), g_stream));
+        CKH(stencil_residual_cast(L.g1p, L.g1p.ty, b, u, r, rs, c.part_a.as<Pair>(), g_stream));
         CKH(reduce_to(sc, c.part_a.as<Pair>(), nrb, 2, g_stream));
         CKH(hipMemcpyAsync(c.host_scal, sc, 3 * sizeof(double), hipMemcpyDeviceToHost, g_stream));
         CKH(hipStreamSynchronize(g_stream));
@@ -868,7 +921,7 @@ int level_solve_reliable(const Level &L, const double *b, double *u, double eps,
     int since_start = 0;  // replacements in the current run
     // fresh run on the current residual: rho_0 = r.r of the FP32 copy
     auto start_run = [&]() -> int {
-        CKH(dot_partials<float>(L.nu, r, r, c.part_b.as<Pair>(), nvb, g_stream));
+        CKH(dot_partials<float>(L.nu, r, r, c.part_b.as<Pair>(), nvb, g_stream, rows));
         CKH(reduce_to((double *)&S->bb, c.part_b.as<Pair>(), nvb, 0, g_stream));
         CKH(bicg_start(S, c.part_b.as<Pair>(), nvb, delta, std::max(1, maxit - done), g_stream));
         CKH(state_resume(S, std::max((delta * delta) * rr, 0.25 * target), g_stream));
@@ -913,7 +966,7 @@ int level_solve_reliable(const Level &L, const double *b, double *u, double eps,
                 continue;
             }
             since_start++;
-            CKH(rho_partials<float>(L.nu, r, rs, c.part_b.as<Pair>(), g_stream));
+            CKH(rho_partials<float>(L.nu, r, rs, c.part_b.as<Pair>(), g_stream, nullptr, rows));
             CKH(state_resume(S, std::max((delta * delta) * rr, 0.25 * target), g_stream));
             CKR(read_state(hs));
             // the run stopped inside the last window: go on from the iteration it reached
@@ -952,6 +1005,19 @@ int solve_cascade(const excmg_opts &o, const double *f, const double *g1, const 
     const bool jacobi = (o.precond == EXCMG_PRECOND_JACOBI);
     const double inner_tol = o.inner_tol > 0 ? o.inner_tol : (reliable ? 0.1 : 1e-4);
     const bool mixed = (o.precision == EXCMG_MIXED);
+    if (c.dim == 3) {
+        // padded rows: the FP64 copies of b and u they are solved with, made on first use
+        long long flat = 0;
+        for (Level &Lv : c.lv) {
+            set_rows(Lv, level_ld(Lv.n, mixed ? o.row_pad : 0), c.dim);
+            if (Lv.ld != Lv.n) flat = std::max(flat, Lv.nflat);
+        }
+        if (flat > 0) {
+            CKR(c.xp.ensure((size_t)flat * 8));
+            CKR(c.bp.ensure((size_t)flat * 8));
+            CKR(c.ubest.ensure((size_t)std::max(flat, c.lv.back().nu) * 8));
+        }
+    }
     hipEvent_t ev0, ev1, evl0, evl1;
     CKH(hipEventCreate(&ev0));
     CKH(hipEventCreate(&ev1));
@@ -987,11 +1053,17 @@ int solve_cascade(const excmg_opts &o, const double *f, const double *g1, const 
             const long long fp32_min = o.fp32_min_unknowns > 0 ? o.fp32_min_unknowns : (1LL << 18);
             const bool lmixed = mixed && (!reliable || Lv.nu >= fp32_min);
             if (lmixed && reliable)
-                CKR(level_solve_reliable(Lv, Lv.b.as<double>(), Lv.x.as<double>(), eps, maxit,
-                                         max_outer, inner_tol, &ls));
+                CKR(with_level_rows(Lv, Lv.b.as<double>(), Lv.x.as<double>(),
+                                    [&](const double *b, double *u) {
+                                        return level_solve_reliable(Lv, b, u, eps, maxit,
+                                                                    max_outer, inner_tol, &ls);
+                                    }));
             else if (lmixed)
-                CKR(level_solve_mixed(Lv, Lv.b.as<double>(), Lv.x.as<double>(), eps, maxit,
-                                      max_outer, inner_tol, &ls));
+                CKR(with_level_rows(Lv, Lv.b.as<double>(), Lv.x.as<double>(),
+                                    [&](const double *b, double *u) {
+                                        return level_solve_mixed(Lv, b, u, eps, maxit, max_outer,
+                                                                 inner_tol, &ls);
+                                    }));
             else
                 CKR(level_solve(Lv, Lv.b.as<double>(), Lv.x.as<double>(), eps, maxit, max_runs,
                                 &ls, jacobi ? level_diagonal(Lv) : nullptr));
@@ -1689,6 +1761,7 @@ int solve_ex_dim(const excmg_opts *opts, const double *f, const double *g1, cons
         return fail(EXCMG_EINVAL, "precond %d not supported", o.precond);
     if (o.fp32_min_unknowns < 0)
         return fail(EXCMG_EINVAL, "fp32_min_unknowns must be >= 0");
+    if (o.row_pad != 0 && o.row_pad != 1) return fail(EXCMG_EINVAL, "row_pad must be 0 or 1");
     if (o.precond == EXCMG_PRECOND_JACOBI && (o.precision != EXCMG_FP64 || o.method != EXCMG_BICG))
         return fail(EXCMG_EINVAL, "the Jacobi preconditioner runs with FP64 Bi-CG only");
     CKR(setup(o.n_finest, o.n_levels, o.bc_kind, dim));
@@ -1784,11 +1857,18 @@ int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launc
     Ctx &c = g_ctx;
     const Level &L = c.lv.back();
     const size_t es = precision == EXCMG_FP64 ? 8 : 4;
-    const size_t vb = (size_t)L.nu * es;
+    // mixed sweeps run on the row layout of the mixed solve (padded on large grids)
+    const bool mixed = precision == EXCMG_MIXED;
+    const long long nv = mixed ? L.nflat : L.nu;
+    const Rows rows = mixed ? L.rows() : Rows{};
+    const bool padded = mixed && L.ld != L.n;
+    double *xv = padded ? c.xp.as<double>() : L.x.as<double>();
+    double *bv = padded ? c.bp.as<double>() : L.b.as<double>();
+    const size_t vb = (size_t)nv * es;
     DBuf *vecs[8] = {&c.r, &c.rs, &c.p[0], &c.p[1], &c.ps[0], &c.ps[1], &c.q, &c.qs};
     for (DBuf *v : vecs) CKH(hipMemsetAsync(v->p, 0, vb, g_stream));
-    CKH(hipMemsetAsync(L.x.p, 0, (size_t)L.nu * 8, g_stream));
-    CKH(hipMemsetAsync(L.b.p, 0, (size_t)L.nu * 8, g_stream));
+    CKH(hipMemsetAsync(xv, 0, (size_t)nv * 8, g_stream));
+    CKH(hipMemsetAsync(bv, 0, (size_t)nv * 8, g_stream));
     BicgState hs{};
     hs.status = kRunning;
     hs.rho = 1.0;
@@ -1819,24 +1899,26 @@ int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launc
         }
         float *r = c.r.as<float>(), *rs = c.rs.as<float>();
         switch (which) {
-            case 0: return stencil_apply<float>(L.g1, L.g1.ty, r, c.q.as<float>(), g_stream);
-            case 1: return stencil_residual_cast(L.g1, L.g1.ty, L.b.as<double>(), L.x.as<double>(),
-                                                 r, rs, c.part_a.as<Pair>(), g_stream);
+            case 0: return stencil_apply<float>(L.g1p, L.g1p.ty, r, c.q.as<float>(), g_stream);
+            case 1: return stencil_residual_cast(L.g1p, L.g1p.ty, bv, xv, r, rs,
+                                                 c.part_a.as<Pair>(), g_stream);
             case 2: return stencil_pair_direction<float>(
                         L.g2f, L.g2f.ty, r, rs, c.p[0].as<float>(), c.ps[0].as<float>(), &S->beta,
                         0, c.p[1].as<float>(), c.ps[1].as<float>(), c.q.as<float>(),
                         c.qs.as<float>(), c.part_a.as<Pair>(), &S->status, g_stream);
-            case 3: return bicg_update<double, float>(L.nu, S, L.x.as<double>(), c.p[1].as<float>(),
-                                                      r, c.q.as<float>(), rs, c.qs.as<float>(),
-                                                      c.part_b.as<Pair>(), g_stream);
+            case 3: return bicg_update<double, float>(L.nu, S, xv, c.p[1].as<float>(), r,
+                                                      c.q.as<float>(), rs, c.qs.as<float>(),
+                                                      c.part_b.as<Pair>(), g_stream, StepLink{},
+                                                      rows);
             case 5: return stencil_pair_direction_x(
                         L.g2f, L.g2f.ty, r, rs, c.p[0].as<float>(), c.ps[0].as<float>(), &S->beta,
                         c.p[1].as<float>(), c.ps[1].as<float>(), c.q.as<float>(),
-                        c.qs.as<float>(), c.part_a.as<Pair>(), &S->status, L.x.as<double>(),
-                        &S->alpha, g_stream, StepLink{});
+                        c.qs.as<float>(), c.part_a.as<Pair>(), &S->status, xv, &S->alpha,
+                        g_stream, StepLink{});
             case 6: return bicg_update<double, float>(L.nu, S, nullptr, c.p[1].as<float>(), r,
                                                       c.q.as<float>(), rs, c.qs.as<float>(),
-                                                      c.part_b.as<Pair>(), g_stream);
+                                                      c.part_b.as<Pair>(), g_stream, StepLink{},
+                                                      rows);
             default: return copy_convert<float, float>(L.nu, r, c.q.as<float>(), g_stream);
         }
     };
@@ -1918,12 +2000,13 @@ int excmg_autotune(int n, int kind, int precision, int reps, int *ty_out, int *z
     if (precision != EXCMG_FP64 && precision != EXCMG_MIXED) return fail(EXCMG_EINVAL, "bad precision");
     if (reps < 1) reps = 5;
     const int nn = n - 1;
-    const long long nu = (long long)nn * nn * nn;
     const size_t es = precision == EXCMG_FP64 ? 8 : 4;
+    const int ld = nn;  // contiguous rows, the solver's default
+    const long long nv = (long long)nn * nn * ld;
     DBuf v[8], part, stb;
     for (auto &b : v) {
-        CKR(b.ensure((size_t)nu * es));
-        CKH(hipMemsetAsync(b.p, 0, (size_t)nu * es, g_stream));
+        CKR(b.ensure((size_t)nv * es));
+        CKH(hipMemsetAsync(b.p, 0, (size_t)nv * es, g_stream));
     }
     CKR(stb.ensure(sizeof(BicgState)));
     BicgState hs{};
@@ -1943,7 +2026,7 @@ int excmg_autotune(int n, int kind, int precision, int reps, int *ty_out, int *z
     for (int ty : tys) {
         for (int zc = 4; zc <= 512; zc *= 2) {
             if (zc > nn && zc != 4) break;
-            Geom g = make_geom(nn, 1, ty, std::min(zc, nn));
+            Geom g = with_rows(make_geom(nn, 1, ty, std::min(zc, nn)), ld);
             rc = part.ensure((size_t)stencil_blocks(g) * sizeof(Pair));
             if (rc) break;
             auto launch = [&]() -> hipError_t {
@@ -2020,7 +2103,7 @@ int excmg_set_shape(int n, int kind, int ty, int zc) {
     release_graphs();  // captured iteration windows hold the old launch shapes
     for (Level &L : g_ctx.lv) {
         if (L.N != n) continue;
-        choose_shapes(L, g_ctx.bc);
+        choose_shapes(L, g_ctx.bc, g_ctx.dim);
         const size_t need = (size_t)std::max({stencil_blocks(L.g1), stencil_blocks(L.g2),
                                               stencil_blocks(L.g2f)}) * sizeof(Pair);
         if (need > g_ctx.part_a.bytes) CKR(g_ctx.part_a.ensure(need));

@@ -16,6 +16,22 @@ struct Geom {
     int ntiles;
     double sgn;                     // fictitious-point sign: +1 first kind, -1 second kind
     int dim = 3;                    // 3: n^3 unknowns (z-marched); 2: n^2 unknowns (one plane)
+    int ld = 0;                     // elements from one row of a vector to the next (>= n)
+    i64 ps = 0;                     // elements from one plane to the next (n * ld)
+};
+
+// The same launch on vectors whose rows are ld elements apart (ld >= n).
+inline Geom with_rows(Geom g, int ld) {
+    g.ld = ld;
+    g.ps = (i64)g.n * ld;
+    return g;
+}
+
+// Row layout of a vector: rows of len elements, ld apart (positions whose column is len or
+// more are padding).  The vector kernels walk the unknowns in contiguous order and address
+// them through the layout, so they read and write no padding.  {1, 1}: contiguous.
+struct Rows {
+    int len = 1, ld = 1;
 };
 
 Geom make_geom(int n, int bc, int ty, int zc);
@@ -109,12 +125,13 @@ int update_blocks(long long n);   // workgroups (= partial pairs per value) of t
 template <typename TX, typename T>
 hipError_t bicg_update(long long n, const BicgState *s, TX *x, const T *p, T *r, const T *q,
                        T *rs, const T *qs, Pair *partials, hipStream_t st,
-                       StepLink link = StepLink{});
+                       StepLink link = StepLink{}, Rows rows = Rows{});
 
 // CG sweep B: x += alpha p; r -= alpha q; partials of r.r
 template <typename TX, typename T>
 hipError_t cg_update(long long n, const BicgState *s, TX *x, const T *p, T *r, const T *q,
-                     Pair *partials, hipStream_t st, StepLink link = StepLink{});
+                     Pair *partials, hipStream_t st, StepLink link = StepLink{},
+                     Rows rows = Rows{});
 hipError_t cg_beta(BicgState *s, const Pair *part, int count, hipStream_t st);
 // the end-of-iteration checks of a folded step as a kernel of its own (one workgroup), run
 // before the host reads the state
@@ -123,7 +140,7 @@ hipError_t step_check(StepLink link, hipStream_t st);
 // with d, of rs.(r / d) and r.r
 template <typename T>
 hipError_t rho_partials(long long n, const T *r, const T *rs, Pair *partials, hipStream_t st,
-                        const T *d = nullptr);
+                        const T *d = nullptr, Rows rows = Rows{});
 // Algorithm 2's sweep B with its options (FP64): d != NULL divides by the diagonal
 // preconditioner in rho' = r*.(M^-1 r); xs != NULL also updates the dual iterate
 // x* += alpha p* (ps)
@@ -143,7 +160,12 @@ hipError_t state_resume(BicgState *s, double thr, hipStream_t st);
 // partials of x.y
 template <typename T>
 hipError_t dot_partials(long long n, const T *x, const T *y, Pair *partials, int nblocks,
-                        hipStream_t st);
+                        hipStream_t st, Rows rows = Rows{});
+
+// Row padding of an n^3 FP64 vector: dst (rows ld apart, padding set to 0) from src
+// (contiguous), and back.
+hipError_t pad_rows(int n, int ld, const double *src, double *dst, hipStream_t st);
+hipError_t unpad_rows(int n, int ld, const double *src, double *dst, hipStream_t st);
 
 template <typename TD, typename TS>
 hipError_t copy_convert(long long n, const TS *src, TD *dst, hipStream_t st);

@@ -3,6 +3,8 @@
 // Every kernel here reproduces the arithmetic order its operation is specified with
 // (contraction off, sums left to right as the formulas are written), so results are
 // deterministic and independent of the launch shape.
+#include <algorithm>
+
 #include "common.hpp"
 #include "internal.hpp"
 #include "step.hpp"
@@ -29,6 +31,40 @@ int update_blocks(long long n) {
     return (int)b;
 }
 
+// Address of element v of a grid-stride walk v = v0, v0 + stride, ... over the n unknowns
+// of a vector stored with padded rows (Rows): the walk, and so the elements each thread
+// takes and the order of its partial sums, is the contiguous vector's; only the address
+// moves.  Row and column are carried by additions, so no division per element.
+template <bool PAD>
+struct Walk {
+    long long row = 0, srow = 0;
+    int col = 0, scol = 0, len = 1, ld = 1;
+    __device__ Walk(Rows r, long long v0, long long stride) {
+        if constexpr (PAD) {
+            len = r.len;
+            ld = r.ld;
+            row = v0 / len;
+            col = (int)(v0 % len);
+            srow = stride / len;
+            scol = (int)(stride % len);
+        }
+    }
+    __device__ long long at(long long v) const {
+        if constexpr (PAD) return row * ld + col;
+        else return v;
+    }
+    __device__ void advance() {
+        if constexpr (PAD) {
+            col += scol;
+            row += srow;
+            if (col >= len) {
+                col -= len;
+                row++;
+            }
+        }
+    }
+};
+
 // ------------------------------------------------------------------ Bi-CG updates
 
 // Algorithm 2: x_{k+1} = x_k + alpha p_k, r_{k+1} = r_k - alpha A p_k,
@@ -36,19 +72,21 @@ int update_blocks(long long n) {
 // The iterate x may be FP64 while the Bi-CG vectors are FP32 (iterative refinement updates
 // the FP64 solution directly).
 // With a StepLink the kernel first merges sweep A's partials itself (sigma, alpha).
-template <typename TX, typename T>
+template <typename TX, typename T, bool PAD>
 __global__ void __launch_bounds__(kUpdateThreads)
     k_bicg_update(long long n, const BicgState *s, TX *x, const T *p, T *r, const T *q, T *rs,
-                  const T *qs, Pair *partials, StepLink link) {
+                  const T *qs, Pair *partials, StepLink link, Rows rows) {
     __shared__ Pair sh[2 * (kUpdateThreads / kWave)];
     const long long stride = (long long)gridDim.x * blockDim.x;
-    const long long i0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long v0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    Walk<PAD> w(rows, v0, stride);
     // this thread's first element is requested before the status and the scalars, whose
     // loads and merge would otherwise be waited for first (launch latency on small grids)
     TX x0 = 0;
     T p0 = 0, r0 = 0, q0 = 0, s0 = 0, t0 = 0;
     const bool upd_x = (x != nullptr);   // else the next sweep A applies x += alpha p
-    if (i0 < n) {
+    if (v0 < n) {
+        const long long i0 = w.at(v0);
         if (upd_x) {
             x0 = x[i0];
             p0 = p[i0];
@@ -72,8 +110,9 @@ __global__ void __launch_bounds__(kUpdateThreads)
         alpha = s->alpha;
     }
     Pair acc[2] = {{0.0, 0.0}, {0.0, 0.0}};
-    for (long long i = i0; i < n; i += stride) {
-        if (i != i0) {
+    for (long long v = v0; v < n; v += stride, w.advance()) {
+        const long long i = w.at(v);
+        if (v != v0) {
             if (upd_x) {
                 x0 = x[i];
                 p0 = p[i];
@@ -101,33 +140,41 @@ __global__ void __launch_bounds__(kUpdateThreads)
 
 template <typename TX, typename T>
 hipError_t bicg_update(long long n, const BicgState *s, TX *x, const T *p, T *r, const T *q,
-                       T *rs, const T *qs, Pair *partials, hipStream_t st, StepLink link) {
-    hipLaunchKernelGGL((k_bicg_update<TX, T>), dim3(update_blocks(n)), dim3(kUpdateThreads), 0, st, n,
-                       s, x, p, r, q, rs, qs, partials, link);
+                       T *rs, const T *qs, Pair *partials, hipStream_t st, StepLink link,
+                       Rows rows) {
+    if (rows.ld != rows.len)
+        hipLaunchKernelGGL((k_bicg_update<TX, T, true>), dim3(update_blocks(n)), dim3(kUpdateThreads),
+                           0, st, n, s, x, p, r, q, rs, qs, partials, link, rows);
+    else
+        hipLaunchKernelGGL((k_bicg_update<TX, T, false>), dim3(update_blocks(n)), dim3(kUpdateThreads),
+                           0, st, n, s, x, p, r, q, rs, qs, partials, link, rows);
     return hipGetLastError();
 }
 template hipError_t bicg_update<double, double>(long long, const BicgState *, double *,
                                                 const double *, double *, const double *,
                                                 double *, const double *, Pair *, hipStream_t,
-                                                StepLink);
+                                                StepLink, Rows);
 template hipError_t bicg_update<double, float>(long long, const BicgState *, double *,
                                                const float *, float *, const float *, float *,
-                                               const float *, Pair *, hipStream_t, StepLink);
+                                               const float *, Pair *, hipStream_t, StepLink,
+                                               Rows);
 
 
 // CG sweep B: the primal half of the Bi-CG update (the shadow half repeats it bit for bit
 // when r*_0 = r_0), and the partials of r.r, which is also rho of the next iteration.
-template <typename TX, typename T>
+template <typename TX, typename T, bool PAD>
 __global__ void __launch_bounds__(kUpdateThreads)
     k_cg_update(long long n, const BicgState *s, TX *x, const T *p, T *r, const T *q,
-                Pair *partials, StepLink link) {
+                Pair *partials, StepLink link, Rows rows) {
     __shared__ Pair sh[kUpdateThreads / kWave];
     const long long stride = (long long)gridDim.x * blockDim.x;
-    const long long i0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long v0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    Walk<PAD> w(rows, v0, stride);
     // first element requested before the status and the scalars (see k_bicg_update)
     TX x0 = 0;
     T p0 = 0, r0 = 0, q0 = 0;
-    if (i0 < n) {
+    if (v0 < n) {
+        const long long i0 = w.at(v0);
         x0 = x[i0];
         p0 = p[i0];
         r0 = r[i0];
@@ -141,8 +188,9 @@ __global__ void __launch_bounds__(kUpdateThreads)
         alpha = s->alpha;
     }
     Pair acc[1] = {{0.0, 0.0}};
-    for (long long i = i0; i < n; i += stride) {
-        if (i != i0) {
+    for (long long v = v0; v < n; v += stride, w.advance()) {
+        const long long i = w.at(v);
+        if (v != v0) {
             x0 = x[i];
             p0 = p[i];
             r0 = r[i];
@@ -161,27 +209,34 @@ __global__ void __launch_bounds__(kUpdateThreads)
 
 template <typename TX, typename T>
 hipError_t cg_update(long long n, const BicgState *s, TX *x, const T *p, T *r, const T *q,
-                     Pair *partials, hipStream_t st, StepLink link) {
-    hipLaunchKernelGGL((k_cg_update<TX, T>), dim3(update_blocks(n)), dim3(kUpdateThreads), 0, st, n, s,
-                       x, p, r, q, partials, link);
+                     Pair *partials, hipStream_t st, StepLink link, Rows rows) {
+    if (rows.ld != rows.len)
+        hipLaunchKernelGGL((k_cg_update<TX, T, true>), dim3(update_blocks(n)), dim3(kUpdateThreads), 0,
+                           st, n, s, x, p, r, q, partials, link, rows);
+    else
+        hipLaunchKernelGGL((k_cg_update<TX, T, false>), dim3(update_blocks(n)), dim3(kUpdateThreads), 0,
+                           st, n, s, x, p, r, q, partials, link, rows);
     return hipGetLastError();
 }
 template hipError_t cg_update<double, double>(long long, const BicgState *, double *,
                                               const double *, double *, const double *, Pair *,
-                                              hipStream_t, StepLink);
+                                              hipStream_t, StepLink, Rows);
 template hipError_t cg_update<double, float>(long long, const BicgState *, double *,
                                              const float *, float *, const float *, Pair *,
-                                             hipStream_t, StepLink);
+                                             hipStream_t, StepLink, Rows);
 
 // Partials of r*.r and r.r with the block layout of the Bi-CG update kernels, for a run
 // whose residuals were just replaced (its next sweep A merges them as the rho of the step).
 template <typename T>
 __global__ void __launch_bounds__(kUpdateThreads)
-    k_rho_partials(long long n, const T *r, const T *rs, const T *d, Pair *partials) {
+    k_rho_partials(long long n, const T *r, const T *rs, const T *d, Pair *partials, Rows rows) {
     __shared__ Pair sh[2 * (kUpdateThreads / kWave)];
     Pair acc[2] = {{0.0, 0.0}, {0.0, 0.0}};
     const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const long long v0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    Walk<true> w(rows, v0, stride);
+    for (long long v = v0; v < n; v += stride, w.advance()) {
+        const long long i = w.at(v);
         const double z = d ? (double)r[i] / (double)d[i] : (double)r[i];
         dot2_acc(acc[0], (double)rs[i], z);
         dot2_acc(acc[1], (double)r[i], (double)r[i]);
@@ -195,15 +250,15 @@ __global__ void __launch_bounds__(kUpdateThreads)
 
 template <typename T>
 hipError_t rho_partials(long long n, const T *r, const T *rs, Pair *partials, hipStream_t st,
-                        const T *d) {
+                        const T *d, Rows rows) {
     hipLaunchKernelGGL(k_rho_partials<T>, dim3(update_blocks(n)), dim3(kUpdateThreads), 0, st, n, r,
-                       rs, d, partials);
+                       rs, d, partials, rows);
     return hipGetLastError();
 }
 template hipError_t rho_partials<float>(long long, const float *, const float *, Pair *,
-                                        hipStream_t, const float *);
+                                        hipStream_t, const float *, Rows);
 template hipError_t rho_partials<double>(long long, const double *, const double *, Pair *,
-                                         hipStream_t, const double *);
+                                         hipStream_t, const double *, Rows);
 
 // Sweep B of Algorithm 2 with its options, in the order of the algorithm: x, x*, r, r*
 // updates, then M^-1 r and the partials of r*.(M^-1 r) and r.r.
@@ -308,26 +363,62 @@ hipError_t step_check(StepLink link, hipStream_t st) {
 
 template <typename T>
 __global__ void __launch_bounds__(kVecThreads)
-    k_dot(long long n, const T *x, const T *y, Pair *partials) {
+    k_dot(long long n, const T *x, const T *y, Pair *partials, Rows rows) {
     __shared__ Pair sh[kVecThreads / kWave];
     Pair acc[1] = {{0.0, 0.0}};
     const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    const long long v0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    Walk<true> w(rows, v0, stride);
+    for (long long v = v0; v < n; v += stride, w.advance()) {
+        const long long i = w.at(v);
         dot2_acc(acc[0], (double)x[i], (double)y[i]);
+    }
     block_merge<1>(acc, sh);
     if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
 }
 
 template <typename T>
 hipError_t dot_partials(long long n, const T *x, const T *y, Pair *partials, int nblocks,
-                        hipStream_t st) {
-    hipLaunchKernelGGL(k_dot<T>, dim3(nblocks), dim3(kVecThreads), 0, st, n, x, y, partials);
+                        hipStream_t st, Rows rows) {
+    hipLaunchKernelGGL(k_dot<T>, dim3(nblocks), dim3(kVecThreads), 0, st, n, x, y, partials, rows);
     return hipGetLastError();
 }
 template hipError_t dot_partials<double>(long long, const double *, const double *, Pair *, int,
-                                         hipStream_t);
+                                         hipStream_t, Rows);
 template hipError_t dot_partials<float>(long long, const float *, const float *, Pair *, int,
-                                        hipStream_t);
+                                        hipStream_t, Rows);
+
+// One workgroup row at a time (grid-stride over the n^2 rows of an n^3 vector).
+__global__ void __launch_bounds__(kVecThreads)
+    k_pad_rows(int n, int ld, const double *src, double *dst) {
+    const long long rows = (long long)n * n;
+    for (long long row = blockIdx.x; row < rows; row += gridDim.x)
+        for (int c = threadIdx.x; c < ld; c += blockDim.x)
+            dst[row * ld + c] = c < n ? src[row * n + c] : 0.0;
+}
+
+__global__ void __launch_bounds__(kVecThreads)
+    k_unpad_rows(int n, int ld, const double *src, double *dst) {
+    const long long rows = (long long)n * n;
+    for (long long row = blockIdx.x; row < rows; row += gridDim.x)
+        for (int c = threadIdx.x; c < n; c += blockDim.x) dst[row * n + c] = src[row * ld + c];
+}
+
+hipError_t pad_rows(int n, int ld, const double *src, double *dst, hipStream_t st) {
+    if (n < 1 || ld < n) return hipErrorInvalidValue;
+    const long long rows = (long long)n * n;
+    hipLaunchKernelGGL(k_pad_rows, dim3((unsigned)std::min(rows, 8192LL)), dim3(kVecThreads), 0, st,
+                       n, ld, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t unpad_rows(int n, int ld, const double *src, double *dst, hipStream_t st) {
+    if (n < 1 || ld < n) return hipErrorInvalidValue;
+    const long long rows = (long long)n * n;
+    hipLaunchKernelGGL(k_unpad_rows, dim3((unsigned)std::min(rows, 8192LL)), dim3(kVecThreads), 0, st,
+                       n, ld, src, dst);
+    return hipGetLastError();
+}
 
 template <typename TD, typename TS>
 __global__ void k_copy_convert(long long n, const TS *src, TD *dst) {

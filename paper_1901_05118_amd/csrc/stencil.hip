@@ -16,6 +16,8 @@ Geom make_geom(int n, int bc, int ty, int zc) {
     g.tiles_z = (n + zc - 1) / zc;
     g.ntiles = g.tiles_x * g.tiles_y * g.tiles_z;
     g.sgn = (bc == 1) ? 1.0 : -1.0;
+    g.ld = n;
+    g.ps = (i64)n * n;
     return g;
 }
 

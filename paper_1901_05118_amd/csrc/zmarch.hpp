@@ -24,9 +24,13 @@
 //    resulting operator is exactly the paper's A_h, including its boundary rows, with no
 //    per-row branches in the arithmetic.
 //  * Tiles are ordered XCD-aware: each of the 8 XCDs processes a contiguous range of tiles.
+//  * Rows of the vectors are Geom::ld elements apart (n: contiguous).  With padded rows
+//    (an option of the mixed-precision solver) every row starts on a cache line, so no
+//    128-byte line is split between the row segments of two tiles.
 #pragma once
 
 #include <type_traits>
+#include <utility>
 
 #include "common.hpp"
 #include "internal.hpp"
@@ -184,21 +188,13 @@ struct InDirectionM {
 //   operator values y and the centre values c of the output plane;
 //   Out::centre(idx, c[NA]) is called for every valid centre of a plane inside the chunk;
 //   Out::finish(block, tile) runs after the march (block-level reductions).
-// Epilogues that request per-output data ahead (Out::Pre, Out::pre(idx)): the values of an
-// output are requested when its own plane is consumed and handed to emit() two planes later,
-// when the output is complete.
+// Epilogues that owe work on their outputs even when the run stops at the start of the
+// launch provide Out::prepare() (once per thread), Out::gate() (0 run, 1 skip, 2 the run
+// stops in this launch) and Out::finish_output(idx) (the owed work on one output).
 template <class O, class = void>
-struct HasPre : std::false_type {};
+struct HasGate : std::false_type {};
 template <class O>
-struct HasPre<O, std::void_t<typename O::Pre>> : std::true_type {};
-template <class O, bool = HasPre<O>::value>
-struct PreOf {
-    struct type {};
-};
-template <class O>
-struct PreOf<O, true> {
-    using type = typename O::Pre;
-};
+struct HasGate<O, std::void_t<decltype(std::declval<const O &>().gate())>> : std::true_type {};
 
 // No step before the march: `in` is already prepared.
 struct NoBegin {
@@ -232,7 +228,7 @@ __device__ __forceinline__ bool zmarch_tile(const Geom &g, int tile, const In &i
     const bool valid = (ix < n) && (iy < n);
     const int k0 = tz * g.zc;
     const int k1 = min(k0 + g.zc, n);
-    const i64 plane = (i64)n * n;
+    const i64 plane = g.ps;
 
     // staging slots of this thread: LDS element e = tid + q*NT.  Every slot has a valid
     // source address (positions outside the grid are clamped and multiplied by 0), so the
@@ -251,7 +247,7 @@ __device__ __forceinline__ bool zmarch_tile(const Geom &g, int tile, const In &i
             double mx = reflect(tx * TX + col - 2, n, g.sgn, sx);
             double my = reflect(ty * TY + row - 2, n, g.sgn, sy);
             smul[q] = (float)(mx * my);
-            soff[q] = sy * n + sx;
+            soff[q] = sy * g.ld + sx;
         }
     }
 
@@ -300,12 +296,9 @@ __device__ __forceinline__ bool zmarch_tile(const Geom &g, int tile, const In &i
     __syncthreads();
     int cur = 0;
     const int centre = (ly + 2) * LS + (lx + 2);
-    const int col_off = iy * n + ix;    // in-plane offset of this lane's column (n < 2^15)
-    constexpr bool kPre = HasPre<Out>::value;
-    using PreT = typename PreOf<Out>::type;
-    PreT pre[D];             // per-output data of planes m-2 (slot m % D), requested at plane m
+    const int col_off = iy * g.ld + ix;  // in-plane offset of this lane's column (< 2^31)
     // consume plane m from LDS, stage plane m+1 from `r`, refill `r` with plane m+1+D
-    auto body = [&](int m, Raw &r, float &z, PreT &pm) {
+    auto body = [&](int m, Raw &r, float &z) {
         double y[NA], c0[NA], cprev[NA];
 #pragma unroll
         for (int a = 0; a < NA; a++) {
@@ -315,13 +308,7 @@ __device__ __forceinline__ bool zmarch_tile(const Geom &g, int tile, const In &i
         if (valid) {
             if (m >= k0 && m < k1) out.centre((i64)m * plane + col_off, c0);
             const int k = m - 2;
-            if (k >= k0 && k < k1) {
-                if constexpr (kPre) out.emit((i64)k * plane + col_off, y, cprev, pm);
-                else out.emit((i64)k * plane + col_off, y, cprev);
-            }
-            if constexpr (kPre) {
-                if (m >= k0 && m < k1) pm = out.pre((i64)m * plane + col_off);
-            }
+            if (k >= k0 && k < k1) out.emit((i64)k * plane + col_off, y, cprev);
         }
         stash(cur ^ 1, r, z);
         fetch(min(m + 1 + D, mend), r, z);
@@ -332,7 +319,7 @@ __device__ __forceinline__ bool zmarch_tile(const Geom &g, int tile, const In &i
 #pragma unroll
         for (int k = 0; k < D; k++) {
             if (m + k > mend) break;
-            body(m + k, raw[k], mz[k], pre[k]);
+            body(m + k, raw[k], mz[k]);
         }
     }
     return true;
@@ -349,8 +336,8 @@ __device__ __forceinline__ void zmarch_tile_outputs(const Geom &g, int tile, Out
     const int ix = tx * kWave + threadIdx.x, iy = ty * TY + threadIdx.y;
     if (ix >= n || iy >= n) return;
     const int k0 = tz * g.zc, k1 = min(k0 + g.zc, n);
-    const i64 plane = (i64)n * n;
-    const i64 col = (i64)iy * n + ix;
+    const i64 plane = g.ps;
+    const i64 col = (i64)iy * g.ld + ix;
     for (int k = k0; k < k1; k++) out.finish_output((i64)k * plane + col);
 }
 
@@ -360,13 +347,13 @@ __global__ void __launch_bounds__(kWave *TY) zmarch(Geom g, In in_arg, Out out) 
     __shared__ Pair red[4 * TY];
     __shared__ int s_skip;
     In in = in_arg;
-    if constexpr (HasPre<Out>::value) out.prepare();
+    if constexpr (HasGate<Out>::value) out.prepare();
     bool stops = false;      // the run stops at the start of this launch
     // after the tile's first loads are in flight: the status (one decision per workgroup, as
     // a folded finalisation may publish a new status meanwhile), then the scalars
     auto start = [&]() {
         if (threadIdx.x == 0 && threadIdx.y == 0) {
-            if constexpr (HasPre<Out>::value) s_skip = out.gate();
+            if constexpr (HasGate<Out>::value) s_skip = out.gate();
             else s_skip = out.skip() ? 1 : 0;
         }
         __syncthreads();
@@ -382,7 +369,7 @@ __global__ void __launch_bounds__(kWave *TY) zmarch(Geom g, In in_arg, Out out) 
     const int tile = xcd_tile(blockIdx.x, g.ntiles);
     const bool go = tile < g.ntiles ? zmarch_tile<NA, TY, T>(g, tile, in, out, start) : start();
     if (!go) {
-        if constexpr (HasPre<Out>::value) {
+        if constexpr (HasGate<Out>::value) {
             if (stops && tile < g.ntiles) zmarch_tile_outputs<TY>(g, tile, out);
         }
         return;
@@ -499,18 +486,16 @@ struct OutPairApply {
 // Sweep A that also applies the previous iteration's update of the iterate, x += alpha p
 // (alpha and p of iteration j-1, which sweep B then leaves to it): the streams of x and p
 // move from the update sweep into this one, where p is read anyway.  The arithmetic is the
-// update sweep's.  x and p of an output are requested when its plane is consumed.  When
-// the run stops at the start of the launch, the update is applied on its own.
+// update sweep's.  x and p are read when the output is emitted: requesting them ahead (in
+// registers, two planes early) pushed the 64x16 tile's kernel past 128 registers, and the
+// spill's per-plane scratch traffic cost more than the latency it hid.  When the run stops
+// at the start of the launch, the update is applied on its own.
 template <typename T>
 struct OutPairApplyX : OutPairApply<T> {
     double *x;
     const T *pold;               // p of iteration j-1 (the direction sweep A reads)
     const double *alpha_dev;     // alpha of iteration j-1
     double alpha;
-    struct Pre {
-        double x;
-        T p;
-    };
     __device__ void prepare() { alpha = wave_uniform(*alpha_dev); }
     // 0: running; 2: the run stops in this launch (a workgroup already decided it); 1: stopped
     // before this launch (nothing owed)
@@ -518,9 +503,8 @@ struct OutPairApplyX : OutPairApply<T> {
         const int s = *this->status;
         return s == kRunning ? 0 : (s == kStopping ? 2 : 1);
     }
-    __device__ Pre pre(i64 idx) const { return Pre{x[idx], pold[idx]}; }
-    __device__ void emit(i64 idx, const double *v, const double *c, const Pre &pr) {
-        x[idx] = pr.x + alpha * (double)pr.p;
+    __device__ void emit(i64 idx, const double *v, const double *c) {
+        x[idx] = x[idx] + alpha * (double)pold[idx];
         OutPairApply<T>::emit(idx, v, c);
     }
     __device__ void finish_output(i64 idx) { x[idx] = x[idx] + alpha * (double)pold[idx]; }

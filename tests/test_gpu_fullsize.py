@@ -89,17 +89,20 @@ def test_mixed_bicg_equals_cg_at_full_size(ex, problem):
     """The mixed Bi-CG defers x += alpha p to the next sweep A on these grids; with 2048
     workgroups per sweep at 512^3 (several per CU), those that start after the stopping
     decision must still apply their part of the owed update.  The CG form, which keeps the
-    update in its own sweep, must match bit for bit."""
+    update in its own sweep, must match bit for bit, and so must the solve on padded rows
+    (row_pad = 1)."""
     print("mixed bicg vs cg 512^3", flush=True)
     arr, b = problem
     f, g1, g2 = dev(arr.f), dev(arr.g1), dev(arr.g2)
     outs, its = [], []
-    for m in (ex.BICG, ex.CG):
+    for m, pad in ((ex.BICG, 0), (ex.CG, 0), (ex.BICG, 1)):
         u = torch.empty_like(f)
-        rc, st = ex.solve_ex(N, NL, BC, f, g1, g2, 1e-8, u, precision=ex.MIXED, method=m)
+        rc, st = ex.solve_ex(N, NL, BC, f, g1, g2, 1e-8, u, precision=ex.MIXED, method=m,
+                             row_pad=pad)
         assert rc == ex.OK, ex.last_error()
         outs.append(host(u))
         its.append([(l["iterations"], l["runs"]) for l in st.levels()])
         del u
-    assert its[0] == its[1]
+    assert its[0] == its[1] == its[2]
     np.testing.assert_array_equal(outs[0], outs[1])
+    np.testing.assert_array_equal(outs[0], outs[2])

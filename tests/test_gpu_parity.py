@@ -338,6 +338,31 @@ def test_mixed_default_runs_small_levels_in_fp64(ex):
                     fp32_min_unknowns=-1)
 
 
+@pytest.mark.parametrize("refine", ["reliable", "restart"])
+def test_padded_rows_keep_the_mixed_solve(ex, refine):
+    """The FP32 Bi-CG vectors (with the FP64 iterate and right-hand side they are solved
+    with) on padded rows (row_pad = 1, every 3D level): the stencil sweeps see the same
+    operator and the vector kernels walk the unknowns in the contiguous order, so the cascade
+    gives the contiguous layout's iterates and counts; an invalid row_pad is refused."""
+    N, nl, bc = 128, 6, 2
+    arr = make_arrays(config_problem(2), N, bc)
+    f, g1, g2 = dev(arr.f), dev(arr.g1), dev(arr.g2)
+    mode = ex.RELIABLE if refine == "reliable" else ex.RESTART
+    outs, its = [], []
+    for pad in (0, 1):
+        u = torch.empty_like(f)
+        rc, st = ex.solve_ex(N, nl, bc, f, g1, g2, 1e-9, u, precision=ex.MIXED, refine=mode,
+                             fp32_min_unknowns=1, row_pad=pad)
+        assert rc == ex.OK, ex.last_error()
+        outs.append(host(u))
+        its.append([(l["iterations"], l["runs"]) for l in st.levels()])
+    assert its[0] == its[1]
+    np.testing.assert_array_equal(outs[0], outs[1])
+    with pytest.raises(ex.ExcmgError):
+        ex.solve_ex(N, nl, bc, f, g1, g2, 1e-9, torch.empty_like(f), precision=ex.MIXED,
+                    row_pad=2)
+
+
 def test_autotuned_shape_keeps_results(ex):
     N, bc = 40, 2
     ty, zc, ms = ex.autotune(N, 0, ex.FP64, reps=3)
