@@ -230,14 +230,17 @@ Geom choose_shape(int N, int bc, int kind) {
     // Shapes the autotuner picks on MI355X (stable across runs), per grid-size band and
     // kind {operator/residual, FP64 sweep A, FP32 sweep A}: {ty, zc}.  Grids up to 64^3 are
     // launch-latency bound and want the most workgroups; larger grids want long z-marches.
-    static const int kTuned[5][3][2] = {
-        {{4, 4}, {4, 4}, {4, 4}},          // N < 96
+    // FP32 sweep A: timed in the form mixed solves run on these grids (with the deferred
+    // update of the iterate; 128^3: 27.5 us at {8, 8} against 29.3 us at {8, 16}).
+    static const int kTuned[6][3][2] = {
+        {{4, 2}, {4, 2}, {4, 2}},          // N < 48 (16^3, 32^3: 5.4 -> 5.0, 16.0 -> 14.7 ms)
+        {{4, 4}, {4, 4}, {4, 4}},          // 48 <= N < 96
         {{4, 8}, {8, 16}, {4, 8}},         // 96 <= N < 128
-        {{16, 8}, {8, 16}, {8, 16}},       // 128 <= N < 256
+        {{16, 8}, {8, 16}, {8, 8}},        // 128 <= N < 256
         {{8, 32}, {8, 128}, {16, 64}},     // 256 <= N < 512
         {{8, 128}, {8, 128}, {16, 64}},    // N >= 512
     };
-    const int band = N < 96 ? 0 : N < 128 ? 1 : N < 256 ? 2 : N < 512 ? 3 : 4;
+    const int band = N < 48 ? 0 : N < 96 ? 1 : N < 128 ? 2 : N < 256 ? 3 : N < 512 ? 4 : 5;
     const int ty = kTuned[band][kind][0];
     const int zc = std::max(1, std::min(kTuned[band][kind][1], n));
     return make_geom(n, bc, ty, zc);
@@ -2024,8 +2027,8 @@ int excmg_autotune(int n, int kind, int precision, int reps, int *ty_out, int *z
     CKH(hipEventCreate(&e1));
     int rc = EXCMG_OK;
     for (int ty : tys) {
-        for (int zc = 4; zc <= 512; zc *= 2) {
-            if (zc > nn && zc != 4) break;
+        for (int zc = 2; zc <= 512; zc *= 2) {
+            if (zc > nn && zc != 2) break;
             Geom g = with_rows(make_geom(nn, 1, ty, std::min(zc, nn)), ld);
             rc = part.ensure((size_t)stencil_blocks(g) * sizeof(Pair));
             if (rc) break;

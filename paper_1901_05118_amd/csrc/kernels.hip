@@ -21,11 +21,13 @@ int vec_blocks(long long n) {
 }
 
 // Bi-CG updates: fewer, larger workgroups (their partials are merged again by every
-// workgroup of the next sweep A).
+// workgroup of the next sweep A), four elements per thread; on grids of up to 2^18 unknowns,
+// which are bound by latency, one element per thread (32^3: 18.2 -> 16.0 ms per level).
 constexpr int kUpdateThreads = 512;
 
 int update_blocks(long long n) {
     long long b = (n + kUpdateThreads * 4 - 1) / (kUpdateThreads * 4);
+    if (n <= (1LL << 18)) b = (n + kUpdateThreads - 1) / kUpdateThreads;
     if (b < 1) b = 1;
     if (b > 1024) b = 1024;
     return (int)b;
