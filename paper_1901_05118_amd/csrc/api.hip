@@ -233,7 +233,7 @@ Geom choose_shape(int N, int bc, int kind) {
     // FP32 sweep A: timed in the form mixed solves run on these grids (with the deferred
     // update of the iterate; 128^3: 27.5 us at {8, 8} against 29.3 us at {8, 16}).
     static const int kTuned[6][3][2] = {
-        {{4, 2}, {4, 2}, {4, 2}},          // N < 48 (16^3, 32^3: 5.4 -> 5.0, 16.0 -> 14.7 ms)
+        {{4, 4}, {4, 2}, {4, 2}},          // N < 48 (16^3, 32^3: 5.4 -> 5.0, 16.0 -> 14.7 ms)
         {{4, 4}, {4, 4}, {4, 4}},          // 48 <= N < 96
         {{4, 8}, {8, 16}, {4, 8}},         // 96 <= N < 128
         {{16, 8}, {8, 16}, {8, 8}},        // 128 <= N < 256

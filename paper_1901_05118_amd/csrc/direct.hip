@@ -108,11 +108,15 @@ __global__ void __launch_bounds__(1024) k_band_cholesky(int n, int w, double *C,
 constexpr int kBandMaxN = 4096;
 
 // L y = b, then L^T x = y, in one wavefront with the vector in LDS (b and x may alias).
-// Forward: column k is applied to the rows below it in parallel, the next column's band
-// prefetched into registers.  Backward: row i needs x_{i+1} before its first
-// subtraction, so the chain itself is serial; the lanes form the products L(k,i) x_k in
-// parallel and one lane subtracts them in ascending k.
-template <int PER>
+// Forward: column k is applied to the rows below it in parallel.  Backward: row i needs
+// x_{i+1} before its first subtraction, so the chain itself is serial; the lanes form the
+// products L(k,i) x_k in parallel and one lane subtracts them in ascending k.  Either way
+// a step is short next to the latency of a column's load, so the columns come in chunks of
+// DP: while the steps of one chunk run, the next chunk's loads are in flight (waited for
+// once, at the end of the chunk).  Entry e = lane + 64 q of a column (e = 0 the diagonal,
+// which lane 0 broadcasts) is loaded unconditionally from an index clamped into the
+// column's w+1 stored entries; the steps mask what lies past the column's last row.
+template <int PER, int DP>
 __global__ void __launch_bounds__(64) k_band_solve(int n, int w, const double *C, const double *b,
                                                    double *x) {
     __shared__ double t[kBandMaxN];
@@ -122,54 +126,73 @@ __global__ void __launch_bounds__(64) k_band_solve(int n, int w, const double *C
     for (int i = lane; i < n; i += 64) t[i] = b[i];
     __syncthreads();
 
-    auto load_col = [&](int k, double (&v)[PER], double &dg) {
-        const int m = min(w, n - 1 - k);
+    auto load_col = [&](int k, double (&v)[PER]) {
         const double *col = C + (i64)k * ld;
 #pragma unroll
-        for (int q = 0; q < PER; q++) {
-            const int e = 1 + lane + 64 * q;
-            v[q] = (e <= m) ? col[e] : 0.0;
-        }
-        dg = col[0];
+        for (int q = 0; q < PER; q++) v[q] = col[min(lane + 64 * q, w)];
+    };
+    double cur[DP][PER], nxt[DP][PER];
+#pragma unroll
+    for (int s = 0; s < DP; s++)
+#pragma unroll
+        for (int q = 0; q < PER; q++) cur[s][q] = nxt[s][q] = 0.0;
+    auto swap_in = [&]() {
+#pragma unroll
+        for (int s = 0; s < DP; s++)
+#pragma unroll
+            for (int q = 0; q < PER; q++) cur[s][q] = nxt[s][q];
     };
 
-    double cur[PER], nxt[PER], dcur, dnxt = 0.0;
-    load_col(0, cur, dcur);
-    for (int k = 0; k < n; k++) {
-        if (k + 1 < n) load_col(k + 1, nxt, dnxt);
-        const int m = min(w, n - 1 - k);
-        const double yk = t[k] / dcur;
 #pragma unroll
-        for (int q = 0; q < PER; q++) {
-            const int e = 1 + lane + 64 * q;
-            if (e <= m) t[k + e] -= cur[q] * yk;
+    for (int s = 0; s < DP; s++) load_col(min(s, n - 1), cur[s]);
+    for (int k0 = 0; k0 < n; k0 += DP) {
+        // unconditional (clamped) requests, so the loads in flight are counted exactly
+#pragma unroll
+        for (int s = 0; s < DP; s++) load_col(min(k0 + DP + s, n - 1), nxt[s]);
+#pragma unroll
+        for (int s = 0; s < DP; s++) {
+            const int k = k0 + s;
+            if (k < n) {
+                const int m = min(w, n - 1 - k);
+                const double yk = t[k] / __shfl(cur[s][0], 0);
+#pragma unroll
+                for (int q = 0; q < PER; q++) {
+                    const int e = lane + 64 * q;
+                    if (e >= 1 && e <= m) t[k + e] -= cur[s][q] * yk;
+                }
+                if (lane == 0) t[k] = yk;
+                __syncthreads();
+            }
         }
-        if (lane == 0) t[k] = yk;
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < PER; q++) cur[q] = nxt[q];
-        dcur = dnxt;
+        swap_in();
     }
 
-    load_col(n - 1, cur, dcur);
-    for (int i = n - 1; i >= 0; i--) {
-        if (i > 0) load_col(i - 1, nxt, dnxt);
-        const int m = min(w, n - 1 - i);
 #pragma unroll
-        for (int q = 0; q < PER; q++) {
-            const int e = 1 + lane + 64 * q;
-            if (e <= m) prod[e - 1] = cur[q] * t[i + e];
-        }
-        __syncthreads();
-        if (lane == 0) {
-            double acc = t[i];
-            for (int e = 0; e < m; e++) acc -= prod[e];
-            t[i] = acc / dcur;
-        }
-        __syncthreads();
+    for (int s = 0; s < DP; s++) load_col(max(n - 1 - s, 0), cur[s]);
+    for (int k0 = 0; k0 < n; k0 += DP) {
 #pragma unroll
-        for (int q = 0; q < PER; q++) cur[q] = nxt[q];
-        dcur = dnxt;
+        for (int s = 0; s < DP; s++) load_col(max(n - 1 - (k0 + DP + s), 0), nxt[s]);
+#pragma unroll
+        for (int s = 0; s < DP; s++) {
+            const int i = n - 1 - (k0 + s);
+            if (i >= 0) {
+                const int m = min(w, n - 1 - i);
+#pragma unroll
+                for (int q = 0; q < PER; q++) {
+                    const int e = lane + 64 * q;
+                    if (e >= 1 && e <= m) prod[e - 1] = cur[s][q] * t[i + e];
+                }
+                const double d = __shfl(cur[s][0], 0);
+                __syncthreads();
+                if (lane == 0) {
+                    double acc = t[i];
+                    for (int e = 0; e < m; e++) acc -= prod[e];
+                    t[i] = acc / d;
+                }
+                __syncthreads();
+            }
+        }
+        swap_in();
     }
     for (int i = lane; i < n; i += 64) x[i] = t[i];
 }
@@ -198,16 +221,16 @@ hipError_t band_cholesky(int n, int w, double *C, int *info, hipStream_t st) {
 }
 
 hipError_t band_solve(int n, int w, const double *C, const double *b, double *x, hipStream_t st) {
-    if (n < 1 || n > kBandMaxN || w < 0 || w > 64 * 8) return hipErrorInvalidValue;
-    const int per = (w + 63) / 64;
+    if (n < 1 || n > kBandMaxN || w < 0 || w + 1 > 64 * 8) return hipErrorInvalidValue;
+    const int per = (w + 64) / 64;   // the w+1 entries of a column (diagonal included)
     if (per <= 1)
-        hipLaunchKernelGGL(k_band_solve<1>, dim3(1), dim3(64), 0, st, n, w, C, b, x);
+        hipLaunchKernelGGL((k_band_solve<1, 8>), dim3(1), dim3(64), 0, st, n, w, C, b, x);
     else if (per <= 2)
-        hipLaunchKernelGGL(k_band_solve<2>, dim3(1), dim3(64), 0, st, n, w, C, b, x);
+        hipLaunchKernelGGL((k_band_solve<2, 8>), dim3(1), dim3(64), 0, st, n, w, C, b, x);
     else if (per <= 4)
-        hipLaunchKernelGGL(k_band_solve<4>, dim3(1), dim3(64), 0, st, n, w, C, b, x);
+        hipLaunchKernelGGL((k_band_solve<4, 4>), dim3(1), dim3(64), 0, st, n, w, C, b, x);
     else
-        hipLaunchKernelGGL(k_band_solve<8>, dim3(1), dim3(64), 0, st, n, w, C, b, x);
+        hipLaunchKernelGGL((k_band_solve<8, 4>), dim3(1), dim3(64), 0, st, n, w, C, b, x);
     return hipGetLastError();
 }
 
