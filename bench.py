@@ -37,16 +37,23 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def sweep_a_launch(N, ty, zc, fp32):
-    """Name (as the profiler shows it) and launch size in threads of Bi-CG sweep A on the
-    grid of N cells with tiles of 64 x ty columns and zc planes.  In the mixed solve, sweep A
-    on such grids also applies the previous iteration's update of the FP64 iterate."""
+# Grids from which mixed-precision Bi-CG takes the recomputing form (the library's default)
+RECOMPUTE_MIN = 1 << 22
+
+
+def sweep_launch(N, ty, zc, form):
+    """Name (as the profiler shows it) and launch size in threads of a Bi-CG stencil sweep on
+    the grid of N cells with tiles of 64 x ty columns and zc planes.  form: "fp64" (sweep A),
+    "deferred" (mixed sweep A that also applies the previous iteration's x update),
+    "sigma" / "update" (the two sweeps of the mixed recomputing form)."""
     n = N - 1
     tiles = -(-n // 64) * -(-n // ty) * -(-n // zc)
     tiles = -(-tiles // 8) * 8  # the grid is padded to whole XCD shares
-    t = "float" if fp32 else "double"
-    out = "OutPairApplyX" if fp32 else "OutPairApply"
-    return f"zmarch<2, {ty}, {t}, InDirection<{t}>, {out}<{t}> >", tiles * 64 * ty
+    name = {"fp64": "zmarch<2, {ty}, double, InDirection<double>, OutPairApply<double> >",
+            "deferred": "zmarch<2, {ty}, float, InDirection<float>, OutPairApplyX<float> >",
+            "sigma": "zmarch<1, {ty}, float, InDirection<float>, OutDirSigma<float> >",
+            "update": "zmarch<2, {ty}, float, InPlainAlpha<float>, OutPairUpdate<float> >"}[form]
+    return name.format(ty=ty), tiles * 64 * ty
 
 
 def recorded_traffic(kernel, grid):
@@ -300,41 +307,59 @@ def main():
     glups = head["glups"]
     levels = head["levels"]
 
-    # Roofline of the dominant kernel, Bi-CG sweep A (direction update + pair apply), on the
-    # finest level: one more solve of the headline form with every sweep bracketed by device
-    # events on the library stream; achieved = algorithmic bytes per launch / mean duration.
+    # Roofline of the dominant kernel on the finest level: one more solve of the headline
+    # form with every sweep bracketed by device events on the library stream; achieved =
+    # algorithmic bytes per launch / mean duration.
     prec = ex.MIXED if gate else ex.FP64
     ex.set_timing(True)
     st_t = solve(prec)
     if [lv["iterations"] for lv in st_t.levels()] != [lv["iterations"] for lv in levels]:
         raise RuntimeError("the event-timed solve took other iterations than the timed one")
-    # mixed: the sweep A that applies the deferred x update (the first sweep A of each run,
-    # which owes none, is the plain kernel and is timed apart)
-    ms_a, n_a = ex.get_timing(nl - 1, 2 if gate else 0)
+    nu = (N - 1) ** 3
+    rq = gate and nu >= RECOMPUTE_MIN
+    # Bytes per unknown.  FP64: sweep A reads r, r*, p, p* and writes p, p*, q, q* (64);
+    # sweep B reads x, p, r, q, r*, q* and writes x, r, r* (72).  Mixed, recomputing form:
+    # sweep A reads r, p, r*, p* and writes p, p* (24); sweep B reads p, p*, r, r* and x
+    # (FP64) and writes r, r*, x (40).  Mixed, stored form: sweep A also applies x += alpha p
+    # of the previous iteration (48); sweep B streams r, q, r*, q* and writes r, r* (24).
+    if rq:
+        form_a, form_b, bytes_a, bytes_b, kind_a = "sigma", "update", 24.0, 40.0, 0
+    elif gate:
+        # the sweep A that applies the deferred x update (the first of each run, which owes
+        # none, is the plain kernel and is timed apart)
+        form_a, form_b, bytes_a, bytes_b, kind_a = "deferred", None, 48.0, 24.0, 2
+    else:
+        form_a, form_b, bytes_a, bytes_b, kind_a = "fp64", None, 64.0, 72.0, 0
+    bytes_a, bytes_b = bytes_a * nu, bytes_b * nu
+    ms_a, n_a = ex.get_timing(nl - 1, kind_a)
     ms_b, n_b = ex.get_timing(nl - 1, 1)
     ex.set_timing(False)
-    nu = (N - 1) ** 3
-    # FP64: sweep A reads r, r*, p, p* and writes p, p*, q, q*; sweep B reads x, p, r, q, r*,
-    # q* and writes x, r, r*.  Mixed: sweep A also applies x += alpha p of the previous
-    # iteration (x read and written in FP64), sweep B streams r, q, r*, q* and writes r, r*.
-    bytes_a = (48.0 if gate else 64.0) * nu
-    bytes_b = (24.0 if gate else 72.0) * nu
     avg_a, avg_b = ms_a / max(n_a, 1), ms_b / max(n_b, 1)
-    gbs_a = bytes_a / (avg_a * 1e-3) / 1e9
     ms_c, bytes_c = ex.profile_sweep(4, ex.FP64, reps=10)
-    ty_a, zc_a = ex.get_shape(N, 2 if gate else 1)
-    kname, grid = sweep_a_launch(N, ty_a, zc_a, gate)
+    ty_s, zc_s = ex.get_shape(N, 2 if gate else 1)
+    sweeps = {"A": {"launches": n_a, "ms_per_launch": round(avg_a, 4),
+                    "bytes_per_launch": bytes_a,
+                    "gbs": round(bytes_a / (avg_a * 1e-3) / 1e9, 1)},
+              "B": {"launches": n_b, "ms_per_launch": round(avg_b, 4),
+                    "bytes_per_launch": bytes_b,
+                    "gbs": round(bytes_b / (avg_b * 1e-3) / 1e9, 1)}}
+    # the dominant kernel: the stencil sweep that takes longer
+    dom = "B" if (form_b and avg_b > avg_a) else "A"
+    kname, grid = sweep_launch(N, ty_s, zc_s, form_b if dom == "B" else form_a)
     traffic, traffic_src = recorded_traffic(kname, grid)
-    roofline = {"bound": "hbm", "achieved": round(gbs_a, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(gbs_a / HBM_PEAK_GBS, 4),
+    d = sweeps[dom]
+    roofline = {"bound": "hbm", "achieved": d["gbs"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(d["gbs"] / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else round(traffic),
                 "traffic_source": traffic_src,
-                "kernel": f"{kname} (Bi-CG sweep A, {N}^3 level, tile 64x{ty_a}, "
-                          f"{zc_a} planes, {grid} threads)",
-                "launches": n_a, "ms_per_launch": round(avg_a, 4), "bytes_per_launch": bytes_a,
-                "sweep_b": {"launches": n_b, "ms_per_launch": round(avg_b, 4),
-                            "gbs": round(bytes_b / (avg_b * 1e-3) / 1e9, 1)},
-                # one Bi-CG iteration (both sweeps): 76 (mixed) or 136 (FP64) bytes per unknown
+                "kernel": f"{kname} (Bi-CG sweep {dom}, {N}^3 level, tile 64x{ty_s}, "
+                          f"{zc_s} planes, {grid} threads)",
+                "launches": d["launches"], "ms_per_launch": d["ms_per_launch"],
+                "bytes_per_launch": d["bytes_per_launch"],
+                "other_sweep": dict(sweeps["B" if dom == "A" else "A"],
+                                    name="B" if dom == "A" else "A"),
+                # one Bi-CG iteration (both sweeps): 64 (mixed, recomputing), 72 (mixed,
+                # stored) or 136 (FP64) bytes per unknown
                 "iteration": {"ms": round(avg_a + avg_b, 4),
                               "gbs": round((bytes_a + bytes_b) / ((avg_a + avg_b) * 1e-3) / 1e9, 1),
                               "frac": round((bytes_a + bytes_b) / ((avg_a + avg_b) * 1e-3) / 1e9

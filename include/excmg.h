@@ -103,6 +103,11 @@ typedef struct excmg_opts {
                         /* in and out.  0 (default): contiguous rows.  Same results bit for */
                         /* bit; padded rows speed up the Bi-CG stencil sweep on large grids */
                         /* and slow the vector updates, about even for the whole solve      */
+    int recompute_min_unknowns; /* mixed precision, 3D, Bi-CG: levels with at least this many */
+                        /* unknowns form q = A p and q* = A^T p* again in the update sweep   */
+                        /* instead of storing them (64 instead of 72 bytes per unknown and  */
+                        /* iteration, a second stencil pass); 0: 4194304 (2^22), 1: every   */
+                        /* level.  Same results bit for bit                                   */
 } excmg_opts;
 
 /* Per-level record filled by excmg_solve_ex (levels 0 and 1 report iterations = 0). */
@@ -242,10 +247,15 @@ int excmg_solve_ex(const excmg_opts *opts, const double *f, const double *g1, co
  *         3: Bi-CG sweep B: x, r, r* update + rho, r.r (mixed: FP64 x, FP32 rest)
  *                                                               FP64 72 B, mixed 44 B
  *         4: plain copy y = x (bandwidth reference)            FP64 16 B, mixed 8 B
- *         5: sweep A also applying the previous iteration's x += alpha p (the form a
- *            mixed-precision solve runs on grids of 64^3 and up)        mixed 48 B
+ *         5: sweep A also applying the previous iteration's x += alpha p (the stored
+ *            form with the deferred update)                            mixed 48 B
  *         6: sweep B without x (its partner)                              mixed 24 B
- * (bytes per unknown).  precision selects EXCMG_FP64 or EXCMG_MIXED (sweeps 5 and 6: mixed,
+ *         7: sweep A of the recomputing form (the form mixed-precision solves run on
+ *            3D grids of 2^17 unknowns and up): p, p* update + A p + sigma, stores p, p*
+ *                                                                         mixed 24 B
+ *         8: its sweep B: A p, A^T p* formed again, x, r, r* update + rho, r.r
+ *                                                                         mixed 40 B
+ * (bytes per unknown).  precision selects EXCMG_FP64 or EXCMG_MIXED (sweeps 5 to 8: mixed,
  * 3D contexts only). */
 int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launch,
                         double *bytes_per_launch);
@@ -254,8 +264,8 @@ int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launc
  * device events on the library stream and its duration is added to a per-level total
  * (sweep 0 = sweep A: direction update, A p, A^T p*, sigma; sweep 1 = sweep B: x, r, r*
  * updates, rho, r.r; sweep 2 = sweep A that also applies the previous iteration's x update,
- * which mixed-precision solves use on grids of 64^3 and up, their sweep B then leaving x
- * alone).  Only launches that did work are counted.  Turning it on resets the totals;
+ * in the stored form with the deferred update, its sweep B then leaving x alone).  Only
+ * launches that did work are counted.  Turning it on resets the totals;
  * excmg_get_timing reads them. */
 int excmg_set_timing(int on);
 int excmg_get_timing(int level, int sweep, double *ms_total, long long *launches);

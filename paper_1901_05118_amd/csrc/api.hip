@@ -367,7 +367,9 @@ int setup_levels(int n_finest, int n_levels, int bc, int dim) {
     for (auto &L : c.lv)
         maxblk = std::max({maxblk, stencil_blocks(L.g1), stencil_blocks(L.g2), stencil_blocks(L.g2f)});
     CKR(c.part_a.ensure((size_t)maxblk * sizeof(Pair)));
-    CKR(c.part_b.ensure((size_t)2 * 4096 * sizeof(Pair)));
+    // two values per partial: the update kernels (at most 4096) or the recomputing update
+    // sweep (one per tile)
+    CKR(c.part_b.ensure((size_t)2 * std::max(4096, maxblk) * sizeof(Pair)));
     CKR(c.state.ensure(sizeof(BicgState)));
     CKR(c.scal.ensure(64 * sizeof(double)));
     CKR(c.info.ensure(64));
@@ -457,8 +459,29 @@ struct RunVariant {
 };
 RunVariant g_var;
 
+// Mixed Bi-CG on large 3D grids (plain Algorithm 2, folded finalisations) takes the
+// recomputing form: its update sweep marches p and p* again for q and q* instead of
+// reading them back (64 instead of 72 bytes per unknown and iteration).  Smaller grids keep
+// the stored form (x's update deferred to the next sweep A from 2^17 unknowns up): there a
+// second march per iteration costs more latency than the bytes it saves (measured, 128^3
+// level: 81.9 ms stored, 88.0 ms recomputing; 256^3: 532.0 and 513.7 ms).
+constexpr long long kRecomputeMin = 1LL << 22;
+long long g_rq_min = kRecomputeMin;   // opts.recompute_min_unknowns of the solve in progress
+
+template <typename TX, typename T>
+bool recompute_q(const Level &L) {
+    return sizeof(T) == 4 && sizeof(TX) == 8 && !g_cg && g_fold && !g_var.d && !g_var.xs &&
+           g_ctx.dim == 3 && L.nu >= g_rq_min;
+}
+
+// Partials (per value) that the update sweep of level L leaves for the next sweep A.
+template <typename TX, typename T>
+int b_partials(const Level &L) {
+    return recompute_q<TX, T>(L) ? stencil_blocks(L.g2f) : update_blocks(L.nu);
+}
+
 struct GraphEntry {
-    int level, tsize, cg, fold, K, defer, ld;
+    int level, tsize, cg, fold, K, defer, ld, rq;
     const void *x, *d, *xs;
     hipGraph_t graph;
     hipGraphExec_t exec;
@@ -488,7 +511,7 @@ int launch_iteration(const Level &L, TX *x, long long j, int ev, hipStream_t st,
     // FP32 vectors (and the iterate solved with them) have the level's row layout
     const Rows rows = sizeof(T) == 4 ? L.rows() : Rows{};
     const int nsb = stencil_blocks(G);
-    const int nvb = update_blocks(L.nu);
+    const int nvb = b_partials<TX, T>(L);
     const int cur = (int)(j & 1), nxt = cur ^ 1;
     T *pn = c.p[nxt].as<T>(), *psn = c.ps[nxt].as<T>();
     // folded: sweep A merges the previous sweep B's partials (rho, r.r, beta, stopping
@@ -499,6 +522,19 @@ int launch_iteration(const Level &L, TX *x, long long j, int ev, hipStream_t st,
         lb = StepLink{S, c.part_a.as<Pair>(), nsb, 1, cur};
     }
     if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev], st));
+    if constexpr (sizeof(T) == 4 && sizeof(TX) == 8) {
+        if (recompute_q<TX, T>(L)) {
+            CKH(stencil_dir_sigma(G, G.ty, r, rs, c.p[cur].as<T>(), c.ps[cur].as<T>(), &S->beta,
+                                  j == 0 ? 1 : 0, pn, psn, c.part_a.as<Pair>(), &S->status, st,
+                                  la));
+            if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev + 1], st));
+            if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev + 2], st));
+            CKH(stencil_pair_update(G, G.ty, pn, psn, x, r, rs, c.part_b.as<Pair>(), &S->status,
+                                    &S->alpha, st, lb));
+            if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev + 3], st));
+            return EXCMG_OK;
+        }
+    }
     if constexpr (sizeof(T) == 8 && sizeof(TX) == 8) {
         if (g_var.d || g_var.xs) {  // Algorithm 2 with its options
             if (g_var.d)
@@ -559,7 +595,7 @@ template <typename T>
 int close_window(const Level &L, long long j_next, hipStream_t st, int defer = 0) {
     if (!g_fold) return EXCMG_OK;
     Ctx &c = g_ctx;
-    const StepLink l{c.state.as<BicgState>(), c.part_b.as<Pair>(), update_blocks(L.nu), g_cg ? 1 : 2,
+    const StepLink l{c.state.as<BicgState>(), c.part_b.as<Pair>(), b_partials<double, T>(L), g_cg ? 1 : 2,
                      (int)(j_next & 1), defer ? 1 : 0};
     CKH(step_check(l, st));
     return EXCMG_OK;
@@ -571,6 +607,7 @@ int window_graph(const Level &L, TX *x, int K, hipGraphExec_t *out, int defer = 
     for (GraphEntry &e : g_graph_cache)
         if (e.level == L.index && e.tsize == (int)sizeof(T) && e.cg == (int)g_cg &&
             e.fold == (int)g_fold && e.K == K && e.defer == defer && e.ld == L.ld &&
+            e.rq == (int)recompute_q<TX, T>(L) &&
             e.x == (const void *)x &&
             e.d == g_var.d && e.xs == g_var.xs) {
             *out = e.exec;
@@ -592,7 +629,7 @@ int window_graph(const Level &L, TX *x, int K, hipGraphExec_t *out, int defer = 
     hipGraphExec_t exec = nullptr;
     CKH(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
     g_graph_cache.push_back(GraphEntry{L.index, (int)sizeof(T), (int)g_cg, (int)g_fold, K, defer,
-                                       L.ld, (const void *)x, g_var.d, g_var.xs, graph, exec});
+                                       L.ld, (int)recompute_q<TX, T>(L), (const void *)x, g_var.d, g_var.xs, graph, exec});
     *out = exec;
     return EXCMG_OK;
 }
@@ -611,7 +648,7 @@ int bicg_iterate(const Level &L, TX *x, BicgState &hs, long long &j) {
     const bool graphs = g_graphs && !g_timing;
     // x += alpha p deferred to the next sweep A (large grids, FP32 vectors, plain Bi-CG):
     // sweep B then streams r, q, r*, q* only
-    const int defer = ((graphs || g_timing) && K <= 16 && g_defer && sizeof(T) == 4 &&
+    const int defer = (!recompute_q<TX, T>(L) && (graphs || g_timing) && K <= 16 && g_defer && sizeof(T) == 4 &&
                        sizeof(TX) == 8 && !g_cg && g_fold && !g_var.d && !g_var.xs &&
                        g_ctx.dim == 3) ? 1 : 0;
     hipGraphExec_t exec = nullptr;
@@ -969,7 +1006,8 @@ int level_solve_reliable(const Level &L, const double *b, double *u, double eps,
                 continue;
             }
             since_start++;
-            CKH(rho_partials<float>(L.nu, r, rs, c.part_b.as<Pair>(), g_stream, nullptr, rows));
+            CKH(rho_partials<float>(L.nu, r, rs, c.part_b.as<Pair>(), g_stream, nullptr, rows,
+                                    b_partials<double, float>(L)));
             CKH(state_resume(S, std::max((delta * delta) * rr, 0.25 * target), g_stream));
             CKR(read_state(hs));
             // the run stopped inside the last window: go on from the iteration it reached
@@ -1765,6 +1803,8 @@ int solve_ex_dim(const excmg_opts *opts, const double *f, const double *g1, cons
     if (o.fp32_min_unknowns < 0)
         return fail(EXCMG_EINVAL, "fp32_min_unknowns must be >= 0");
     if (o.row_pad != 0 && o.row_pad != 1) return fail(EXCMG_EINVAL, "row_pad must be 0 or 1");
+    if (o.recompute_min_unknowns < 0)
+        return fail(EXCMG_EINVAL, "recompute_min_unknowns must be >= 0");
     if (o.precond == EXCMG_PRECOND_JACOBI && (o.precision != EXCMG_FP64 || o.method != EXCMG_BICG))
         return fail(EXCMG_EINVAL, "the Jacobi preconditioner runs with FP64 Bi-CG only");
     CKR(setup(o.n_finest, o.n_levels, o.bc_kind, dim));
@@ -1779,9 +1819,11 @@ int solve_ex_dim(const excmg_opts *opts, const double *f, const double *g1, cons
     if (st) memset(st, 0, sizeof(*st));
     g_cg = (o.method == EXCMG_CG);
     g_graphs = getenv("EXCMG_NO_GRAPHS") == nullptr;
+    g_rq_min = o.recompute_min_unknowns > 0 ? o.recompute_min_unknowns : kRecomputeMin;
     int rc = solve_cascade(o, af.p<double>(), a1.p<double>(), a2.p<double>(), au.p<double>(),
                         ut_out ? at.p<double>() : nullptr, st);
     g_graphs = false;
+    g_rq_min = kRecomputeMin;
     if (rc != EXCMG_OK && rc != EXCMG_ENOCONV && rc != EXCMG_EBREAKDOWN) return rc;
     CKR(au.back());
     if (ut_out) CKR(at.back());
@@ -1852,11 +1894,11 @@ int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launc
                         double *bytes_per_launch) {
     g_err[0] = 0;
     if (!g_ctx.ready) return fail(EXCMG_EINVAL, "no context: call excmg_setup first");
-    if (which < 0 || which > 6 || reps < 1) return fail(EXCMG_EINVAL, "bad sweep or reps");
+    if (which < 0 || which > 8 || reps < 1) return fail(EXCMG_EINVAL, "bad sweep or reps");
     if (precision != EXCMG_FP64 && precision != EXCMG_MIXED)
         return fail(EXCMG_EINVAL, "bad precision");
     if (which >= 5 && (precision != EXCMG_MIXED || g_ctx.dim != 3))
-        return fail(EXCMG_EINVAL, "sweeps 5 and 6 are the mixed-precision 3D ones");
+        return fail(EXCMG_EINVAL, "sweeps 5 to 8 are the mixed-precision 3D ones");
     Ctx &c = g_ctx;
     const Level &L = c.lv.back();
     const size_t es = precision == EXCMG_FP64 ? 8 : 4;
@@ -1879,8 +1921,8 @@ int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launc
     CKH(hipMemcpyAsync(c.state.p, &hs, sizeof(hs), hipMemcpyHostToDevice, g_stream));
     BicgState *S = c.state.as<BicgState>();
     // algorithmic bytes per unknown of each sweep
-    const double fp64_bytes[7] = {16, 24, 64, 72, 16, 0, 0};
-    const double mixed_bytes[7] = {8, 24, 32, 44, 8, 48, 24};
+    const double fp64_bytes[9] = {16, 24, 64, 72, 16, 0, 0, 0, 0};
+    const double mixed_bytes[9] = {8, 24, 32, 44, 8, 48, 24, 24, 40};
     auto launch_once = [&]() -> hipError_t {
         if (precision == EXCMG_FP64) {
             double *r = c.r.as<double>(), *rs = c.rs.as<double>();
@@ -1922,6 +1964,15 @@ int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launc
                                                       c.q.as<float>(), rs, c.qs.as<float>(),
                                                       c.part_b.as<Pair>(), g_stream, StepLink{},
                                                       rows);
+            case 7: return stencil_dir_sigma(L.g2f, L.g2f.ty, r, rs, c.p[0].as<float>(),
+                                             c.ps[0].as<float>(), &S->beta, 0,
+                                             c.p[1].as<float>(), c.ps[1].as<float>(),
+                                             c.part_a.as<Pair>(), &S->status, g_stream,
+                                             StepLink{});
+            case 8: return stencil_pair_update(L.g2f, L.g2f.ty, c.p[1].as<float>(),
+                                               c.ps[1].as<float>(), xv, r, rs,
+                                               c.part_b.as<Pair>(), &S->status, &S->alpha,
+                                               g_stream, StepLink{});
             default: return copy_convert<float, float>(L.nu, r, c.q.as<float>(), g_stream);
         }
     };
@@ -2110,6 +2161,7 @@ int excmg_set_shape(int n, int kind, int ty, int zc) {
         const size_t need = (size_t)std::max({stencil_blocks(L.g1), stencil_blocks(L.g2),
                                               stencil_blocks(L.g2f)}) * sizeof(Pair);
         if (need > g_ctx.part_a.bytes) CKR(g_ctx.part_a.ensure(need));
+        if (2 * need > g_ctx.part_b.bytes) CKR(g_ctx.part_b.ensure(2 * need));
     }
     return EXCMG_OK;
 }

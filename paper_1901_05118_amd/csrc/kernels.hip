@@ -252,15 +252,16 @@ __global__ void __launch_bounds__(kUpdateThreads)
 
 template <typename T>
 hipError_t rho_partials(long long n, const T *r, const T *rs, Pair *partials, hipStream_t st,
-                        const T *d, Rows rows) {
-    hipLaunchKernelGGL(k_rho_partials<T>, dim3(update_blocks(n)), dim3(kUpdateThreads), 0, st, n, r,
-                       rs, d, partials, rows);
+                        const T *d, Rows rows, int nblocks) {
+    // nblocks: the partial count the next sweep A merges (default: the update sweep's)
+    hipLaunchKernelGGL(k_rho_partials<T>, dim3(nblocks > 0 ? nblocks : update_blocks(n)),
+                       dim3(kUpdateThreads), 0, st, n, r, rs, d, partials, rows);
     return hipGetLastError();
 }
 template hipError_t rho_partials<float>(long long, const float *, const float *, Pair *,
-                                        hipStream_t, const float *, Rows);
+                                        hipStream_t, const float *, Rows, int);
 template hipError_t rho_partials<double>(long long, const double *, const double *, Pair *,
-                                         hipStream_t, const double *, Rows);
+                                         hipStream_t, const double *, Rows, int);
 
 // Sweep B of Algorithm 2 with its options, in the order of the algorithm: x, x*, r, r*
 // updates, then M^-1 r and the partials of r*.(M^-1 r) and r.r.

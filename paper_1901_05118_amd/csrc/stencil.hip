@@ -42,6 +42,14 @@ static hipError_t launch(const Geom &g, const In &in, const Out &out, hipStream_
     return hipGetLastError();
 }
 
+// Launcher of epilogues that exist for 3D grids only.
+template <int TY, typename T, class In, class Out, int NA>
+static hipError_t launch3d(const Geom &g, const In &in, const Out &out, hipStream_t st) {
+    hipLaunchKernelGGL((zmarch<NA, TY, T, In, Out>), dim3(xcd_grid(g.ntiles)), dim3(kWave, TY), 0,
+                       st, g, in, out);
+    return hipGetLastError();
+}
+
 #define EXCMG_DISPATCH_TY(TYV, ...)                                                          \
     switch (TYV) {                                                                           \
         case 4: { constexpr int TY = 4; __VA_ARGS__; } break;                              \
@@ -169,6 +177,60 @@ hipError_t stencil_pair_direction_x(const Geom &g, int ty, const float *r, const
             return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// The recomputing form's two sweeps (3D grids; see OutDirSigma and OutPairUpdate).
+hipError_t stencil_dir_sigma(const Geom &g, int ty, const float *r, const float *rs,
+                             const float *p_old, const float *ps_old, const double *beta_dev,
+                             int first, float *p_new, float *ps_new, Pair *partials,
+                             const int *status, hipStream_t st, StepLink link) {
+    if (g.dim != 3) return hipErrorInvalidValue;
+    InDirection<float> in;
+    in.link = link;
+    in.r[0] = r;
+    in.r[1] = r;
+    in.p[0] = p_old;
+    in.p[1] = p_old;
+    in.beta_dev = beta_dev;
+    in.first = first;
+    in.beta = 0.0;
+    OutDirSigma<float> out;
+    out.p_new = p_new;
+    out.ps_new = ps_new;
+    out.rs = rs;
+    out.ps_old = ps_old;
+    out.partials = partials;
+    out.status = status;
+    out.beta = 0.0;
+    out.first = first;
+    out.acc = Pair{0.0, 0.0};
+    EXCMG_DISPATCH_TY(ty, return (launch3d<TY, float, InDirection<float>, OutDirSigma<float>, 1>(
+                              g, in, out, st)));
+    return hipSuccess;
+}
+
+hipError_t stencil_pair_update(const Geom &g, int ty, const float *p, const float *ps, double *x,
+                               float *r, float *rs, Pair *partials, const int *status,
+                               const double *alpha_dev, hipStream_t st, StepLink link) {
+    if (g.dim != 3) return hipErrorInvalidValue;
+    InPlainAlpha<float> in;
+    in.x[0] = p;
+    in.x[1] = ps;
+    in.alpha_dev = alpha_dev;
+    in.link = link;
+    in.alpha = 0.0;
+    OutPairUpdate<float> out;
+    out.x = x;
+    out.r = r;
+    out.rs = rs;
+    out.partials = partials;
+    out.status = status;
+    out.alpha = 0.0;
+    out.acc[0] = Pair{0.0, 0.0};
+    out.acc[1] = Pair{0.0, 0.0};
+    EXCMG_DISPATCH_TY(ty, return (launch3d<TY, float, InPlainAlpha<float>, OutPairUpdate<float>, 2>(
+                              g, in, out, st)));
+    return hipSuccess;
 }
 
 hipError_t stencil_pair_direction_m(const Geom &g, int ty, const double *r, const double *rs,

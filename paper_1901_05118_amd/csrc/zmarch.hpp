@@ -183,6 +183,27 @@ struct InDirectionM {
     }
 };
 
+// Stored vectors (the directions of the current iteration), with alpha of Algorithm 2 from
+// the partials of sweep A merged at the start (the update sweep of the recomputing form).
+template <typename T>
+struct InPlainAlpha {
+    static constexpr int R = 1;
+    const T *x[2];
+    const double *alpha_dev;  // alpha as finalised by a separate kernel (no link)
+    StepLink link;
+    double alpha;
+    __device__ __forceinline__ void prepare() {}
+    __device__ __forceinline__ bool begin(Pair *sh) {
+        if (link.state == nullptr) {
+            alpha = wave_uniform(*alpha_dev);
+            return true;
+        }
+        return link_alpha(link, alpha, sh);
+    }
+    __device__ __forceinline__ void load(int a, i64 idx, T (&raw)[R]) const { raw[0] = x[a][idx]; }
+    __device__ __forceinline__ double combine(const T (&raw)[R]) const { return (double)raw[0]; }
+};
+
 // Kernel: NA marched arrays (1 or 2), input policy In, epilogue Out.
 //   Out::emit(lane_state, idx, y[NA], c[NA]) is called for every valid output with the
 //   operator values y and the centre values c of the output plane;
@@ -195,6 +216,28 @@ template <class O, class = void>
 struct HasGate : std::false_type {};
 template <class O>
 struct HasGate<O, std::void_t<decltype(std::declval<const O &>().gate())>> : std::true_type {};
+// Epilogues that request per-output data ahead (Out::Pre, Out::pre(idx)): the values of an
+// output are requested when its own plane is consumed and handed to emit() two planes
+// later, when the output is complete (for epilogues with registers to spare).
+template <class O, class = void>
+struct HasPre : std::false_type {};
+template <class O>
+struct HasPre<O, std::void_t<typename O::Pre>> : std::true_type {};
+template <class O, bool = HasPre<O>::value>
+struct PreOf {
+    struct type {};
+};
+template <class O>
+struct PreOf<O, true> {
+    using type = typename O::Pre;
+};
+// Epilogues that take scalars of the input policy once its begin() has made them
+// (Out::bind(in)).
+template <class O, class I, class = void>
+struct HasBind : std::false_type {};
+template <class O, class I>
+struct HasBind<O, I, std::void_t<decltype(std::declval<O &>().bind(std::declval<const I &>()))>>
+    : std::true_type {};
 
 // No step before the march: `in` is already prepared.
 struct NoBegin {
@@ -297,8 +340,11 @@ __device__ __forceinline__ bool zmarch_tile(const Geom &g, int tile, const In &i
     int cur = 0;
     const int centre = (ly + 2) * LS + (lx + 2);
     const int col_off = iy * g.ld + ix;  // in-plane offset of this lane's column (< 2^31)
+    constexpr bool kPre = HasPre<Out>::value;
+    using PreT = typename PreOf<Out>::type;
+    PreT pre[D];             // per-output data of planes m-2 (slot m % D), requested at plane m
     // consume plane m from LDS, stage plane m+1 from `r`, refill `r` with plane m+1+D
-    auto body = [&](int m, Raw &r, float &z) {
+    auto body = [&](int m, Raw &r, float &z, PreT &pm) {
         double y[NA], c0[NA], cprev[NA];
 #pragma unroll
         for (int a = 0; a < NA; a++) {
@@ -308,7 +354,13 @@ __device__ __forceinline__ bool zmarch_tile(const Geom &g, int tile, const In &i
         if (valid) {
             if (m >= k0 && m < k1) out.centre((i64)m * plane + col_off, c0);
             const int k = m - 2;
-            if (k >= k0 && k < k1) out.emit((i64)k * plane + col_off, y, cprev);
+            if (k >= k0 && k < k1) {
+                if constexpr (kPre) out.emit((i64)k * plane + col_off, y, cprev, pm);
+                else out.emit((i64)k * plane + col_off, y, cprev);
+            }
+            if constexpr (kPre) {
+                if (m >= k0 && m < k1) pm = out.pre((i64)m * plane + col_off);
+            }
         }
         stash(cur ^ 1, r, z);
         fetch(min(m + 1 + D, mend), r, z);
@@ -319,7 +371,7 @@ __device__ __forceinline__ bool zmarch_tile(const Geom &g, int tile, const In &i
 #pragma unroll
         for (int k = 0; k < D; k++) {
             if (m + k > mend) break;
-            body(m + k, raw[k], mz[k]);
+            body(m + k, raw[k], mz[k], pre[k]);
         }
     }
     return true;
@@ -364,6 +416,9 @@ __global__ void __launch_bounds__(kWave *TY) zmarch(Geom g, In in_arg, Out out) 
         if (s_skip) return false;
         const bool run = in.begin(red);
         stops = !run;
+        if constexpr (HasBind<Out, In>::value) {
+            if (run) out.bind(in);
+        }
         return run;
     };
     const int tile = xcd_tile(blockIdx.x, g.ntiles);
@@ -508,6 +563,87 @@ struct OutPairApplyX : OutPairApply<T> {
         OutPairApply<T>::emit(idx, v, c);
     }
     __device__ void finish_output(i64 idx) { x[idx] = x[idx] + alpha * (double)pold[idx]; }
+};
+
+// The recomputing form of a Bi-CG iteration (FP32 vectors on large 3D grids): q = A p and
+// q* = A^T p* are not stored but formed again where they are used, which saves their
+// stream (a pair of stores and a pair of loads per unknown) for a second pass of the
+// stencil, whose arithmetic does not limit these memory-bound sweeps.
+//
+// Sweep A: p_new = r + beta p is marched (one array) for q = A p_new, which here only feeds
+// sigma = p*_new . q; p*_new = r* + beta p* is formed at the output from r* and p* requested
+// two planes ahead.  Stores p_new and p*_new.  Same values, roundings and products as
+// OutPairApply.
+template <typename T>
+struct OutDirSigma {
+    T *p_new;
+    T *ps_new;
+    const T *rs;         // r*
+    const T *ps_old;     // p* of the previous iteration
+    Pair *partials;
+    const int *status;
+    double beta;
+    int first;
+    Pair acc;
+    struct Pre {
+        T r, p;
+    };
+    template <class In>
+    __device__ void bind(const In &in) {
+        beta = in.beta;
+        first = in.first;
+    }
+    __device__ bool skip() const { return *status != 0; }
+    __device__ void centre(i64, const double *) {}
+    __device__ Pre pre(i64 idx) const { return Pre{rs[idx], ps_old[idx]}; }
+    __device__ void emit(i64 idx, const double *v, const double *c, const Pre &pr) {
+        p_new[idx] = (T)c[0];
+        const double rv = (double)pr.r;
+        const T psn = (T)(first ? rv : (double)(T)(rv + beta * (double)pr.p));
+        ps_new[idx] = psn;
+        dot2_acc(acc, (double)psn, (double)(T)v[0]);
+    }
+    __device__ void finish(int block, Pair *sh) {
+        Pair w[1] = {acc};
+        block_merge<1>(w, sh);
+        if (threadIdx.x == 0 && threadIdx.y == 0) partials[block] = w[0];
+    }
+};
+
+// Sweep B: p and p* (stored by sweep A) are marched for q = A p and q* = A^T p*, then
+// x += alpha p, r -= alpha q, r* -= alpha q*, and the partials of r*.r and r.r: the
+// arithmetic of the update sweep, element by element, with q and q* rounded as if stored.
+template <typename T>
+struct OutPairUpdate {
+    double *x;
+    T *r;
+    T *rs;
+    Pair *partials;
+    const int *status;
+    double alpha;
+    Pair acc[2];
+    template <class In>
+    __device__ void bind(const In &in) { alpha = in.alpha; }
+    __device__ bool skip() const { return *status != 0; }
+    __device__ void centre(i64, const double *) {}
+    __device__ void emit(i64 idx, const double *v, const double *c) {
+        const T q0 = (T)v[0], q1 = (T)v[1];
+        x[idx] = x[idx] + alpha * c[0];
+        const double ri = (double)r[idx] - alpha * (double)q0;
+        const double si = (double)rs[idx] - alpha * (double)q1;
+        const T rt = (T)ri, st = (T)si;
+        r[idx] = rt;
+        rs[idx] = st;
+        dot2_acc(acc[0], (double)st, (double)rt);
+        dot2_acc(acc[1], (double)rt, (double)rt);
+    }
+    __device__ void finish(int block, Pair *sh) {
+        block_merge<2>(acc, sh);
+        if (threadIdx.x == 0 && threadIdx.y == 0) {
+            partials[block] = acc[0];
+            partials[gridDim.x + block] = acc[1];
+        }
+    }
 };
 
 }  // namespace excmg

@@ -48,7 +48,8 @@ class Opts(ctypes.Structure):
                 ("max_runs", ctypes.c_int), ("inner_tol", ctypes.c_double),
                 ("max_outer", ctypes.c_int), ("batch_mode", ctypes.c_int),
                 ("method", ctypes.c_int), ("refine", ctypes.c_int), ("precond", ctypes.c_int),
-                ("fp32_min_unknowns", ctypes.c_int), ("row_pad", ctypes.c_int)]
+                ("fp32_min_unknowns", ctypes.c_int), ("row_pad", ctypes.c_int),
+                ("recompute_min_unknowns", ctypes.c_int)]
 
 
 class LevelStats(ctypes.Structure):
@@ -261,10 +262,11 @@ def solve_ex(n_finest: int, n_levels: int, bc_kind: int, f, g1, g2, tol: float, 
              ut_out=None, precision: int = FP64, max_iters: int = 0, max_runs: int = 0,
              inner_tol: float = 0.0, max_outer: int = 0, method: int = BICG,
              refine: int = RELIABLE, precond: int = PRECOND_NONE, fp32_min_unknowns: int = 0,
-             row_pad: int = 0):
+             row_pad: int = 0, recompute_min_unknowns: int = 0):
     """Algorithm 1 with options.  Returns (code, Stats)."""
     o = Opts(n_finest, n_levels, bc_kind, precision, tol, max_iters, max_runs, inner_tol,
-             max_outer, 0, method, refine, precond, fp32_min_unknowns, row_pad)
+             max_outer, 0, method, refine, precond, fp32_min_unknowns, row_pad,
+             recompute_min_unknowns)
     st = Stats()
     rc = load().excmg_solve_ex(ctypes.byref(o), _ptr(f, name="f"), _ptr(g1, name="g1"),
                                _ptr(g2, name="g2"), _ptr(u_out, name="u_out"),
@@ -286,7 +288,7 @@ def solve_ex_2d(n_finest: int, n_levels: int, bc_kind: int, f, g1, g2, tol: floa
                 fp32_min_unknowns: int = 0):
     """Algorithm 1 for the 2D equation.  Returns (code, Stats)."""
     o = Opts(n_finest, n_levels, bc_kind, precision, tol, max_iters, max_runs, inner_tol,
-             max_outer, 0, method, refine, precond, fp32_min_unknowns, 0)
+             max_outer, 0, method, refine, precond, fp32_min_unknowns, 0, 0)
     st = Stats()
     rc = load().excmg2d_solve_ex(ctypes.byref(o), _ptr(f, name="f"), _ptr(g1, name="g1"),
                                  _ptr(g2, name="g2"), _ptr(u_out, name="u_out"),

@@ -9,8 +9,11 @@ copies of one finest-level vector: a kernel of known traffic (16 bytes per unkno
 which HBM byte counters are calibrated.  Sweeps: 0 operator apply, 1 residual, 2 sweep A
 (direction update and the pair of operator products), 3 sweep B (x, r, r* updates with the
 next rho), 4 copy, 5 sweep A applying the previous iteration's x update and 6 the sweep B
-that then leaves x alone (the pair a mixed-precision solve runs on grids of 64^3 and up).  Prints one line per sweep: mean ms per launch, algorithmic bytes per
-launch and the rate.  Uses no torch: every launch comes from the library.
+that then leaves x alone (the stored form's pair on grids from 64^3 to 128^3), 7 and 8 the
+two sweeps of the recomputing form (mixed-precision solves on grids of 2^22 unknowns and
+up: sweep A marches p alone; sweep B marches p and p* again for q and q* and updates x, r,
+r*).  Prints one line per sweep: mean ms per launch, algorithmic bytes per launch and the
+rate.  Uses no torch: every launch comes from the library.
 """
 import argparse
 import sys

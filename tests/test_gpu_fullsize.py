@@ -86,11 +86,9 @@ def test_benchmark_solves_meet_tolerance(ex, problem):
 
 
 def test_mixed_bicg_equals_cg_at_full_size(ex, problem):
-    """The mixed Bi-CG defers x += alpha p to the next sweep A on these grids; with 2048
-    workgroups per sweep at 512^3 (several per CU), those that start after the stopping
-    decision must still apply their part of the owed update.  The CG form, which keeps the
-    update in its own sweep, must match bit for bit, and so must the solve on padded rows
-    (row_pad = 1)."""
+    """The mixed Bi-CG takes the recomputing form on the 256^3 and 512^3 levels (q and q*
+    formed again in the update sweep, whose partials are per tile).  The CG form, which
+    stores q, must match bit for bit, and so must the solve on padded rows (row_pad = 1)."""
     print("mixed bicg vs cg 512^3", flush=True)
     arr, b = problem
     f, g1, g2 = dev(arr.f), dev(arr.g1), dev(arr.g2)

@@ -382,8 +382,8 @@ def test_autotuned_shape_keeps_results(ex):
 # ------------------------------------------------------------------ CG specialisation
 
 def test_deferred_update_keeps_bicg_equal_to_cg(ex):
-    """On grids of 64^3 and up the mixed Bi-CG moves x += alpha p from sweep B into the next
-    sweep A (same arithmetic, applied one launch later, and on its own when a run stops);
+    """On the 64^3 and 128^3 grids the mixed Bi-CG moves x += alpha p from sweep B into the
+    next sweep A (same arithmetic, applied one launch later, and on its own when a run stops);
     the CG form keeps it in its update sweep.  Both must give the same iterates bit for bit,
     through residual replacements and window ends."""
     N, nl, bc = 128, 6, 2
@@ -399,6 +399,44 @@ def test_deferred_update_keeps_bicg_equal_to_cg(ex):
         [(l["iterations"], l["runs"]) for l in st2.levels()]
     assert st1.levels()[-1]["runs"] > 1
     np.testing.assert_array_equal(host(u_b), host(u_c))
+
+def test_recomputing_form_keeps_the_mixed_solve(ex):
+    """On large 3D grids the mixed Bi-CG forms q = A p and q* = A^T p* again in its update
+    sweep instead of storing them (same roundings, same update arithmetic).  Forced on every
+    level at 128^3 (recompute_min_unknowns = 1) it gives the stored form's iterates and
+    counts bit for bit, and the CG form's; launch by launch (event timing) too, one sweep A
+    and one sweep B per iteration; a negative threshold is refused."""
+    N, nl, bc = 128, 6, 2
+    arr = make_arrays(config_problem(2), N, bc)
+    f, g1, g2 = dev(arr.f), dev(arr.g1), dev(arr.g2)
+    outs, its = [], []
+    for kw in (dict(recompute_min_unknowns=1 << 30), dict(recompute_min_unknowns=1),
+               dict(method=ex.CG)):
+        u = torch.empty_like(f)
+        rc, st = ex.solve_ex(N, nl, bc, f, g1, g2, 1e-9, u, precision=ex.MIXED,
+                             fp32_min_unknowns=1, **kw)
+        assert rc == ex.OK, ex.last_error()
+        outs.append(host(u))
+        its.append([(l["iterations"], l["runs"]) for l in st.levels()])
+    assert its[0] == its[1] == its[2]
+    assert its[1][-1][1] > 1                      # residual replacements happened
+    np.testing.assert_array_equal(outs[0], outs[1])
+    np.testing.assert_array_equal(outs[2], outs[1])
+    ex.set_timing(True)
+    u = torch.empty_like(f)
+    rc, st = ex.solve_ex(N, nl, bc, f, g1, g2, 1e-9, u, precision=ex.MIXED,
+                         fp32_min_unknowns=1, recompute_min_unknowns=1)
+    _, n_a = ex.get_timing(nl - 1, 0)
+    _, n_b = ex.get_timing(nl - 1, 1)
+    _, n_x = ex.get_timing(nl - 1, 2)
+    ex.set_timing(False)
+    assert rc == ex.OK
+    assert n_x == 0 and n_a == n_b == its[1][-1][0]
+    np.testing.assert_array_equal(host(u), outs[1])
+    with pytest.raises(ex.ExcmgError):
+        ex.solve_ex(N, nl, bc, f, g1, g2, 1e-9, torch.empty_like(f), precision=ex.MIXED,
+                    recompute_min_unknowns=-1)
+
 
 def test_event_timed_solve_equals_the_graph_solve(ex):
     """With per-sweep timing on, a solve runs its iterations launch by launch (no captured
