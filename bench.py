@@ -37,7 +37,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-# Grids from which mixed-precision Bi-CG takes the recomputing form (the library's default)
+# Grids from which Bi-CG takes the recomputing form (the library's default)
 RECOMPUTE_MIN = 1 << 22
 
 
@@ -45,14 +45,17 @@ def sweep_launch(N, ty, zc, form):
     """Name (as the profiler shows it) and launch size in threads of a Bi-CG stencil sweep on
     the grid of N cells with tiles of 64 x ty columns and zc planes.  form: "fp64" (sweep A),
     "deferred" (mixed sweep A that also applies the previous iteration's x update),
-    "sigma" / "update" (the two sweeps of the mixed recomputing form)."""
+    "sigma" / "update" (the two sweeps of the recomputing form, FP32 vectors), "sigma64" /
+    "update64" (the same with FP64 vectors)."""
     n = N - 1
     tiles = -(-n // 64) * -(-n // ty) * -(-n // zc)
     tiles = -(-tiles // 8) * 8  # the grid is padded to whole XCD shares
     name = {"fp64": "zmarch<2, {ty}, double, InDirection<double>, OutPairApply<double> >",
             "deferred": "zmarch<2, {ty}, float, InDirection<float>, OutPairApplyX<float> >",
             "sigma": "zmarch<1, {ty}, float, InDirection<float>, OutDirSigma<float> >",
-            "update": "zmarch<2, {ty}, float, InPlainAlpha<float>, OutPairUpdate<float> >"}[form]
+            "update": "zmarch<2, {ty}, float, InPlainAlpha<float>, OutPairUpdate<float> >",
+            "sigma64": "zmarch<1, {ty}, double, InDirection<double>, OutDirSigma<double> >",
+            "update64": "zmarch<2, {ty}, double, InPlainAlpha<double>, OutPairUpdate<double> >"}[form]
     return name.format(ty=ty), tiles * 64 * ty
 
 
@@ -316,14 +319,17 @@ def main():
     if [lv["iterations"] for lv in st_t.levels()] != [lv["iterations"] for lv in levels]:
         raise RuntimeError("the event-timed solve took other iterations than the timed one")
     nu = (N - 1) ** 3
-    rq = gate and nu >= RECOMPUTE_MIN
-    # Bytes per unknown.  FP64: sweep A reads r, r*, p, p* and writes p, p*, q, q* (64);
-    # sweep B reads x, p, r, q, r*, q* and writes x, r, r* (72).  Mixed, recomputing form:
-    # sweep A reads r, p, r*, p* and writes p, p* (24); sweep B reads p, p*, r, r* and x
-    # (FP64) and writes r, r*, x (40).  Mixed, stored form: sweep A also applies x += alpha p
-    # of the previous iteration (48); sweep B streams r, q, r*, q* and writes r, r* (24).
-    if rq:
+    rq = nu >= RECOMPUTE_MIN
+    # Bytes per unknown.  Recomputing form: sweep A reads r, p, r*, p* and writes p, p*
+    # (mixed 24, FP64 48); sweep B reads p, p*, r, r* and x (FP64) and writes r, r*, x
+    # (mixed 40, FP64 64).  Stored form, FP64: sweep A reads r, r*, p, p* and writes p, p*,
+    # q, q* (64); sweep B reads x, p, r, q, r*, q* and writes x, r, r* (72).  Stored form,
+    # mixed: sweep A also applies x += alpha p of the previous iteration (48); sweep B
+    # streams r, q, r*, q* and writes r, r* (24).
+    if rq and gate:
         form_a, form_b, bytes_a, bytes_b, kind_a = "sigma", "update", 24.0, 40.0, 0
+    elif rq:
+        form_a, form_b, bytes_a, bytes_b, kind_a = "sigma64", "update64", 48.0, 64.0, 0
     elif gate:
         # the sweep A that applies the deferred x update (the first of each run, which owes
         # none, is the plain kernel and is timed apart)
@@ -358,8 +364,8 @@ def main():
                 "bytes_per_launch": d["bytes_per_launch"],
                 "other_sweep": dict(sweeps["B" if dom == "A" else "A"],
                                     name="B" if dom == "A" else "A"),
-                # one Bi-CG iteration (both sweeps): 64 (mixed, recomputing), 72 (mixed,
-                # stored) or 136 (FP64) bytes per unknown
+                # one Bi-CG iteration (both sweeps): 64 (mixed) or 112 (FP64) bytes per
+                # unknown in the recomputing form, 72 or 136 in the stored one
                 "iteration": {"ms": round(avg_a + avg_b, 4),
                               "gbs": round((bytes_a + bytes_b) / ((avg_a + avg_b) * 1e-3) / 1e9, 1),
                               "frac": round((bytes_a + bytes_b) / ((avg_a + avg_b) * 1e-3) / 1e9

@@ -103,11 +103,11 @@ typedef struct excmg_opts {
                         /* in and out.  0 (default): contiguous rows.  Same results bit for */
                         /* bit; padded rows speed up the Bi-CG stencil sweep on large grids */
                         /* and slow the vector updates, about even for the whole solve      */
-    int recompute_min_unknowns; /* mixed precision, 3D, Bi-CG: levels with at least this many */
+    int recompute_min_unknowns; /* 3D Bi-CG (FP64 and mixed): levels with at least this many */
                         /* unknowns form q = A p and q* = A^T p* again in the update sweep   */
-                        /* instead of storing them (64 instead of 72 bytes per unknown and  */
-                        /* iteration, a second stencil pass); 0: 4194304 (2^22), 1: every   */
-                        /* level.  Same results bit for bit                                   */
+                        /* instead of storing them (mixed 64 instead of 72 bytes per unknown */
+                        /* and iteration, FP64 112 instead of 136; a second stencil pass);  */
+                        /* 0: 4194304 (2^22), 1: every level.  Same results bit for bit      */
 } excmg_opts;
 
 /* Per-level record filled by excmg_solve_ex (levels 0 and 1 report iterations = 0). */
@@ -250,13 +250,13 @@ int excmg_solve_ex(const excmg_opts *opts, const double *f, const double *g1, co
  *         5: sweep A also applying the previous iteration's x += alpha p (the stored
  *            form with the deferred update)                            mixed 48 B
  *         6: sweep B without x (its partner)                              mixed 24 B
- *         7: sweep A of the recomputing form (the form mixed-precision solves run on
- *            3D grids of 2^17 unknowns and up): p, p* update + A p + sigma, stores p, p*
- *                                                                         mixed 24 B
+ *         7: sweep A of the recomputing form (the form solves run on 3D grids of 2^22
+ *            unknowns and up): p, p* update + A p + sigma, stores p, p*
+ *                                                               FP64 48 B, mixed 24 B
  *         8: its sweep B: A p, A^T p* formed again, x, r, r* update + rho, r.r
- *                                                                         mixed 40 B
- * (bytes per unknown).  precision selects EXCMG_FP64 or EXCMG_MIXED (sweeps 5 to 8: mixed,
- * 3D contexts only). */
+ *                                                               FP64 64 B, mixed 40 B
+ * (bytes per unknown).  precision selects EXCMG_FP64 or EXCMG_MIXED (sweeps 5 and 6: mixed
+ * only; 5 to 8: 3D contexts only). */
 int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launch,
                         double *bytes_per_launch);
 

@@ -459,25 +459,27 @@ struct RunVariant {
 };
 RunVariant g_var;
 
-// Mixed Bi-CG on large 3D grids (plain Algorithm 2, folded finalisations) takes the
-// recomputing form: its update sweep marches p and p* again for q and q* instead of
-// reading them back (64 instead of 72 bytes per unknown and iteration).  Smaller grids keep
-// the stored form (x's update deferred to the next sweep A from 2^17 unknowns up): there a
-// second march per iteration costs more latency than the bytes it saves (measured, 128^3
-// level: 81.9 ms stored, 88.0 ms recomputing; 256^3: 532.0 and 513.7 ms).
+// Bi-CG on large 3D grids (plain Algorithm 2, folded finalisations, an FP64 iterate) takes
+// the recomputing form: its update sweep marches p and p* again for q and q* instead of
+// reading them back (mixed: 64 instead of 72 bytes per unknown and iteration; FP64: 112
+// instead of 136).  Smaller grids keep the stored form (mixed: x's update deferred to the
+// next sweep A from 2^17 unknowns up): there a second march per iteration costs more
+// latency than the bytes it saves (measured, mixed: 128^3 level 81.9 ms stored, 88.0 ms
+// recomputing; 256^3: 532.0 and 513.7 ms; FP64 256^3: 874.7 and 843.9 ms).
 constexpr long long kRecomputeMin = 1LL << 22;
 long long g_rq_min = kRecomputeMin;   // opts.recompute_min_unknowns of the solve in progress
 
 template <typename TX, typename T>
 bool recompute_q(const Level &L) {
-    return sizeof(T) == 4 && sizeof(TX) == 8 && !g_cg && g_fold && !g_var.d && !g_var.xs &&
-           g_ctx.dim == 3 && L.nu >= g_rq_min;
+    return sizeof(TX) == 8 && !g_cg && g_fold && !g_var.d && !g_var.xs && g_ctx.dim == 3 &&
+           L.nu >= g_rq_min;
 }
 
 // Partials (per value) that the update sweep of level L leaves for the next sweep A.
 template <typename TX, typename T>
 int b_partials(const Level &L) {
-    return recompute_q<TX, T>(L) ? stencil_blocks(L.g2f) : update_blocks(L.nu);
+    return recompute_q<TX, T>(L) ? stencil_blocks(sizeof(T) == 4 ? L.g2f : L.g2)
+                                 : update_blocks(L.nu);
 }
 
 struct GraphEntry {
@@ -522,15 +524,15 @@ int launch_iteration(const Level &L, TX *x, long long j, int ev, hipStream_t st,
         lb = StepLink{S, c.part_a.as<Pair>(), nsb, 1, cur};
     }
     if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev], st));
-    if constexpr (sizeof(T) == 4 && sizeof(TX) == 8) {
+    if constexpr (sizeof(TX) == 8) {
         if (recompute_q<TX, T>(L)) {
-            CKH(stencil_dir_sigma(G, G.ty, r, rs, c.p[cur].as<T>(), c.ps[cur].as<T>(), &S->beta,
-                                  j == 0 ? 1 : 0, pn, psn, c.part_a.as<Pair>(), &S->status, st,
-                                  la));
+            CKH(stencil_dir_sigma<T>(G, G.ty, r, rs, c.p[cur].as<T>(), c.ps[cur].as<T>(),
+                                     &S->beta, j == 0 ? 1 : 0, pn, psn, c.part_a.as<Pair>(),
+                                     &S->status, st, la));
             if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev + 1], st));
             if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev + 2], st));
-            CKH(stencil_pair_update(G, G.ty, pn, psn, x, r, rs, c.part_b.as<Pair>(), &S->status,
-                                    &S->alpha, st, lb));
+            CKH(stencil_pair_update<T>(G, G.ty, pn, psn, x, r, rs, c.part_b.as<Pair>(),
+                                       &S->status, &S->alpha, st, lb));
             if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev + 3], st));
             return EXCMG_OK;
         }
@@ -1897,8 +1899,9 @@ int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launc
     if (which < 0 || which > 8 || reps < 1) return fail(EXCMG_EINVAL, "bad sweep or reps");
     if (precision != EXCMG_FP64 && precision != EXCMG_MIXED)
         return fail(EXCMG_EINVAL, "bad precision");
-    if (which >= 5 && (precision != EXCMG_MIXED || g_ctx.dim != 3))
-        return fail(EXCMG_EINVAL, "sweeps 5 to 8 are the mixed-precision 3D ones");
+    if (which >= 5 && g_ctx.dim != 3) return fail(EXCMG_EINVAL, "sweeps 5 to 8 are 3D ones");
+    if ((which == 5 || which == 6) && precision != EXCMG_MIXED)
+        return fail(EXCMG_EINVAL, "sweeps 5 and 6 are mixed-precision ones");
     Ctx &c = g_ctx;
     const Level &L = c.lv.back();
     const size_t es = precision == EXCMG_FP64 ? 8 : 4;
@@ -1921,7 +1924,7 @@ int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launc
     CKH(hipMemcpyAsync(c.state.p, &hs, sizeof(hs), hipMemcpyHostToDevice, g_stream));
     BicgState *S = c.state.as<BicgState>();
     // algorithmic bytes per unknown of each sweep
-    const double fp64_bytes[9] = {16, 24, 64, 72, 16, 0, 0, 0, 0};
+    const double fp64_bytes[9] = {16, 24, 64, 72, 16, 0, 0, 48, 64};
     const double mixed_bytes[9] = {8, 24, 32, 44, 8, 48, 24, 24, 40};
     auto launch_once = [&]() -> hipError_t {
         if (precision == EXCMG_FP64) {
@@ -1939,6 +1942,14 @@ int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launc
                 case 3: return bicg_update<double, double>(
                             L.nu, S, L.x.as<double>(), c.p[1].as<double>(), r, c.q.as<double>(),
                             rs, c.qs.as<double>(), c.part_b.as<Pair>(), g_stream);
+                case 7: return stencil_dir_sigma<double>(
+                            L.g2, L.g2.ty, r, rs, c.p[0].as<double>(), c.ps[0].as<double>(),
+                            &S->beta, 0, c.p[1].as<double>(), c.ps[1].as<double>(),
+                            c.part_a.as<Pair>(), &S->status, g_stream, StepLink{});
+                case 8: return stencil_pair_update<double>(
+                            L.g2, L.g2.ty, c.p[1].as<double>(), c.ps[1].as<double>(),
+                            L.x.as<double>(), r, rs, c.part_b.as<Pair>(), &S->status, &S->alpha,
+                            g_stream, StepLink{});
                 default: return copy_convert<double, double>(L.nu, r, c.q.as<double>(), g_stream);
             }
         }
@@ -1964,12 +1975,12 @@ int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launc
                                                       c.q.as<float>(), rs, c.qs.as<float>(),
                                                       c.part_b.as<Pair>(), g_stream, StepLink{},
                                                       rows);
-            case 7: return stencil_dir_sigma(L.g2f, L.g2f.ty, r, rs, c.p[0].as<float>(),
+            case 7: return stencil_dir_sigma<float>(L.g2f, L.g2f.ty, r, rs, c.p[0].as<float>(),
                                              c.ps[0].as<float>(), &S->beta, 0,
                                              c.p[1].as<float>(), c.ps[1].as<float>(),
                                              c.part_a.as<Pair>(), &S->status, g_stream,
                                              StepLink{});
-            case 8: return stencil_pair_update(L.g2f, L.g2f.ty, c.p[1].as<float>(),
+            case 8: return stencil_pair_update<float>(L.g2f, L.g2f.ty, c.p[1].as<float>(),
                                                c.ps[1].as<float>(), xv, r, rs,
                                                c.part_b.as<Pair>(), &S->status, &S->alpha,
                                                g_stream, StepLink{});

@@ -101,17 +101,19 @@ hipError_t stencil_pair_direction_x(const Geom &g, int ty, const float *r, const
                                    float *p_new, float *ps_new, float *q, float *qs,
                                    Pair *partials, const int *status, double *x,
                                    const double *alpha_dev, hipStream_t st, StepLink link);
-// The recomputing form of a Bi-CG iteration (FP32 vectors, 3D): sweep A marches p only
+// The recomputing form of a Bi-CG iteration (3D): sweep A marches p only
 // (p_new, p*_new, partial of sigma = p*_new . A p_new); sweep B marches the stored p_new,
 // p*_new again for q, q* and applies x += alpha p, r -= alpha q, r* -= alpha q* with the
 // partials of r*.r and r.r (two values per workgroup, the layout of bicg_update's).
-hipError_t stencil_dir_sigma(const Geom &g, int ty, const float *r, const float *rs,
-                             const float *p_old, const float *ps_old, const double *beta_dev,
-                             int first, float *p_new, float *ps_new, Pair *partials,
-                             const int *status, hipStream_t st, StepLink link);
-hipError_t stencil_pair_update(const Geom &g, int ty, const float *p, const float *ps, double *x,
-                               float *r, float *rs, Pair *partials, const int *status,
-                               const double *alpha_dev, hipStream_t st, StepLink link);
+template <typename T>
+hipError_t stencil_dir_sigma(const Geom &g, int ty, const T *r, const T *rs, const T *p_old,
+                             const T *ps_old, const double *beta_dev, int first, T *p_new,
+                             T *ps_new, Pair *partials, const int *status, hipStream_t st,
+                             StepLink link);
+template <typename T>
+hipError_t stencil_pair_update(const Geom &g, int ty, const T *p, const T *ps, double *x, T *r,
+                               T *rs, Pair *partials, const int *status, const double *alpha_dev,
+                               hipStream_t st, StepLink link);
 hipError_t stencil_pair_direction_m(const Geom &g, int ty, const double *r, const double *rs,
                                    const double *p_old, const double *ps_old, const double *d,
                                    const double *beta_dev, int first, double *p_new,

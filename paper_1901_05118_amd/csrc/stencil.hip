@@ -180,12 +180,13 @@ hipError_t stencil_pair_direction_x(const Geom &g, int ty, const float *r, const
 }
 
 // The recomputing form's two sweeps (3D grids; see OutDirSigma and OutPairUpdate).
-hipError_t stencil_dir_sigma(const Geom &g, int ty, const float *r, const float *rs,
-                             const float *p_old, const float *ps_old, const double *beta_dev,
-                             int first, float *p_new, float *ps_new, Pair *partials,
-                             const int *status, hipStream_t st, StepLink link) {
+template <typename T>
+hipError_t stencil_dir_sigma(const Geom &g, int ty, const T *r, const T *rs, const T *p_old,
+                             const T *ps_old, const double *beta_dev, int first, T *p_new,
+                             T *ps_new, Pair *partials, const int *status, hipStream_t st,
+                             StepLink link) {
     if (g.dim != 3) return hipErrorInvalidValue;
-    InDirection<float> in;
+    InDirection<T> in;
     in.link = link;
     in.r[0] = r;
     in.r[1] = r;
@@ -194,7 +195,7 @@ hipError_t stencil_dir_sigma(const Geom &g, int ty, const float *r, const float 
     in.beta_dev = beta_dev;
     in.first = first;
     in.beta = 0.0;
-    OutDirSigma<float> out;
+    OutDirSigma<T> out;
     out.p_new = p_new;
     out.ps_new = ps_new;
     out.rs = rs;
@@ -204,22 +205,23 @@ hipError_t stencil_dir_sigma(const Geom &g, int ty, const float *r, const float 
     out.beta = 0.0;
     out.first = first;
     out.acc = Pair{0.0, 0.0};
-    EXCMG_DISPATCH_TY(ty, return (launch3d<TY, float, InDirection<float>, OutDirSigma<float>, 1>(
-                              g, in, out, st)));
+    EXCMG_DISPATCH_TY(ty, return (launch3d<TY, T, InDirection<T>, OutDirSigma<T>, 1>(g, in, out,
+                                                                                    st)));
     return hipSuccess;
 }
 
-hipError_t stencil_pair_update(const Geom &g, int ty, const float *p, const float *ps, double *x,
-                               float *r, float *rs, Pair *partials, const int *status,
-                               const double *alpha_dev, hipStream_t st, StepLink link) {
+template <typename T>
+hipError_t stencil_pair_update(const Geom &g, int ty, const T *p, const T *ps, double *x, T *r,
+                               T *rs, Pair *partials, const int *status, const double *alpha_dev,
+                               hipStream_t st, StepLink link) {
     if (g.dim != 3) return hipErrorInvalidValue;
-    InPlainAlpha<float> in;
+    InPlainAlpha<T> in;
     in.x[0] = p;
     in.x[1] = ps;
     in.alpha_dev = alpha_dev;
     in.link = link;
     in.alpha = 0.0;
-    OutPairUpdate<float> out;
+    OutPairUpdate<T> out;
     out.x = x;
     out.r = r;
     out.rs = rs;
@@ -228,10 +230,25 @@ hipError_t stencil_pair_update(const Geom &g, int ty, const float *p, const floa
     out.alpha = 0.0;
     out.acc[0] = Pair{0.0, 0.0};
     out.acc[1] = Pair{0.0, 0.0};
-    EXCMG_DISPATCH_TY(ty, return (launch3d<TY, float, InPlainAlpha<float>, OutPairUpdate<float>, 2>(
-                              g, in, out, st)));
+    EXCMG_DISPATCH_TY(ty, return (launch3d<TY, T, InPlainAlpha<T>, OutPairUpdate<T>, 2>(g, in, out,
+                                                                                       st)));
     return hipSuccess;
 }
+template hipError_t stencil_dir_sigma<float>(const Geom &, int, const float *, const float *,
+                                             const float *, const float *, const double *, int,
+                                             float *, float *, Pair *, const int *, hipStream_t,
+                                             StepLink);
+template hipError_t stencil_dir_sigma<double>(const Geom &, int, const double *, const double *,
+                                              const double *, const double *, const double *,
+                                              int, double *, double *, Pair *, const int *,
+                                              hipStream_t, StepLink);
+template hipError_t stencil_pair_update<float>(const Geom &, int, const float *, const float *,
+                                               double *, float *, float *, Pair *, const int *,
+                                               const double *, hipStream_t, StepLink);
+template hipError_t stencil_pair_update<double>(const Geom &, int, const double *,
+                                                const double *, double *, double *, double *,
+                                                Pair *, const int *, const double *, hipStream_t,
+                                                StepLink);
 
 hipError_t stencil_pair_direction_m(const Geom &g, int ty, const double *r, const double *rs,
                                    const double *p_old, const double *ps_old, const double *d,

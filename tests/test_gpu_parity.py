@@ -202,6 +202,27 @@ def test_config1_solve(ex):
     assert [l["iterations"] for l in st.levels()[2:]] == [lv.iters for lv in ref.levels]
 
 
+@pytest.mark.parametrize("bc", [1, 2])
+def test_recomputing_form_fp64_matches_oracle(ex, bc):
+    """FP64 Bi-CG in the recomputing form on every level (recompute_min_unknowns = 1): q and
+    q* formed again in the update sweep, rho and r.r summed per tile.  The cascade equals
+    the stored form's bit for bit and the oracle's counts and solution (1e-10)."""
+    N, nl = 48, 5
+    arr = make_arrays(config_problem(2), N, bc)
+    f, g1, g2 = dev(arr.f), dev(arr.g1), dev(arr.g2)
+    outs = []
+    for m in (1 << 30, 1):
+        u = torch.empty_like(f)
+        rc, st = ex.solve_ex(N, nl, bc, f, g1, g2, 1e-9, u, recompute_min_unknowns=m)
+        assert rc == ex.OK, ex.last_error()
+        outs.append((host(u), [l["iterations"] for l in st.levels()]))
+    assert outs[0][1] == outs[1][1]
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    ref = O.excmg(N, nl, bc, arr.f, arr.g1, arr.g2, 1e-9)
+    assert outs[1][1][2:] == [lv.iters for lv in ref.levels]
+    assert rel_l2(outs[1][0], ref.u.ravel()) <= 1e-10
+
+
 @pytest.mark.parametrize("k", [2, 3])
 def test_paper_problem_32cube(ex, k, golden_tables):
     """The cascade reproduces Table 2/3's 32^3 error columns (8^3 and 16^3 direct)."""
