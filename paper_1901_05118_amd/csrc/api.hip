@@ -462,7 +462,9 @@ RunVariant g_var;
 // Bi-CG on large 3D grids (plain Algorithm 2, folded finalisations, an FP64 iterate) takes
 // the recomputing form: its update sweep marches p and p* again for q and q* instead of
 // reading them back (mixed: 64 instead of 72 bytes per unknown and iteration; FP64: 112
-// instead of 136).  Smaller grids keep the stored form (mixed: x's update deferred to the
+// instead of 136).  The CG specialisation keeps the stored form: its streaming update sweep
+// is cheap, and a second march cost more than the 16 bytes it saves (measured at 512^3:
+// FP64 CG 704 -> 807 ms, mixed 480 -> 477 ms).  Smaller grids keep the stored form (mixed: x's update deferred to the
 // next sweep A from 2^17 unknowns up): there a second march per iteration costs more
 // latency than the bytes it saves (measured, mixed: 128^3 level 81.9 ms stored, 88.0 ms
 // recomputing; 256^3: 532.0 and 513.7 ms; FP64 256^3: 874.7 and 843.9 ms).
@@ -498,13 +500,17 @@ void release_graphs() {
     g_graph_cache.clear();
 }
 
-// The four launches of iteration j of a run: sweep A (direction update + products + sigma),
-// alpha, sweep B (updates + rho, r.r), beta.  ev >= 0 brackets the sweeps with timing events.
+// The launches of iteration j of a run: sweep A (direction update + products + sigma),
+// alpha, sweep B (updates + rho, r.r), beta; with folded finalisations (the default) alpha
+// and beta are merged by the sweeps themselves, so two launches.  Forms: the recomputing
+// one on large 3D grids (recompute_q: sweep A stores p, p* only, sweep B forms q, q* again),
+// else the stored one (q, q* written by sweep A, read by sweep B).  ev >= 0 brackets the
+// sweeps with timing events.
+// defer (stored form): 0 = sweep B updates x; 1 = x's update is left to the next sweep A
+// (deferred), this sweep A has none pending (first launch of a run or of a resumed run);
+// 2 = deferred, and this sweep A applies the pending update of iteration j-1.  Deferral:
+// FP32 vectors, FP64 iterate, Bi-CG with folded finalisations and no options.
 template <typename TX, typename T>
-// defer: 0 = sweep B updates x; 1 = x's update is left to the next sweep A (deferred), this
-// sweep A has none pending (first launch of a run or of a resumed run); 2 = deferred, and
-// this sweep A applies the pending update of iteration j-1.  Deferral: FP32 vectors, FP64
-// iterate, Bi-CG with folded finalisations and no options.
 int launch_iteration(const Level &L, TX *x, long long j, int ev, hipStream_t st, int defer = 0) {
     Ctx &c = g_ctx;
     BicgState *S = c.state.as<BicgState>();

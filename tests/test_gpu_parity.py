@@ -484,21 +484,25 @@ def test_event_timed_solve_equals_the_graph_solve(ex):
     assert n_a + n_x == n_b == its[1][-1][0]
     assert n_x > n_a > 0 and ms_x > 0 and ms_b > 0
 
+@pytest.mark.parametrize("form", ["stored", "recomputing"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed-restart"])
 @pytest.mark.parametrize("case", [(32, 4, 1, 1), (48, 5, 2, 2)])
-def test_cg_specialisation_is_bit_identical_to_bicg(ex, prec, case):
+def test_cg_specialisation_is_bit_identical_to_bicg(ex, prec, case, form):
     """With A_h = A_h^T and r*_0 = r_0 the shadow vectors of Algorithm 2 equal the primal
-    ones, so the CG form (one operator product per iteration) reproduces Bi-CG exactly."""
+    ones, so the CG form (one operator product per iteration) reproduces Bi-CG exactly; also
+    when Bi-CG takes the recomputing form (forced on every level here; CG keeps the stored
+    one)."""
     N, nl, bc, c = case
     p = ex.FP64 if prec == "fp64" else ex.MIXED
     mode = ex.RESTART if prec == "mixed-restart" else ex.RELIABLE
+    rq = 1 if form == "recomputing" else 1 << 30
     arr = make_arrays(config_problem(c), N, bc)
     f, g1, g2 = dev(arr.f), dev(arr.g1), dev(arr.g2)
     u_b, u_c = torch.empty_like(f), torch.empty_like(f)
     rc1, st1 = ex.solve_ex(N, nl, bc, f, g1, g2, 1e-9, u_b, precision=p, method=ex.BICG,
-                           refine=mode, fp32_min_unknowns=1)
+                           refine=mode, fp32_min_unknowns=1, recompute_min_unknowns=rq)
     rc2, st2 = ex.solve_ex(N, nl, bc, f, g1, g2, 1e-9, u_c, precision=p, method=ex.CG,
-                           refine=mode, fp32_min_unknowns=1)
+                           refine=mode, fp32_min_unknowns=1, recompute_min_unknowns=rq)
     assert rc1 == rc2 == ex.OK
     assert [l["iterations"] for l in st1.levels()] == [l["iterations"] for l in st2.levels()]
     np.testing.assert_array_equal(host(u_b), host(u_c))
