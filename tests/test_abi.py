@@ -68,3 +68,38 @@ def test_binding_rejects_wrong_arrays():
         mod._ptr(np.zeros(4, dtype=np.float32))
     with pytest.raises(ValueError):
         mod._ptr(np.zeros(4), count=5)
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes mirrors of excmg_opts, excmg_level_stats, excmg_stats and excmg_problem
+    have the header's sizes and field offsets (a C program compiled against excmg.h prints
+    them)."""
+    import shutil
+    import subprocess
+
+    from paper_1901_05118_amd import excmg as ex
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    structs = {"excmg_opts": ex.Opts, "excmg_level_stats": ex.LevelStats,
+               "excmg_stats": ex.Stats, "excmg_problem": ex.Problem}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "excmg.h"',
+             "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'    printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in py._fields_:
+            lines.append(f'    printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe),
+                    str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for line in out.splitlines():
+        cname, field, val = line.split()
+        got[(cname, field)] = int(val)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for field, _ in py._fields_:
+            assert got[(cname, field)] == getattr(py, field).offset, (cname, field)
