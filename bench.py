@@ -50,12 +50,13 @@ def sweep_launch(N, ty, zc, form):
     n = N - 1
     tiles = -(-n // 64) * -(-n // ty) * -(-n // zc)
     tiles = -(-tiles // 8) * 8  # the grid is padded to whole XCD shares
-    name = {"fp64": "zmarch<2, {ty}, double, InDirection<double>, OutPairApply<double> >",
-            "deferred": "zmarch<2, {ty}, float, InDirection<float>, OutPairApplyX<float> >",
-            "sigma": "zmarch<1, {ty}, float, InDirection<float>, OutDirSigma<float> >",
-            "update": "zmarch<2, {ty}, float, InPlainAlpha<float>, OutPairUpdate<float> >",
-            "sigma64": "zmarch<1, {ty}, double, InDirection<double>, OutDirSigma<double> >",
-            "update64": "zmarch<2, {ty}, double, InPlainAlpha<double>, OutPairUpdate<double> >"}[form]
+    # the last template argument: planes in flight
+    name = {"fp64": "zmarch<2, {ty}, double, InDirection<double>, OutPairApply<double>, 2>",
+            "deferred": "zmarch<2, {ty}, float, InDirection<float>, OutPairApplyX<float>, 2>",
+            "sigma": "zmarch<1, {ty}, float, InDirection<float>, OutDirSigma<float>, 3>",
+            "update": "zmarch<2, {ty}, float, InPlainAlpha<float>, OutPairUpdate<float>, 2>",
+            "sigma64": "zmarch<1, {ty}, double, InDirection<double>, OutDirSigma<double>, 2>",
+            "update64": "zmarch<2, {ty}, double, InPlainAlpha<double>, OutPairUpdate<double>, 2>"}[form]
     return name.format(ty=ty), tiles * 64 * ty
 
 

@@ -42,13 +42,19 @@ static hipError_t launch(const Geom &g, const In &in, const Out &out, hipStream_
     return hipGetLastError();
 }
 
-// Launcher of epilogues that exist for 3D grids only.
-template <int TY, typename T, class In, class Out, int NA>
+// Launcher of epilogues that exist for 3D grids only (D: planes in flight).
+template <int TY, typename T, class In, class Out, int NA, int D = 2>
 static hipError_t launch3d(const Geom &g, const In &in, const Out &out, hipStream_t st) {
-    hipLaunchKernelGGL((zmarch<NA, TY, T, In, Out>), dim3(xcd_grid(g.ntiles)), dim3(kWave, TY), 0,
-                       st, g, in, out);
+    hipLaunchKernelGGL((zmarch<NA, TY, T, In, Out, D>), dim3(xcd_grid(g.ntiles)), dim3(kWave, TY),
+                       0, st, g, in, out);
     return hipGetLastError();
 }
+
+// Planes in flight of the recomputing form's sweep A (one marched array, registers to spare):
+// three for FP32 vectors (measured at 512^3: 752 us with two, 733 us with three; four
+// spill), two for FP64 (three would take 161 registers and drop occupancy).
+template <typename T>
+constexpr int kSigmaDepth = sizeof(T) == 4 ? 3 : 2;
 
 #define EXCMG_DISPATCH_TY(TYV, ...)                                                          \
     switch (TYV) {                                                                           \
@@ -205,8 +211,8 @@ hipError_t stencil_dir_sigma(const Geom &g, int ty, const T *r, const T *rs, con
     out.beta = 0.0;
     out.first = first;
     out.acc = Pair{0.0, 0.0};
-    EXCMG_DISPATCH_TY(ty, return (launch3d<TY, T, InDirection<T>, OutDirSigma<T>, 1>(g, in, out,
-                                                                                    st)));
+    EXCMG_DISPATCH_TY(ty, return (launch3d<TY, T, InDirection<T>, OutDirSigma<T>, 1, kSigmaDepth<T>>(
+                              g, in, out, st)));
     return hipSuccess;
 }
 

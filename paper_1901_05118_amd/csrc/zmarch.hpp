@@ -249,7 +249,7 @@ struct NoBegin {
 // partials of the previous sweep); it is called after the first planes have been requested,
 // so that their loads and the scalars' merge overlap.  Returns false (nothing written) when
 // begin() ends the run.
-template <int NA, int TY, typename T, class In, class Out, class Begin = NoBegin>
+template <int NA, int TY, typename T, class In, class Out, class Begin = NoBegin, int D = 2>
 __device__ __forceinline__ bool zmarch_tile(const Geom &g, int tile, const In &in, Out &out,
                                             Begin begin = Begin{}) {
     constexpr int TX = kWave;
@@ -325,9 +325,8 @@ __device__ __forceinline__ bool zmarch_tile(const Geom &g, int tile, const In &i
 #pragma unroll
     for (int a = 0; a < NA; a++) column_init(col[a]);
 
-    // Planes mbeg..mend are staged; D planes are in flight in registers at any time (measured:
-    // deeper pipelines cost more occupancy than they hide, for FP32 vectors too).
-    constexpr int D = 2;
+    // Planes mbeg..mend are staged; D planes are in flight in registers at any time (measured
+    // on the two-array sweeps: deeper pipelines cost more occupancy than they hide).
     const int mbeg = k0 - 2, mend = k1 + 1;
     Raw raw[D], raw0;
     float mz[D], mz0;
@@ -342,9 +341,9 @@ __device__ __forceinline__ bool zmarch_tile(const Geom &g, int tile, const In &i
     const int col_off = iy * g.ld + ix;  // in-plane offset of this lane's column (< 2^31)
     constexpr bool kPre = HasPre<Out>::value;
     using PreT = typename PreOf<Out>::type;
-    PreT pre[D];             // per-output data of planes m-2 (slot m % D), requested at plane m
+    PreT pre1{}, pre2{};     // per-output data requested at planes m-1 and m-2
     // consume plane m from LDS, stage plane m+1 from `r`, refill `r` with plane m+1+D
-    auto body = [&](int m, Raw &r, float &z, PreT &pm) {
+    auto body = [&](int m, Raw &r, float &z) {
         double y[NA], c0[NA], cprev[NA];
 #pragma unroll
         for (int a = 0; a < NA; a++) {
@@ -355,11 +354,12 @@ __device__ __forceinline__ bool zmarch_tile(const Geom &g, int tile, const In &i
             if (m >= k0 && m < k1) out.centre((i64)m * plane + col_off, c0);
             const int k = m - 2;
             if (k >= k0 && k < k1) {
-                if constexpr (kPre) out.emit((i64)k * plane + col_off, y, cprev, pm);
+                if constexpr (kPre) out.emit((i64)k * plane + col_off, y, cprev, pre2);
                 else out.emit((i64)k * plane + col_off, y, cprev);
             }
             if constexpr (kPre) {
-                if (m >= k0 && m < k1) pm = out.pre((i64)m * plane + col_off);
+                pre2 = pre1;
+                if (m >= k0 && m < k1) pre1 = out.pre((i64)m * plane + col_off);
             }
         }
         stash(cur ^ 1, r, z);
@@ -371,7 +371,7 @@ __device__ __forceinline__ bool zmarch_tile(const Geom &g, int tile, const In &i
 #pragma unroll
         for (int k = 0; k < D; k++) {
             if (m + k > mend) break;
-            body(m + k, raw[k], mz[k], pre[k]);
+            body(m + k, raw[k], mz[k]);
         }
     }
     return true;
@@ -393,8 +393,9 @@ __device__ __forceinline__ void zmarch_tile_outputs(const Geom &g, int tile, Out
     for (int k = k0; k < k1; k++) out.finish_output((i64)k * plane + col);
 }
 
-// One workgroup per tile (XCD-aware order), then the epilogue's block-level reduction.
-template <int NA, int TY, typename T, class In, class Out>
+// One workgroup per tile (XCD-aware order), then the epilogue's block-level reduction.  D:
+// planes in flight.
+template <int NA, int TY, typename T, class In, class Out, int D = 2>
 __global__ void __launch_bounds__(kWave *TY) zmarch(Geom g, In in_arg, Out out) {
     __shared__ Pair red[4 * TY];
     __shared__ int s_skip;
@@ -422,7 +423,9 @@ __global__ void __launch_bounds__(kWave *TY) zmarch(Geom g, In in_arg, Out out) 
         return run;
     };
     const int tile = xcd_tile(blockIdx.x, g.ntiles);
-    const bool go = tile < g.ntiles ? zmarch_tile<NA, TY, T>(g, tile, in, out, start) : start();
+    const bool go = tile < g.ntiles
+                        ? zmarch_tile<NA, TY, T, In, Out, decltype(start), D>(g, tile, in, out, start)
+                        : start();
     if (!go) {
         if constexpr (HasGate<Out>::value) {
             if (stops && tile < g.ntiles) zmarch_tile_outputs<TY>(g, tile, out);
