@@ -55,7 +55,7 @@ def sweep_launch(N, ty, zc, form):
             "deferred": "zmarch<2, {ty}, float, InDirection<float>, OutPairApplyX<float>, 2>",
             "sigma": "zmarch<1, {ty}, float, InDirection<float>, OutDirSigma<float>, 3>",
             "update": "zmarch<2, {ty}, float, InPlainAlpha<float>, OutPairUpdate<float>, 2>",
-            "sigma64": "zmarch<1, {ty}, double, InDirection<double>, OutDirSigma<double>, 2>",
+            "sigma64": "zmarch<1, {ty}, double, InDirection<double>, OutDirSigma<double>, 3>",
             "update64": "zmarch<2, {ty}, double, InPlainAlpha<double>, OutPairUpdate<double>, 2>"}[form]
     return name.format(ty=ty), tiles * 64 * ty
 

@@ -51,10 +51,10 @@ static hipError_t launch3d(const Geom &g, const In &in, const Out &out, hipStrea
 }
 
 // Planes in flight of the recomputing form's sweep A (one marched array, registers to spare):
-// three for FP32 vectors (measured at 512^3: 752 us with two, 733 us with three; four
-// spill), two for FP64 (three would take 161 registers and drop occupancy).
+// three (measured, FP32 at 512^3: 752 us with two, 733 us with three, four spill; FP64 at
+// 256^3: 166 and 157 us, although three take 161 registers and lower the occupancy).
 template <typename T>
-constexpr int kSigmaDepth = sizeof(T) == 4 ? 3 : 2;
+constexpr int kSigmaDepth = 3;
 
 #define EXCMG_DISPATCH_TY(TYV, ...)                                                          \
     switch (TYV) {                                                                           \
