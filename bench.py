@@ -131,6 +131,47 @@ def plane_leg(ex, torch, np, steps):
     return res
 
 
+def configs_leg(ex, torch, np, steps):
+    """The smaller configurations of the same family: 32^3 cells, first kind, FP64 to 1e-10
+    (4 levels); 128^3, second kind, FP64 to 1e-10 (6 levels); 256^3, first kind, mixed and
+    FP64 to 1e-8 (7 levels).  Time to solution, Bi-CG GLUPS, the max-norm error against the
+    exact solution and, for the mixed solve, against the FP64 one."""
+    from manufactured import config_problem, make_arrays
+    res = {}
+    for c, N, nl, bc, tol, precs in ((1, 32, 4, 1, 1e-10, ("fp64",)),
+                                      (2, 128, 6, 2, 1e-10, ("fp64",)),
+                                      (3, 256, 7, 1, 1e-8, ("fp64", "mixed"))):
+        arr = make_arrays(config_problem(c), N, bc)
+        f, g1, g2 = (torch.from_numpy(a).cuda() for a in (arr.f, arr.g1, arr.g2))
+        u = torch.empty_like(f)
+        entry = {"workload": f"EXCMG {N}^3 cells, bc kind {bc}, seeded family {c}, tol {tol:g}"}
+        sols = {}
+        for name in precs:
+            prec = ex.FP64 if name == "fp64" else ex.MIXED
+            ex.solve_ex(N, nl, bc, f, g1, g2, tol, u, precision=prec)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                rc, st = ex.solve_ex(N, nl, bc, f, g1, g2, tol, u, precision=prec)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / steps
+            if rc != ex.OK:
+                raise RuntimeError(f"config {c} {name} solve failed: {rc} {ex.last_error()}")
+            lv = st.levels()
+            lups = sum(((l["n"] - 1) ** 3) * l["iterations"] for l in lv)
+            ug = u.view(N + 1, N + 1, N + 1).cpu().numpy()
+            sols[name] = ug
+            entry[name] = {"ms": round(ms, 2), "glups": round(lups / (ms * 1e-3) / 1e9, 3),
+                           "iterations": [l["iterations"] for l in lv],
+                           "max_err_vs_exact": float(np.abs(ug - arr.u).max())}
+        if "mixed" in sols:
+            entry["mixed_vs_fp64_max"] = float(np.abs(sols["mixed"] - sols["fp64"]).max())
+        log(f"config {c}: {entry}")
+        res[f"config{c}"] = entry
+        del f, g1, g2, u
+    return res
+
+
 def jacobi_leg(ex, torch, np, N, nl, bc, tol, f, g1, g2, u, steps):
     """Algorithm 2 with the Jacobi preconditioner M = diag(A_h) on the same 3D workload."""
     ex.solve_ex(N, nl, bc, f, g1, g2, tol, u, precond=ex.PRECOND_JACOBI)
@@ -203,6 +244,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch leg")
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D (4096^2) leg")
     ap.add_argument("--no-jacobi", action="store_true", help="skip the Jacobi-preconditioned leg")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the smaller configurations (32^3, 128^3, 256^3)")
     ap.add_argument("--only-2d", action="store_true",
                     help="run the 2D (4096^2) leg alone (for profiling it); its line reports "
                          "the 2D mixed solve")
@@ -343,6 +386,8 @@ def main():
     ex.set_timing(False)
     avg_a, avg_b = ms_a / max(n_a, 1), ms_b / max(n_b, 1)
     ms_c, bytes_c = ex.profile_sweep(4, ex.FP64, reps=10)
+    # the stencil alone: y = A x on the finest level (FP64, 16 bytes per unknown)
+    ms_s, bytes_s = ex.profile_sweep(0, ex.FP64, reps=10)
     ty_s, zc_s = ex.get_shape(N, 2 if gate else 1)
     sweeps = {"A": {"launches": n_a, "ms_per_launch": round(avg_a, 4),
                     "bytes_per_launch": bytes_a,
@@ -371,6 +416,10 @@ def main():
                               "gbs": round((bytes_a + bytes_b) / ((avg_a + avg_b) * 1e-3) / 1e9, 1),
                               "frac": round((bytes_a + bytes_b) / ((avg_a + avg_b) * 1e-3) / 1e9
                                             / HBM_PEAK_GBS, 4)},
+                "stencil_apply": {"ms_per_launch": round(ms_s, 4),
+                                  "glups": round(nu / (ms_s * 1e-3) / 1e9, 1),
+                                  "gbs": round(bytes_s / (ms_s * 1e-3) / 1e9, 1),
+                                  "frac": round(bytes_s / (ms_s * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
                 "copy_gbs": round(bytes_c / (ms_c * 1e-3) / 1e9, 1)}
 
     out = {
@@ -405,6 +454,8 @@ def main():
         out["batch"] = batch_leg(ex, torch, np)
     if not args.no_2d:
         out["plane_2d"] = plane_leg(ex, torch, np, args.steps)
+    if not args.no_configs:
+        out["configs"] = configs_leg(ex, torch, np, args.steps)
     if not args.no_cpu:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(arr, N, nl, bc, args.cpu_iters)
