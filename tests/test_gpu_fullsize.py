@@ -2,7 +2,7 @@
 launch shapes): the operator element by element, the first Bi-CG iterations of the finest
 level bit for bit against the oracle, and the benchmark's solves through properties that
 hold at any size (the oracle's FP64 residual of the returned solution, the discretisation
-error against the exact solution)."""
+error against the exact solution).  The 256^3 first-kind case is solved at its full size too."""
 import numpy as np
 import pytest
 
@@ -83,6 +83,32 @@ def test_benchmark_solves_meet_tolerance(ex, problem):
         assert np.sqrt(O.dot(r, r) / O.dot(b, b)) <= 1e-8
         errs[name] = O.norm2(ug - arr.u)
     assert abs(errs["mixed"] - errs["fp64"]) <= 0.01 * errs["fp64"]
+
+
+def test_first_kind_256_mixed_against_fp64(ex):
+    """256^3 cells, first kind, the seeded four-mode family, tol 1e-8, 7 levels: both solves
+    leave an FP64 residual (the oracle's) within the tolerance; the mixed solution is within
+    1% of the FP64 solution's max-norm error against the exact u, and so is its distance from
+    the FP64 solution."""
+    n, nl, bc = 256, 7, 1
+    print("generating the 256^3 first-kind problem", flush=True)
+    arr = make_arrays(config_problem(3), n, bc)
+    b = O.rhs(n, bc, arr.f, arr.g1, arr.g2)
+    f, g1, g2 = dev(arr.f), dev(arr.g1), dev(arr.g2)
+    sols, errs = {}, {}
+    for name, p in (("fp64", ex.FP64), ("mixed", ex.MIXED)):
+        print(f"solve 256^3 first kind {name}", flush=True)
+        u = torch.empty_like(f)
+        rc, st = ex.solve_ex(n, nl, bc, f, g1, g2, 1e-8, u, precision=p)
+        assert rc == ex.OK, ex.last_error()
+        ug = host(u).reshape((n + 1,) * 3)
+        del u
+        r = O.residual(n, bc, b, O.interior(ug))
+        assert np.sqrt(O.dot(r, r) / O.dot(b, b)) <= 1e-8
+        sols[name] = ug
+        errs[name] = float(np.abs(ug - arr.u).max())
+    assert abs(errs["mixed"] - errs["fp64"]) <= 0.01 * errs["fp64"]
+    assert float(np.abs(sols["mixed"] - sols["fp64"]).max()) <= 0.01 * errs["fp64"]
 
 
 def test_mixed_bicg_equals_cg_at_full_size(ex, problem):
