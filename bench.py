@@ -438,6 +438,11 @@ def main():
         "iterations": {"fp64": [lv["iterations"] for lv in r64["levels"]],
                        "mixed": [lv["iterations"] for lv in r32["levels"]],
                        "mixed_restarted_refinement": [lv["iterations"] for lv in r32r["levels"]]},
+        # the paper's cost measure (Sec. 6): iterations on each level weighted by 8^-(levels
+        # below the finest), in finest-grid sweeps
+        "work_units": {k: round(sum(lv["iterations"] * 8.0 ** -(len(r["levels"]) - 1 - i)
+                                    for i, lv in enumerate(r["levels"])), 2)
+                       for k, r in (("fp64", r64), ("mixed", r32))},
         "runs": {"fp64": [lv["runs"] for lv in r64["levels"]],
                  "mixed": [lv["runs"] for lv in r32["levels"]]},
         "error_vs_exact": {"fp64_u_rms": e64, "mixed_u_rms": e32,
