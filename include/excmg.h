@@ -303,9 +303,10 @@ int excmg_solve_batch(int nprob, const excmg_problem *probs, const excmg_opts *o
 /* Autotuner: time the z-marched kernel of `kind` (0: one-array operator, 1: Bi-CG sweep A)
  * on a grid of n cells for every tile height and z-chunk length it supports, in FP64 or
  * FP32 (precision), `reps` launches each on scratch vectors, and record the fastest shape
- * for later launches (as excmg_set_shape; sweep A in FP32 is stored as kind 2).  Outputs (may
- * be NULL): the chosen shape and its
- * mean ms per launch. */
+ * for later launches (as excmg_set_shape; sweep A in FP32 is stored as kind 2).  On grids of
+ * 2^22 unknowns and up, where Bi-CG forms q and q* again in its update sweep (which takes
+ * sweep A's launch shape), kind 1 times that pair of sweeps together.  Outputs (may be
+ * NULL): the chosen shape and its mean ms per launch (per pair of launches for the pair). */
 int excmg_autotune(int n, int kind, int precision, int reps, int *ty, int *zc, double *ms);
 
 /* Description of the last error (empty string if none). */

@@ -231,14 +231,16 @@ Geom choose_shape(int N, int bc, int kind) {
     // kind {operator/residual, FP64 sweep A, FP32 sweep A}: {ty, zc}.  Grids up to 64^3 are
     // launch-latency bound and want the most workgroups; larger grids want long z-marches.
     // FP32 sweep A: timed in the form mixed solves run on these grids (with the deferred
-    // update of the iterate; 128^3: 27.5 us at {8, 8} against 29.3 us at {8, 16}).
+    // update of the iterate; 128^3: 27.5 us at {8, 8} against 29.3 us at {8, 16}; from 256^3
+    // the recomputing pair of sweeps).  From 512^3 one march through the whole depth (511
+    // planes) gives exactly one 64x16 tile per CU: the pair 1.91 -> 1.75 ms per iteration.
     static const int kTuned[6][3][2] = {
         {{4, 4}, {4, 2}, {4, 2}},          // N < 48 (16^3, 32^3: 5.4 -> 5.0, 16.0 -> 14.7 ms)
         {{4, 4}, {4, 4}, {4, 4}},          // 48 <= N < 96
         {{4, 8}, {8, 16}, {4, 8}},         // 96 <= N < 128
         {{16, 8}, {8, 16}, {8, 8}},        // 128 <= N < 256
         {{8, 32}, {8, 128}, {16, 64}},     // 256 <= N < 512
-        {{8, 128}, {8, 128}, {16, 64}},    // N >= 512
+        {{8, 128}, {8, 128}, {16, 512}},   // N >= 512
     };
     const int band = N < 48 ? 0 : N < 96 ? 1 : N < 128 ? 2 : N < 256 ? 3 : N < 512 ? 4 : 5;
     const int ty = kTuned[band][kind][0];
@@ -2074,10 +2076,18 @@ int excmg_autotune(int n, int kind, int precision, int reps, int *ty_out, int *z
     const size_t es = precision == EXCMG_FP64 ? 8 : 4;
     const int ld = nn;  // contiguous rows, the solver's default
     const long long nv = (long long)nn * nn * ld;
-    DBuf v[8], part, stb;
+    // on grids where Bi-CG takes the recomputing form, sweep A is timed with the sweep B it
+    // shares its launch shape with (the pair the solver runs; x is FP64 in both precisions)
+    const bool rq = kind == 1 && (long long)nn * nn * nn >= kRecomputeMin && g_fold && !g_var.d &&
+                    !g_var.xs;
+    DBuf v[8], part, stb, xd;
     for (auto &b : v) {
         CKR(b.ensure((size_t)nv * es));
         CKH(hipMemsetAsync(b.p, 0, (size_t)nv * es, g_stream));
+    }
+    if (rq) {
+        CKR(xd.ensure((size_t)nv * 8));
+        CKH(hipMemsetAsync(xd.p, 0, (size_t)nv * 8, g_stream));
     }
     CKR(stb.ensure(sizeof(BicgState)));
     BicgState hs{};
@@ -2095,15 +2105,39 @@ int excmg_autotune(int n, int kind, int precision, int reps, int *ty_out, int *z
     CKH(hipEventCreate(&e1));
     int rc = EXCMG_OK;
     for (int ty : tys) {
-        for (int zc = 2; zc <= 512; zc *= 2) {
-            if (zc > nn && zc != 2) break;
-            Geom g = with_rows(make_geom(nn, 1, ty, std::min(zc, nn)), ld);
-            rc = part.ensure((size_t)stencil_blocks(g) * sizeof(Pair));
+        // chunks of 2, 4, ... planes and, last, the whole depth in one march
+        for (int zp = 2;; zp *= 2) {
+            const int zc = std::min(zp, nn);
+            Geom g = with_rows(make_geom(nn, 1, ty, zc), ld);
+            rc = part.ensure((size_t)stencil_blocks(g) * sizeof(Pair) * (rq ? 2 : 1));
             if (rc) break;
             auto launch = [&]() -> hipError_t {
                 if (kind == 0) {
                     if (es == 8) return stencil_apply<double>(g, ty, v[0].as<double>(), v[1].as<double>(), g_stream);
                     return stencil_apply<float>(g, ty, v[0].as<float>(), v[1].as<float>(), g_stream);
+                }
+                if (rq) {
+                    // r, r*, p, p* -> p_new, p*_new (sigma); then p_new, p*_new -> x, r, r*
+                    const StepLink nl{};
+                    hipError_t e;
+                    if (es == 8) {
+                        e = stencil_dir_sigma<double>(g, ty, v[0].as<double>(), v[1].as<double>(),
+                                                      v[2].as<double>(), v[3].as<double>(), &S->beta, 0,
+                                                      v[4].as<double>(), v[5].as<double>(), part.as<Pair>(),
+                                                      &S->status, g_stream, nl);
+                        if (e != hipSuccess) return e;
+                        return stencil_pair_update<double>(g, ty, v[4].as<double>(), v[5].as<double>(),
+                                                           xd.as<double>(), v[0].as<double>(),
+                                                           v[1].as<double>(), part.as<Pair>(), &S->status,
+                                                           &S->alpha, g_stream, nl);
+                    }
+                    e = stencil_dir_sigma<float>(g, ty, v[0].as<float>(), v[1].as<float>(), v[2].as<float>(),
+                                                 v[3].as<float>(), &S->beta, 0, v[4].as<float>(),
+                                                 v[5].as<float>(), part.as<Pair>(), &S->status, g_stream, nl);
+                    if (e != hipSuccess) return e;
+                    return stencil_pair_update<float>(g, ty, v[4].as<float>(), v[5].as<float>(), xd.as<double>(),
+                                                      v[0].as<float>(), v[1].as<float>(), part.as<Pair>(),
+                                                      &S->status, &S->alpha, g_stream, nl);
                 }
                 if (es == 8)
                     return stencil_pair_direction<double>(g, ty, v[0].as<double>(), v[1].as<double>(),
@@ -2125,8 +2159,9 @@ int excmg_autotune(int n, int kind, int precision, int reps, int *ty_out, int *z
             if (ms / reps < best) {
                 best = ms / reps;
                 bty = ty;
-                bzc = std::min(zc, nn);
+                bzc = zc;
             }
+            if (zc == nn) break;
         }
         if (rc) break;
     }
@@ -2135,6 +2170,7 @@ int excmg_autotune(int n, int kind, int precision, int reps, int *ty_out, int *z
     for (auto &b : v) b.release();
     part.release();
     stb.release();
+    xd.release();
     if (rc) return rc;
     CKR(excmg_set_shape(n, (kind == 1 && es == 4) ? 2 : kind, bty, bzc));
     if (ty_out) *ty_out = bty;

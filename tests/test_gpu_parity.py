@@ -400,6 +400,35 @@ def test_autotuned_shape_keeps_results(ex):
         ex.set_shape(N, kind, 0, 0)
 
 
+def test_autotune_on_recomputing_grids_keeps_results(ex):
+    """On grids of 2^22 unknowns and up (here 192^3 cells: 191^3 = 6.97e6 unknowns) the
+    autotuner's kind 1 times the pair of sweeps Bi-CG runs there (sweep A marching p, sweep B
+    forming q, q* again).  The shape it records leaves the mixed and the FP64 solve exactly as
+    they are with the built-in shape."""
+    N, nl, bc = 192, 7, 1
+    print(f"autotune recomputing pair {N}^3", flush=True)
+    arr = make_arrays(config_problem(3), N, bc, with_u=False)
+    f, g1, g2 = dev(arr.f), dev(arr.g1), dev(arr.g2)
+
+    def solve(prec):
+        u = torch.empty_like(f)
+        rc, st = ex.solve_ex(N, nl, bc, f, g1, g2, 1e-8, u, precision=prec)
+        assert rc == ex.OK, ex.last_error()
+        return host(u), [(lv["iterations"], lv["runs"]) for lv in st.levels()]
+
+    for prec, kind, tys in ((ex.MIXED, 2, (4, 8, 16)), (ex.FP64, 1, (4, 8))):
+        u0, it0 = solve(prec)
+        ty, zc, ms = ex.autotune(N, 1, prec, reps=2)
+        try:
+            assert ty in tys and 1 <= zc <= N - 1 and ms > 0
+            assert ex.get_shape(N, kind) == (ty, zc)
+            u1, it1 = solve(prec)
+        finally:
+            ex.set_shape(N, kind, 0, 0)
+        assert it1 == it0
+        np.testing.assert_array_equal(u1, u0)
+
+
 # ------------------------------------------------------------------ CG specialisation
 
 def test_deferred_update_keeps_bicg_equal_to_cg(ex):
