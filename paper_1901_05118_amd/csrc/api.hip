@@ -234,13 +234,15 @@ Geom choose_shape(int N, int bc, int kind) {
     // update of the iterate; 128^3: 27.5 us at {8, 8} against 29.3 us at {8, 16}; from 256^3
     // the recomputing pair of sweeps).  From 512^3 one march through the whole depth (511
     // planes) gives exactly one 64x16 tile per CU: the pair 1.91 -> 1.75 ms per iteration.
+    // The FP64 pair there prefers 64x4 tiles (three workgroups of four waves per CU at its
+    // 150-160 registers instead of one of eight): 3.69-3.79 -> 3.46 ms.
     static const int kTuned[6][3][2] = {
         {{4, 4}, {4, 2}, {4, 2}},          // N < 48 (16^3, 32^3: 5.4 -> 5.0, 16.0 -> 14.7 ms)
         {{4, 4}, {4, 4}, {4, 4}},          // 48 <= N < 96
         {{4, 8}, {8, 16}, {4, 8}},         // 96 <= N < 128
         {{16, 8}, {8, 16}, {8, 8}},        // 128 <= N < 256
         {{8, 32}, {8, 128}, {16, 64}},     // 256 <= N < 512
-        {{8, 128}, {8, 128}, {16, 512}},   // N >= 512
+        {{8, 128}, {4, 128}, {16, 512}},   // N >= 512
     };
     const int band = N < 48 ? 0 : N < 96 ? 1 : N < 128 ? 2 : N < 256 ? 3 : N < 512 ? 4 : 5;
     const int ty = kTuned[band][kind][0];
