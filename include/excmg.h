@@ -28,7 +28,9 @@
  *  * The library holds one context per process (levels, workspace, cached factors).  Calls
  *    are not thread-safe.
  *  * Return codes: EXCMG_OK (0) or a negative code; excmg_last_error() describes the last
- *    failure.  On EXCMG_ENOCONV the outputs hold the last iterate.
+ *    failure.  On EXCMG_ENOCONV the outputs hold the last iterate (the per-level records say
+ *    whether a cap or the FP64 residual floor stopped it).  Calls that act on the current
+ *    context (levels, workspace) return EXCMG_ENOCTX when there is none.
  *
  * Levels: a cascade of n_levels grids with N_l = N_0 * 2^l cells, l = 0 .. n_levels-1, where
  * N_0 = n_finest / 2^(n_levels-1) >= 2 (n_finest must be divisible by 2^(n_levels-1)),
@@ -45,11 +47,13 @@ extern "C" {
 #endif
 
 #define EXCMG_OK 0
-#define EXCMG_EINVAL (-1)     /* bad size, level count, bc kind, NULL pointer, no context  */
+#define EXCMG_EINVAL (-1)     /* bad size, level count, bc kind, NULL pointer              */
 #define EXCMG_ENOMEM (-2)     /* device allocation failed                                 */
 #define EXCMG_ENOCONV (-3)    /* iteration cap reached before the tolerance               */
 #define EXCMG_EBREAKDOWN (-4) /* Bi-CG denominator zero or non-finite (Algorithm 2)        */
 #define EXCMG_EHIP (-5)       /* a HIP runtime call failed                                */
+#define EXCMG_ENOCTX (-6)     /* the call needs a context (excmg_setup / a solve) and none */
+                              /* exists                                                    */
 
 /* Precision of the Bi-CG vectors and stencil storage. */
 #define EXCMG_FP64 0          /* everything in FP64                                        */
@@ -110,6 +114,18 @@ typedef struct excmg_opts {
                         /* 0: 4194304 (2^22), 1: every level.  Same results bit for bit      */
 } excmg_opts;
 
+/* Why a Bi-CG level stopped (excmg_level_stats.exit).  Algorithm 1 repeats Bi-CG on a level
+ * until the true relative residual meets the level's tolerance; in FP64 arithmetic that
+ * residual cannot fall below a floor of about 22 u ||x||_2 / ||b||_2 (u = 2^-53, x the
+ * level's solution), so a tolerance near the floor ends in stagnation rather than
+ * convergence. */
+#define EXCMG_EXIT_TOL 0       /* the true relative residual met the tolerance               */
+#define EXCMG_EXIT_CAP 1       /* iteration, run or refinement-step cap reached               */
+#define EXCMG_EXIT_FLOOR 2     /* floor-limited: the tolerance is below 10 x the estimated    */
+                               /* floor and a further run or residual replacement no longer   */
+                               /* halved the squared residual (status EXCMG_ENOCONV)          */
+#define EXCMG_EXIT_BREAKDOWN 3 /* Bi-CG breakdown (status EXCMG_EBREAKDOWN)                  */
+
 /* Per-level record filled by excmg_solve_ex (levels 0 and 1 report iterations = 0). */
 typedef struct excmg_level_stats {
     int n;              /* cells per axis                                                    */
@@ -120,6 +136,9 @@ typedef struct excmg_level_stats {
     double eps;         /* tolerance of the level                                             */
     double rel_residual;/* final true ||b - A x||_2 / ||b||_2                                 */
     double ms;          /* wall time of the level (device events)                            */
+    double floor;       /* estimated FP64 relative-residual floor, 22 u ||x||_2 / ||b||_2 of  */
+                        /* the returned iterate (0 on the direct levels)                     */
+    int exit;           /* EXCMG_EXIT_TOL / _CAP / _FLOOR / _BREAKDOWN                       */
 } excmg_level_stats;
 
 typedef struct excmg_stats {

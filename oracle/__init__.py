@@ -69,6 +69,8 @@ def lib():
             "oracle2d_exp_finite": (c_int, [c_int, dp, dp, dp]),
             "oracle2d_exp_true": (c_int, [c_int, dp, dp, dp]),
             "oracle_exp_true": (c_int, [c_int, dp, dp, dp]),
+            "oracle_threads": (c_int, []),
+            "oracle_set_threads": (None, [c_int]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -92,6 +94,17 @@ def _f64(a):
 def _check(name, rc):
     if rc != OK:
         raise OracleError(name, rc)
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's loops use."""
+    return int(lib().oracle_threads())
+
+
+def set_threads(n: int) -> None:
+    """Set the OpenMP threads of the oracle's loops (timing runs; results do not depend on
+    the thread count)."""
+    lib().oracle_set_threads(int(n))
 
 
 def n_interior(N: int) -> int:

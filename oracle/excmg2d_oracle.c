@@ -245,9 +245,16 @@ int oracle2d_level_solve(int N, int bc, const double *b, double *x, double eps, 
         int brc = oracle2d_bicg(N, bc, b, x, eps, maxit, &it, &rrr);
         total += it;
         nrun++;
+        double prev = rr;
         oracle2d_residual(N, bc, b, x, r);
         rr = oracle_dot(n, r, r);
         if (brc == ORC_EBREAKDOWN || brc == ORC_ENOMEM || brc == ORC_EINVAL) { rc = brc; break; }
+        /* floor-limited: the same stop as the 3D while loop (tolerance within a factor 10 of
+         * the FP64 floor 22 u ||x||_2 / ||b||_2 and a run that no longer halves r.r) */
+        if (!(rr <= thr)) {
+            double floor_est = bb > 0.0 ? 22.0 * 0x1p-53 * sqrt(oracle_dot(n, x, x) / bb) : 0.0;
+            if (eps < 10.0 * floor_est && !(rr < 0.5 * prev)) { rc = ORC_ENOCONV; break; }
+        }
     }
     if (iters) *iters = total;
     if (runs) *runs = nrun;

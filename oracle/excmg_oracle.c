@@ -36,6 +36,7 @@
  * -4 Bi-CG breakdown (a zero or non-finite denominator in Algorithm 2).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -90,14 +91,18 @@ double oracle_dot(i64 n, const double *x, const double *y) {
 /* --------------------------------------------------------------- eq. method1 */
 
 /* Left-hand side of eq. (method1) at the padded position c.  s1 and s2 are the padded
- * strides in y and z.  Sums run left to right in the printed order. */
+ * strides in y and z.  Sums run left to right in the printed order; the twelve terms of the
+ * factor 2 are printed as three groups of four (the diagonals in plane k, the axis
+ * neighbours in plane k-1, those in plane k+1): each group is summed first, then the three
+ * group sums. */
 static inline double eval25(const double *P, i64 c, i64 s1, i64 s2) {
     double S1 = P[c - 1] + P[c + 1] + P[c - s1] + P[c + s1] + P[c - s2] + P[c + s2];
     double S2 = P[c - 2] + P[c + 2] + P[c - 2 * s1] + P[c + 2 * s1] + P[c - 2 * s2] +
                 P[c + 2 * s2];
-    double S3 = P[c - 1 - s1] + P[c - 1 + s1] + P[c + 1 - s1] + P[c + 1 + s1] +
-                P[c - 1 - s2] + P[c + 1 - s2] + P[c - s1 - s2] + P[c + s1 - s2] +
-                P[c - 1 + s2] + P[c + 1 + s2] + P[c - s1 + s2] + P[c + s1 + s2];
+    double Dk = P[c - 1 - s1] + P[c - 1 + s1] + P[c + 1 - s1] + P[c + 1 + s1];
+    double Dm = P[c - 1 - s2] + P[c + 1 - s2] + P[c - s1 - s2] + P[c + s1 - s2];
+    double Dp = P[c - 1 + s2] + P[c + 1 + s2] + P[c - s1 + s2] + P[c + s1 + s2];
+    double S3 = Dk + Dm + Dp;
     return 42.0 * P[c] - 12.0 * S1 + S2 + 2.0 * S3;
 }
 
@@ -505,10 +510,19 @@ int oracle_level_solve_ex(int N, int bc, const double *b, double *x, const doubl
                                  &it, &rrr);
         total += it;
         nrun++;
+        double prev = rr;
         oracle_residual(N, bc, b, x, r);
         rr = oracle_dot(n, r, r);
         if (brc == ORC_EBREAKDOWN) { rc = brc; break; }
         if (brc == ORC_ENOMEM || brc == ORC_EINVAL) { rc = brc; break; }
+        /* The true residual of FP64 arithmetic cannot fall below a floor of about
+         * 22 u ||x||_2 / ||b||_2 (u = 2^-53): when the tolerance is within a factor 10 of that
+         * floor, a run that no longer halves the squared residual ends the while loop
+         * (floor-limited) instead of restarting Bi-CG until max_runs. */
+        if (!(rr <= thr)) {
+            double floor_est = bb > 0.0 ? 22.0 * 0x1p-53 * sqrt(oracle_dot(n, x, x) / bb) : 0.0;
+            if (eps < 10.0 * floor_est && !(rr < 0.5 * prev)) { rc = ORC_ENOCONV; break; }
+        }
     }
     if (iters) *iters = total;
     if (runs) *runs = nrun;
@@ -650,3 +664,8 @@ int oracle_exp_true(int N, const double *uh, const double *u2h, double *ut) {
             }
     return ORC_OK;
 }
+
+/* OpenMP threads of the loops above (for timing runs of the oracle; results do not depend
+ * on the thread count). */
+int oracle_threads(void) { return omp_get_max_threads(); }
+void oracle_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }

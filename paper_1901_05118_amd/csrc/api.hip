@@ -227,22 +227,21 @@ Geom choose_shape(int N, int bc, int kind) {
     const int n = N - 1;
     for (const ShapeOverride &o : g_shapes)
         if (o.N == N && o.kind == kind) return make_geom(n, bc, o.ty, std::max(1, std::min(o.zc, n)));
-    // Shapes the autotuner picks on MI355X (stable across runs), per grid-size band and
-    // kind {operator/residual, FP64 sweep A, FP32 sweep A}: {ty, zc}.  Grids up to 64^3 are
-    // launch-latency bound and want the most workgroups; larger grids want long z-marches.
-    // FP32 sweep A: timed in the form mixed solves run on these grids (with the deferred
-    // update of the iterate; 128^3: 27.5 us at {8, 8} against 29.3 us at {8, 16}; from 256^3
-    // the recomputing pair of sweeps).  From 512^3 one march through the whole depth (511
-    // planes) gives exactly one 64x16 tile per CU: the pair 1.91 -> 1.75 ms per iteration.
-    // The FP64 pair there prefers 64x4 tiles (three workgroups of four waves per CU at its
-    // 150-160 registers instead of one of eight): 3.69-3.79 -> 3.46 ms.
+    // Shapes the autotuner picks on MI355X, per grid-size band and kind {operator/residual,
+    // FP64 sweep A, FP32 sweep A}: {ty, zc}.  Grids up to 64^3 are launch-latency bound and
+    // want the most workgroups; larger grids want long z-marches.  FP32 sweep A: timed in the
+    // form mixed solves run on these grids (128^3: the stored form with the deferred update
+    // of the iterate; from 256^3 the recomputing pair of sweeps, which shares the shape).
+    // From 256^3 both pairs take 64x8 tiles of 128 planes (one 512-thread workgroup per CU;
+    // its update sweep keeps three planes in flight); from 512^3 the mixed pair marches the
+    // whole depth (511 planes) on 64x16 tiles, one per CU, and the FP64 pair on 64x8.
     static const int kTuned[6][3][2] = {
-        {{4, 4}, {4, 2}, {4, 2}},          // N < 48 (16^3, 32^3: 5.4 -> 5.0, 16.0 -> 14.7 ms)
-        {{4, 4}, {4, 4}, {4, 4}},          // 48 <= N < 96
+        {{4, 2}, {4, 2}, {4, 2}},          // N < 48
+        {{4, 4}, {8, 2}, {8, 2}},          // 48 <= N < 96
         {{4, 8}, {8, 16}, {4, 8}},         // 96 <= N < 128
-        {{16, 8}, {8, 16}, {8, 8}},        // 128 <= N < 256
-        {{8, 32}, {8, 128}, {16, 64}},     // 256 <= N < 512
-        {{8, 128}, {4, 128}, {16, 512}},   // N >= 512
+        {{8, 8}, {8, 16}, {8, 16}},        // 128 <= N < 256
+        {{16, 64}, {8, 128}, {8, 128}},    // 256 <= N < 512
+        {{16, 512}, {8, 512}, {16, 512}},  // N >= 512
     };
     const int band = N < 48 ? 0 : N < 96 ? 1 : N < 128 ? 2 : N < 256 ? 3 : N < 512 ? 4 : 5;
     const int ty = kTuned[band][kind][0];
@@ -395,7 +394,7 @@ int setup_levels(int n_finest, int n_levels, int bc, int dim) {
 }
 
 int need_ctx(int level) {
-    if (!g_ctx.ready) return fail(EXCMG_EINVAL, "no context: call excmg_setup first");
+    if (!g_ctx.ready) return fail(EXCMG_ENOCTX, "no context: call excmg_setup first");
     if (level < 0 || level >= g_ctx.n_levels)
         return fail(EXCMG_EINVAL, "level %d outside 0..%d", level, g_ctx.n_levels - 1);
     return EXCMG_OK;
@@ -419,6 +418,27 @@ int read_state(BicgState &s) {
     CKH(hipStreamSynchronize(g_stream));
     s = *c.host_state;
     return EXCMG_OK;
+}
+
+// The relative-residual floor of FP64 arithmetic for the iterate x of level L (the reading of
+// Algorithm 1's while loop): about 22 u ||x||_2 / ||b||_2 with u = 2^-53, the constant fitted
+// to the floors measured on 128^3 grids with zero and with smooth boundary data.
+constexpr double kFloorConst = 22.0 * 0x1p-53;
+int level_floor(const Level &L, const double *x, Rows rows, double bb, double *floor) {
+    Ctx &c = g_ctx;
+    double *sc = c.scal.as<double>();
+    CKR(device_dot(L.nu, x, x, sc, 3, rows));
+    CKH(hipMemcpyAsync(c.host_scal + 3, sc + 3, sizeof(double), hipMemcpyDeviceToHost, g_stream));
+    CKH(hipStreamSynchronize(g_stream));
+    *floor = bb > 0 ? kFloorConst * std::sqrt(c.host_scal[3] / bb) : 0.0;
+    return EXCMG_OK;
+}
+
+// Why a level stopped, from its status, tolerance and floor.
+int level_exit(int status, double eps, double floor) {
+    if (status == EXCMG_OK) return EXCMG_EXIT_TOL;
+    if (status == EXCMG_EBREAKDOWN) return EXCMG_EXIT_BREAKDOWN;
+    return eps < 10.0 * floor ? EXCMG_EXIT_FLOOR : EXCMG_EXIT_CAP;
 }
 
 // r = b - A x on the level, and r.r into scal[slot]
@@ -446,12 +466,6 @@ int poll_interval(long long nu) {
 // run has stopped, so the host launches K iterations between two polls of the state.
 bool g_cg = false;          // current solve uses the CG specialisation (opts.method)
 bool g_graphs = false;      // replay iteration windows from captured hipGraphs (solves only)
-// fold the sigma and rho finalisations into the sweeps (two launches per iteration instead
-// of four); off: separate one-workgroup finalisation kernels
-bool g_fold = getenv("EXCMG_SEPARATE_FINALISE") == nullptr;
-// mixed-precision Bi-CG on large grids: x's update moves from sweep B to the next sweep A
-// (off: the update stays in sweep B; results are the same bit for bit)
-bool g_defer = getenv("EXCMG_NO_DEFERRED_UPDATE") == nullptr;
 hipStream_t g_capture = nullptr;
 
 // Captured windows of K iterations, per level, vector type, method and iterate pointer.
@@ -477,7 +491,7 @@ long long g_rq_min = kRecomputeMin;   // opts.recompute_min_unknowns of the solv
 
 template <typename TX, typename T>
 bool recompute_q(const Level &L) {
-    return sizeof(TX) == 8 && !g_cg && g_fold && !g_var.d && !g_var.xs && g_ctx.dim == 3 &&
+    return sizeof(TX) == 8 && !g_cg && !g_var.d && !g_var.xs && g_ctx.dim == 3 &&
            L.nu >= g_rq_min;
 }
 
@@ -489,7 +503,7 @@ int b_partials(const Level &L) {
 }
 
 struct GraphEntry {
-    int level, tsize, cg, fold, K, defer, ld, rq;
+    int level, tsize, cg, K, defer, ld, rq;
     const void *x, *d, *xs;
     hipGraph_t graph;
     hipGraphExec_t exec;
@@ -504,9 +518,9 @@ void release_graphs() {
     g_graph_cache.clear();
 }
 
-// The launches of iteration j of a run: sweep A (direction update + products + sigma),
-// alpha, sweep B (updates + rho, r.r), beta; with folded finalisations (the default) alpha
-// and beta are merged by the sweeps themselves, so two launches.  Forms: the recomputing
+// The launches of iteration j of a run: sweep A (direction update + products + sigma) and
+// sweep B (updates + rho, r.r); the finalisations (alpha, beta, the stopping checks) are
+// folded into the sweeps, so two launches.  Forms: the recomputing
 // one on large 3D grids (recompute_q: sweep A stores p, p* only, sweep B forms q, q* again),
 // else the stored one (q, q* written by sweep A, read by sweep B).  ev >= 0 brackets the
 // sweeps with timing events.
@@ -526,13 +540,10 @@ int launch_iteration(const Level &L, TX *x, long long j, int ev, hipStream_t st,
     const int nvb = b_partials<TX, T>(L);
     const int cur = (int)(j & 1), nxt = cur ^ 1;
     T *pn = c.p[nxt].as<T>(), *psn = c.ps[nxt].as<T>();
-    // folded: sweep A merges the previous sweep B's partials (rho, r.r, beta, stopping
-    // checks), sweep B merges sweep A's (sigma, alpha)
-    StepLink la, lb;
-    if (g_fold) {
-        la = StepLink{S, c.part_b.as<Pair>(), nvb, g_cg ? 1 : 2, cur};
-        lb = StepLink{S, c.part_a.as<Pair>(), nsb, 1, cur};
-    }
+    // sweep A merges the previous sweep B's partials (rho, r.r, beta, stopping checks),
+    // sweep B merges sweep A's (sigma, alpha)
+    StepLink la{S, c.part_b.as<Pair>(), nvb, g_cg ? 1 : 2, cur};
+    StepLink lb{S, c.part_a.as<Pair>(), nsb, 1, cur};
     if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev], st));
     if constexpr (sizeof(TX) == 8) {
         if (recompute_q<TX, T>(L)) {
@@ -558,12 +569,10 @@ int launch_iteration(const Level &L, TX *x, long long j, int ev, hipStream_t st,
                                               &S->beta, j == 0 ? 1 : 0, pn, psn, q, qs,
                                               c.part_a.as<Pair>(), &S->status, st, la));
             if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev + 1], st));
-            if (!g_fold) CKH(bicg_alpha(S, c.part_a.as<Pair>(), nsb, st));
             if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev + 2], st));
             CKH(bicg_update_ex(L.nu, S, x, pn, r, q, rs, qs, g_var.d, g_var.xs, psn,
                                c.part_b.as<Pair>(), st, lb));
             if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev + 3], st));
-            if (!g_fold) CKH(bicg_beta(S, c.part_b.as<Pair>(), nvb, st));
             return EXCMG_OK;
         }
     }
@@ -583,7 +592,6 @@ int launch_iteration(const Level &L, TX *x, long long j, int ev, hipStream_t st,
                                       &S->beta, j == 0 ? 1 : 0, pn, psn, q, qs,
                                       c.part_a.as<Pair>(), &S->status, st, la));
     if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev + 1], st));
-    if (!g_fold) CKH(bicg_alpha(S, c.part_a.as<Pair>(), nsb, st));
     if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev + 2], st));
     if (g_cg)
         CKH((cg_update<TX, T>(L.nu, S, x, pn, r, q, c.part_b.as<Pair>(), st, lb, rows)));
@@ -591,21 +599,16 @@ int launch_iteration(const Level &L, TX *x, long long j, int ev, hipStream_t st,
         CKH((bicg_update<TX, T>(L.nu, S, defer ? nullptr : x, pn, r, q, rs, qs,
                                 c.part_b.as<Pair>(), st, lb, rows)));
     if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev + 3], st));
-    if (!g_fold) {
-        if (g_cg) CKH(cg_beta(S, c.part_b.as<Pair>(), nvb, st));
-        else CKH(bicg_beta(S, c.part_b.as<Pair>(), nvb, st));
-    }
     return EXCMG_OK;
 }
 
-// Folded steps leave the end-of-iteration checks of iteration j to the next sweep A; before
+// The folded steps leave the end-of-iteration checks of iteration j to the next sweep A; before
 // the host reads the state, run them on their own (the next sweep A repeats them with the
 // same result).
 // With a deferred update pending the check only publishes its decision (poll_status): the
 // next sweep A stops the run after applying the update.
 template <typename T>
 int close_window(const Level &L, long long j_next, hipStream_t st, int defer = 0) {
-    if (!g_fold) return EXCMG_OK;
     Ctx &c = g_ctx;
     const StepLink l{c.state.as<BicgState>(), c.part_b.as<Pair>(), b_partials<double, T>(L), g_cg ? 1 : 2,
                      (int)(j_next & 1), defer ? 1 : 0};
@@ -618,7 +621,7 @@ template <typename TX, typename T>
 int window_graph(const Level &L, TX *x, int K, hipGraphExec_t *out, int defer = 0) {
     for (GraphEntry &e : g_graph_cache)
         if (e.level == L.index && e.tsize == (int)sizeof(T) && e.cg == (int)g_cg &&
-            e.fold == (int)g_fold && e.K == K && e.defer == defer && e.ld == L.ld &&
+            e.K == K && e.defer == defer && e.ld == L.ld &&
             e.rq == (int)recompute_q<TX, T>(L) &&
             e.x == (const void *)x &&
             e.d == g_var.d && e.xs == g_var.xs) {
@@ -640,7 +643,7 @@ int window_graph(const Level &L, TX *x, int K, hipGraphExec_t *out, int defer = 
     CKH(e);
     hipGraphExec_t exec = nullptr;
     CKH(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-    g_graph_cache.push_back(GraphEntry{L.index, (int)sizeof(T), (int)g_cg, (int)g_fold, K, defer,
+    g_graph_cache.push_back(GraphEntry{L.index, (int)sizeof(T), (int)g_cg, K, defer,
                                        L.ld, (int)recompute_q<TX, T>(L), (const void *)x, g_var.d, g_var.xs, graph, exec});
     *out = exec;
     return EXCMG_OK;
@@ -660,8 +663,8 @@ int bicg_iterate(const Level &L, TX *x, BicgState &hs, long long &j) {
     const bool graphs = g_graphs && !g_timing;
     // x += alpha p deferred to the next sweep A (large grids, FP32 vectors, plain Bi-CG):
     // sweep B then streams r, q, r*, q* only
-    const int defer = (!recompute_q<TX, T>(L) && (graphs || g_timing) && K <= 16 && g_defer && sizeof(T) == 4 &&
-                       sizeof(TX) == 8 && !g_cg && g_fold && !g_var.d && !g_var.xs &&
+    const int defer = (!recompute_q<TX, T>(L) && (graphs || g_timing) && K <= 16 && sizeof(T) == 4 &&
+                       sizeof(TX) == 8 && !g_cg && !g_var.d && !g_var.xs &&
                        g_ctx.dim == 3) ? 1 : 0;
     hipGraphExec_t exec = nullptr;
     if (graphs) CKR((window_graph<TX, T>(L, x, K, &exec, defer)));
@@ -815,6 +818,7 @@ int level_solve(const Level &L, const double *b, double *x, double eps, int maxi
     double rr = c.host_scal[2];
     const double thr = (eps * eps) * bb;
     int total = 0, runs = 0, status = EXCMG_OK;
+    double floor = 0.0;
     while (!(rr <= thr)) {
         if (runs >= max_runs) {
             status = EXCMG_ENOCONV;
@@ -825,6 +829,7 @@ int level_solve(const Level &L, const double *b, double *x, double eps, int maxi
         CKR(bicg_run(L, b, x, eps, maxit, &it, &rrr, &bst, d));
         total += it;
         runs++;
+        const double prev = rr;
         CKR(true_residual(L, b, x, c.r.as<double>(), 2));
         CKH(hipMemcpyAsync(c.host_scal + 2, sc + 2, sizeof(double), hipMemcpyDeviceToHost,
                            g_stream));
@@ -834,6 +839,14 @@ int level_solve(const Level &L, const double *b, double *x, double eps, int maxi
             status = EXCMG_EBREAKDOWN;
             break;
         }
+        // a tolerance near the FP64 floor: stop once a run no longer halves the residual
+        if (!(rr <= thr)) {
+            CKR(level_floor(L, x, Rows{}, bb, &floor));
+            if (eps < 10.0 * floor && !(rr < 0.5 * prev)) {
+                status = EXCMG_ENOCONV;
+                break;
+            }
+        }
     }
     if (st) {
         st->n = L.N;
@@ -842,6 +855,9 @@ int level_solve(const Level &L, const double *b, double *x, double eps, int maxi
         st->status = status;
         st->eps = eps;
         st->rel_residual = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+        if (floor == 0.0) CKR(level_floor(L, x, Rows{}, bb, &floor));
+        st->floor = floor;
+        st->exit = level_exit(status, eps, floor);
     }
     return EXCMG_OK;
 }
@@ -923,12 +939,16 @@ int level_solve_mixed(const Level &L, const double *b, double *u, double eps, in
         }
     }
     if (st) {
+        double floor = 0.0;
+        CKR(level_floor(L, u, L.rows(), bb, &floor));
         st->n = L.N;
         st->iterations = total;
         st->runs = outer;
         st->status = status;
         st->eps = eps;
         st->rel_residual = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+        st->floor = floor;
+        st->exit = level_exit(status, eps, floor);
     }
     return EXCMG_OK;
 }
@@ -1028,12 +1048,16 @@ int level_solve_reliable(const Level &L, const double *b, double *u, double eps,
         }
     }
     if (st) {
+        double floor = 0.0;
+        CKR(level_floor(L, u, rows, bb, &floor));
         st->n = L.N;
         st->iterations = iters;
         st->runs = replaced;
         st->status = status;
         st->eps = eps;
         st->rel_residual = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+        st->floor = floor;
+        st->exit = level_exit(status, eps, floor);
     }
     return EXCMG_OK;
 }
@@ -1054,7 +1078,7 @@ int solve_cascade(const excmg_opts &o, const double *f, const double *g1, const 
     const int maxit = o.max_iters > 0 ? o.max_iters : 100000;
     const int max_runs = o.max_runs > 0 ? o.max_runs : 5;
     const int max_outer = o.max_outer > 0 ? o.max_outer : 60;
-    const bool reliable = (o.refine == EXCMG_RELIABLE) && g_fold;
+    const bool reliable = o.refine == EXCMG_RELIABLE;
     const bool jacobi = (o.precond == EXCMG_PRECOND_JACOBI);
     const double inner_tol = o.inner_tol > 0 ? o.inner_tol : (reliable ? 0.1 : 1e-4);
     const bool mixed = (o.precision == EXCMG_MIXED);
@@ -1198,7 +1222,9 @@ struct BProb {
     Arg *af = nullptr, *a1 = nullptr, *a2 = nullptr, *au = nullptr, *at = nullptr;
     int level = 0, phase = kPhaseCheck;
     int runs = 0, iters = 0, outer = 0, worst = EXCMG_OK;
-    double eps = 0.0, prev = INFINITY;
+    int broke = 0;              // the last run broke down (Algorithm 2's denominators)
+    double eps = 0.0, prev = INFINITY, last_bb = 0.0;
+    double level_bb[EXCMG_MAX_LEVELS] = {};   // b.b of each finished level
     excmg_stats stats{};
     ~BProb() {
         for (auto &l : lv) { l.b.release(); l.x.release(); l.u.release(); }
@@ -1217,7 +1243,7 @@ struct BatchSolver {
     hipStream_t st = nullptr;
     std::vector<BProb *> pb;
     FactorCache fc;
-    DBuf states, runs, items, ctl, scal;
+    DBuf states, runs, items, ctl, scal, xx;
     BatchRun *h_runs = nullptr;
     int2 *h_items = nullptr;
     double *h_scal = nullptr;
@@ -1233,6 +1259,7 @@ struct BatchSolver {
         if (graph) (void)hipGraphDestroy(graph);
         for (BProb *b : pb) delete b;
         states.release(); runs.release(); items.release(); ctl.release(); scal.release();
+        xx.release();
         fc.release();
         if (h_runs) (void)hipHostFree(h_runs);
         if (h_items) (void)hipHostFree(h_items);
@@ -1395,6 +1422,7 @@ struct BatchSolver {
         ls.status = status;
         ls.eps = b.eps;
         ls.rel_residual = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+        if (b.level < EXCMG_MAX_LEVELS) b.level_bb[b.level] = bb;
         if (status != EXCMG_OK && b.worst == EXCMG_OK) b.worst = status;
         CKH(to_nodes<double>(Lv.N, s, b.N, Lv.x.as<double>(), b.a1->p<double>(), Lv.u.as<double>(), st));
         if (b.level == b.nl - 1) {
@@ -1413,6 +1441,13 @@ struct BatchSolver {
         Level &Lv = b.lv[b.level];
         const double bb = h_scal[4 * j + 1], rr = h_scal[4 * j + 2];
         const double thr = (b.eps * b.eps) * bb;
+        if (b.broke) {
+            // a breakdown ends the level, as in a single solve: FP64 reports the residual of
+            // the iterate after the broken run, mixed precision the residual it was started on
+            b.broke = 0;
+            if (mixed) return finish_level(j, EXCMG_EBREAKDOWN, b.prev, b.last_bb);
+            return finish_level(j, EXCMG_EBREAKDOWN, rr, bb);
+        }
         if (rr <= thr) return finish_level(j, EXCMG_OK, rr, bb);
         BicgState *Sj = S(j);
         if (!mixed) {
@@ -1422,6 +1457,7 @@ struct BatchSolver {
         } else {
             if (b.outer >= max_outer || !(rr < b.prev)) return finish_level(j, EXCMG_ENOCONV, rr, bb);
             b.prev = rr;
+            b.last_bb = bb;
             double it = std::max(inner_tol, 0.3 * b.eps * std::sqrt(bb / rr));
             if (it > 0.5) it = 0.5;
             const int nvb = vec_blocks(Lv.nu);
@@ -1541,7 +1577,7 @@ struct BatchSolver {
                     b.runs++;
                     changed = true;
                     b.phase = kPhaseCheck;
-                    if (h_states[j].status == kBreakdown) b.worst = EXCMG_EBREAKDOWN;
+                    if (h_states[j].status == kBreakdown) b.broke = 1;
                 }
                 int err = 0;
                 CKH(hipMemcpyAsync(&err, (char *)ctl.p + offsetof(BatchCtl, error), sizeof(int),
@@ -1551,11 +1587,42 @@ struct BatchSolver {
                 if (changed) break;
             }
         }
+        CKR(level_floors());
         for (BProb *b : pb) {
             CKR(b->au->back());
             if (b->at) CKR(b->at->back());
         }
         CKH(hipStreamSynchronize(st));
+        return EXCMG_OK;
+    }
+
+    // The FP64 residual floor of every Bi-CG level's solution (22 u ||x||_2 / ||b||_2) and why
+    // each level stopped.
+    int level_floors() {
+        const int np = (int)pb.size();
+        CKR(xx.ensure((size_t)np * EXCMG_MAX_LEVELS * sizeof(double)));
+        for (int j = 0; j < np; j++) {
+            BProb &b = *pb[j];
+            for (int l = 2; l < b.nl && l < EXCMG_MAX_LEVELS; l++) {
+                const Level &Lv = b.lv[l];
+                const int nb = vec_blocks(Lv.nu);
+                CKH(dot_partials<double>(Lv.nu, Lv.x.as<double>(), Lv.x.as<double>(),
+                                         b.part_b.as<Pair>(), nb, st));
+                CKH(reduce_to(xx.as<double>(), b.part_b.as<Pair>(), nb, j * EXCMG_MAX_LEVELS + l, st));
+            }
+        }
+        std::vector<double> h((size_t)np * EXCMG_MAX_LEVELS);
+        CKH(hipMemcpyAsync(h.data(), xx.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        CKH(hipStreamSynchronize(st));
+        for (int j = 0; j < np; j++) {
+            BProb &b = *pb[j];
+            for (int l = 2; l < b.nl && l < EXCMG_MAX_LEVELS; l++) {
+                excmg_level_stats &ls = b.stats.level[l];
+                const double bb = b.level_bb[l];
+                ls.floor = bb > 0 ? kFloorConst * std::sqrt(h[(size_t)j * EXCMG_MAX_LEVELS + l] / bb) : 0.0;
+                ls.exit = level_exit(ls.status, ls.eps, ls.floor);
+            }
+        }
         return EXCMG_OK;
     }
 };
@@ -1830,7 +1897,7 @@ int solve_ex_dim(const excmg_opts *opts, const double *f, const double *g1, cons
     if (ut_out) CKR(at.out());
     if (st) memset(st, 0, sizeof(*st));
     g_cg = (o.method == EXCMG_CG);
-    g_graphs = getenv("EXCMG_NO_GRAPHS") == nullptr;
+    g_graphs = true;
     g_rq_min = o.recompute_min_unknowns > 0 ? o.recompute_min_unknowns : kRecomputeMin;
     int rc = solve_cascade(o, af.p<double>(), a1.p<double>(), a2.p<double>(), au.p<double>(),
                         ut_out ? at.p<double>() : nullptr, st);
@@ -1905,7 +1972,7 @@ int excmg_solve(int n_finest, int n_levels, int bc_kind, const double *f, const 
 int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launch,
                         double *bytes_per_launch) {
     g_err[0] = 0;
-    if (!g_ctx.ready) return fail(EXCMG_EINVAL, "no context: call excmg_setup first");
+    if (!g_ctx.ready) return fail(EXCMG_ENOCTX, "no context: call excmg_setup first");
     if (which < 0 || which > 8 || reps < 1) return fail(EXCMG_EINVAL, "bad sweep or reps");
     if (precision != EXCMG_FP64 && precision != EXCMG_MIXED)
         return fail(EXCMG_EINVAL, "bad precision");
@@ -2025,45 +2092,51 @@ int excmg_solve_batch(int nprob, const excmg_problem *probs, const excmg_opts *o
     if (opts->precision != EXCMG_FP64 && opts->precision != EXCMG_MIXED)
         return fail(EXCMG_EINVAL, "precision %d not supported", opts->precision);
     for (int j = 0; j < nprob; j++) CKR(check_sizes(probs[j].n_finest, probs[j].n_levels, probs[j].bc_kind));
-    hipStream_t bs;
-    CKH(hipStreamCreateWithFlags(&bs, hipStreamNonBlocking));
-    hipEvent_t e0, e1, ein;
-    CKH(hipEventCreate(&e0));
-    CKH(hipEventCreate(&e1));
-    CKH(hipEventCreate(&ein));
-    CKH(hipEventRecord(ein, g_stream));
-    CKH(hipStreamWaitEvent(bs, ein, 0));
-    hipStream_t saved = g_stream;
-    g_stream = bs;  // host-array staging of the batch goes through the batch stream
-    int rc;
+    // every failure below is recorded in rc and the stream, events and library stream are
+    // restored and released on the way out
+    int rc = EXCMG_OK;
+    auto hip_ok = [&](hipError_t e, const char *what) {
+        if (e != hipSuccess && rc == EXCMG_OK)
+            rc = fail(EXCMG_EHIP, "%s failed: %s", what, hipGetErrorString(e));
+        return rc == EXCMG_OK;
+    };
+    hipStream_t bs = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr, ein = nullptr;
     float ms = 0.f;
-    {
-        BatchSolver B;
-        B.st = bs;
-        rc = B.init(nprob, probs, *opts);
-        if (rc == EXCMG_OK) {
-            CKH(hipEventRecord(e0, bs));
-            rc = B.run();
-            CKH(hipEventRecord(e1, bs));
-            CKH(hipEventSynchronize(e1));
-            CKH(hipEventElapsedTime(&ms, e0, e1));
-        }
-        if (rc == EXCMG_OK) {
-            int worst = EXCMG_OK;
-            for (int j = 0; j < nprob; j++) {
-                B.pb[j]->stats.total_ms = ms;
-                if (stats) stats[j] = B.pb[j]->stats;
-                if (B.pb[j]->worst != EXCMG_OK && worst == EXCMG_OK) worst = B.pb[j]->worst;
+    if (hip_ok(hipStreamCreateWithFlags(&bs, hipStreamNonBlocking), "hipStreamCreate") &&
+        hip_ok(hipEventCreate(&e0), "hipEventCreate") && hip_ok(hipEventCreate(&e1), "hipEventCreate") &&
+        hip_ok(hipEventCreate(&ein), "hipEventCreate") &&
+        hip_ok(hipEventRecord(ein, g_stream), "hipEventRecord") &&
+        hip_ok(hipStreamWaitEvent(bs, ein, 0), "hipStreamWaitEvent")) {
+        hipStream_t saved = g_stream;
+        g_stream = bs;  // host-array staging of the batch goes through the batch stream
+        {
+            BatchSolver B;
+            B.st = bs;
+            rc = B.init(nprob, probs, *opts);
+            if (rc == EXCMG_OK && hip_ok(hipEventRecord(e0, bs), "hipEventRecord")) {
+                rc = B.run();
+                if (rc == EXCMG_OK && hip_ok(hipEventRecord(e1, bs), "hipEventRecord") &&
+                    hip_ok(hipEventSynchronize(e1), "hipEventSynchronize"))
+                    hip_ok(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
             }
-            if (worst != EXCMG_OK) rc = fail(worst, "a level of a batched problem stopped early");
+            if (rc == EXCMG_OK) {
+                int worst = EXCMG_OK;
+                for (int j = 0; j < nprob; j++) {
+                    B.pb[j]->stats.total_ms = ms;
+                    if (stats) stats[j] = B.pb[j]->stats;
+                    if (B.pb[j]->worst != EXCMG_OK && worst == EXCMG_OK) worst = B.pb[j]->worst;
+                }
+                if (worst != EXCMG_OK) rc = fail(worst, "a level of a batched problem stopped early");
+            }
+            (void)hipStreamSynchronize(bs);
         }
-        (void)hipStreamSynchronize(bs);
+        g_stream = saved;
     }
-    g_stream = saved;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipEventDestroy(ein);
-    (void)hipStreamDestroy(bs);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (ein) (void)hipEventDestroy(ein);
+    if (bs) (void)hipStreamDestroy(bs);
     return rc;
 }
 
@@ -2080,7 +2153,7 @@ int excmg_autotune(int n, int kind, int precision, int reps, int *ty_out, int *z
     const long long nv = (long long)nn * nn * ld;
     // on grids where Bi-CG takes the recomputing form, sweep A is timed with the sweep B it
     // shares its launch shape with (the pair the solver runs; x is FP64 in both precisions)
-    const bool rq = kind == 1 && (long long)nn * nn * nn >= kRecomputeMin && g_fold && !g_var.d &&
+    const bool rq = kind == 1 && (long long)nn * nn * nn >= kRecomputeMin && !g_var.d &&
                     !g_var.xs;
     DBuf v[8], part, stb, xd;
     for (auto &b : v) {

@@ -145,7 +145,6 @@ template <typename TX, typename T>
 hipError_t cg_update(long long n, const BicgState *s, TX *x, const T *p, T *r, const T *q,
                      Pair *partials, hipStream_t st, StepLink link = StepLink{},
                      Rows rows = Rows{});
-hipError_t cg_beta(BicgState *s, const Pair *part, int count, hipStream_t st);
 // the end-of-iteration checks of a folded step as a kernel of its own (one workgroup), run
 // before the host reads the state
 hipError_t step_check(StepLink link, hipStream_t st);
@@ -186,8 +185,6 @@ hipError_t copy_convert(long long n, const TS *src, TD *dst, hipStream_t st);
 // finalisation kernels (one workgroup): merge `count` partials
 hipError_t bicg_start(BicgState *s, const Pair *rr_part, int count, double eps, int maxit,
                       hipStream_t st);   // rr = rho = r.r (r* = r), bb precomputed
-hipError_t bicg_alpha(BicgState *s, const Pair *part, int count, hipStream_t st);
-hipError_t bicg_beta(BicgState *s, const Pair *part, int count, hipStream_t st);
 hipError_t reduce_to(double *out, const Pair *part, int count, int slot, hipStream_t st);
 
 // ---------------------------------------------------------------- level kernels

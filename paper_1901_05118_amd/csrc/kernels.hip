@@ -511,57 +511,6 @@ hipError_t bicg_start2(BicgState *s, const Pair *part, int count, double eps, in
 }
 
 __global__ void __launch_bounds__(kReduceThreads)
-    k_bicg_alpha(BicgState *s, const Pair *part, int count) {
-    __shared__ Pair sh[kReduceThreads / kWave];
-    if (s->status != kRunning) return;
-    Pair v[1];
-    merge_partials<1>(part, count, v, sh);
-    if (threadIdx.x == 0) {
-        double sigma = pair_value(v[0]);
-        s->sigma = sigma;
-        if (sigma == 0.0 || !isfinite(sigma)) s->status = s->poll_status = kBreakdown;
-        else s->alpha = s->rho / sigma;
-    }
-}
-
-__global__ void __launch_bounds__(kReduceThreads)
-    k_bicg_beta(BicgState *s, const Pair *part, int count) {
-    __shared__ Pair sh[2 * (kReduceThreads / kWave)];
-    if (s->status != kRunning) return;
-    Pair v[2];
-    merge_partials<2>(part, count, v, sh);
-    if (threadIdx.x == 0) {
-        double rho_new = pair_value(v[0]);
-        s->rr = pair_value(v[1]);
-        s->beta = rho_new / s->rho;
-        s->rho = rho_new;
-        s->iter = s->iter + 1;
-        set_status(s);
-    }
-}
-
-__global__ void __launch_bounds__(kReduceThreads)
-    k_cg_beta(BicgState *s, const Pair *part, int count) {
-    __shared__ Pair sh[kReduceThreads / kWave];
-    if (s->status != kRunning) return;
-    Pair v[1];
-    merge_partials<1>(part, count, v, sh);
-    if (threadIdx.x == 0) {
-        const double rr = pair_value(v[0]);
-        s->rr = rr;
-        s->beta = rr / s->rho;
-        s->rho = rr;
-        s->iter = s->iter + 1;
-        set_status(s);
-    }
-}
-
-hipError_t cg_beta(BicgState *s, const Pair *part, int count, hipStream_t st) {
-    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(kReduceThreads), 0, st, s, part, count);
-    return hipGetLastError();
-}
-
-__global__ void __launch_bounds__(kReduceThreads)
     k_reduce_to(double *out, const Pair *part, int count, int slot) {
     __shared__ Pair sh[kReduceThreads / kWave];
     Pair v[1];
@@ -573,14 +522,6 @@ hipError_t bicg_start(BicgState *s, const Pair *rr_part, int count, double eps, 
                       hipStream_t st) {
     hipLaunchKernelGGL(k_bicg_start, dim3(1), dim3(kReduceThreads), 0, st, s, rr_part, count, eps,
                        maxit);
-    return hipGetLastError();
-}
-hipError_t bicg_alpha(BicgState *s, const Pair *part, int count, hipStream_t st) {
-    hipLaunchKernelGGL(k_bicg_alpha, dim3(1), dim3(kReduceThreads), 0, st, s, part, count);
-    return hipGetLastError();
-}
-hipError_t bicg_beta(BicgState *s, const Pair *part, int count, hipStream_t st) {
-    hipLaunchKernelGGL(k_bicg_beta, dim3(1), dim3(kReduceThreads), 0, st, s, part, count);
     return hipGetLastError();
 }
 hipError_t reduce_to(double *out, const Pair *part, int count, int slot, hipStream_t st) {
@@ -648,9 +589,11 @@ __global__ void __launch_bounds__(256)
                       KV(0, 0, 1);
     const double S2 = KV(-2, 0, 0) + KV(2, 0, 0) + KV(0, -2, 0) + KV(0, 2, 0) + KV(0, 0, -2) +
                       KV(0, 0, 2);
-    const double S3 = KV(-1, -1, 0) + KV(-1, 1, 0) + KV(1, -1, 0) + KV(1, 1, 0) +
-                      KV(-1, 0, -1) + KV(1, 0, -1) + KV(0, -1, -1) + KV(0, 1, -1) +
-                      KV(-1, 0, 1) + KV(1, 0, 1) + KV(0, -1, 1) + KV(0, 1, 1);
+    // the three printed groups of four (plane k, k-1, k+1), each summed first
+    const double Dk = KV(-1, -1, 0) + KV(-1, 1, 0) + KV(1, -1, 0) + KV(1, 1, 0);
+    const double Dm = KV(-1, 0, -1) + KV(1, 0, -1) + KV(0, -1, -1) + KV(0, 1, -1);
+    const double Dp = KV(-1, 0, 1) + KV(1, 0, 1) + KV(0, -1, 1) + KV(0, 1, 1);
+    const double S3 = Dk + Dm + Dp;
 #undef KV
     const double E = 42.0 * c - 12.0 * S1 + S2 + 2.0 * S3;
     b[t] = h4 * fv - E;

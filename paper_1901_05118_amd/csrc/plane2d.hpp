@@ -78,7 +78,8 @@ __device__ __forceinline__ bool plane_tile(const Geom &g, int tile, const In &in
         }
         const i64 idx = (i64)iy * n + ix;
         out.centre(idx, c0);
-        out.emit(idx, y, c0);
+        if constexpr (HasPre<Out>::value) out.emit(idx, y, c0, out.pre(idx));
+        else out.emit(idx, y, c0);
     }
     return true;
 }

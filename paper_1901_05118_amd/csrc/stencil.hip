@@ -55,6 +55,10 @@ static hipError_t launch3d(const Geom &g, const In &in, const Out &out, hipStrea
 // 256^3: 166 and 157 us, although three take 161 registers and lower the occupancy).
 template <typename T>
 constexpr int kSigmaDepth = 3;
+// Planes in flight of its update sweep (two marched arrays plus the iterate and both
+// residuals per output): three on tiles of up to 8 rows (512-thread workgroups, registers to
+// spare), two on 16-row tiles (1024 threads, at most 128 registers).
+constexpr int update_depth(int ty) { return ty >= 16 ? 2 : 3; }
 
 #define EXCMG_DISPATCH_TY(TYV, ...)                                                          \
     switch (TYV) {                                                                           \
@@ -236,8 +240,8 @@ hipError_t stencil_pair_update(const Geom &g, int ty, const T *p, const T *ps, d
     out.alpha = 0.0;
     out.acc[0] = Pair{0.0, 0.0};
     out.acc[1] = Pair{0.0, 0.0};
-    EXCMG_DISPATCH_TY(ty, return (launch3d<TY, T, InPlainAlpha<T>, OutPairUpdate<T>, 2>(g, in, out,
-                                                                                       st)));
+    EXCMG_DISPATCH_TY(ty, return (launch3d<TY, T, InPlainAlpha<T>, OutPairUpdate<T>, 2,
+                                           update_depth(TY)>(g, in, out, st)));
     return hipSuccess;
 }
 template hipError_t stencil_dir_sigma<float>(const Geom &, int, const float *, const float *,

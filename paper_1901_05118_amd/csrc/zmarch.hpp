@@ -8,16 +8,25 @@
 //    y (double-buffered, so one barrier per plane); the next plane's global loads are issued
 //    before the current plane is consumed, which hides HBM latency behind the LDS work.
 //  * Every lane keeps the z-direction terms of its column in registers: the centre values
-//    of the last two planes, the four in-plane neighbours of the previous plane and the
+//    of the last two planes, the sum of the previous plane's four axis neighbours and the
 //    partial sums of the two outputs that are still open, each term added as soon as its
 //    plane is consumed (a two-deep pipeline, so an unroll by two renames it for free).  An
 //    output on plane k is complete when plane k+2 arrives.
-//  * The left-hand side of eq. (method1) is summed left to right in the order the paper
-//    prints it, with contraction off:
+//  * Every global load of the march belongs to one pipeline: a stage holds the raw values
+//    of one staged plane and the per-output data (e.g. the iterate of an update sweep) of
+//    the output that is complete when that plane is staged, and is consumed D planes after
+//    it was requested.  The planes are marched in whole groups of D with no exit inside a
+//    group, so the compiler keeps D planes of loads in flight (a load consumed in the plane
+//    it is requested in, or a loop path that skips a group's loads, makes it wait for every
+//    load in flight).
+//  * The left-hand side of eq. (method1) is summed in the order the paper prints it, with
+//    contraction off; the twelve terms of the factor 2 are summed per printed group of four
+//    (in-plane diagonals, then plane k-1, then plane k+1) and the three group sums left to
+//    right:
 //      y = 42 c - 12 S1 + S2 + 2 S3,
 //      S1 = x- + x+ + y- + y+ + z- + z+,   S2 = the same at distance 2,
-//      S3 = (x-y-) + (x-y+) + (x+y-) + (x+y+) + [x-, x+, y-, y+ on plane k-1]
-//           + [x-, x+, y-, y+ on plane k+1].
+//      S3 = [(x-y-) + (x-y+) + (x+y-) + (x+y+)] + [x- + x+ + y- + y+ on plane k-1]
+//           + [x- + x+ + y- + y+ on plane k+1].
 //  * Fictitious points (eqs. reflection2 / reflection4 with zero boundary data) are produced
 //    while staging: a halo position one step outside the boundary node holds +x (first kind)
 //    or -x (second kind) of the mirrored interior node, a boundary node holds 0.  The
@@ -62,15 +71,14 @@ __device__ __forceinline__ double reflect(int c, int n, double sgn, int &src) {
 // two-deep pipeline: output k = m-2 (completed by plane m) and output j = m-1.
 struct Column {
     double c1, c2;               // centre values of planes m-1, m-2
-    double np0, np1, np2, np3;   // in-plane neighbours (x-, x+, y-, y+) of plane m-1
+    double ap;                   // x- + x+ + y- + y+ of plane m-1
     double s1k, s1j;             // S1 of output k (complete); of output j (without z+)
     double s2k, s2j;             // S2 of outputs k and j without their z+2 term
     double ek, ej;               // S3 of output k (complete); of output j (without plane j+1)
 };
 
 __device__ __forceinline__ void column_init(Column &s) {
-    s.c1 = s.c2 = 0.0;
-    s.np0 = s.np1 = s.np2 = s.np3 = 0.0;
+    s.c1 = s.c2 = s.ap = 0.0;
     s.s1k = s.s1j = s.s2k = s.s2j = s.ek = s.ej = 0.0;
 }
 
@@ -84,13 +92,13 @@ __device__ __forceinline__ double column_step(Column &s, const TL *B, double &c0
     const double d0 = B[-1 - LS], d1 = B[-1 + LS], d2 = B[1 - LS], d3 = B[1 + LS];
     // output m-2 is complete once its S2 has this plane's centre (z+2)
     const double y = 42.0 * s.c2 - 12.0 * s.s1k + (s.s2k + c) + 2.0 * s.ek;
-    // output m-1 receives z+ (S1) and its plane k+1 terms (S3)
-    const double s1 = s.s1j + c;
-    const double e1 = s.ej + n0 + n1 + n2 + n3;
-    // output m opens with the terms of planes m, m-1 and m-2 that are already known
     const double a0 = n0 + n1 + n2 + n3;
+    // output m-1 receives z+ (S1) and its plane k+1 group (S3)
+    const double s1 = s.s1j + c;
+    const double e1 = s.ej + a0;
+    // output m opens with the terms of planes m, m-1 and m-2 that are already known
     const double b0 = f0 + f1 + f2 + f3;
-    const double e0 = d0 + d1 + d2 + d3 + s.np0 + s.np1 + s.np2 + s.np3;
+    const double e0 = (d0 + d1 + d2 + d3) + s.ap;
     s.s1k = s1;
     s.s1j = a0 + s.c1;
     s.s2k = s.s2j;
@@ -99,10 +107,7 @@ __device__ __forceinline__ double column_step(Column &s, const TL *B, double &c0
     s.ej = e0;
     s.c2 = s.c1;
     s.c1 = c;
-    s.np0 = n0;
-    s.np1 = n1;
-    s.np2 = n2;
-    s.np3 = n3;
+    s.ap = a0;
     c0 = c;
     return y;
 }
@@ -216,9 +221,9 @@ template <class O, class = void>
 struct HasGate : std::false_type {};
 template <class O>
 struct HasGate<O, std::void_t<decltype(std::declval<const O &>().gate())>> : std::true_type {};
-// Epilogues that request per-output data ahead (Out::Pre, Out::pre(idx)): the values of an
-// output are requested when its own plane is consumed and handed to emit() two planes
-// later, when the output is complete (for epilogues with registers to spare).
+// Epilogues that read per-output data (Out::Pre, Out::pre(idx)): the values of an output
+// are requested with the loads of a staged plane, D planes before the output is complete,
+// and handed to emit() then.
 template <class O, class = void>
 struct HasPre : std::false_type {};
 template <class O>
@@ -295,27 +300,43 @@ __device__ __forceinline__ bool zmarch_tile(const Geom &g, int tile, const In &i
     }
 
     constexpr int R = In::R;
-    using Raw = T[NL][NA][R];
-    auto fetch = [&](int m, Raw &raw, float &mz) {
+    constexpr bool kPre = HasPre<Out>::value;
+    using PreT = typename PreOf<Out>::type;
+    const int mbeg = k0 - 2, mend = k1 + 1;     // planes mbeg..mend are staged
+    // in-plane offset of this lane's column (< 2^31), clamped so that lanes outside the grid
+    // request valid addresses
+    const int col_off = min(iy, n - 1) * g.ld + min(ix, n - 1);
+
+    // One stage of the load pipeline: the raw values of staged plane p and the per-output
+    // data of output p - 3 (complete when plane p is staged, i.e. in the body of plane p - 1).
+    struct Stage {
+        T raw[NL][NA][R];
+        float mz;
+        PreT pre;
+    };
+    auto fetch = [&](int p, Stage &st) {
         int sz;
-        mz = (float)reflect(m, n, g.sgn, sz);
+        st.mz = (float)reflect(min(p, mend), n, g.sgn, sz);
 #pragma unroll
         for (int q = 0; q < NL; q++) {
             const i64 idx = (i64)sz * plane + soff[q];
 #pragma unroll
-            for (int a = 0; a < NA; a++) in.load(a, idx, raw[q][a]);
+            for (int a = 0; a < NA; a++) in.load(a, idx, st.raw[q][a]);
         }
+        if constexpr (kPre)
+            st.pre = out.pre((i64)min(max(p - 3, k0), k1 - 1) * plane + col_off);
     };
-    auto stash = [&](int b, const Raw &raw, float mz) {
+    // the staged value is the input times 0 or +-1, which is exact in the storage type
+    auto stash = [&](int b, const Stage &st) {
 #pragma unroll
         for (int q = 0; q < NL; q++) {
             const int e = tid + q * NT;
-            const float mul = smul[q] * mz;
+            const float mul = smul[q] * st.mz;
             if (e < LE) {
 #pragma unroll
                 for (int a = 0; a < NA; a++) {
-                    const double v = in.combine(raw[q][a]);
-                    buf[b][a][e] = (T)((mul != 0.0f) ? (double)mul * v : 0.0);
+                    const T v = (T)in.combine(st.raw[q][a]);
+                    buf[b][a][e] = mul == 0.0f ? (T)0 : (mul > 0.0f ? v : -v);
                 }
             }
         }
@@ -325,25 +346,17 @@ __device__ __forceinline__ bool zmarch_tile(const Geom &g, int tile, const In &i
 #pragma unroll
     for (int a = 0; a < NA; a++) column_init(col[a]);
 
-    // Planes mbeg..mend are staged; D planes are in flight in registers at any time (measured
-    // on the two-array sweeps: deeper pipelines cost more occupancy than they hide).
-    const int mbeg = k0 - 2, mend = k1 + 1;
-    Raw raw[D], raw0;
-    float mz[D], mz0;
-    fetch(mbeg, raw0, mz0);
+    Stage stage[D], stage0;
+    fetch(mbeg, stage0);
 #pragma unroll
-    for (int k = 0; k < D; k++) fetch(min(mbeg + 1 + k, mend), raw[k], mz[k]);
+    for (int k = 0; k < D; k++) fetch(mbeg + 1 + k, stage[k]);
     if (!begin()) return false;
-    stash(0, raw0, mz0);
+    stash(0, stage0);
     __syncthreads();
     int cur = 0;
     const int centre = (ly + 2) * LS + (lx + 2);
-    const int col_off = iy * g.ld + ix;  // in-plane offset of this lane's column (< 2^31)
-    constexpr bool kPre = HasPre<Out>::value;
-    using PreT = typename PreOf<Out>::type;
-    PreT pre1{}, pre2{};     // per-output data requested at planes m-1 and m-2
-    // consume plane m from LDS, stage plane m+1 from `r`, refill `r` with plane m+1+D
-    auto body = [&](int m, Raw &r, float &z) {
+    // consume plane m from LDS, stage plane m+1 from `st`, refill `st` with plane m+1+D
+    auto body = [&](int m, Stage &st) {
         double y[NA], c0[NA], cprev[NA];
 #pragma unroll
         for (int a = 0; a < NA; a++) {
@@ -354,26 +367,25 @@ __device__ __forceinline__ bool zmarch_tile(const Geom &g, int tile, const In &i
             if (m >= k0 && m < k1) out.centre((i64)m * plane + col_off, c0);
             const int k = m - 2;
             if (k >= k0 && k < k1) {
-                if constexpr (kPre) out.emit((i64)k * plane + col_off, y, cprev, pre2);
+                if constexpr (kPre) out.emit((i64)k * plane + col_off, y, cprev, st.pre);
                 else out.emit((i64)k * plane + col_off, y, cprev);
             }
-            if constexpr (kPre) {
-                pre2 = pre1;
-                if (m >= k0 && m < k1) pre1 = out.pre((i64)m * plane + col_off);
-            }
         }
-        stash(cur ^ 1, r, z);
-        fetch(min(m + 1 + D, mend), r, z);
+        stash(cur ^ 1, st);
+        fetch(m + 1 + D, st);
         __syncthreads();
         cur ^= 1;
     };
-    for (int m = mbeg; m <= mend; m += D) {
+    // Whole groups of D planes with no exit inside a group, then the remaining planes.
+    const int groups = (mend - mbeg + 1) / D;
+    int m = mbeg;
+    for (int grp = 0; grp < groups; grp++, m += D) {
 #pragma unroll
-        for (int k = 0; k < D; k++) {
-            if (m + k > mend) break;
-            body(m + k, raw[k], mz[k]);
-        }
+        for (int u = 0; u < D; u++) body(m + u, stage[u]);
     }
+#pragma unroll
+    for (int u = 0; u < D - 1; u++)
+        if (m + u <= mend) body(m + u, stage[u]);
     return true;
 }
 
@@ -452,10 +464,14 @@ struct OutResidual {        // r = b - A x, partial of r.r
     T *r;
     Pair *partials;
     Pair acc;
+    struct Pre {
+        double b;
+    };
     __device__ bool skip() const { return false; }
     __device__ void centre(i64, const double *) {}
-    __device__ void emit(i64 idx, const double *v, const double *) {
-        double rv = b[idx] - v[0];
+    __device__ Pre pre(i64 idx) const { return Pre{b[idx]}; }
+    __device__ void emit(i64 idx, const double *v, const double *, const Pre &pr) {
+        double rv = pr.b - v[0];
         r[idx] = (T)rv;
         dot2_acc(acc, rv, rv);
     }
@@ -474,10 +490,14 @@ struct OutResidualCast {
     float *rs32;
     Pair *partials;
     Pair acc;
+    struct Pre {
+        double b;
+    };
     __device__ bool skip() const { return false; }
     __device__ void centre(i64, const double *) {}
-    __device__ void emit(i64 idx, const double *v, const double *) {
-        const double rv = b[idx] - v[0];
+    __device__ Pre pre(i64 idx) const { return Pre{b[idx]}; }
+    __device__ void emit(i64 idx, const double *v, const double *, const Pre &pr) {
+        const double rv = pr.b - v[0];
         const float rf = (float)rv;
         r32[idx] = rf;
         rs32[idx] = rf;
@@ -544,16 +564,18 @@ struct OutPairApply {
 // Sweep A that also applies the previous iteration's update of the iterate, x += alpha p
 // (alpha and p of iteration j-1, which sweep B then leaves to it): the streams of x and p
 // move from the update sweep into this one, where p is read anyway.  The arithmetic is the
-// update sweep's.  x and p are read when the output is emitted: requesting them ahead (in
-// registers, two planes early) pushed the 64x16 tile's kernel past 128 registers, and the
-// spill's per-plane scratch traffic cost more than the latency it hid.  When the run stops
-// at the start of the launch, the update is applied on its own.
+// update sweep's; x and p of an output are requested with the march's loads.  When the run
+// stops at the start of the launch, the update is applied on its own.
 template <typename T>
 struct OutPairApplyX : OutPairApply<T> {
     double *x;
     const T *pold;               // p of iteration j-1 (the direction sweep A reads)
     const double *alpha_dev;     // alpha of iteration j-1
     double alpha;
+    struct Pre {
+        double x;
+        T p;
+    };
     __device__ void prepare() { alpha = wave_uniform(*alpha_dev); }
     // 0: running; 2: the run stops in this launch (a workgroup already decided it); 1: stopped
     // before this launch (nothing owed)
@@ -561,8 +583,9 @@ struct OutPairApplyX : OutPairApply<T> {
         const int s = *this->status;
         return s == kRunning ? 0 : (s == kStopping ? 2 : 1);
     }
-    __device__ void emit(i64 idx, const double *v, const double *c) {
-        x[idx] = x[idx] + alpha * (double)pold[idx];
+    __device__ Pre pre(i64 idx) const { return Pre{x[idx], pold[idx]}; }
+    __device__ void emit(i64 idx, const double *v, const double *c, const Pre &pr) {
+        x[idx] = pr.x + alpha * (double)pr.p;
         OutPairApply<T>::emit(idx, v, c);
     }
     __device__ void finish_output(i64 idx) { x[idx] = x[idx] + alpha * (double)pold[idx]; }
@@ -575,7 +598,7 @@ struct OutPairApplyX : OutPairApply<T> {
 //
 // Sweep A: p_new = r + beta p is marched (one array) for q = A p_new, which here only feeds
 // sigma = p*_new . q; p*_new = r* + beta p* is formed at the output from r* and p* requested
-// two planes ahead.  Stores p_new and p*_new.  Same values, roundings and products as
+// with the march's loads.  Stores p_new and p*_new.  Same values, roundings and products as
 // OutPairApply.
 template <typename T>
 struct OutDirSigma {
@@ -625,15 +648,20 @@ struct OutPairUpdate {
     const int *status;
     double alpha;
     Pair acc[2];
+    struct Pre {
+        double x;
+        T r, rs;
+    };
     template <class In>
     __device__ void bind(const In &in) { alpha = in.alpha; }
     __device__ bool skip() const { return *status != 0; }
     __device__ void centre(i64, const double *) {}
-    __device__ void emit(i64 idx, const double *v, const double *c) {
+    __device__ Pre pre(i64 idx) const { return Pre{x[idx], r[idx], rs[idx]}; }
+    __device__ void emit(i64 idx, const double *v, const double *c, const Pre &pr) {
         const T q0 = (T)v[0], q1 = (T)v[1];
-        x[idx] = x[idx] + alpha * c[0];
-        const double ri = (double)r[idx] - alpha * (double)q0;
-        const double si = (double)rs[idx] - alpha * (double)q1;
+        x[idx] = pr.x + alpha * c[0];
+        const double ri = (double)pr.r - alpha * (double)q0;
+        const double si = (double)pr.rs - alpha * (double)q1;
         const T rt = (T)ri, st = (T)si;
         r[idx] = rt;
         rs[idx] = st;

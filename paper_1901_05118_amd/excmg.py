@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 __all__ = [
-    "ExcmgError", "OK", "EINVAL", "ENOMEM", "ENOCONV", "EBREAKDOWN", "EHIP", "FP64", "MIXED",
+    "ExcmgError", "OK", "EINVAL", "ENOMEM", "ENOCONV", "EBREAKDOWN", "EHIP", "ENOCTX", "FP64",
+    "MIXED", "EXIT_TOL", "EXIT_CAP", "EXIT_FLOOR", "EXIT_BREAKDOWN",
     "BICG", "CG", "RELIABLE", "RESTART", "PRECOND_NONE", "PRECOND_JACOBI", "bicg_ex", "diagonal",
     "lib_path", "load", "set_stream", "setup", "apply_stencil", "apply_operator", "rhs", "dsolve", "bicg",
     "level_solve", "exp_finite", "exp_true", "solve", "solve_ex", "profile_sweep",
@@ -24,7 +25,8 @@ __all__ = [
     "LevelStats", "Stats",
 ]
 
-OK, EINVAL, ENOMEM, ENOCONV, EBREAKDOWN, EHIP = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, ENOCONV, EBREAKDOWN, EHIP, ENOCTX = 0, -1, -2, -3, -4, -5, -6
+EXIT_TOL, EXIT_CAP, EXIT_FLOOR, EXIT_BREAKDOWN = 0, 1, 2, 3
 FP64, MIXED = 0, 1
 BICG, CG = 0, 1
 RELIABLE, RESTART = 0, 1
@@ -55,7 +57,8 @@ class Opts(ctypes.Structure):
 class LevelStats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("iterations", ctypes.c_int), ("runs", ctypes.c_int),
                 ("status", ctypes.c_int), ("eps", ctypes.c_double),
-                ("rel_residual", ctypes.c_double), ("ms", ctypes.c_double)]
+                ("rel_residual", ctypes.c_double), ("ms", ctypes.c_double),
+                ("floor", ctypes.c_double), ("exit", ctypes.c_int)]
 
     def asdict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

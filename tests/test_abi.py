@@ -49,7 +49,7 @@ def test_bad_arguments_are_rejected(lib):
     assert lib.excmg_exp_true(7, c, c, c) == ex.EINVAL
     assert lib.excmg_apply_operator(1, 1, 0, c, c) == ex.EINVAL
     assert lib.excmg_apply_operator(8, 1, 0, None, None) == ex.EINVAL
-    assert lib.excmg_apply_stencil(0, 0, c, c) == ex.EINVAL  # no context
+    assert lib.excmg_apply_stencil(0, 0, c, c) == ex.ENOCTX  # no context
     assert "context" in ex.last_error()
 
 

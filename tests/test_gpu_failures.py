@@ -36,7 +36,49 @@ def test_nan_forcing_reports_breakdown(ex):
     u = torch.empty_like(f)
     rc, st = ex.solve_ex(32, 4, 1, f, g1, g2, 1e-8, u)
     assert rc == ex.EBREAKDOWN
-    assert any(l["status"] == ex.EBREAKDOWN for l in st.levels())
+    broken = [l for l in st.levels() if l["status"] == ex.EBREAKDOWN]
+    assert broken and all(l["exit"] == ex.EXIT_BREAKDOWN for l in broken)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batched_breakdown_ends_the_level_as_a_single_solve_does(ex, prec):
+    """A NaN in one problem of a batch: that problem's levels end as in a single solve (FP64:
+    the Bi-CG run breaks down, the level reports EBREAKDOWN and the cascade goes on; mixed
+    precision with restarts: the FP64 residual is not finite, so refinement stops at once),
+    and the other problem is unharmed."""
+    p = ex.FP64 if prec == "fp64" else ex.MIXED
+    arr, f, g1, g2 = _inputs()
+    f[16, 16, 16] = float("nan")
+    arr2, f2, g12, g22 = _inputs(3, 32, 2)
+    u_single = torch.empty_like(f)
+    rc1, st1 = ex.solve_ex(32, 4, 1, f, g1, g2, 1e-8, u_single, precision=p, refine=ex.RESTART)
+    assert rc1 == (ex.EBREAKDOWN if prec == "fp64" else ex.ENOCONV)
+    ub, ub2 = torch.empty_like(f), torch.empty_like(f2)
+    probs = [dict(n_finest=32, n_levels=4, bc_kind=1, f=f, g1=g1, g2=g2, u_out=ub),
+             dict(n_finest=32, n_levels=4, bc_kind=2, f=f2, g1=g12, g2=g22, u_out=ub2)]
+    rc, sts = ex.solve_batch(probs, 1e-8, precision=p)
+    assert rc == rc1
+    single = st1.levels()
+    batched = sts[0].levels()
+    assert [l["status"] for l in batched] == [l["status"] for l in single]
+    assert [l["exit"] for l in batched] == [l["exit"] for l in single]
+    assert [l["iterations"] for l in batched] == [l["iterations"] for l in single]
+    assert all(l["status"] == ex.OK for l in sts[1].levels())
+    if prec == "fp64":
+        np.testing.assert_array_equal(ub.cpu().numpy(), u_single.cpu().numpy())
+
+
+def test_call_without_context_returns_enoctx(ex):
+    ex.finalize()
+    x = torch.zeros(27, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    with pytest.raises(ex.ExcmgError) as e:
+        ex.apply_stencil(0, 0, x, y)
+    assert e.value.code == ex.ENOCTX
+    assert ex.load().excmg_profile_sweep(0, ex.FP64, 1, None, None) == ex.ENOCTX
+    # a context made afterwards works again
+    ex.setup(16, 3, 1)
+    ex.apply_stencil(0, 0, x, y)
 
 
 def test_iteration_cap_reports_no_convergence(ex):
@@ -46,6 +88,8 @@ def test_iteration_cap_reports_no_convergence(ex):
     assert rc == ex.ENOCONV
     lv = st.levels()
     assert all(l["iterations"] <= 6 for l in lv[2:])
+    # the tolerances are far above the floor: the caps stopped these levels
+    assert all(l["exit"] == ex.EXIT_CAP and l["eps"] > 10 * l["floor"] > 0 for l in lv[2:])
     assert np.isfinite(u.cpu().numpy()).all()
 
 
@@ -55,16 +99,22 @@ def test_tolerance_below_the_fp64_floor_stops(ex):
     arr = make_arrays(paper_problem(1), 32, 1)
     f, g1, g2 = dev(arr.f), dev(arr.g1), dev(arr.g2)
     u = torch.empty_like(f)
-    rc, st = ex.solve_ex(32, 3, 1, f, g1, g2, 1e-14, u, max_runs=3)
+    rc, st = ex.solve_ex(32, 3, 1, f, g1, g2, 1e-14, u, max_runs=5)
     assert rc == ex.ENOCONV
     last = st.levels()[-1]
-    assert last["runs"] == 3 and last["rel_residual"] > 1e-14
+    assert last["rel_residual"] > 1e-14
+    # the level's tolerance is below 10x the estimated floor, and the level stops as soon
+    # as a further run no longer halves the squared residual
+    assert 1e-14 < 10 * last["floor"] and last["exit"] == ex.EXIT_FLOOR
+    assert last["runs"] < 5
     for mode in (ex.RELIABLE, ex.RESTART):
         # refinement stops when a step no longer reduces the FP64 residual
         rc, st = ex.solve_ex(32, 3, 1, f, g1, g2, 1e-14, u, precision=ex.MIXED, refine=mode,
                              fp32_min_unknowns=1)
         assert rc == ex.ENOCONV
-        assert st.levels()[-1]["rel_residual"] < 1e-9
+        last = st.levels()[-1]
+        assert last["rel_residual"] < 1e-9
+        assert last["exit"] == ex.EXIT_FLOOR
 
 
 def test_solves_are_deterministic(ex):

@@ -281,6 +281,60 @@ def test_batch_fp64_matches_single_solves_and_oracle(ex, persistent):
         assert rel_l2(host(p["ut_out"]), ref.ut) <= 1e-10
 
 
+# Problem sizes of the 64-problem batch workload (32^3 ... 128^3 cells): coarsest grids of
+# 4 and 3 cells, both boundary kinds; from 96^3 on the grids split into several 64-wide
+# x tiles.
+BATCH_LARGE = [(64, 5, 2, 2), (96, 6, 1, 3), (128, 6, 2, 4)]
+_LARGE_REF = {}
+
+
+def _large_ref(N, nl, bc, c, arr):
+    key = (N, nl, bc, c)
+    if key not in _LARGE_REF:
+        print(f"oracle {N}^3 bc={bc}", flush=True)
+        _LARGE_REF[key] = O.excmg(N, nl, bc, arr.f, arr.g1, arr.g2, 1e-9)
+    return _LARGE_REF[key]
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_batch_fp64_large_grids_match_single_solves_and_oracle(ex, persistent):
+    data = _batch_inputs([(N, nl, bc, config_problem(c)) for (N, nl, bc, c) in BATCH_LARGE])
+    probs = [dict(n_finest=N, n_levels=nl, bc_kind=bc, f=f, g1=g1, g2=g2,
+                  u_out=torch.empty_like(f), ut_out=torch.empty_like(f))
+             for (N, nl, bc, arr, f, g1, g2) in data]
+    rc, stats = ex.solve_batch(probs, 1e-9, persistent=persistent)
+    assert rc == ex.OK, ex.last_error()
+    for (N, nl, bc, arr, f, g1, g2), item, p, st in zip(data, BATCH_LARGE, probs, stats):
+        print(f"batch N={N} bc={bc}", [l["iterations"] for l in st.levels()], flush=True)
+        u1 = torch.empty_like(f)
+        rc1, st1 = ex.solve_ex(N, nl, bc, f, g1, g2, 1e-9, u1)
+        assert rc1 == ex.OK
+        assert [l["iterations"] for l in st.levels()] == [l["iterations"] for l in st1.levels()]
+        np.testing.assert_array_equal(host(p["u_out"]), host(u1))
+        ref = _large_ref(N, nl, bc, item[3], arr)
+        assert [l["iterations"] for l in st.levels()[2:]] == [l.iters for l in ref.levels]
+        assert rel_l2(host(p["u_out"]), ref.u) <= 1e-10
+        assert rel_l2(host(p["ut_out"]), ref.ut) <= 1e-10
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_batch_mixed_large_grids_meet_tolerance_and_accuracy(ex, persistent):
+    data = _batch_inputs([(N, nl, bc, config_problem(c)) for (N, nl, bc, c) in BATCH_LARGE])
+    probs = [dict(n_finest=N, n_levels=nl, bc_kind=bc, f=f, g1=g1, g2=g2,
+                  u_out=torch.empty_like(f)) for (N, nl, bc, arr, f, g1, g2) in data]
+    rc, stats = ex.solve_batch(probs, 1e-9, precision=ex.MIXED, persistent=persistent)
+    assert rc == ex.OK, ex.last_error()
+    for (N, nl, bc, arr, f, g1, g2), item, p, st in zip(data, BATCH_LARGE, probs, stats):
+        u = host(p["u_out"]).reshape((N + 1,) * 3)
+        b = O.rhs(N, bc, arr.f, arr.g1, arr.g2)
+        r = O.residual(N, bc, b, O.interior(u))
+        assert np.sqrt(O.dot(r, r) / O.dot(b, b)) <= 1e-9
+        ref = _large_ref(N, nl, bc, item[3], arr)
+        e_fp64 = O.norm2(ref.u - arr.u)
+        assert abs(O.norm2(u - arr.u) - e_fp64) <= 0.01 * e_fp64
+        print(f"batch mixed N={N}: max |u - u_oracle| = {np.abs(u - ref.u).max():.3e}", flush=True)
+
+
 def test_batch_mixed_meets_tolerance_and_accuracy(ex):
     data = _batch_problems()
     probs = [dict(n_finest=N, n_levels=nl, bc_kind=bc, f=f, g1=g1, g2=g2,
@@ -535,3 +589,26 @@ def test_cg_specialisation_is_bit_identical_to_bicg(ex, prec, case, form):
     assert rc1 == rc2 == ex.OK
     assert [l["iterations"] for l in st1.levels()] == [l["iterations"] for l in st2.levels()]
     np.testing.assert_array_equal(host(u_b), host(u_c))
+    # against the oracle (Algorithm 2 with r*_0 = r_0, both products, in FP64)
+    ref = _cg_oracle(N, nl, bc, c)
+    uc = host(u_c).reshape((N + 1,) * 3)
+    if prec == "fp64":
+        assert [l["iterations"] for l in st2.levels()[2:]] == [l.iters for l in ref.levels]
+        assert rel_l2(uc, ref.u) <= 1e-10
+    else:
+        b = O.rhs(N, bc, arr.f, arr.g1, arr.g2)
+        r = O.residual(N, bc, b, O.interior(uc))
+        assert np.sqrt(O.dot(r, r) / O.dot(b, b)) <= 1e-9
+        e_ref = O.norm2(ref.u - arr.u)
+        assert abs(O.norm2(uc - arr.u) - e_ref) <= 0.01 * e_ref
+
+
+_CG_ORACLE = {}
+
+
+def _cg_oracle(N, nl, bc, c):
+    key = (N, nl, bc, c)
+    if key not in _CG_ORACLE:
+        arr = make_arrays(config_problem(c), N, bc)
+        _CG_ORACLE[key] = O.excmg(N, nl, bc, arr.f, arr.g1, arr.g2, 1e-9)
+    return _CG_ORACLE[key]

@@ -88,6 +88,25 @@ def test_level_solve_restarts_until_true_residual():
     assert st.rr_true == O.dot(r, r)
 
 
+def test_level_solve_stops_at_the_fp64_floor():
+    """The while loop of Algorithm 1 cannot push the true residual below the FP64 floor:
+    with zero boundary data (paper Problem 1) the floor at 16^3 is ~7e-13 relative.  A
+    tolerance of 1e-15 (below 10x the estimate 22 u ||x|| / ||b||) ends the level as soon
+    as a run no longer halves r.r, long before max_runs; the estimate is within two orders
+    of the floor actually reached; a tolerance above the floor converges."""
+    from manufactured import make_arrays, paper_problem
+    N = 16
+    arr = make_arrays(paper_problem(1), N, 1)
+    b = O.rhs(N, 1, arr.f, arr.g1, arr.g2)
+    x, st = O.level_solve(N, 1, b, np.zeros((N - 1) ** 3), 1e-15, max_runs=20)
+    assert st.code == O.ENOCONV and st.runs < 5
+    reached = np.sqrt(st.rr_true / st.bb)
+    est = 22 * 2.0 ** -53 * np.sqrt(O.dot(x, x) / O.dot(b, b))
+    assert 1e-15 < 10 * est and est < reached < 100 * est
+    x, st = O.level_solve(N, 1, b, np.zeros((N - 1) ** 3), 1e-11, max_runs=20)
+    assert st.code == O.OK and np.sqrt(st.rr_true / st.bb) <= 1e-11
+
+
 def test_level_solve_skips_converged_start():
     N = 6
     n = (N - 1) ** 3
