@@ -37,27 +37,77 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-# Grids from which Bi-CG takes the recomputing form (the library's default)
+# Grids from which Bi-CG takes the recomputing form, and from which mixed solves use FP32
+# vectors (the library's defaults)
 RECOMPUTE_MIN = 1 << 22
+FP32_MIN = 1 << 18
+
+
+def update_depth(ty):
+    """Planes in flight of the recomputing form's update sweep (the library's choice)."""
+    return 2 if ty >= 16 else 3
+
+
+def update_blocks(nu):
+    """Workgroups of the streaming Bi-CG update kernels (the library's choice)."""
+    b = -(-nu // (512 * 4)) if nu > (1 << 18) else -(-nu // 512)
+    return max(1, min(b, 1024))
 
 
 def sweep_launch(N, ty, zc, form):
-    """Name (as the profiler shows it) and launch size in threads of a Bi-CG stencil sweep on
-    the grid of N cells with tiles of 64 x ty columns and zc planes.  form: "fp64" (sweep A),
-    "deferred" (mixed sweep A that also applies the previous iteration's x update),
-    "sigma" / "update" (the two sweeps of the recomputing form, FP32 vectors), "sigma64" /
-    "update64" (the same with FP64 vectors)."""
+    """Name (as the profiler shows it) and launch size in threads of a Bi-CG sweep on the
+    grid of N cells with stencil tiles of 64 x ty columns and zc planes.  form: "sigma" /
+    "update" (the two sweeps of the recomputing form, FP32 vectors), "sigma64" / "update64"
+    (the same with FP64 vectors), "fp64" / "stored32" (sweep A of the stored form), "deferred"
+    (FP32 sweep A that also applies the previous iteration's x update), "update_stored64" /
+    "update32" (the stored form's streaming sweep B)."""
     n = N - 1
+    if form in ("update32", "update_stored64"):
+        t = "float" if form == "update32" else "double"
+        return f"k_bicg_update<double, {t}, false>", update_blocks(n ** 3) * 512
     tiles = -(-n // 64) * -(-n // ty) * -(-n // zc)
     tiles = -(-tiles // 8) * 8  # the grid is padded to whole XCD shares
+    d = update_depth(ty)
     # the last template argument: planes in flight
     name = {"fp64": "zmarch<2, {ty}, double, InDirection<double>, OutPairApply<double>, 2>",
+            "stored32": "zmarch<2, {ty}, float, InDirection<float>, OutPairApply<float>, 2>",
             "deferred": "zmarch<2, {ty}, float, InDirection<float>, OutPairApplyX<float>, 2>",
             "sigma": "zmarch<1, {ty}, float, InDirection<float>, OutDirSigma<float>, 3>",
-            "update": "zmarch<2, {ty}, float, InPlainAlpha<float>, OutPairUpdate<float>, 2>",
+            "update": "zmarch<2, {ty}, float, InPlainAlpha<float>, OutPairUpdate<float>, {d}>",
             "sigma64": "zmarch<1, {ty}, double, InDirection<double>, OutDirSigma<double>, 3>",
-            "update64": "zmarch<2, {ty}, double, InPlainAlpha<double>, OutPairUpdate<double>, 2>"}[form]
-    return name.format(ty=ty), tiles * 64 * ty
+            "update64": "zmarch<2, {ty}, double, InPlainAlpha<double>, OutPairUpdate<double>, {d}>"}[form]
+    return name.format(ty=ty, d=d), tiles * 64 * ty
+
+
+class _Forms(dict):
+    fp32 = False
+
+
+def sweep_forms(N, mixed):
+    """The Bi-CG sweeps a solve runs on the level of N cells, as {timing kind: (kernel form,
+    algorithmic bytes per unknown, label)}; timing kinds as excmg_get_timing's (0 sweep A,
+    1 sweep B, 2 sweep A applying the deferred iterate update).  Mixed solves run FP32
+    vectors from 2^18 unknowns up (smaller levels FP64); both precisions take the
+    recomputing form from 2^22 unknowns up.  Bytes: recomputing form, sweep A reads r, p,
+    r*, p* and writes p, p* (FP32 24, FP64 48), sweep B reads p, p*, r, r* and the FP64
+    iterate and writes r, r*, x (FP32 40, FP64 64); stored form, FP64: sweep A reads r, r*,
+    p, p* and writes p, p*, q, q* (64), sweep B reads x, p, r, q, r*, q* and writes x, r, r*
+    (72); stored form with FP32 vectors: sweep A 32 (48 when it also applies the previous
+    iteration's x += alpha p), sweep B streams r, q, r*, q* and writes r, r* (24)."""
+    nu = (N - 1) ** 3
+    f = _Forms()
+    f.fp32 = mixed and nu >= FP32_MIN
+    if nu >= RECOMPUTE_MIN:
+        if f.fp32:
+            f.update({0: ("sigma", 24.0, "A"), 1: ("update", 40.0, "B")})
+        else:
+            f.update({0: ("sigma64", 48.0, "A"), 1: ("update64", 64.0, "B")})
+    elif f.fp32:
+        f.update({0: ("stored32", 32.0, "A"), 2: ("deferred", 48.0, "A+x"),
+                  1: ("update32", 24.0, "B")})
+    else:
+        f.update({0: ("fp64", 64.0, "A"), 1: ("update_stored64", 72.0, "B")})
+    return f
 
 
 def recorded_traffic(kernel, grid):
@@ -83,21 +133,95 @@ def recorded_traffic(kernel, grid):
     return None, None
 
 
-def cpu_baseline(arr, N, nl, bc, iters):
-    """The oracle's Bi-CG on the finest level of the same problem, a few iterations."""
+def cpu_model():
+    """CPU model, physical cores and threads per core of this host (lscpu)."""
+    import subprocess
+    info = {}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            info[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        phys = int(info["Core(s) per socket"]) * int(info["Socket(s)"])
+    except (KeyError, ValueError):
+        phys = None
+    return info.get("Model name"), phys, info.get("Thread(s) per core")
+
+
+# FP64 Bi-CG iteration in the algorithmic-bytes convention of the GPU sweeps (recomputing
+# form: sweep A 48 + sweep B 64 bytes per unknown)
+FP64_ITERATION_BYTES = 112.0
+
+
+def cpu_baseline(arr, N, nl, bc, iters, cfg_sols):
+    """The oracle (plain FP64 C with OpenMP, never tuned for speed) on the host cores:
+    (a) Bi-CG iterations on the finest level of the headline problem, median of 3 runs;
+    (b) the same on a 128^3 level with one thread, median of 3; (c) its time to solution of
+    configurations 1 (32^3, median of 3) and 2 (128^3, one run), with the max-norm
+    distance of the GPU's FP64 and mixed solutions of the same inputs to its solution."""
+    import statistics
+
     import numpy as np
     import oracle
+    from manufactured import config_problem, make_arrays
+
+    model, phys, tpc = cpu_model()
+    threads = oracle.threads()
+
+    def bicg_rate(Nl, bcl, b, its):
+        x0 = np.zeros((Nl - 1) ** 3)
+        t0 = time.perf_counter()
+        _, it, _, _ = oracle.bicg(Nl, bcl, b, x0, 1e-30, maxit=its)
+        dt = time.perf_counter() - t0
+        return (Nl - 1) ** 3 * it / dt / 1e9, it, dt
 
     b = oracle.rhs(N, bc, arr.f, arr.g1, arr.g2)
-    x0 = np.zeros((N - 1) ** 3)
-    t0 = time.perf_counter()
-    _, it, _, _ = oracle.bicg(N, bc, b, x0, 1e-30, maxit=iters)
-    dt = time.perf_counter() - t0
-    nu = (N - 1) ** 3
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": nu * it / dt / 1e9, "unit": "GLUPS", "cores": cores, "kind": "oracle",
-            "sample": f"{it} Bi-CG iterations (plus the initial residual) of the oracle on the "
-                      f"{N}^3-cell finest level of the same problem, {dt:.1f} s"}
+    runs = [bicg_rate(N, bc, b, iters) for _ in range(3)]
+    glups = statistics.median(r[0] for r in runs)
+    it_done = runs[0][1]
+    t_each = statistics.median(r[2] for r in runs)
+    del b
+    # one thread, 128^3 level of configuration 2
+    arr2 = make_arrays(config_problem(2), 128, 2)
+    b2 = oracle.rhs(128, 2, arr2.f, arr2.g1, arr2.g2)
+    oracle.set_threads(1)
+    try:
+        one = [bicg_rate(128, 2, b2, 3) for _ in range(3)]
+    finally:
+        oracle.set_threads(threads)
+    glups1 = statistics.median(r[0] for r in one)
+    # time to solution of configurations 1 and 2
+    tts = {}
+    for c, Nc, nlc, bcc, tol, reps in ((1, 32, 4, 1, 1e-10, 3), (2, 128, 6, 2, 1e-10, 1)):
+        a = make_arrays(config_problem(c), Nc, bcc)
+        times = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            ref = oracle.excmg(Nc, nlc, bcc, a.f, a.g1, a.g2, tol)
+            times.append(time.perf_counter() - t0)
+        ms = statistics.median(times) * 1e3
+        lups = sum((lv.N - 1) ** 3 * lv.iters for lv in ref.levels)
+        entry = {"ms": round(ms, 1), "runs": reps, "glups": round(lups / (ms * 1e-3) / 1e9, 4),
+                 "iterations": [lv.iters for lv in ref.levels]}
+        for name, ug in cfg_sols.get(c, {}).items():
+            entry[f"gpu_{name}_max_dist"] = float(np.abs(ug - ref.u.reshape(ug.shape)).max())
+        tts[f"config{c}"] = entry
+        log(f"oracle config {c}: {entry}")
+    return {"value": glups, "unit": "GLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{it_done} Bi-CG iterations (plus the initial residual) of the oracle on "
+                      f"the {N}^3-cell finest level of the same problem, median of 3 runs of "
+                      f"{t_each:.1f} s on {threads} OpenMP threads",
+            "gbs": round(glups * FP64_ITERATION_BYTES, 2),
+            "gbs_convention": "FP64 Bi-CG iteration, 112 algorithmic bytes per unknown",
+            "cpu_model": model, "physical_cores": phys, "threads_per_core": tpc,
+            "one_thread_128": {"value": glups1, "unit": "GLUPS",
+                               "gbs": round(glups1 * FP64_ITERATION_BYTES, 3),
+                               "sample": "3 Bi-CG iterations on the 128^3 level of "
+                                         "configuration 2, median of 3 runs, 1 thread"},
+            "time_to_solution": tts}
 
 
 def plane_leg(ex, torch, np, steps):
@@ -131,15 +255,16 @@ def plane_leg(ex, torch, np, steps):
     return res
 
 
-def configs_leg(ex, torch, np, steps):
+def configs_leg(ex, torch, np, steps, kept):
     """The smaller configurations of the same family: 32^3 cells, first kind, FP64 to 1e-10
-    (4 levels); 128^3, second kind, FP64 to 1e-10 (6 levels); 256^3, first kind, mixed and
-    FP64 to 1e-8 (7 levels).  Time to solution, Bi-CG GLUPS, the max-norm error against the
-    exact solution and, for the mixed solve, against the FP64 one."""
+    (4 levels); 128^3, second kind, to 1e-10 (6 levels); 256^3, first kind, to 1e-8 (7
+    levels); each in FP64 and mixed precision.  Time to solution, Bi-CG GLUPS, the max-norm error against the
+    exact solution and, for the mixed solve, against the FP64 one.  The solutions of
+    configurations 1 and 2 are kept in `kept` for the comparison with the oracle."""
     from manufactured import config_problem, make_arrays
     res = {}
-    for c, N, nl, bc, tol, precs in ((1, 32, 4, 1, 1e-10, ("fp64",)),
-                                      (2, 128, 6, 2, 1e-10, ("fp64",)),
+    for c, N, nl, bc, tol, precs in ((1, 32, 4, 1, 1e-10, ("fp64", "mixed")),
+                                      (2, 128, 6, 2, 1e-10, ("fp64", "mixed")),
                                       (3, 256, 7, 1, 1e-8, ("fp64", "mixed"))):
         arr = make_arrays(config_problem(c), N, bc)
         f, g1, g2 = (torch.from_numpy(a).cuda() for a in (arr.f, arr.g1, arr.g2))
@@ -166,8 +291,11 @@ def configs_leg(ex, torch, np, steps):
                            "max_err_vs_exact": float(np.abs(ug - arr.u).max())}
         if "mixed" in sols:
             entry["mixed_vs_fp64_max"] = float(np.abs(sols["mixed"] - sols["fp64"]).max())
+            entry["speedup_mixed"] = round(entry["fp64"]["ms"] / entry["mixed"]["ms"], 3)
         log(f"config {c}: {entry}")
         res[f"config{c}"] = entry
+        if c in (1, 2):
+            kept[c] = sols
         del f, g1, g2, u
     return res
 
@@ -191,7 +319,9 @@ def jacobi_leg(ex, torch, np, N, nl, bc, tol, f, g1, g2, u, steps):
 
 def batch_leg(ex, torch, np):
     """64 independent problems of 32^3..128^3 cells (mixed boundary kinds), tol 1e-8:
-    batched against one solve after another, FP64 and mixed precision."""
+    batched (both forms: four graph-captured phase launches per Bi-CG step, and one
+    persistent work-queue launch per step) against one solve after another, FP64 and mixed
+    precision."""
     from manufactured import batch_problems, make_arrays
     items = batch_problems(64)
     dev = torch.device("cuda:0")
@@ -210,12 +340,13 @@ def batch_leg(ex, torch, np):
         probs = [dict(n_finest=it.N, n_levels=it.n_levels, bc_kind=it.bc, f=f, g1=g1, g2=g2,
                       u_out=u) for (it, f, g1, g2, u) in data]
 
-        def bat():
-            rc, _ = ex.solve_batch(probs, 1e-8, precision=prec)
+        def bat(persistent):
+            rc, _ = ex.solve_batch(probs, 1e-8, precision=prec, persistent=persistent)
             if rc != ex.OK:
                 raise RuntimeError(ex.last_error())
         times = {}
-        for label, fn in (("sequential", seq), ("batched", bat)):
+        for label, fn in (("sequential", seq), ("batched", lambda: bat(False)),
+                          ("batched_persistent", lambda: bat(True))):
             fn()  # warm-up
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -225,8 +356,28 @@ def batch_leg(ex, torch, np):
         log(f"batch {name}: {times}")
         res[name] = {"sequential_ms": round(times["sequential"], 1),
                      "batched_ms": round(times["batched"], 1),
-                     "speedup": round(times["sequential"] / times["batched"], 2)}
+                     "batched_persistent_ms": round(times["batched_persistent"], 1),
+                     "speedup": round(times["sequential"] / times["batched"], 2),
+                     "speedup_persistent": round(times["sequential"] /
+                                                 times["batched_persistent"], 2)}
     return res
+
+
+def profile_sweeps(ex, args):
+    """Launch single solver sweeps for profiler and hardware-counter runs (see --help)."""
+    prec = ex.MIXED if args.precision == "mixed" else ex.FP64
+    ex.setup(args.n, args.levels, args.bc)
+    ty, zc = ex.get_shape(args.n, 2 if prec == ex.MIXED else 1)
+    print(f"n={args.n} bc={args.bc} precision={args.precision} sweep A tile 64x{ty}, "
+          f"{zc} planes per tile", flush=True)
+    runs = [(int(w), prec) for w in args.profile_sweeps.split(",") if w.strip()]
+    runs.append((4, ex.FP64))   # the copy of known traffic
+    for which, p in runs:
+        ms, nb = ex.profile_sweep(which, p, args.reps)
+        print(f"sweep {which} {'fp64' if p == ex.FP64 else 'mixed'}: {args.reps} launches, "
+              f"{ms:.4f} ms/launch, {nb:.6g} bytes/launch, {nb / (ms * 1e-3) / 1e9:.1f} GB/s",
+              flush=True)
+    ex.finalize()
 
 
 def main():
@@ -239,7 +390,8 @@ def main():
     ap.add_argument("--bc", type=int, default=2)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--config", type=int, default=4, help="seeded problem family (1-4)")
-    ap.add_argument("--cpu-iters", type=int, default=4)
+    ap.add_argument("--cpu-iters", type=int, default=2,
+                    help="oracle Bi-CG iterations per timed run on the finest level")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch leg")
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D (4096^2) leg")
@@ -251,6 +403,15 @@ def main():
                          "the 2D mixed solve")
     ap.add_argument("--autotune", action="store_true",
                     help="re-time every tile shape first instead of the built-in tuned table")
+    ap.add_argument("--profile-sweeps", default="",
+                    help="only launch the listed solver sweeps (excmg_profile_sweep numbers, "
+                         "e.g. 7,8) on the finest level of --n/--levels/--bc, --reps times "
+                         "each after one warm-up launch, then as many FP64 copies of one "
+                         "finest-level vector (the calibration kernel of the HBM byte "
+                         "counters); for profiler and counter runs; prints one line per sweep")
+    ap.add_argument("--precision", choices=("fp64", "mixed"), default="mixed",
+                    help="vectors of the --profile-sweeps launches")
+    ap.add_argument("--reps", type=int, default=5, help="launches per sweep (--profile-sweeps)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the solver has no multi-GPU path (one "
@@ -265,6 +426,9 @@ def main():
     from manufactured import config_problem, make_arrays
 
     torch.cuda.set_device(0)
+    if args.profile_sweeps:
+        profile_sweeps(ex, args)
+        return
     if args.only_2d:
         ex.set_stream(torch.cuda.current_stream())
         res = plane_leg(ex, torch, np, args.steps)
@@ -354,73 +518,83 @@ def main():
     glups = head["glups"]
     levels = head["levels"]
 
-    # Roofline of the dominant kernel on the finest level: one more solve of the headline
-    # form with every sweep bracketed by device events on the library stream; achieved =
-    # algorithmic bytes per launch / mean duration.
+    # Roofline: one more solve of the headline form with every Bi-CG sweep bracketed by
+    # device events on the library stream; per level and sweep, achieved = algorithmic
+    # bytes per launch / mean duration.  The headline kernel is the (level, sweep) with the
+    # largest share of the step's time.
     prec = ex.MIXED if gate else ex.FP64
     ex.set_timing(True)
     st_t = solve(prec)
     if [lv["iterations"] for lv in st_t.levels()] != [lv["iterations"] for lv in levels]:
         raise RuntimeError("the event-timed solve took other iterations than the timed one")
-    nu = (N - 1) ** 3
-    rq = nu >= RECOMPUTE_MIN
-    # Bytes per unknown.  Recomputing form: sweep A reads r, p, r*, p* and writes p, p*
-    # (mixed 24, FP64 48); sweep B reads p, p*, r, r* and x (FP64) and writes r, r*, x
-    # (mixed 40, FP64 64).  Stored form, FP64: sweep A reads r, r*, p, p* and writes p, p*,
-    # q, q* (64); sweep B reads x, p, r, q, r*, q* and writes x, r, r* (72).  Stored form,
-    # mixed: sweep A also applies x += alpha p of the previous iteration (48); sweep B
-    # streams r, q, r*, q* and writes r, r* (24).
-    if rq and gate:
-        form_a, form_b, bytes_a, bytes_b, kind_a = "sigma", "update", 24.0, 40.0, 0
-    elif rq:
-        form_a, form_b, bytes_a, bytes_b, kind_a = "sigma64", "update64", 48.0, 64.0, 0
-    elif gate:
-        # the sweep A that applies the deferred x update (the first of each run, which owes
-        # none, is the plain kernel and is timed apart)
-        form_a, form_b, bytes_a, bytes_b, kind_a = "deferred", None, 48.0, 24.0, 2
-    else:
-        form_a, form_b, bytes_a, bytes_b, kind_a = "fp64", None, 64.0, 72.0, 0
-    bytes_a, bytes_b = bytes_a * nu, bytes_b * nu
-    ms_a, n_a = ex.get_timing(nl - 1, kind_a)
-    ms_b, n_b = ex.get_timing(nl - 1, 1)
+    per_level = []
+    for li, lv in enumerate(st_t.levels()):
+        if li < 2:
+            continue
+        n_l = lv["n"]
+        forms = sweep_forms(n_l, gate)
+        for kind, (form, bpu, label) in forms.items():
+            ms_tot, nl_ = ex.get_timing(li, kind)
+            if nl_ == 0:
+                continue
+            nu_l = (n_l - 1) ** 3
+            ty_l, zc_l = ex.get_shape(n_l, 2 if forms.fp32 else 1)
+            kname, grid = sweep_launch(n_l, ty_l, zc_l, form)
+            bpl = bpu * nu_l
+            avg = ms_tot / nl_
+            per_level.append({"n": n_l, "sweep": label, "kernel": kname, "grid": grid,
+                              "tile": f"64x{ty_l}, {zc_l} planes", "launches": nl_,
+                              "ms_total": round(ms_tot, 3), "ms_per_launch": round(avg, 5),
+                              "bytes_per_unknown": bpu, "bytes_per_launch": bpl,
+                              "gbs": round(bpl / (avg * 1e-3) / 1e9, 1),
+                              "frac": round(bpl / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
     ex.set_timing(False)
-    avg_a, avg_b = ms_a / max(n_a, 1), ms_b / max(n_b, 1)
+    swept_ms = sum(e["ms_total"] for e in per_level)
+    swept_bytes = sum(e["bytes_per_launch"] * e["launches"] for e in per_level)
+    dom = max(per_level, key=lambda e: e["ms_total"])
+    traffic, traffic_src = recorded_traffic(dom["kernel"], dom["grid"])
     ms_c, bytes_c = ex.profile_sweep(4, ex.FP64, reps=10)
     # the stencil alone: y = A x on the finest level (FP64, 16 bytes per unknown)
+    nu = (N - 1) ** 3
     ms_s, bytes_s = ex.profile_sweep(0, ex.FP64, reps=10)
-    ty_s, zc_s = ex.get_shape(N, 2 if gate else 1)
-    sweeps = {"A": {"launches": n_a, "ms_per_launch": round(avg_a, 4),
-                    "bytes_per_launch": bytes_a,
-                    "gbs": round(bytes_a / (avg_a * 1e-3) / 1e9, 1)},
-              "B": {"launches": n_b, "ms_per_launch": round(avg_b, 4),
-                    "bytes_per_launch": bytes_b,
-                    "gbs": round(bytes_b / (avg_b * 1e-3) / 1e9, 1)}}
-    # the dominant kernel: the stencil sweep that takes longer
-    dom = "B" if (form_b and avg_b > avg_a) else "A"
-    kname, grid = sweep_launch(N, ty_s, zc_s, form_b if dom == "B" else form_a)
-    traffic, traffic_src = recorded_traffic(kname, grid)
-    d = sweeps[dom]
-    roofline = {"bound": "hbm", "achieved": d["gbs"], "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(d["gbs"] / HBM_PEAK_GBS, 4),
+    finest = [e for e in per_level if e["n"] == N]
+    pair_of = lambda n_l: [e for e in per_level if e["n"] == n_l]  # noqa: E731
+    dom_pair = pair_of(dom["n"])
+    roofline = {"bound": "hbm", "achieved": dom["gbs"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": dom["frac"],
                 "traffic": None if traffic is None else round(traffic),
                 "traffic_source": traffic_src,
-                "kernel": f"{kname} (Bi-CG sweep {dom}, {N}^3 level, tile 64x{ty_s}, "
-                          f"{zc_s} planes, {grid} threads)",
-                "launches": d["launches"], "ms_per_launch": d["ms_per_launch"],
-                "bytes_per_launch": d["bytes_per_launch"],
-                "other_sweep": dict(sweeps["B" if dom == "A" else "A"],
-                                    name="B" if dom == "A" else "A"),
-                # one Bi-CG iteration (both sweeps): 64 (mixed) or 112 (FP64) bytes per
-                # unknown in the recomputing form, 72 or 136 in the stored one
-                "iteration": {"ms": round(avg_a + avg_b, 4),
-                              "gbs": round((bytes_a + bytes_b) / ((avg_a + avg_b) * 1e-3) / 1e9, 1),
-                              "frac": round((bytes_a + bytes_b) / ((avg_a + avg_b) * 1e-3) / 1e9
-                                            / HBM_PEAK_GBS, 4)},
-                "stencil_apply": {"ms_per_launch": round(ms_s, 4),
+                "kernel": f"{dom['kernel']} (Bi-CG sweep {dom['sweep']}, {dom['n']}^3 level, "
+                          f"tile {dom['tile']}, {dom['grid']} threads)",
+                "share_of_step": round(dom["ms_total"] / ms_step, 4),
+                "launches": dom["launches"], "ms_per_launch": dom["ms_per_launch"],
+                "bytes_per_launch": dom["bytes_per_launch"],
+                # the dominant level's Bi-CG iteration (all its sweeps, time-weighted)
+                "dominant_level_iteration": {
+                    "n": dom["n"],
+                    "gbs": round(sum(e["bytes_per_launch"] * e["launches"] for e in dom_pair)
+                                 / (sum(e["ms_total"] for e in dom_pair) * 1e-3) / 1e9, 1),
+                    "frac": round(sum(e["bytes_per_launch"] * e["launches"] for e in dom_pair)
+                                  / (sum(e["ms_total"] for e in dom_pair) * 1e-3) / 1e9
+                                  / HBM_PEAK_GBS, 4)},
+                # every timed Bi-CG sweep of the step, weighted by its time
+                "all_sweeps_time_weighted": {
+                    "ms": round(swept_ms, 2), "share_of_step": round(swept_ms / ms_step, 4),
+                    "gbs": round(swept_bytes / (swept_ms * 1e-3) / 1e9, 1),
+                    "frac": round(swept_bytes / (swept_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+                # the same bytes over the whole step's wall time (direct solves, transfers,
+                # residual replacements, polls and launch gaps included)
+                "step_effective": {
+                    "gbs": round(swept_bytes / (ms_step * 1e-3) / 1e9, 1),
+                    "frac": round(swept_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+                "levels": per_level,
+                "finest_level": finest,
+                "stencil_apply": {"n": N, "ms_per_launch": round(ms_s, 4),
                                   "glups": round(nu / (ms_s * 1e-3) / 1e9, 1),
                                   "gbs": round(bytes_s / (ms_s * 1e-3) / 1e9, 1),
                                   "frac": round(bytes_s / (ms_s * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
-                "copy_gbs": round(bytes_c / (ms_c * 1e-3) / 1e9, 1)}
+                "copy_gbs": round(bytes_c / (ms_c * 1e-3) / 1e9, 1),
+                "copy_frac": round(bytes_c / (ms_c * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
     out = {
         "metric": METRIC, "value": round(glups, 3), "unit": "GLUPS", "n_gpus": 1,
@@ -459,11 +633,12 @@ def main():
         out["batch"] = batch_leg(ex, torch, np)
     if not args.no_2d:
         out["plane_2d"] = plane_leg(ex, torch, np, args.steps)
+    kept = {}
     if not args.no_configs:
-        out["configs"] = configs_leg(ex, torch, np, args.steps)
+        out["configs"] = configs_leg(ex, torch, np, args.steps, kept)
     if not args.no_cpu:
         log("cpu baseline")
-        out["cpu_baseline"] = cpu_baseline(arr, N, nl, bc, args.cpu_iters)
+        out["cpu_baseline"] = cpu_baseline(arr, N, nl, bc, args.cpu_iters, kept)
     print(json.dumps(out), flush=True)
 
 
