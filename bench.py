@@ -339,6 +339,14 @@ def batch_leg(ex, torch, np):
                     raise RuntimeError(ex.last_error())
         probs = [dict(n_finest=it.N, n_levels=it.n_levels, bc_kind=it.bc, f=f, g1=g1, g2=g2,
                       u_out=u) for (it, f, g1, g2, u) in data]
+        # the batched sweep A's shapes, tuned on this batch's own work list
+        t0 = time.perf_counter()
+        ty, ms_step = ex.autotune_batch(probs, precision=prec, reps=3)
+        tune_s = time.perf_counter() - t0
+        shapes = {int(N): list(ex.get_batch_shape(int(N), prec))
+                  for N in sorted({it.N for it in items})}
+        log(f"batch {name}: tuned tile height {ty}, shapes {shapes}, {ms_step:.3f} ms per step "
+            f"({tune_s:.1f} s)")
 
         def bat(persistent):
             rc, _ = ex.solve_batch(probs, 1e-8, precision=prec, persistent=persistent)
@@ -354,7 +362,10 @@ def batch_leg(ex, torch, np):
             torch.cuda.synchronize()
             times[label] = (time.perf_counter() - t0) * 1e3
         log(f"batch {name}: {times}")
-        res[name] = {"sequential_ms": round(times["sequential"], 1),
+        res[name] = {"tuned_shapes": {"tile_rows": ty, "ty_zc_per_grid": shapes,
+                                      "ms_per_batch_step": round(ms_step, 4),
+                                      "tuning_s": round(tune_s, 1)},
+                     "sequential_ms": round(times["sequential"], 1),
                      "batched_ms": round(times["batched"], 1),
                      "batched_persistent_ms": round(times["batched_persistent"], 1),
                      "speedup": round(times["sequential"] / times["batched"], 2),

@@ -95,11 +95,12 @@ typedef struct excmg_opts {
                         /* Bi-CG step, 1 = one persistent work-queue launch per step        */
     int method;         /* EXCMG_BICG (default) or EXCMG_CG (excmg_solve_ex only)           */
     int refine;         /* mixed precision: EXCMG_RELIABLE (default) or EXCMG_RESTART;     */
-                        /* excmg_solve_batch always restarts                                */
+                        /* excmg_solve_batch always restarts (its FP32 levels)              */
     int precond;        /* EXCMG_PRECOND_NONE (default) or EXCMG_PRECOND_JACOBI (solve_ex) */
-    int fp32_min_unknowns; /* mixed precision with EXCMG_RELIABLE: levels with fewer        */
-                        /* unknowns run FP64 Bi-CG (launch-latency bound, so FP32 vectors    */
-                        /* gain nothing there); 0: 262144 (2^18), 1: FP32 on every level    */
+    int fp32_min_unknowns; /* mixed precision: levels with fewer unknowns run FP64 Bi-CG    */
+                        /* (launch-latency bound, so FP32 vectors gain nothing there);       */
+                        /* 0: 262144 (2^18) with EXCMG_RELIABLE and in excmg_solve_batch,    */
+                        /* every level FP32 with EXCMG_RESTART; 1: FP32 on every level      */
     int row_pad;        /* mixed precision, 3D: 1 stores the rows of the FP32 Bi-CG vectors */
                         /* (and of the FP64 iterate and right-hand side they are solved     */
                         /* with) on a 128-byte multiple plus 128 bytes, so no cache line is */
@@ -310,14 +311,37 @@ typedef struct excmg_problem {
 } excmg_problem;
 
 /* Algorithm 1 for nprob independent problems (1..256) of possibly different grids, levels
- * and boundary kinds, advanced together: every Bi-CG iteration of all running systems is
- * one launch of a persistent work-queue kernel (replayed from a captured hipGraph), while
- * each problem follows its own cascade, tolerances and stopping decisions exactly as
- * excmg_solve_ex would.  opts supplies tol, precision and the iteration limits (its
- * n_finest, n_levels and bc_kind are ignored).  stats, if not NULL, is an array of nprob
- * records.  Runs on a stream of its own, ordered after the library stream's earlier work. */
+ * and boundary kinds, advanced together: one Bi-CG iteration of all running systems is four
+ * phase launches (opts.batch_mode 0) or one launch of a persistent work-queue kernel
+ * (batch_mode 1), replayed in windows from captured hipGraphs, while each problem follows
+ * its own cascade, tolerances and stopping decisions exactly as excmg_solve_ex would.
+ * Mixed precision: levels of at least opts.fp32_min_unknowns unknowns (0: 2^18) run FP32
+ * Bi-CG inside restarted FP64 refinement (excmg_solve_ex with EXCMG_RESTART and the same
+ * fp32_min_unknowns); smaller levels run FP64 Bi-CG, as in an FP64 solve (systems of the
+ * two kinds advance in separate launches); opts.refine is not used.  opts supplies tol,
+ * precision and the iteration limits (its n_finest, n_levels and bc_kind are ignored).
+ * stats, if not NULL, is an array of nprob records.  Runs on a stream of its own, ordered
+ * after the library stream's earlier work.  Tile shapes of the batched sweep A: those
+ * recorded by excmg_autotune_batch. */
 int excmg_solve_batch(int nprob, const excmg_problem *probs, const excmg_opts *opts,
                       excmg_stats *stats);
+
+/* Autotuner of the batched Bi-CG step (configuration of excmg_solve_batch): puts the finest
+ * level of every problem of the batch into a running Bi-CG run and times whole steps of the
+ * batch (the phase launches, replayed from a captured graph; `reps` graph replays of 8 steps
+ * per shape) for tile heights of 4 and 8 rows and, per distinct grid size, z-chunks of 2, 4,
+ * ..., 128 planes and the whole depth (a coordinate descent over the sizes).  The fastest
+ * height (one per batch: a launch has one workgroup shape) and the chunk of every size are
+ * recorded for later excmg_solve_batch calls, per grid size and vector precision (FP32
+ * for the finest levels that a mixed batch runs in FP32); sizes never tuned keep the
+ * single-problem table's chunk.  opts supplies precision and fp32_min_unknowns (its
+ * tolerance is not used).  Outputs (may be NULL): the tile height and the mean ms per batch
+ * step.  No caller array is written. */
+int excmg_autotune_batch(int nprob, const excmg_problem *probs, const excmg_opts *opts, int reps,
+                         int *ty, double *ms_per_step);
+/* The batched sweep A's tile height and the z-chunk it takes on grids of n cells with FP32
+ * (precision EXCMG_MIXED) or FP64 (EXCMG_FP64) vectors. */
+int excmg_get_batch_shape(int n, int precision, int *ty, int *zc);
 
 /* Autotuner: time the z-marched kernel of `kind` (0: one-array operator, 1: Bi-CG sweep A)
  * on a grid of n cells for every tile height and z-chunk length it supports, in FP64 or

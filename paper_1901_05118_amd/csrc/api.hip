@@ -7,6 +7,7 @@
 // iterations to decide whether to launch more.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -1125,10 +1126,12 @@ int solve_cascade(const excmg_opts &o, const double *f, const double *g1, const 
                 CKH(from_nodes(Lv.N, Lv.u.as<double>(), Lv.x.as<double>(), g_stream));
             }
             const double eps = level_tolerance(o.tol, l - 1, L);
-            // with residual replacement, small levels run FP64 Bi-CG: they are bound by launch
-            // latency, so FP32 vectors save nothing and the replacements cost extra
-            const long long fp32_min = o.fp32_min_unknowns > 0 ? o.fp32_min_unknowns : (1LL << 18);
-            const bool lmixed = mixed && (!reliable || Lv.nu >= fp32_min);
+            // small levels run FP64 Bi-CG: they are bound by launch latency, so FP32 vectors
+            // save nothing and the refinement costs extra (default: with residual
+            // replacement below 2^18 unknowns; restarted refinement on every level)
+            const long long fp32_min = o.fp32_min_unknowns > 0 ? o.fp32_min_unknowns
+                                                               : (reliable ? (1LL << 18) : 1);
+            const bool lmixed = mixed && Lv.nu >= fp32_min;
             if (lmixed && reliable)
                 CKR(with_level_rows(Lv, Lv.b.as<double>(), Lv.x.as<double>(),
                                     [&](const double *b, double *u) {
@@ -1215,12 +1218,37 @@ struct FactorCache {
 
 enum { kPhaseCheck = 0, kPhaseRun = 1, kPhaseDone = 2 };
 
+// Launch shape of the batched sweep A: one tile height for the whole batch (a launch has
+// one workgroup shape; 4 or 8 rows) and a z-chunk per grid size and vector precision,
+// chosen by excmg_autotune_batch on the batch's own work list; sizes it has not tuned take
+// the single-problem table's z-chunk.
+struct BatchZc {
+    int N;
+    bool f32;
+    int zc;
+};
+int g_batch_ty = kBatchTY;
+std::vector<BatchZc> g_batch_zc;
+
+int batch_zc(int N, int bc, bool f32) {
+    for (const auto &e : g_batch_zc)
+        if (e.N == N && e.f32 == f32) return std::max(1, std::min(e.zc, N - 1));
+    return choose_shape(N, bc, f32 ? 2 : 1).zc;
+}
+
+// Sweep-A tiles of a grid of n unknowns per axis for the smallest batch tile (4 rows, 2
+// planes): the size of the per-system work lists and partials whatever shape is tuned.
+long long batch_max_tiles(int n) {
+    return (long long)((n + kWave - 1) / kWave) * ((n + 3) / 4) * ((n + 1) / 2);
+}
+
 struct BProb {
     int N = 0, nl = 0, bc = 0, L = 0;
     std::vector<Level> lv;
     DBuf r, rs, p[2], ps[2], q, qs, part_a, part_b, ubuf;
     Arg *af = nullptr, *a1 = nullptr, *a2 = nullptr, *au = nullptr, *at = nullptr;
     int level = 0, phase = kPhaseCheck;
+    bool f32 = false;           // the current level runs FP32 Bi-CG inside FP64 refinement
     int runs = 0, iters = 0, outer = 0, worst = EXCMG_OK;
     int broke = 0;              // the last run broke down (Algorithm 2's denominators)
     double eps = 0.0, prev = INFINITY, last_bb = 0.0;
@@ -1235,45 +1263,69 @@ struct BProb {
     }
 };
 
+// The systems of a batch whose current level has vectors of one precision, advanced by
+// their own step launches (work list, control block, captured graph).
+struct StepSet {
+    bool f32 = false;
+    DBuf items, ctl;
+    int2 *h_items = nullptr;
+    int *h_hdr = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    int grid = 0, ni = 0;
+    void drop_graph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    }
+    ~StepSet() {
+        drop_graph();
+        items.release();
+        ctl.release();
+        if (h_items) (void)hipHostFree(h_items);
+        if (h_hdr) (void)hipHostFree(h_hdr);
+    }
+};
+
 struct BatchSolver {
     bool mixed = false;
+    long long fp32_min = 1LL << 18;  // mixed: levels with fewer unknowns run FP64 Bi-CG
     bool persistent = false;  // one persistent launch per step instead of four phase launches
+    int ty = kBatchTY;        // tile height of the batched sweep A
     int maxit = 100000, max_runs = 5, max_outer = 60;
     double tol = 0.0, inner_tol = 1e-4;
     hipStream_t st = nullptr;
     std::vector<BProb *> pb;
     FactorCache fc;
-    DBuf states, runs, items, ctl, scal, xx;
+    DBuf states, runs, scal, xx;
     BatchRun *h_runs = nullptr;
-    int2 *h_items = nullptr;
     double *h_scal = nullptr;
     BicgState *h_states = nullptr;
-    int *h_hdr = nullptr;
-    hipGraphExec_t exec = nullptr;
-    hipGraph_t graph = nullptr;
-    int grid = 0, steps_per_graph = 8;
+    StepSet set[2];           // systems with FP64 vectors, with FP32 vectors
+    int steps_per_graph = 8;
     long long launches = 0;
 
     ~BatchSolver() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
         for (BProb *b : pb) delete b;
-        states.release(); runs.release(); items.release(); ctl.release(); scal.release();
+        states.release(); runs.release(); scal.release();
         xx.release();
         fc.release();
         if (h_runs) (void)hipHostFree(h_runs);
-        if (h_items) (void)hipHostFree(h_items);
         if (h_scal) (void)hipHostFree(h_scal);
         if (h_states) (void)hipHostFree(h_states);
-        if (h_hdr) (void)hipHostFree(h_hdr);
     }
+
+    bool level_f32(const BProb &b, int l) const { return mixed && b.lv[l].nu >= fp32_min; }
 
     BicgState *S(int j) { return states.as<BicgState>() + j; }
     double *sc(int j) { return scal.as<double>() + 4 * j; }
 
     int init(int nprob, const excmg_problem *probs, const excmg_opts &o) {
         mixed = (o.precision == EXCMG_MIXED);
+        fp32_min = o.fp32_min_unknowns > 0 ? o.fp32_min_unknowns : (1LL << 18);
         persistent = (o.batch_mode == 1);
+        ty = g_batch_ty;
         tol = o.tol;
         maxit = o.max_iters > 0 ? o.max_iters : 100000;
         max_runs = o.max_runs > 0 ? o.max_runs : 5;
@@ -1281,17 +1333,21 @@ struct BatchSolver {
         inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-4;
         CKR(states.ensure((size_t)nprob * sizeof(BicgState)));
         CKR(runs.ensure((size_t)nprob * sizeof(BatchRun)));
-        CKR(ctl.ensure(sizeof(BatchCtl)));
         CKR(scal.ensure((size_t)nprob * 4 * sizeof(double)));
-        // epoch starts at 1: alpha_epoch[] = 0 must not read as "published" in launch 1
-        CKH(hipMemsetAsync(ctl.p, 0, sizeof(BatchCtl), st));
         const int one = 1;
-        CKH(hipMemcpyAsync((char *)ctl.p + offsetof(BatchCtl, epoch), &one, sizeof(int),
-                           hipMemcpyHostToDevice, st));
+        for (int k = 0; k < 2; k++) {
+            StepSet &S = set[k];
+            S.f32 = (k == 1);
+            CKR(S.ctl.ensure(sizeof(BatchCtl)));
+            // epoch starts at 1: alpha_epoch[] = 0 must not read as "published" in launch 1
+            CKH(hipMemsetAsync(S.ctl.p, 0, sizeof(BatchCtl), st));
+            CKH(hipMemcpyAsync((char *)S.ctl.p + offsetof(BatchCtl, epoch), &one, sizeof(int),
+                               hipMemcpyHostToDevice, st));
+            CKH(hipHostMalloc((void **)&S.h_hdr, (4 + kMaxRuns) * sizeof(int), hipHostMallocDefault));
+        }
         CKH(hipHostMalloc((void **)&h_runs, (size_t)nprob * sizeof(BatchRun), hipHostMallocDefault));
         CKH(hipHostMalloc((void **)&h_scal, (size_t)nprob * 4 * sizeof(double), hipHostMallocDefault));
         CKH(hipHostMalloc((void **)&h_states, (size_t)nprob * sizeof(BicgState), hipHostMallocDefault));
-        CKH(hipHostMalloc((void **)&h_hdr, (4 + kMaxRuns) * sizeof(int), hipHostMallocDefault));
         long long max_items = 0;
         for (int j = 0; j < nprob; j++) {
             const excmg_problem &P = probs[j];
@@ -1327,15 +1383,15 @@ struct BatchSolver {
                 Lv.nu = (long long)Lv.n * Lv.n * Lv.n;
                 Lv.nodes = (long long)(Lv.N + 1) * (Lv.N + 1) * (Lv.N + 1);
                 Lv.g1 = choose_shape(Lv.N, b->bc, 0);
-                Geom gb = choose_shape(Lv.N, b->bc, mixed ? 2 : 1);
-                Lv.g2 = make_geom(Lv.n, b->bc, kBatchTY, gb.zc);
+                Lv.g2 = make_geom(Lv.n, b->bc, ty, batch_zc(Lv.N, b->bc, level_f32(*b, l)));
                 CKR(Lv.b.ensure(Lv.nu * 8));
                 CKR(Lv.x.ensure(Lv.nu * 8));
                 CKR(Lv.u.ensure(Lv.nodes * 8));
                 const long long nch = (Lv.nu + kChunkGraph - 1) / kChunkGraph;
-                max_pa = std::max({max_pa, (size_t)stencil_blocks(Lv.g1), (size_t)Lv.g2.ntiles});
+                const long long mt = batch_max_tiles(Lv.n);
+                max_pa = std::max({max_pa, (size_t)stencil_blocks(Lv.g1), (size_t)mt});
                 max_pb = std::max({max_pb, (size_t)(2 * nch), (size_t)(2 * vec_blocks(Lv.nu))});
-                if (l >= 2) max_items += Lv.g2.ntiles + nch;
+                if (l >= 2) max_items += mt + nch;
             }
             const size_t vb = (size_t)b->lv.back().nu * 8;
             CKR(b->r.ensure(vb)); CKR(b->rs.ensure(vb));
@@ -1348,11 +1404,13 @@ struct BatchSolver {
             CKR(b->ubuf.ensure((size_t)m1 * m1 * m1 * 8));
             b->stats.n_levels = b->nl;
         }
-        CKR(items.ensure((size_t)std::max(1LL, max_items) * sizeof(int2)));
-        CKH(hipHostMalloc((void **)&h_items, (size_t)std::max(1LL, max_items) * sizeof(int2),
-                          hipHostMallocDefault));
-        if (mixed) CKH(batch_step_grid<float>(&grid));
-        else CKH(batch_step_grid<double>(&grid));
+        for (StepSet &S : set) {
+            CKR(S.items.ensure((size_t)std::max(1LL, max_items) * sizeof(int2)));
+            CKH(hipHostMalloc((void **)&S.h_items, (size_t)std::max(1LL, max_items) * sizeof(int2),
+                              hipHostMallocDefault));
+        }
+        CKH(batch_step_grid<double>(ty, &set[0].grid));
+        CKH(batch_step_grid<float>(ty, &set[1].grid));
         return EXCMG_OK;
     }
 
@@ -1390,6 +1448,7 @@ struct BatchSolver {
         CKH(reduce_to(sc(j), b.part_b.as<Pair>(), nvb, 1, st));
         CKH(reduce_to((double *)&S(j)->bb, b.part_b.as<Pair>(), nvb, 0, st));
         b.level = l;
+        b.f32 = level_f32(b, l);
         b.phase = kPhaseCheck;
         b.runs = b.iters = b.outer = 0;
         b.prev = INFINITY;
@@ -1401,7 +1460,7 @@ struct BatchSolver {
     int launch_check(int j) {
         BProb &b = *pb[j];
         Level &Lv = b.lv[b.level];
-        if (mixed)
+        if (b.f32)
             CKH(stencil_residual_cast(Lv.g1, Lv.g1.ty, Lv.b.as<double>(), Lv.x.as<double>(),
                                       b.r.as<float>(), b.rs.as<float>(), b.part_a.as<Pair>(), st));
         else
@@ -1418,7 +1477,7 @@ struct BatchSolver {
         excmg_level_stats &ls = b.stats.level[b.level];
         ls.n = Lv.N;
         ls.iterations = b.iters;
-        ls.runs = mixed ? b.outer : b.runs;
+        ls.runs = b.f32 ? b.outer : b.runs;
         ls.status = status;
         ls.eps = b.eps;
         ls.rel_residual = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
@@ -1445,12 +1504,12 @@ struct BatchSolver {
             // a breakdown ends the level, as in a single solve: FP64 reports the residual of
             // the iterate after the broken run, mixed precision the residual it was started on
             b.broke = 0;
-            if (mixed) return finish_level(j, EXCMG_EBREAKDOWN, b.prev, b.last_bb);
+            if (b.f32) return finish_level(j, EXCMG_EBREAKDOWN, b.prev, b.last_bb);
             return finish_level(j, EXCMG_EBREAKDOWN, rr, bb);
         }
         if (rr <= thr) return finish_level(j, EXCMG_OK, rr, bb);
         BicgState *Sj = S(j);
-        if (!mixed) {
+        if (!b.f32) {
             if (b.runs >= max_runs) return finish_level(j, EXCMG_ENOCONV, rr, bb);
             CKH((copy_convert<double, double>(Lv.nu, b.r.as<double>(), b.rs.as<double>(), st)));
             CKH(bicg_start(Sj, b.part_a.as<Pair>(), stencil_blocks(Lv.g1), b.eps, maxit, st));
@@ -1470,10 +1529,11 @@ struct BatchSolver {
         return EXCMG_OK;
     }
 
-    // Work list of the running systems: all sweep-A tiles, then all sweep-B chunks.
-    int build_items(int *n_a, int *n_items) {
-        int na = 0;
-        for (size_t j = 0; j < pb.size(); j++) {
+    // Work lists of the running systems, one per vector precision: all sweep-A tiles, then
+    // all sweep-B chunks.
+    int build_items() {
+        const int np = (int)pb.size();
+        for (int j = 0; j < np; j++) {
             BProb &b = *pb[j];
             Level &Lv = b.lv[b.level];
             BatchRun &R = h_runs[j];
@@ -1486,55 +1546,69 @@ struct BatchSolver {
             R.p[0] = b.p[0].p; R.p[1] = b.p[1].p; R.ps[0] = b.ps[0].p; R.ps[1] = b.ps[1].p;
             R.q = b.q.p; R.qs = b.qs.p;
             R.x = Lv.x.as<double>();
-            R.state = S((int)j);
+            R.state = S(j);
             R.part_a = b.part_a.as<Pair>();
             R.part_b = b.part_b.as<Pair>();
-            if (b.phase != kPhaseRun) continue;
-            for (int t = 0; t < R.a_count; t++) h_items[na++] = make_int2((int)j, t);
         }
-        int ni = na;
-        for (size_t j = 0; j < pb.size(); j++) {
-            if (pb[j]->phase != kPhaseRun) continue;
-            for (int c = 0; c < h_runs[j].b_count; c++) h_items[ni++] = make_int2((int)j, c);
+        CKH(hipMemcpyAsync(runs.p, h_runs, (size_t)np * sizeof(BatchRun), hipMemcpyHostToDevice, st));
+        for (StepSet &K : set) {
+            auto in_set = [&](int j) { return pb[j]->phase == kPhaseRun && pb[j]->f32 == K.f32; };
+            int na = 0;
+            for (int j = 0; j < np; j++)
+                if (in_set(j))
+                    for (int t = 0; t < h_runs[j].a_count; t++) K.h_items[na++] = make_int2(j, t);
+            int ni = na;
+            for (int j = 0; j < np; j++)
+                if (in_set(j))
+                    for (int c = 0; c < h_runs[j].b_count; c++) K.h_items[ni++] = make_int2(j, c);
+            K.ni = ni;
+            if (ni == 0) continue;
+            CKH(hipMemcpyAsync(K.items.p, K.h_items, (size_t)ni * sizeof(int2),
+                               hipMemcpyHostToDevice, st));
+            // header: n_a, n_items, n_runs, n_active, active[]
+            K.h_hdr[0] = na;
+            K.h_hdr[1] = ni;
+            K.h_hdr[2] = np;
+            int nact = 0;
+            for (int j = 0; j < np; j++)
+                if (in_set(j)) K.h_hdr[4 + nact++] = j;
+            K.h_hdr[3] = nact;
+            CKH(hipMemcpyAsync((char *)K.ctl.p + offsetof(BatchCtl, n_a), K.h_hdr,
+                               (4 + kMaxRuns) * sizeof(int), hipMemcpyHostToDevice, st));
         }
-        *n_a = na;
-        *n_items = ni;
-        CKH(hipMemcpyAsync(runs.p, h_runs, pb.size() * sizeof(BatchRun), hipMemcpyHostToDevice, st));
-        CKH(hipMemcpyAsync(items.p, h_items, (size_t)std::max(ni, 1) * sizeof(int2), hipMemcpyHostToDevice, st));
-        // header: n_a, n_items, n_runs, n_active, active[]
-        h_hdr[0] = na;
-        h_hdr[1] = ni;
-        h_hdr[2] = (int)pb.size();
-        int nact = 0;
-        for (size_t j = 0; j < pb.size(); j++)
-            if (pb[j]->phase == kPhaseRun) h_hdr[4 + nact++] = (int)j;
-        h_hdr[3] = nact;
-        CKH(hipMemcpyAsync((char *)ctl.p + offsetof(BatchCtl, n_a), h_hdr,
-                           (4 + kMaxRuns) * sizeof(int), hipMemcpyHostToDevice, st));
         return EXCMG_OK;
     }
 
+    // steps_per_graph Bi-CG steps of every running system: each precision's steps are
+    // captured once in a graph (the launches read their work list from the control block)
+    // and replayed while it has systems.
     int launch_steps() {
-        if (!exec) {
-            CKH(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
-            for (int t = 0; t < steps_per_graph; t++) {
-                hipError_t e;
-                if (persistent)
-                    e = mixed ? batch_step<float>(grid, runs.as<BatchRun>(), items.as<int2>(), ctl.as<BatchCtl>(), st)
-                              : batch_step<double>(grid, runs.as<BatchRun>(), items.as<int2>(), ctl.as<BatchCtl>(), st);
-                else
-                    e = mixed ? batch_step_phases<float>(runs.as<BatchRun>(), items.as<int2>(), ctl.as<BatchCtl>(), st)
-                              : batch_step_phases<double>(runs.as<BatchRun>(), items.as<int2>(), ctl.as<BatchCtl>(), st);
-                if (e != hipSuccess) {
-                    hipGraph_t g;
-                    (void)hipStreamEndCapture(st, &g);
-                    return fail(EXCMG_EHIP, "batch step launch: %s", hipGetErrorString(e));
+        for (StepSet &K : set) {
+            if (K.ni == 0) continue;
+            if (!K.exec) {
+                BatchCtl *ctl = K.ctl.as<BatchCtl>();
+                const int2 *items = K.items.as<int2>();
+                const BatchRun *rn = runs.as<BatchRun>();
+                CKH(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+                for (int t = 0; t < steps_per_graph; t++) {
+                    hipError_t e;
+                    if (persistent)
+                        e = K.f32 ? batch_step<float>(ty, K.grid, rn, items, ctl, st)
+                                  : batch_step<double>(ty, K.grid, rn, items, ctl, st);
+                    else
+                        e = K.f32 ? batch_step_phases<float>(ty, rn, items, ctl, st)
+                                  : batch_step_phases<double>(ty, rn, items, ctl, st);
+                    if (e != hipSuccess) {
+                        hipGraph_t g;
+                        (void)hipStreamEndCapture(st, &g);
+                        return fail(EXCMG_EHIP, "batch step launch: %s", hipGetErrorString(e));
+                    }
                 }
+                CKH(hipStreamEndCapture(st, &K.graph));
+                CKH(hipGraphInstantiate(&K.exec, K.graph, nullptr, nullptr, 0));
             }
-            CKH(hipStreamEndCapture(st, &graph));
-            CKH(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+            CKH(hipGraphLaunch(K.exec, st));
         }
-        CKH(hipGraphLaunch(exec, st));
         launches += steps_per_graph;
         return EXCMG_OK;
     }
@@ -1561,8 +1635,7 @@ struct BatchSolver {
             bool running = false;
             for (int j = 0; j < np; j++) running |= (pb[j]->phase == kPhaseRun);
             if (!running) break;
-            int na = 0, ni = 0;
-            CKR(build_items(&na, &ni));
+            CKR(build_items());
             // advance every running system until one of them stops
             for (;;) {
                 CKR(launch_steps());
@@ -1579,11 +1652,12 @@ struct BatchSolver {
                     b.phase = kPhaseCheck;
                     if (h_states[j].status == kBreakdown) b.broke = 1;
                 }
-                int err = 0;
-                CKH(hipMemcpyAsync(&err, (char *)ctl.p + offsetof(BatchCtl, error), sizeof(int),
-                                   hipMemcpyDeviceToHost, st));
+                int err[2] = {0, 0};
+                for (int k = 0; k < 2; k++)
+                    CKH(hipMemcpyAsync(&err[k], (char *)set[k].ctl.p + offsetof(BatchCtl, error),
+                                       sizeof(int), hipMemcpyDeviceToHost, st));
                 CKH(hipStreamSynchronize(st));
-                if (err) return fail(EXCMG_EHIP, "batched step: a bounded wait expired");
+                if (err[0] || err[1]) return fail(EXCMG_EHIP, "batched step: a bounded wait expired");
                 if (changed) break;
             }
         }
@@ -1593,6 +1667,137 @@ struct BatchSolver {
             if (b->at) CKR(b->at->back());
         }
         CKH(hipStreamSynchronize(st));
+        return EXCMG_OK;
+    }
+
+    // ------------------------------------------------------------ shape tuning
+    // Every problem's finest level as a running Bi-CG system (from x = 0, with a tolerance
+    // it never reaches), so that steps of the whole batch can be timed with any shape.
+    int tune_prepare() {
+        for (int j = 0; j < (int)pb.size(); j++) {
+            BProb &b = *pb[j];
+            b.level = b.nl - 1;
+            b.f32 = level_f32(b, b.level);
+            Level &Lv = b.lv[b.level];
+            CKH(rhs_assemble(Lv.N, b.bc, 1, b.N, b.af->p<double>(), b.a1->p<double>(),
+                             b.a2->p<double>(), Lv.b.as<double>(), st));
+            CKH(hipMemsetAsync(Lv.x.p, 0, (size_t)Lv.nu * 8, st));
+            const int nvb = vec_blocks(Lv.nu);
+            if (b.f32) {
+                CKH((copy_convert<float, double>(Lv.nu, Lv.b.as<double>(), b.r.as<float>(), st)));
+                CKH((copy_convert<float, double>(Lv.nu, Lv.b.as<double>(), b.rs.as<float>(), st)));
+                CKH(dot_partials<float>(Lv.nu, b.r.as<float>(), b.r.as<float>(),
+                                        b.part_b.as<Pair>(), nvb, st));
+            } else {
+                CKH((copy_convert<double, double>(Lv.nu, Lv.b.as<double>(), b.r.as<double>(), st)));
+                CKH((copy_convert<double, double>(Lv.nu, Lv.b.as<double>(), b.rs.as<double>(), st)));
+                CKH(dot_partials<double>(Lv.nu, b.r.as<double>(), b.r.as<double>(),
+                                         b.part_b.as<Pair>(), nvb, st));
+            }
+            CKH(reduce_to((double *)&S(j)->bb, b.part_b.as<Pair>(), nvb, 0, st));
+            CKH(bicg_start(S(j), b.part_b.as<Pair>(), nvb, 0.0, 1 << 30, st));
+            b.phase = kPhaseRun;
+        }
+        return EXCMG_OK;
+    }
+
+    // The finest levels take tile height `ty` and the z-chunk of their grid in `zc`.
+    void tune_apply(const std::vector<BatchZc> &zc) {
+        for (BProb *b : pb) {
+            Level &Lv = b->lv[b->nl - 1];
+            int z = 1;
+            for (const auto &e : zc)
+                if (e.N == b->N) z = e.zc;
+            Lv.g2 = make_geom(Lv.n, b->bc, ty, std::max(1, std::min(z, Lv.n)));
+        }
+    }
+
+    // Mean ms of one Bi-CG step of the whole batch (phase launches replayed from a graph),
+    // every system restarted first.
+    int tune_time(int reps, double *ms) {
+        CKR(tune_prepare());
+        CKR(build_items());
+        for (StepSet &K : set) K.drop_graph();
+        CKR(launch_steps());  // captures the graphs; warm-up
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        CKH(hipEventCreate(&e0));
+        hipError_t e = hipEventCreate(&e1);
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        int rc = EXCMG_OK;
+        for (int t = 0; t < reps && e == hipSuccess && rc == EXCMG_OK; t++) rc = launch_steps();
+        if (e == hipSuccess && rc == EXCMG_OK) e = hipEventRecord(e1, st);
+        if (e == hipSuccess && rc == EXCMG_OK) e = hipEventSynchronize(e1);
+        float f = 0.f;
+        if (e == hipSuccess && rc == EXCMG_OK) e = hipEventElapsedTime(&f, e0, e1);
+        (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        CKR(rc);
+        CKH(e);
+        *ms = (double)f / ((double)reps * steps_per_graph);
+        return EXCMG_OK;
+    }
+
+    // For each tile height (4 and 8 rows), a coordinate descent over the batch's grid sizes:
+    // each size in turn tries z-chunks of 2, 4, ... planes and the whole depth, keeping the
+    // fastest step of the whole batch.  The fastest (height, chunks) is recorded for later
+    // batches.
+    int tune(int reps, int *ty_out, double *ms_out) {
+        persistent = false;
+        std::vector<int> sizes;
+        for (BProb *b : pb)
+            if (std::find(sizes.begin(), sizes.end(), b->N) == sizes.end()) sizes.push_back(b->N);
+        std::sort(sizes.begin(), sizes.end());
+        int best_ty = ty;
+        double best = INFINITY;
+        std::vector<BatchZc> best_zc;
+        for (int cand : {4, 8}) {
+            ty = cand;
+            CKH(batch_step_grid<double>(ty, &set[0].grid));
+            CKH(batch_step_grid<float>(ty, &set[1].grid));
+            std::vector<BatchZc> zc;
+            for (int N : sizes) {
+                const bool f32 = mixed && (long long)(N - 1) * (N - 1) * (N - 1) >= fp32_min;
+                zc.push_back({N, f32, batch_zc(N, 1, f32)});
+            }
+            tune_apply(zc);
+            double cur = 0.0;
+            CKR(tune_time(reps, &cur));
+            for (auto &e : zc) {
+                const int n = e.N - 1;
+                int keep = e.zc;
+                for (int z : {2, 4, 8, 16, 32, 64, 128, n}) {
+                    if (z > n || z == keep) continue;
+                    e.zc = z;
+                    tune_apply(zc);
+                    double t = 0.0;
+                    CKR(tune_time(reps, &t));
+                    if (t < cur) {
+                        cur = t;
+                        keep = z;
+                    }
+                }
+                e.zc = keep;
+                tune_apply(zc);
+            }
+            if (cur < best) {
+                best = cur;
+                best_ty = cand;
+                best_zc = zc;
+            }
+        }
+        ty = best_ty;
+        g_batch_ty = best_ty;
+        for (const auto &e : best_zc) {
+            bool found = false;
+            for (auto &g : g_batch_zc)
+                if (g.N == e.N && g.f32 == e.f32) {
+                    g.zc = e.zc;
+                    found = true;
+                }
+            if (!found) g_batch_zc.push_back(e);
+        }
+        *ty_out = best_ty;
+        *ms_out = best;
         return EXCMG_OK;
     }
 
@@ -2091,6 +2296,7 @@ int excmg_solve_batch(int nprob, const excmg_problem *probs, const excmg_opts *o
     if (!(opts->tol > 0.0)) return fail(EXCMG_EINVAL, "tol must be positive");
     if (opts->precision != EXCMG_FP64 && opts->precision != EXCMG_MIXED)
         return fail(EXCMG_EINVAL, "precision %d not supported", opts->precision);
+    if (opts->fp32_min_unknowns < 0) return fail(EXCMG_EINVAL, "fp32_min_unknowns must be >= 0");
     for (int j = 0; j < nprob; j++) CKR(check_sizes(probs[j].n_finest, probs[j].n_levels, probs[j].bc_kind));
     // every failure below is recorded in rc and the stream, events and library stream are
     // restored and released on the way out
@@ -2138,6 +2344,49 @@ int excmg_solve_batch(int nprob, const excmg_problem *probs, const excmg_opts *o
     if (ein) (void)hipEventDestroy(ein);
     if (bs) (void)hipStreamDestroy(bs);
     return rc;
+}
+
+int excmg_autotune_batch(int nprob, const excmg_problem *probs, const excmg_opts *opts, int reps,
+                         int *ty_out, double *ms_out) {
+    g_err[0] = 0;
+    if (nprob < 1 || nprob > kMaxRuns) return fail(EXCMG_EINVAL, "nprob must be in 1..%d", kMaxRuns);
+    if (!probs || !opts || reps < 1) return fail(EXCMG_EINVAL, "NULL problems or options, or reps < 1");
+    if (opts->precision != EXCMG_FP64 && opts->precision != EXCMG_MIXED)
+        return fail(EXCMG_EINVAL, "precision %d not supported", opts->precision);
+    if (opts->fp32_min_unknowns < 0) return fail(EXCMG_EINVAL, "fp32_min_unknowns must be >= 0");
+    for (int j = 0; j < nprob; j++) CKR(check_sizes(probs[j].n_finest, probs[j].n_levels, probs[j].bc_kind));
+    hipStream_t bs = nullptr;
+    CKH(hipStreamCreateWithFlags(&bs, hipStreamNonBlocking));
+    hipStream_t saved = g_stream;
+    g_stream = bs;
+    int rc;
+    int ty = 0;
+    double ms = 0.0;
+    {
+        BatchSolver B;
+        B.st = bs;
+        excmg_opts o = *opts;
+        o.batch_mode = 0;
+        if (!(o.tol > 0.0)) o.tol = 1e-8;
+        rc = B.init(nprob, probs, o);
+        if (rc == EXCMG_OK) rc = B.tune(reps, &ty, &ms);
+        (void)hipStreamSynchronize(bs);
+    }
+    g_stream = saved;
+    (void)hipStreamDestroy(bs);
+    if (rc == EXCMG_OK) {
+        if (ty_out) *ty_out = ty;
+        if (ms_out) *ms_out = ms;
+    }
+    return rc;
+}
+
+int excmg_get_batch_shape(int n, int precision, int *ty, int *zc) {
+    g_err[0] = 0;
+    if (n < 3) return fail(EXCMG_EINVAL, "n must be at least 3");
+    if (ty) *ty = g_batch_ty;
+    if (zc) *zc = batch_zc(n, 1, precision == EXCMG_MIXED);
+    return EXCMG_OK;
 }
 
 int excmg_autotune(int n, int kind, int precision, int reps, int *ty_out, int *zc_out,

@@ -48,7 +48,7 @@ __device__ void merge_remote(const Pair *part, int count, Pair (&out)[NV], Pair 
     block_merge<NV>(out, sh);
 }
 
-template <typename T>
+template <typename T, int TY>
 __device__ void sweep_a_item(const BatchRun &R, int run, int tile, BatchCtl *ctl, int epoch,
                              Pair *red) {
     __shared__ int sh_last;
@@ -74,7 +74,7 @@ __device__ void sweep_a_item(const BatchRun &R, int run, int tile, BatchCtl *ctl
         in.beta_dev = &S->beta;
         in.first = (iter == 0);
         in.prepare();
-        zmarch_tile<2, kBatchTY, T>(R.g, tile, in, out);
+        zmarch_tile<2, TY, T>(R.g, tile, in, out);
     }
     __threadfence();  // every thread releases its p, p*, q, q* stores before the arrival count
     Pair v[1] = {out.acc};
@@ -178,11 +178,11 @@ __device__ void sweep_b_item(const BatchRun &R, int run, int chunk, BatchCtl *ct
     __syncthreads();
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kWave *kBatchTY)
+template <typename T, int TY>
+__global__ void __launch_bounds__(kWave *TY)
     k_batch_step(const BatchRun *runs, const int2 *items, BatchCtl *ctl) {
     __shared__ int sh_item, sh_epoch;
-    __shared__ Pair red[2 * kBatchTY];
+    __shared__ Pair red[2 * TY];
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
     if (tid == 0) sh_epoch = __hip_atomic_load(&ctl->epoch, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
@@ -196,7 +196,7 @@ __global__ void __launch_bounds__(kWave *kBatchTY)
         if (it >= n_items) break;
         const int2 item = items[it];
         const BatchRun &R = runs[item.x];
-        if (it < n_a) sweep_a_item<T>(R, item.x, item.y, ctl, epoch, red);
+        if (it < n_a) sweep_a_item<T, TY>(R, item.x, item.y, ctl, epoch, red);
         else sweep_b_item<T>(R, item.x, item.y, ctl, epoch, red);
     }
     if (tid == 0) {
@@ -219,10 +219,10 @@ __global__ void __launch_bounds__(kWave *kBatchTY)
 
 constexpr int kPhaseGridA = 2048, kPhaseGridB = 2048, kPhaseGridR = kMaxRuns;
 
-template <typename T>
-__global__ void __launch_bounds__(kWave *kBatchTY)
+template <typename T, int TY>
+__global__ void __launch_bounds__(kWave *TY)
     k_phase_sweep_a(const BatchRun *runs, const int2 *items, const BatchCtl *ctl) {
-    __shared__ Pair red[kBatchTY];
+    __shared__ Pair red[TY];
     const int n_a = ctl->n_a;
     for (int it = blockIdx.x; it < n_a; it += gridDim.x) {
         const int2 item = items[it];
@@ -247,7 +247,7 @@ __global__ void __launch_bounds__(kWave *kBatchTY)
         in.beta_dev = &S->beta;
         in.first = (iter == 0);
         in.prepare();
-        zmarch_tile<2, kBatchTY, T>(R.g, item.y, in, out);
+        zmarch_tile<2, TY, T>(R.g, item.y, in, out);
         Pair v[1] = {out.acc};
         block_merge<1>(v, red);
         if (threadIdx.x == 0 && threadIdx.y == 0) R.part_a[item.y] = v[0];
@@ -274,10 +274,10 @@ __global__ void __launch_bounds__(kReduceThreads)
     }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kWave *kBatchTY)
+template <typename T, int TY>
+__global__ void __launch_bounds__(kWave *TY)
     k_phase_sweep_b(const BatchRun *runs, const int2 *items, const BatchCtl *ctl) {
-    __shared__ Pair red[2 * kBatchTY];
+    __shared__ Pair red[2 * TY];
     const int n_a = ctl->n_a, n_b = ctl->n_items - ctl->n_a;
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
     const int nt = blockDim.x * blockDim.y;
@@ -343,45 +343,70 @@ __global__ void __launch_bounds__(kReduceThreads)
     }
 }
 
-template <typename T>
-hipError_t batch_step_phases(const BatchRun *runs, const int2 *items, const BatchCtl *ctl,
-                             hipStream_t st) {
-    hipLaunchKernelGGL(k_phase_sweep_a<T>, dim3(kPhaseGridA), dim3(kWave, kBatchTY), 0, st, runs,
+template <typename T, int TY>
+static hipError_t phases(const BatchRun *runs, const int2 *items, const BatchCtl *ctl,
+                         hipStream_t st) {
+    hipLaunchKernelGGL((k_phase_sweep_a<T, TY>), dim3(kPhaseGridA), dim3(kWave, TY), 0, st, runs,
                        items, ctl);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_phase_alpha, dim3(kPhaseGridR), dim3(kReduceThreads), 0, st, runs, ctl);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_phase_sweep_b<T>, dim3(kPhaseGridB), dim3(kWave, kBatchTY), 0, st, runs,
+    hipLaunchKernelGGL((k_phase_sweep_b<T, TY>), dim3(kPhaseGridB), dim3(kWave, TY), 0, st, runs,
                        items, ctl);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_phase_beta, dim3(kPhaseGridR), dim3(kReduceThreads), 0, st, runs, ctl);
     return hipGetLastError();
 }
-template hipError_t batch_step_phases<double>(const BatchRun *, const int2 *, const BatchCtl *,
-                                              hipStream_t);
-template hipError_t batch_step_phases<float>(const BatchRun *, const int2 *, const BatchCtl *,
-                                             hipStream_t);
+
+template <typename T>
+hipError_t batch_step_phases(int ty, const BatchRun *runs, const int2 *items, const BatchCtl *ctl,
+                             hipStream_t st) {
+    switch (ty) {
+        case 4: return phases<T, 4>(runs, items, ctl, st);
+        case 8: return phases<T, 8>(runs, items, ctl, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+template hipError_t batch_step_phases<double>(int, const BatchRun *, const int2 *,
+                                              const BatchCtl *, hipStream_t);
+template hipError_t batch_step_phases<float>(int, const BatchRun *, const int2 *,
+                                             const BatchCtl *, hipStream_t);
 
 // ------------------------------------------------------------------ persistent kernel
 
 template <typename T>
-hipError_t batch_step(int grid, const BatchRun *runs, const int2 *items, BatchCtl *ctl,
+hipError_t batch_step(int ty, int grid, const BatchRun *runs, const int2 *items, BatchCtl *ctl,
                       hipStream_t st) {
-    hipLaunchKernelGGL(k_batch_step<T>, dim3(grid), dim3(kWave, kBatchTY), 0, st, runs, items,
-                       ctl);
+    switch (ty) {
+        case 4:
+            hipLaunchKernelGGL((k_batch_step<T, 4>), dim3(grid), dim3(kWave, 4), 0, st, runs,
+                               items, ctl);
+            break;
+        case 8:
+            hipLaunchKernelGGL((k_batch_step<T, 8>), dim3(grid), dim3(kWave, 8), 0, st, runs,
+                               items, ctl);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
-template hipError_t batch_step<double>(int, const BatchRun *, const int2 *, BatchCtl *, hipStream_t);
-template hipError_t batch_step<float>(int, const BatchRun *, const int2 *, BatchCtl *, hipStream_t);
+template hipError_t batch_step<double>(int, int, const BatchRun *, const int2 *, BatchCtl *,
+                                       hipStream_t);
+template hipError_t batch_step<float>(int, int, const BatchRun *, const int2 *, BatchCtl *,
+                                      hipStream_t);
 
 template <typename T>
-hipError_t batch_step_grid(int *grid) {
+hipError_t batch_step_grid(int ty, int *grid) {
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_step<T>,
-                                                               kWave * kBatchTY, 0);
+    hipError_t e = ty == 4 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_step<T, 4>,
+                                                                         kWave * 4, 0)
+                 : ty == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_step<T, 8>,
+                                                                         kWave * 8, 0)
+                           : hipErrorInvalidValue;
     if (e != hipSuccess) return e;
     int dev = 0;
     e = hipGetDevice(&dev);
@@ -392,7 +417,7 @@ hipError_t batch_step_grid(int *grid) {
     *grid = (per_cu > 0 ? per_cu : 1) * cus;
     return hipSuccess;
 }
-template hipError_t batch_step_grid<double>(int *);
-template hipError_t batch_step_grid<float>(int *);
+template hipError_t batch_step_grid<double>(int, int *);
+template hipError_t batch_step_grid<float>(int, int *);
 
 }  // namespace excmg

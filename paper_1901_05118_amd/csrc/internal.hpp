@@ -226,14 +226,14 @@ hipError_t exp_true_2d(int N, const double *uh, const double *u2h, double *ut, h
 
 // ---------------------------------------------------------------- batched Bi-CG
 
-constexpr int kBatchTY = 8;            // tile height of the batched sweep A
+constexpr int kBatchTY = 8;            // default tile height of the batched sweep A (4 or 8)
 constexpr int kMaxRuns = 256;          // systems per batch
 constexpr long long kChunkGraph = 16384;      // unknowns per sweep-B item (phase kernels)
 constexpr long long kChunkPersistent = 32768; // unknowns per sweep-B item (persistent kernel)
 
 // One running Bi-CG system of a batch (device-resident table).
 struct BatchRun {
-    Geom g;                 // sweep-A geometry (ty = kBatchTY)
+    Geom g;                 // sweep-A geometry (ty: the batch's tile height)
     long long nu;           // unknowns
     int a_count, b_count;   // sweep-A tiles, sweep-B chunks
     long long chunk;        // unknowns per sweep-B chunk
@@ -263,15 +263,15 @@ struct BatchCtl {
 // One Bi-CG iteration of every running system as ONE launch of the persistent work-queue
 // kernel (grid = resident workgroups).
 template <typename T>
-hipError_t batch_step(int grid, const BatchRun *runs, const int2 *items, BatchCtl *ctl,
+hipError_t batch_step(int ty, int grid, const BatchRun *runs, const int2 *items, BatchCtl *ctl,
                       hipStream_t st);
 template <typename T>
-hipError_t batch_step_grid(int *grid);
+hipError_t batch_step_grid(int ty, int *grid);
 
 // The same iteration as four phase launches (sweep A, alpha, sweep B, beta) over the work
 // list in ctl; grid-stride, no inter-workgroup communication inside a launch.
 template <typename T>
-hipError_t batch_step_phases(const BatchRun *runs, const int2 *items, const BatchCtl *ctl,
+hipError_t batch_step_phases(int ty, const BatchRun *runs, const int2 *items, const BatchCtl *ctl,
                              hipStream_t st);
 
 }  // namespace excmg

@@ -19,6 +19,7 @@ __all__ = [
     "lib_path", "load", "set_stream", "setup", "apply_stencil", "apply_operator", "rhs", "dsolve", "bicg",
     "level_solve", "exp_finite", "exp_true", "solve", "solve_ex", "profile_sweep",
     "set_shape", "get_shape", "set_timing", "get_timing", "autotune", "solve_batch",
+    "autotune_batch", "get_batch_shape",
     "get_level_solution", "setup_2d", "solve_ex_2d", "exp_finite_2d", "exp_true_2d",
     "Problem",
     "last_error", "finalize",
@@ -323,7 +324,7 @@ def profile_sweep(which: int, precision: int = FP64, reps: int = 20):
 
 def solve_batch(problems, tol: float, precision: int = FP64, max_iters: int = 0,
                 max_runs: int = 0, inner_tol: float = 0.0, max_outer: int = 0,
-                persistent: bool = False):
+                persistent: bool = False, fp32_min_unknowns: int = 0):
     """Solve independent problems together.  ``problems`` is a list of dicts with keys
     n_finest, n_levels, bc_kind, f, g1, g2, u_out and optionally ut_out.  Returns
     (code, list of Stats)."""
@@ -334,7 +335,7 @@ def solve_batch(problems, tol: float, precision: int = FP64, max_iters: int = 0,
                          _ptr(p["f"], name="f"), _ptr(p["g1"], name="g1"), _ptr(p["g2"], name="g2"),
                          _ptr(p["u_out"], name="u_out"), _ptr(p.get("ut_out"), name="ut_out"))
     o = Opts(0, 0, 0, precision, tol, max_iters, max_runs, inner_tol, max_outer,
-             1 if persistent else 0, BICG, RESTART, PRECOND_NONE, 0)
+             1 if persistent else 0, BICG, RESTART, PRECOND_NONE, fp32_min_unknowns)
     st = (Stats * n)()
     rc = load().excmg_solve_batch(n, arr, ctypes.byref(o), st)
     if rc not in (OK, ENOCONV, EBREAKDOWN):
@@ -350,6 +351,33 @@ def autotune(n: int, kind: int, precision: int = FP64, reps: int = 5):
     _check("excmg_autotune", load().excmg_autotune(n, kind, precision, reps, ctypes.byref(ty),
                                                    ctypes.byref(zc), ctypes.byref(ms)))
     return ty.value, zc.value, ms.value
+
+
+def autotune_batch(problems, precision: int = FP64, reps: int = 3, fp32_min_unknowns: int = 0):
+    """Tune the batched sweep A's tile height and per-size z-chunks on this batch (see
+    excmg_autotune_batch).  ``problems`` as for solve_batch.  Returns (ty, ms per step)."""
+    n = len(problems)
+    arr = (Problem * n)()
+    for i, p in enumerate(problems):
+        arr[i] = Problem(p["n_finest"], p["n_levels"], p["bc_kind"],
+                         _ptr(p["f"], name="f"), _ptr(p["g1"], name="g1"), _ptr(p["g2"], name="g2"),
+                         _ptr(p["u_out"], name="u_out"), _ptr(p.get("ut_out"), name="ut_out"))
+    o = Opts(0, 0, 0, precision, 1e-8, 0, 0, 0.0, 0, 0, BICG, RESTART, PRECOND_NONE,
+             fp32_min_unknowns)
+    ty = ctypes.c_int(0)
+    ms = ctypes.c_double(0.0)
+    _check("excmg_autotune_batch", load().excmg_autotune_batch(n, arr, ctypes.byref(o), reps,
+                                                               ctypes.byref(ty),
+                                                               ctypes.byref(ms)))
+    return ty.value, ms.value
+
+
+def get_batch_shape(n: int, precision: int = FP64):
+    """(tile height, z-chunk) of the batched sweep A on grids of n cells."""
+    ty, zc = ctypes.c_int(0), ctypes.c_int(0)
+    _check("excmg_get_batch_shape", load().excmg_get_batch_shape(n, precision, ctypes.byref(ty),
+                                                                 ctypes.byref(zc)))
+    return ty.value, zc.value
 
 
 def set_timing(on: bool):

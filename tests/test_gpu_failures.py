@@ -44,8 +44,8 @@ def test_nan_forcing_reports_breakdown(ex):
 def test_batched_breakdown_ends_the_level_as_a_single_solve_does(ex, prec):
     """A NaN in one problem of a batch: that problem's levels end as in a single solve (FP64:
     the Bi-CG run breaks down, the level reports EBREAKDOWN and the cascade goes on; mixed
-    precision with restarts: the FP64 residual is not finite, so refinement stops at once),
-    and the other problem is unharmed."""
+    precision with restarts, FP32 on every level: the FP64 residual is not finite, so
+    refinement stops at once), and the other problem is unharmed."""
     p = ex.FP64 if prec == "fp64" else ex.MIXED
     arr, f, g1, g2 = _inputs()
     f[16, 16, 16] = float("nan")
@@ -56,7 +56,7 @@ def test_batched_breakdown_ends_the_level_as_a_single_solve_does(ex, prec):
     ub, ub2 = torch.empty_like(f), torch.empty_like(f2)
     probs = [dict(n_finest=32, n_levels=4, bc_kind=1, f=f, g1=g1, g2=g2, u_out=ub),
              dict(n_finest=32, n_levels=4, bc_kind=2, f=f2, g1=g12, g2=g22, u_out=ub2)]
-    rc, sts = ex.solve_batch(probs, 1e-8, precision=p)
+    rc, sts = ex.solve_batch(probs, 1e-8, precision=p, fp32_min_unknowns=1)
     assert rc == rc1
     single = st1.levels()
     batched = sts[0].levels()

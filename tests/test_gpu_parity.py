@@ -333,13 +333,58 @@ def test_batch_mixed_large_grids_meet_tolerance_and_accuracy(ex, persistent):
         e_fp64 = O.norm2(ref.u - arr.u)
         assert abs(O.norm2(u - arr.u) - e_fp64) <= 0.01 * e_fp64
         print(f"batch mixed N={N}: max |u - u_oracle| = {np.abs(u - ref.u).max():.3e}", flush=True)
+        # levels under 2^18 unknowns run FP64 Bi-CG, the larger ones (95^3, 127^3) FP32 Bi-CG
+        # in restarted refinement: the single solve with the same split, bit for bit
+        single = torch.empty_like(f)
+        rc1, st1 = ex.solve_ex(N, nl, bc, f, g1, g2, 1e-9, single, precision=ex.MIXED,
+                               refine=ex.RESTART, fp32_min_unknowns=1 << 18)
+        assert rc1 == ex.OK
+        assert [l["iterations"] for l in st.levels()] == [l["iterations"] for l in st1.levels()]
+        assert [l["runs"] for l in st.levels()] == [l["runs"] for l in st1.levels()]
+        np.testing.assert_array_equal(u.ravel(), host(single).ravel())
 
 
-def test_batch_mixed_meets_tolerance_and_accuracy(ex):
+def test_batch_autotuned_shapes_keep_results(ex):
+    """The batch shape tuner times whole batch steps on the batch's own work list; the
+    shapes it records leave every batched solution equal to the single solves."""
+    items = [(32, 4, 1, 2), (48, 5, 2, 3), (64, 5, 1, 4), (96, 6, 2, 2)]
+    data = _batch_inputs([(N, nl, bc, config_problem(c)) for (N, nl, bc, c) in items])
+    probs = [dict(n_finest=N, n_levels=nl, bc_kind=bc, f=f, g1=g1, g2=g2,
+                  u_out=torch.empty_like(f)) for (N, nl, bc, arr, f, g1, g2) in data]
+    ty, ms = ex.autotune_batch(probs, precision=ex.FP64, reps=2)
+    assert ty in (4, 8) and ms > 0
+    shapes = {N: ex.get_batch_shape(N) for (N, *_rest) in items}
+    print("batch shapes", shapes, f"{ms:.3f} ms per step", flush=True)
+    assert all(t == ty and 1 <= zc <= N - 1 for N, (t, zc) in shapes.items())
+    for persistent in (False, True):
+        rc, stats = ex.solve_batch(probs, 1e-9, persistent=persistent)
+        assert rc == ex.OK, ex.last_error()
+        for (N, nl, bc, arr, f, g1, g2), p in zip(data, probs):
+            u1 = torch.empty_like(f)
+            assert ex.solve_ex(N, nl, bc, f, g1, g2, 1e-9, u1)[0] == ex.OK
+            np.testing.assert_array_equal(host(p["u_out"]), host(u1))
+    # mixed: the 96^3 problem's finest level runs FP32 (its own tuned chunk)
+    ty, ms = ex.autotune_batch(probs, precision=ex.MIXED, reps=2)
+    print("mixed batch: ty", ty, "96^3 FP32 shape", ex.get_batch_shape(96, ex.MIXED),
+          f"{ms:.3f} ms per step", flush=True)
+    rc, stats = ex.solve_batch(probs, 1e-9, precision=ex.MIXED)
+    assert rc == ex.OK, ex.last_error()
+    for (N, nl, bc, arr, f, g1, g2), p in zip(data, probs):
+        u1 = torch.empty_like(f)
+        assert ex.solve_ex(N, nl, bc, f, g1, g2, 1e-9, u1, precision=ex.MIXED, refine=ex.RESTART,
+                           fp32_min_unknowns=1 << 18)[0] == ex.OK
+        np.testing.assert_array_equal(host(p["u_out"]), host(u1))
+
+
+@pytest.mark.parametrize("fp32_min", [0, 1])
+def test_batch_mixed_meets_tolerance_and_accuracy(ex, fp32_min):
+    """fp32_min 0: every level of these grids (up to 47^3 unknowns) is under 2^18 unknowns
+    and runs FP64 Bi-CG, so the mixed batch equals the FP64 solves; 1: every level runs
+    FP32 Bi-CG in restarted refinement, as the single restarted solve does."""
     data = _batch_problems()
     probs = [dict(n_finest=N, n_levels=nl, bc_kind=bc, f=f, g1=g1, g2=g2,
                   u_out=torch.empty_like(f)) for (N, nl, bc, arr, f, g1, g2) in data]
-    rc, stats = ex.solve_batch(probs, 1e-8, precision=ex.MIXED)
+    rc, stats = ex.solve_batch(probs, 1e-8, precision=ex.MIXED, fp32_min_unknowns=fp32_min)
     assert rc == ex.OK, ex.last_error()
     for (N, nl, bc, arr, f, g1, g2), p, st in zip(data, probs, stats):
         u = host(p["u_out"]).reshape((N + 1,) * 3)
@@ -352,9 +397,13 @@ def test_batch_mixed_meets_tolerance_and_accuracy(ex):
         e_fp64 = O.norm2(ref.u - arr.u)
         assert abs(e_mixed - e_fp64) <= 0.01 * e_fp64
         single = torch.empty_like(f)
-        # the batch path refines by restarted FP32 solves
-        rc1, st1 = ex.solve_ex(N, nl, bc, f, g1, g2, 1e-8, single, precision=ex.MIXED,
-                               refine=ex.RESTART)
+        if fp32_min == 0:
+            rc1, st1 = ex.solve_ex(N, nl, bc, f, g1, g2, 1e-8, single)
+        else:
+            # the batch path refines by restarted FP32 solves
+            rc1, st1 = ex.solve_ex(N, nl, bc, f, g1, g2, 1e-8, single, precision=ex.MIXED,
+                                   refine=ex.RESTART)
+        assert rc1 == ex.OK
         assert [l["iterations"] for l in st.levels()] == [l["iterations"] for l in st1.levels()]
         np.testing.assert_array_equal(u.ravel(), host(single).ravel())
 
