@@ -239,6 +239,18 @@ int excmg_get_level_solution(int level, double *u);
  * cells) and u0 (n/4 cells).  w is a node array of n cells.  Needs no context. */
 int excmg_exp_finite(int n, const double *u1, const double *u0, double *w);
 
+/* EXP_finite for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same operation and the same
+ * results as excmg_exp_finite, with its intermediate grid in a fixed device array of the
+ * library instead of an allocation.  That array holds (256/2 + 1)^3 doubles (17.2 MB), one
+ * per GPU, allocated when the library is loaded and held until the process ends; so
+ * n <= 256 (a multiple of 4).  u1, u0 and w must be device arrays (nothing is staged).
+ * The work is queued on the library stream and the call returns without waiting for it
+ * (results are complete when that stream reaches this point).  Every call on a GPU shares
+ * its array: calls that overlap on one GPU (other streams or host threads) race.  Errors:
+ * EXCMG_EINVAL (n out of range, NULL or host arrays), EXCMG_EHIP. */
+int excmg_exp_finite_noalloc(int n, const double *u1, const double *u0, double *w);
+
 /* ut = EXP_true(uh, u2h) (Sec. 4.2.1, eqs. t1 and chenlin): higher-order approximation of the
  * true solution on the grid of n cells (n even) from the node arrays uh (n cells) and u2h
  * (n/2 cells).  Needs no context. */

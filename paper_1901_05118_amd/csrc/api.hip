@@ -1834,6 +1834,35 @@ struct BatchSolver {
 
 }  // namespace
 
+// ================================================================== fixed scratch
+
+// The intermediate grid of EXP_finite for callers that cannot allocate (excmg_exp_finite
+// without allocation): a fixed device array of the library, one per GPU, held until the
+// process ends.  Its largest use is the (n/2 + 1)^3 Z1 grid of n = kStaticExpFiniteMaxN.
+constexpr int kStaticExpFiniteMaxN = 256;
+constexpr size_t kStaticScratchDoubles =
+    (size_t)(kStaticExpFiniteMaxN / 2 + 1) * (kStaticExpFiniteMaxN / 2 + 1) *
+    (kStaticExpFiniteMaxN / 2 + 1);
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+// Device address of `scratch` on each GPU (the array's name in host code is not a device
+// address).  Looked up once per device, with that device current, on its first use.
+constexpr int kMaxDevices = 64;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+int static_scratch(double **out) {
+    int dev = 0;
+    CKH(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(EXCMG_EINVAL, "device %d out of range", dev);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        CKH(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = (double *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return EXCMG_OK;
+}
+
 // ================================================================== C ABI
 
 extern "C" {
@@ -2051,6 +2080,22 @@ int excmg_exp_finite(int n, const double *u1, const double *u0, double *w) {
     CKH(e);
     CKR(aw.back());
     CKH(hipStreamSynchronize(g_stream));
+    return EXCMG_OK;
+}
+
+int excmg_exp_finite_noalloc(int n, const double *u1, const double *u0, double *w) {
+    g_err[0] = 0;
+    if (n < 4 || n % 4 != 0 || n > kStaticExpFiniteMaxN)
+        return fail(EXCMG_EINVAL, "n must be a multiple of 4 in 4..%d (got %d)",
+                    kStaticExpFiniteMaxN, n);
+    if (!u1 || !u0 || !w) return fail(EXCMG_EINVAL, "NULL array");
+    if (!is_device_ptr(u1) || !is_device_ptr(u0) || !is_device_ptr(w))
+        return fail(EXCMG_EINVAL, "u1, u0 and w must be device arrays (nothing is staged)");
+    double *v = nullptr;
+    CKR(static_scratch(&v));
+    // every node of the Z1 grid is written by the first kernel before the second reads it,
+    // so the array needs no clearing between calls
+    CKH(exp_finite(n, u1, u0, v, w, g_stream));
     return EXCMG_OK;
 }
 

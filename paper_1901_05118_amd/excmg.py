@@ -17,7 +17,7 @@ __all__ = [
     "MIXED", "EXIT_TOL", "EXIT_CAP", "EXIT_FLOOR", "EXIT_BREAKDOWN",
     "BICG", "CG", "RELIABLE", "RESTART", "PRECOND_NONE", "PRECOND_JACOBI", "bicg_ex", "diagonal",
     "lib_path", "load", "set_stream", "setup", "apply_stencil", "apply_operator", "rhs", "dsolve", "bicg",
-    "level_solve", "exp_finite", "exp_true", "solve", "solve_ex", "profile_sweep",
+    "level_solve", "exp_finite", "exp_finite_noalloc", "exp_true", "solve", "solve_ex", "profile_sweep",
     "set_shape", "get_shape", "set_timing", "get_timing", "autotune", "solve_batch",
     "autotune_batch", "get_batch_shape",
     "get_level_solution", "setup_2d", "solve_ex_2d", "exp_finite_2d", "exp_true_2d",
@@ -249,6 +249,14 @@ def get_level_solution(level: int, u):
 def exp_finite(n: int, u1, u0, w):
     _check("excmg_exp_finite", load().excmg_exp_finite(n, _ptr(u1, name="u1"), _ptr(u0, name="u0"),
                                                        _ptr(w, name="w")))
+
+
+def exp_finite_noalloc(n: int, u1, u0, w):
+    """excmg_exp_finite_noalloc: EXP_finite with the library's fixed scratch array (device
+    arrays only, n <= 256); queued on the library stream, not waited for."""
+    _check("excmg_exp_finite_noalloc",
+           load().excmg_exp_finite_noalloc(n, _ptr(u1, name="u1"), _ptr(u0, name="u0"),
+                                           _ptr(w, name="w")))
 
 
 def exp_true(n: int, uh, u2h, ut):
