@@ -105,9 +105,11 @@ typedef struct excmg_opts {
                         /* (and of the FP64 iterate and right-hand side they are solved     */
                         /* with) on a 128-byte multiple plus 128 bytes, so no cache line is */
                         /* split between two stencil tiles; the level's b and u are copied  */
-                        /* in and out.  0 (default): contiguous rows.  Same results bit for */
-                        /* bit; padded rows speed up the Bi-CG stencil sweep on large grids */
-                        /* and slow the vector updates, about even for the whole solve      */
+                        /* in and out.  2: the same on the levels that take the recomputing */
+                        /* form (recompute_min_unknowns), whose two sweeps then process two */
+                        /* adjacent points per lane (8-byte accesses, 128-wide tiles).      */
+                        /* 0 (default): contiguous rows.  Same results bit for bit; in the  */
+                        /* 512^3 solve 1 and 2 are 2-4% slower than 0 on MI355X             */
     int recompute_min_unknowns; /* 3D Bi-CG (FP64 and mixed): levels with at least this many */
                         /* unknowns form q = A p and q* = A^T p* again in the update sweep   */
                         /* instead of storing them (mixed 64 instead of 72 bytes per unknown */
@@ -339,16 +341,16 @@ int excmg_solve_batch(int nprob, const excmg_problem *probs, const excmg_opts *o
                       excmg_stats *stats);
 
 /* Autotuner of the batched Bi-CG step (configuration of excmg_solve_batch): puts the finest
- * level of every problem of the batch into a running Bi-CG run and times whole steps of the
- * batch (the phase launches, replayed from a captured graph; `reps` graph replays of 8 steps
- * per shape) for tile heights of 4 and 8 rows and, per distinct grid size, z-chunks of 2, 4,
- * ..., 128 planes and the whole depth (a coordinate descent over the sizes).  The fastest
- * height (one per batch: a launch has one workgroup shape) and the chunk of every size are
- * recorded for later excmg_solve_batch calls, per grid size and vector precision (FP32
- * for the finest levels that a mixed batch runs in FP32); sizes never tuned keep the
- * single-problem table's chunk.  opts supplies precision and fp32_min_unknowns (its
- * tolerance is not used).  Outputs (may be NULL): the tile height and the mean ms per batch
- * step.  No caller array is written. */
+ * level of the batch's problems into running Bi-CG runs and, for tile heights of 4 and 8
+ * rows and per distinct grid size, times steps of that size's systems alone (the phase
+ * launches, replayed from a captured graph; `reps` graph replays of 8 steps per shape) with
+ * z-chunks of 2, 4, ..., 128 planes and the whole depth.  The height with the smallest sum
+ * of the sizes' best steps (one per batch: a launch has one workgroup shape) and the chunk
+ * of every size are recorded for later excmg_solve_batch calls, per grid size and vector
+ * precision (FP32 for the finest levels that a mixed batch runs in FP32); sizes never tuned
+ * keep the single-problem table's chunk.  opts supplies precision and fp32_min_unknowns (its
+ * tolerance is not used).  Outputs (may be NULL): the tile height and that sum of step
+ * times in ms.  No caller array is written. */
 int excmg_autotune_batch(int nprob, const excmg_problem *probs, const excmg_opts *opts, int reps,
                          int *ty, double *ms_per_step);
 /* The batched sweep A's tile height and the z-chunk it takes on grids of n cells with FP32

@@ -143,6 +143,10 @@ struct Level {
     int ld = 0;
     long long nflat = 0;
     Geom g1p{};
+    // The recomputing form's FP32 sweeps with two points per lane (128-wide tiles) on padded
+    // rows: g2w (tw = 0 where the grid cannot take them), used when `wide` is set.
+    Geom g2w{};
+    bool wide = false;
     DBuf b, x, u;     // right-hand side, unknowns, node array (solution or EXP_finite guess)
     DBuf diag;        // diag(A_h), made when a Jacobi-preconditioned solve first needs it
     Rows rows() const { return ld == n ? Rows{} : Rows{n, ld}; }
@@ -265,6 +269,10 @@ void set_rows(Level &L, int ld, int dim) {
 
 int level_ld(int n, int row_pad) { return row_pad > 0 ? padded_ld(n) : n; }
 
+// z-chunk of the two-point sweeps: 64 planes (four chunks on 256^3: one workgroup per CU
+// with 128 x 8 tiles), the whole depth from 384 unknowns per axis.
+int wide_zc(int n) { return n >= 384 ? n : 64; }
+
 void choose_shapes(Level &L, int bc, int dim = 3) {
     if (dim == 2) {  // one pass per tile: more rows per workgroup on large planes
         const int n = L.N - 1;
@@ -274,6 +282,8 @@ void choose_shapes(Level &L, int bc, int dim = 3) {
         L.g1 = choose_shape(L.N, bc, 0);
         L.g2 = choose_shape(L.N, bc, 1);
         L.g2f = choose_shape(L.N, bc, 2);
+        const int n = L.N - 1;
+        L.g2w = make_geom_wide(n, bc, 8, std::min(wide_zc(n), n), padded_ld(n));
     }
     set_rows(L, L.ld > 0 ? L.ld : L.n, dim);
 }
@@ -369,7 +379,8 @@ int setup_levels(int n_finest, int n_levels, int bc, int dim) {
     CKR(c.ubest.ensure((size_t)F.nu * 8));
     int maxblk = 4096 * 2;
     for (auto &L : c.lv)
-        maxblk = std::max({maxblk, stencil_blocks(L.g1), stencil_blocks(L.g2), stencil_blocks(L.g2f)});
+        maxblk = std::max({maxblk, stencil_blocks(L.g1), stencil_blocks(L.g2), stencil_blocks(L.g2f),
+                           stencil_blocks(L.g2w)});
     CKR(c.part_a.ensure((size_t)maxblk * sizeof(Pair)));
     // two values per partial: the update kernels (at most 4096) or the recomputing update
     // sweep (one per tile)
@@ -497,14 +508,18 @@ bool recompute_q(const Level &L) {
 }
 
 // Partials (per value) that the update sweep of level L leaves for the next sweep A.
+// The geometry of the FP32 recomputing sweeps of level L (two points per lane when the
+// level takes them).
+inline const Geom &rq_geom_f32(const Level &L) { return L.wide ? L.g2w : L.g2f; }
+
 template <typename TX, typename T>
 int b_partials(const Level &L) {
-    return recompute_q<TX, T>(L) ? stencil_blocks(sizeof(T) == 4 ? L.g2f : L.g2)
+    return recompute_q<TX, T>(L) ? stencil_blocks(sizeof(T) == 4 ? rq_geom_f32(L) : L.g2)
                                  : update_blocks(L.nu);
 }
 
 struct GraphEntry {
-    int level, tsize, cg, K, defer, ld, rq;
+    int level, tsize, cg, K, defer, ld, rq, wide;
     const void *x, *d, *xs;
     hipGraph_t graph;
     hipGraphExec_t exec;
@@ -534,7 +549,9 @@ int launch_iteration(const Level &L, TX *x, long long j, int ev, hipStream_t st,
     Ctx &c = g_ctx;
     BicgState *S = c.state.as<BicgState>();
     T *r = c.r.as<T>(), *rs = c.rs.as<T>(), *q = c.q.as<T>(), *qs = c.qs.as<T>();
-    const Geom &G = sizeof(T) == 4 ? L.g2f : L.g2;
+    // the recomputing form's FP32 sweeps may take two points per lane; every other sweep
+    // keeps the level's single-point FP32 or FP64 shape
+    const Geom &G = sizeof(T) == 4 ? (recompute_q<TX, T>(L) ? rq_geom_f32(L) : L.g2f) : L.g2;
     // FP32 vectors (and the iterate solved with them) have the level's row layout
     const Rows rows = sizeof(T) == 4 ? L.rows() : Rows{};
     const int nsb = stencil_blocks(G);
@@ -623,7 +640,7 @@ int window_graph(const Level &L, TX *x, int K, hipGraphExec_t *out, int defer = 
     for (GraphEntry &e : g_graph_cache)
         if (e.level == L.index && e.tsize == (int)sizeof(T) && e.cg == (int)g_cg &&
             e.K == K && e.defer == defer && e.ld == L.ld &&
-            e.rq == (int)recompute_q<TX, T>(L) &&
+            e.rq == (int)recompute_q<TX, T>(L) && e.wide == (int)L.wide &&
             e.x == (const void *)x &&
             e.d == g_var.d && e.xs == g_var.xs) {
             *out = e.exec;
@@ -645,7 +662,8 @@ int window_graph(const Level &L, TX *x, int K, hipGraphExec_t *out, int defer = 
     hipGraphExec_t exec = nullptr;
     CKH(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
     g_graph_cache.push_back(GraphEntry{L.index, (int)sizeof(T), (int)g_cg, K, defer,
-                                       L.ld, (int)recompute_q<TX, T>(L), (const void *)x, g_var.d, g_var.xs, graph, exec});
+                                       L.ld, (int)recompute_q<TX, T>(L), (int)L.wide,
+                                       (const void *)x, g_var.d, g_var.xs, graph, exec});
     *out = exec;
     return EXCMG_OK;
 }
@@ -1087,7 +1105,10 @@ int solve_cascade(const excmg_opts &o, const double *f, const double *g1, const 
         // padded rows: the FP64 copies of b and u they are solved with, made on first use
         long long flat = 0;
         for (Level &Lv : c.lv) {
-            set_rows(Lv, level_ld(Lv.n, mixed ? o.row_pad : 0), c.dim);
+            // row_pad 2: padded rows and two-point sweeps on the levels that take the
+            // recomputing form
+            Lv.wide = mixed && o.row_pad == 2 && Lv.nu >= g_rq_min && Lv.g2w.tw != 0;
+            set_rows(Lv, level_ld(Lv.n, mixed && (o.row_pad == 1 || Lv.wide) ? 1 : 0), c.dim);
             if (Lv.ld != Lv.n) flat = std::max(flat, Lv.nflat);
         }
         if (flat > 0) {
@@ -1671,11 +1692,16 @@ struct BatchSolver {
     }
 
     // ------------------------------------------------------------ shape tuning
-    // Every problem's finest level as a running Bi-CG system (from x = 0, with a tolerance
-    // it never reaches), so that steps of the whole batch can be timed with any shape.
-    int tune_prepare() {
+    // The finest level of every problem of `only_n` cells (0: of every problem) as a running
+    // Bi-CG system (from x = 0, with a tolerance it never reaches), the other problems idle,
+    // so that their steps can be timed with any shape.
+    int tune_prepare(int only_n) {
         for (int j = 0; j < (int)pb.size(); j++) {
             BProb &b = *pb[j];
+            if (only_n && b.N != only_n) {
+                b.phase = kPhaseDone;
+                continue;
+            }
             b.level = b.nl - 1;
             b.f32 = level_f32(b, b.level);
             Level &Lv = b.lv[b.level];
@@ -1712,10 +1738,10 @@ struct BatchSolver {
         }
     }
 
-    // Mean ms of one Bi-CG step of the whole batch (phase launches replayed from a graph),
-    // every system restarted first.
-    int tune_time(int reps, double *ms) {
-        CKR(tune_prepare());
+    // Mean ms of one Bi-CG step of the systems of `only_n` cells (0: of the whole batch;
+    // phase launches replayed from a graph), every system restarted first.
+    int tune_time(int reps, int only_n, double *ms) {
+        CKR(tune_prepare(only_n));
         CKR(build_items());
         for (StepSet &K : set) K.drop_graph();
         CKR(launch_steps());  // captures the graphs; warm-up
@@ -1737,10 +1763,10 @@ struct BatchSolver {
         return EXCMG_OK;
     }
 
-    // For each tile height (4 and 8 rows), a coordinate descent over the batch's grid sizes:
-    // each size in turn tries z-chunks of 2, 4, ... planes and the whole depth, keeping the
-    // fastest step of the whole batch.  The fastest (height, chunks) is recorded for later
-    // batches.
+    // For each tile height (4 and 8 rows) and each of the batch's grid sizes, z-chunks of 2,
+    // 4, ... planes and the whole depth are timed on steps of the systems of that size alone
+    // (in a whole-batch step the largest systems hide the others' shapes); the height with
+    // the smallest sum of the sizes' best steps is kept, with their chunks, for later batches.
     int tune(int reps, int *ty_out, double *ms_out) {
         persistent = false;
         std::vector<int> sizes;
@@ -1759,28 +1785,29 @@ struct BatchSolver {
                 const bool f32 = mixed && (long long)(N - 1) * (N - 1) * (N - 1) >= fp32_min;
                 zc.push_back({N, f32, batch_zc(N, 1, f32)});
             }
-            tune_apply(zc);
-            double cur = 0.0;
-            CKR(tune_time(reps, &cur));
+            double total = 0.0;
             for (auto &e : zc) {
                 const int n = e.N - 1;
+                tune_apply(zc);
+                double cur = 0.0;
+                CKR(tune_time(reps, e.N, &cur));
                 int keep = e.zc;
                 for (int z : {2, 4, 8, 16, 32, 64, 128, n}) {
                     if (z > n || z == keep) continue;
                     e.zc = z;
                     tune_apply(zc);
                     double t = 0.0;
-                    CKR(tune_time(reps, &t));
+                    CKR(tune_time(reps, e.N, &t));
                     if (t < cur) {
                         cur = t;
                         keep = z;
                     }
                 }
                 e.zc = keep;
-                tune_apply(zc);
+                total += cur;
             }
-            if (cur < best) {
-                best = cur;
+            if (total < best) {
+                best = total;
                 best_ty = cand;
                 best_zc = zc;
             }
@@ -2131,7 +2158,7 @@ int solve_ex_dim(const excmg_opts *opts, const double *f, const double *g1, cons
         return fail(EXCMG_EINVAL, "precond %d not supported", o.precond);
     if (o.fp32_min_unknowns < 0)
         return fail(EXCMG_EINVAL, "fp32_min_unknowns must be >= 0");
-    if (o.row_pad != 0 && o.row_pad != 1) return fail(EXCMG_EINVAL, "row_pad must be 0 or 1");
+    if (o.row_pad < 0 || o.row_pad > 2) return fail(EXCMG_EINVAL, "row_pad must be 0, 1 or 2");
     if (o.recompute_min_unknowns < 0)
         return fail(EXCMG_EINVAL, "recompute_min_unknowns must be >= 0");
     if (o.precond == EXCMG_PRECOND_JACOBI && (o.precision != EXCMG_FP64 || o.method != EXCMG_BICG))
@@ -2302,12 +2329,12 @@ int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launc
                                                       c.q.as<float>(), rs, c.qs.as<float>(),
                                                       c.part_b.as<Pair>(), g_stream, StepLink{},
                                                       rows);
-            case 7: return stencil_dir_sigma<float>(L.g2f, L.g2f.ty, r, rs, c.p[0].as<float>(),
+            case 7: return stencil_dir_sigma<float>(rq_geom_f32(L), rq_geom_f32(L).ty, r, rs, c.p[0].as<float>(),
                                              c.ps[0].as<float>(), &S->beta, 0,
                                              c.p[1].as<float>(), c.ps[1].as<float>(),
                                              c.part_a.as<Pair>(), &S->status, g_stream,
                                              StepLink{});
-            case 8: return stencil_pair_update<float>(L.g2f, L.g2f.ty, c.p[1].as<float>(),
+            case 8: return stencil_pair_update<float>(rq_geom_f32(L), rq_geom_f32(L).ty, c.p[1].as<float>(),
                                                c.ps[1].as<float>(), xv, r, rs,
                                                c.part_b.as<Pair>(), &S->status, &S->alpha,
                                                g_stream, StepLink{});
@@ -2581,7 +2608,8 @@ int excmg_set_shape(int n, int kind, int ty, int zc) {
         if (L.N != n) continue;
         choose_shapes(L, g_ctx.bc, g_ctx.dim);
         const size_t need = (size_t)std::max({stencil_blocks(L.g1), stencil_blocks(L.g2),
-                                              stencil_blocks(L.g2f)}) * sizeof(Pair);
+                                              stencil_blocks(L.g2f), stencil_blocks(L.g2w)}) *
+                            sizeof(Pair);
         if (need > g_ctx.part_a.bytes) CKR(g_ctx.part_a.ensure(need));
         if (2 * need > g_ctx.part_b.bytes) CKR(g_ctx.part_b.ensure(2 * need));
     }

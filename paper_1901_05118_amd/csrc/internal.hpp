@@ -18,6 +18,7 @@ struct Geom {
     int dim = 3;                    // 3: n^3 unknowns (z-marched); 2: n^2 unknowns (one plane)
     int ld = 0;                     // elements from one row of a vector to the next (>= n)
     i64 ps = 0;                     // elements from one plane to the next (n * ld)
+    int tw = 64;                    // tile width: 64, or 128 for the two-point sweeps
 };
 
 // The same launch on vectors whose rows are ld elements apart (ld >= n).
@@ -35,6 +36,10 @@ struct Rows {
 };
 
 Geom make_geom(int n, int bc, int ty, int zc);
+// Tiles of 128 x ty columns for the recomputing form's two-point FP32 sweeps, on rows ld
+// apart (ld even); the ld stride is part of the geometry.  Returns tw = 0 when those sweeps
+// cannot address the grid (the 32-bit byte offsets of a chunk of FP64 planes overflow).
+Geom make_geom_wide(int n, int bc, int ty, int zc, int ld);
 Geom make_geom_2d(int n, int bc, int ty);   // the 13-point scheme on an n x n plane
 
 // Device-resident state of one Bi-CG run (Algorithm 2); all scalars FP64.

@@ -1,6 +1,7 @@
-// Launchers of the z-marched stencil kernels (device code in zmarch.hpp).
+// Launchers of the z-marched stencil kernels (device code in zmarch.hpp and zwide.hpp).
 #include "plane2d.hpp"
 #include "zmarch.hpp"
+#include "zwide.hpp"
 
 namespace excmg {
 
@@ -18,6 +19,18 @@ Geom make_geom(int n, int bc, int ty, int zc) {
     g.sgn = (bc == 1) ? 1.0 : -1.0;
     g.ld = n;
     g.ps = (i64)n * n;
+    return g;
+}
+
+Geom make_geom_wide(int n, int bc, int ty, int zc, int ld) {
+    Geom g = with_rows(make_geom(n, bc, ty, zc), ld);
+    g.tw = 2 * kWave;
+    g.tiles_x = (n + g.tw - 1) / g.tw;
+    g.ntiles = g.tiles_x * g.tiles_y * g.tiles_z;
+    // a tile's descriptors start at its first plane; every byte offset of its accesses
+    // (plane offset up to chunk + 3 planes on, plus an in-plane offset below one plane) must
+    // stay below 2^32 for FP64 (the iterate of the update sweep)
+    if (ld % 2 != 0 || (i64)((zc < n ? zc : n) + 4) * g.ps * 8 >= (1LL << 32)) g.tw = 0;
     return g;
 }
 
@@ -190,12 +203,49 @@ hipError_t stencil_pair_direction_x(const Geom &g, int ty, const float *r, const
 }
 
 // The recomputing form's two sweeps (3D grids; see OutDirSigma and OutPairUpdate).
+// Planes in flight of the two-point sweeps (measured at 255^3: two 93 us, three 97 us).
+constexpr int kWideDepth = 2;
+
+#define EXCMG_DISPATCH_WIDE_TY(TYV, ...)                                                     \
+    switch (TYV) {                                                                           \
+        case 4: { constexpr int TY = 4; __VA_ARGS__; } break;                              \
+        case 8: { constexpr int TY = 8; __VA_ARGS__; } break;                              \
+        default: return hipErrorInvalidValue;                                                \
+    }
+
 template <typename T>
 hipError_t stencil_dir_sigma(const Geom &g, int ty, const T *r, const T *rs, const T *p_old,
                              const T *ps_old, const double *beta_dev, int first, T *p_new,
                              T *ps_new, Pair *partials, const int *status, hipStream_t st,
                              StepLink link) {
     if (g.dim != 3) return hipErrorInvalidValue;
+    if (g.tw != kWave) {
+        if constexpr (sizeof(T) == 4) {
+            if (g.tw != 2 * kWave) return hipErrorInvalidValue;
+            WideDirection in;
+            in.r = r;
+            in.p = p_old;
+            in.beta_dev = beta_dev;
+            in.first = first;
+            in.beta = 0.0;
+            in.link = link;
+            WideDirSigma out;
+            out.p_new = p_new;
+            out.ps_new = ps_new;
+            out.rs = rs;
+            out.ps_old = ps_old;
+            out.partials = partials;
+            out.status = status;
+            out.beta = 0.0;
+            out.first = first;
+            out.acc = Pair{0.0, 0.0};
+            EXCMG_DISPATCH_WIDE_TY(ty, hipLaunchKernelGGL(
+                (zwide<1, TY, WideDirection, WideDirSigma, kWideDepth>),
+                dim3(xcd_grid(g.ntiles)), dim3(kWave, TY), 0, st, g, in, out));
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
     InDirection<T> in;
     in.link = link;
     in.r[0] = r;
@@ -225,6 +275,31 @@ hipError_t stencil_pair_update(const Geom &g, int ty, const T *p, const T *ps, d
                                T *rs, Pair *partials, const int *status, const double *alpha_dev,
                                hipStream_t st, StepLink link) {
     if (g.dim != 3) return hipErrorInvalidValue;
+    if (g.tw != kWave) {
+        if constexpr (sizeof(T) == 4) {
+            if (g.tw != 2 * kWave) return hipErrorInvalidValue;
+            WidePlainAlpha in;
+            in.x[0] = p;
+            in.x[1] = ps;
+            in.alpha_dev = alpha_dev;
+            in.link = link;
+            in.alpha = 0.0;
+            WidePairUpdate out;
+            out.x = x;
+            out.r = r;
+            out.rs = rs;
+            out.partials = partials;
+            out.status = status;
+            out.alpha = 0.0;
+            out.acc[0] = Pair{0.0, 0.0};
+            out.acc[1] = Pair{0.0, 0.0};
+            EXCMG_DISPATCH_WIDE_TY(ty, hipLaunchKernelGGL(
+                (zwide<2, TY, WidePlainAlpha, WidePairUpdate, kWideDepth>),
+                dim3(xcd_grid(g.ntiles)), dim3(kWave, TY), 0, st, g, in, out));
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
     InPlainAlpha<T> in;
     in.x[0] = p;
     in.x[1] = ps;

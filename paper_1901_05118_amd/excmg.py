@@ -363,7 +363,8 @@ def autotune(n: int, kind: int, precision: int = FP64, reps: int = 5):
 
 def autotune_batch(problems, precision: int = FP64, reps: int = 3, fp32_min_unknowns: int = 0):
     """Tune the batched sweep A's tile height and per-size z-chunks on this batch (see
-    excmg_autotune_batch).  ``problems`` as for solve_batch.  Returns (ty, ms per step)."""
+    excmg_autotune_batch).  ``problems`` as for solve_batch.  Returns (ty, sum over the grid
+    sizes of the best step time of that size's systems, in ms)."""
     n = len(problems)
     arr = (Problem * n)()
     for i, p in enumerate(problems):

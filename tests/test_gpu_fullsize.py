@@ -114,12 +114,13 @@ def test_first_kind_256_mixed_against_fp64(ex):
 def test_mixed_bicg_equals_cg_at_full_size(ex, problem):
     """The mixed Bi-CG takes the recomputing form on the 256^3 and 512^3 levels (q and q*
     formed again in the update sweep, whose partials are per tile).  The CG form, which
-    stores q, must match bit for bit, and so must the solve on padded rows (row_pad = 1)."""
+    stores q, must match bit for bit, and so must the solves on padded rows (row_pad = 1)
+    and with the two-point sweeps on those levels (row_pad = 2)."""
     print("mixed bicg vs cg 512^3", flush=True)
     arr, b = problem
     f, g1, g2 = dev(arr.f), dev(arr.g1), dev(arr.g2)
     outs, its = [], []
-    for m, pad in ((ex.BICG, 0), (ex.CG, 0), (ex.BICG, 1)):
+    for m, pad in ((ex.BICG, 0), (ex.CG, 0), (ex.BICG, 1), (ex.BICG, 2)):
         u = torch.empty_like(f)
         rc, st = ex.solve_ex(N, NL, BC, f, g1, g2, 1e-8, u, precision=ex.MIXED, method=m,
                              row_pad=pad)
@@ -127,6 +128,7 @@ def test_mixed_bicg_equals_cg_at_full_size(ex, problem):
         outs.append(host(u))
         its.append([(l["iterations"], l["runs"]) for l in st.levels()])
         del u
-    assert its[0] == its[1] == its[2]
+    assert its[0] == its[1] == its[2] == its[3]
     np.testing.assert_array_equal(outs[0], outs[1])
     np.testing.assert_array_equal(outs[0], outs[2])
+    np.testing.assert_array_equal(outs[0], outs[3])

@@ -354,7 +354,7 @@ def test_batch_autotuned_shapes_keep_results(ex):
     ty, ms = ex.autotune_batch(probs, precision=ex.FP64, reps=2)
     assert ty in (4, 8) and ms > 0
     shapes = {N: ex.get_batch_shape(N) for (N, *_rest) in items}
-    print("batch shapes", shapes, f"{ms:.3f} ms per step", flush=True)
+    print("batch shapes", shapes, f"{ms:.3f} ms per step (sizes alone, summed)", flush=True)
     assert all(t == ty and 1 <= zc <= N - 1 for N, (t, zc) in shapes.items())
     for persistent in (False, True):
         rc, stats = ex.solve_batch(probs, 1e-9, persistent=persistent)
@@ -366,7 +366,7 @@ def test_batch_autotuned_shapes_keep_results(ex):
     # mixed: the 96^3 problem's finest level runs FP32 (its own tuned chunk)
     ty, ms = ex.autotune_batch(probs, precision=ex.MIXED, reps=2)
     print("mixed batch: ty", ty, "96^3 FP32 shape", ex.get_batch_shape(96, ex.MIXED),
-          f"{ms:.3f} ms per step", flush=True)
+          f"{ms:.3f} ms per step (sizes alone, summed)", flush=True)
     rc, stats = ex.solve_batch(probs, 1e-9, precision=ex.MIXED)
     assert rc == ex.OK, ex.last_error()
     for (N, nl, bc, arr, f, g1, g2), p in zip(data, probs):
@@ -484,7 +484,34 @@ def test_padded_rows_keep_the_mixed_solve(ex, refine):
     np.testing.assert_array_equal(outs[0], outs[1])
     with pytest.raises(ex.ExcmgError):
         ex.solve_ex(N, nl, bc, f, g1, g2, 1e-9, torch.empty_like(f), precision=ex.MIXED,
-                    row_pad=2)
+                    row_pad=3)
+
+
+@pytest.mark.parametrize("refine", ["reliable", "restart"])
+@pytest.mark.parametrize("case", [(48, 4, 1, 3, 1e-9), (80, 5, 2, 2, 1e-9), (112, 5, 1, 4, 1e-9),
+                                  (160, 6, 2, 1, 1e-6)])
+def test_two_point_sweeps_keep_the_mixed_solve(ex, refine, case):
+    """row_pad = 2: the levels that take the recomputing form (here every level, FP32
+    everywhere) run its two sweeps with two adjacent points per lane on padded rows: 128-wide
+    tiles, ragged in x (47, 79, 111 and 159 unknowns per axis: partial tiles whose last lane
+    holds one point), boundary pairs that mix fictitious points, boundary nodes and points
+    beyond the grid, z-chunks shorter than the grid and whole-depth ones.  Per point the arithmetic is that of the single-point
+    sweeps, so the cascade gives the same iterates, counts and solution bit for bit."""
+    N, nl, bc, c, tol = case
+    arr = make_arrays(config_problem(c), N, bc)
+    f, g1, g2 = dev(arr.f), dev(arr.g1), dev(arr.g2)
+    mode = ex.RELIABLE if refine == "reliable" else ex.RESTART
+    outs, its = [], []
+    for pad in (0, 2):
+        print(f"two-point sweeps N={N} bc={bc} {refine} row_pad={pad}", flush=True)
+        u = torch.empty_like(f)
+        rc, st = ex.solve_ex(N, nl, bc, f, g1, g2, tol, u, precision=ex.MIXED, refine=mode,
+                             fp32_min_unknowns=1, recompute_min_unknowns=1, row_pad=pad)
+        assert rc == ex.OK, ex.last_error()
+        outs.append(host(u))
+        its.append([(l["iterations"], l["runs"]) for l in st.levels()])
+    assert its[0] == its[1]
+    np.testing.assert_array_equal(outs[0], outs[1])
 
 
 def test_autotuned_shape_keeps_results(ex):
