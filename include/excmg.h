@@ -89,7 +89,8 @@ typedef struct excmg_opts {
     int max_iters;      /* Bi-CG iterations per run (0: 100000)                             */
     int max_runs;       /* Bi-CG runs per level in Algorithm 1's while loop (0: 5)          */
     double inner_tol;   /* mixed precision: residual reduction per refinement step        */
-                        /* (0: 0.1 with EXCMG_RELIABLE, 1e-4 with EXCMG_RESTART)           */
+                        /* (0: 0.1 with EXCMG_RELIABLE, 1e-4 with EXCMG_RESTART, 1e-5 in    */
+                        /* excmg_solve_batch)                                               */
     int max_outer;      /* mixed precision: refinement steps per level (0: 60)             */
     int batch_mode;     /* excmg_solve_batch: 0 = four graph-captured phase launches per    */
                         /* Bi-CG step, 1 = one persistent work-queue launch per step        */
@@ -331,8 +332,9 @@ typedef struct excmg_problem {
  * its own cascade, tolerances and stopping decisions exactly as excmg_solve_ex would.
  * Mixed precision: levels of at least opts.fp32_min_unknowns unknowns (0: 2^18) run FP32
  * Bi-CG inside restarted FP64 refinement (excmg_solve_ex with EXCMG_RESTART and the same
- * fp32_min_unknowns); smaller levels run FP64 Bi-CG, as in an FP64 solve (systems of the
- * two kinds advance in separate launches); opts.refine is not used.  opts supplies tol,
+ * fp32_min_unknowns and inner_tol; the batch's default inner_tol is 1e-5); smaller levels
+ * run FP64 Bi-CG, as in an FP64 solve (systems of the two kinds advance in separate
+ * launches on two streams); opts.refine is not used.  opts supplies tol,
  * precision and the iteration limits (its n_finest, n_levels and bc_kind are ignored).
  * stats, if not NULL, is an array of nprob records.  Runs on a stream of its own, ordered
  * after the library stream's earlier work.  Tile shapes of the batched sweep A: those

@@ -1315,7 +1315,7 @@ struct BatchSolver {
     bool persistent = false;  // one persistent launch per step instead of four phase launches
     int ty = kBatchTY;        // tile height of the batched sweep A
     int maxit = 100000, max_runs = 5, max_outer = 60;
-    double tol = 0.0, inner_tol = 1e-4;
+    double tol = 0.0, inner_tol = 1e-5;
     hipStream_t st = nullptr;
     std::vector<BProb *> pb;
     FactorCache fc;
@@ -1324,10 +1324,17 @@ struct BatchSolver {
     double *h_scal = nullptr;
     BicgState *h_states = nullptr;
     StepSet set[2];           // systems with FP64 vectors, with FP32 vectors
+    // while both kinds run, the FP32 systems' steps go to a second stream (forked from and
+    // joined to st by events) and run beside the FP64 systems' steps
+    hipStream_t st2 = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     int steps_per_graph = 8;
     long long launches = 0;
 
     ~BatchSolver() {
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
+        if (st2) (void)hipStreamDestroy(st2);
         for (BProb *b : pb) delete b;
         states.release(); runs.release(); scal.release();
         xx.release();
@@ -1351,7 +1358,7 @@ struct BatchSolver {
         maxit = o.max_iters > 0 ? o.max_iters : 100000;
         max_runs = o.max_runs > 0 ? o.max_runs : 5;
         max_outer = o.max_outer > 0 ? o.max_outer : 60;
-        inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-4;
+        inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-5;
         CKR(states.ensure((size_t)nprob * sizeof(BicgState)));
         CKR(runs.ensure((size_t)nprob * sizeof(BatchRun)));
         CKR(scal.ensure((size_t)nprob * 4 * sizeof(double)));
@@ -1605,30 +1612,46 @@ struct BatchSolver {
     // and replayed while it has systems.
     int launch_steps() {
         for (StepSet &K : set) {
-            if (K.ni == 0) continue;
-            if (!K.exec) {
-                BatchCtl *ctl = K.ctl.as<BatchCtl>();
-                const int2 *items = K.items.as<int2>();
-                const BatchRun *rn = runs.as<BatchRun>();
-                CKH(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
-                for (int t = 0; t < steps_per_graph; t++) {
-                    hipError_t e;
-                    if (persistent)
-                        e = K.f32 ? batch_step<float>(ty, K.grid, rn, items, ctl, st)
-                                  : batch_step<double>(ty, K.grid, rn, items, ctl, st);
-                    else
-                        e = K.f32 ? batch_step_phases<float>(ty, rn, items, ctl, st)
-                                  : batch_step_phases<double>(ty, rn, items, ctl, st);
-                    if (e != hipSuccess) {
-                        hipGraph_t g;
-                        (void)hipStreamEndCapture(st, &g);
-                        return fail(EXCMG_EHIP, "batch step launch: %s", hipGetErrorString(e));
-                    }
+            if (K.ni == 0 || K.exec) continue;
+            BatchCtl *ctl = K.ctl.as<BatchCtl>();
+            const int2 *items = K.items.as<int2>();
+            const BatchRun *rn = runs.as<BatchRun>();
+            CKH(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+            for (int t = 0; t < steps_per_graph; t++) {
+                hipError_t e;
+                if (persistent)
+                    e = K.f32 ? batch_step<float>(ty, K.grid, rn, items, ctl, st)
+                              : batch_step<double>(ty, K.grid, rn, items, ctl, st);
+                else
+                    e = K.f32 ? batch_step_phases<float>(ty, rn, items, ctl, st)
+                              : batch_step_phases<double>(ty, rn, items, ctl, st);
+                if (e != hipSuccess) {
+                    hipGraph_t g;
+                    (void)hipStreamEndCapture(st, &g);
+                    return fail(EXCMG_EHIP, "batch step launch: %s", hipGetErrorString(e));
                 }
-                CKH(hipStreamEndCapture(st, &K.graph));
-                CKH(hipGraphInstantiate(&K.exec, K.graph, nullptr, nullptr, 0));
             }
-            CKH(hipGraphLaunch(K.exec, st));
+            CKH(hipStreamEndCapture(st, &K.graph));
+            CKH(hipGraphInstantiate(&K.exec, K.graph, nullptr, nullptr, 0));
+        }
+        // the phase launches never wait for other workgroups, so the two kinds can share
+        // the GPU; the persistent kernel needs all its workgroups resident, so its two
+        // kinds run one after the other
+        const bool side = !persistent && set[0].ni > 0 && set[1].ni > 0;
+        if (side && !st2) {
+            CKH(hipStreamCreateWithFlags(&st2, hipStreamNonBlocking));
+            CKH(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+            CKH(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+        }
+        if (side) {
+            CKH(hipEventRecord(fork, st));
+            CKH(hipStreamWaitEvent(st2, fork, 0));
+        }
+        for (StepSet &K : set)
+            if (K.ni > 0) CKH(hipGraphLaunch(K.exec, side && K.f32 ? st2 : st));
+        if (side) {
+            CKH(hipEventRecord(join, st2));
+            CKH(hipStreamWaitEvent(st, join, 0));
         }
         launches += steps_per_graph;
         return EXCMG_OK;

@@ -51,7 +51,8 @@ def test_batched_breakdown_ends_the_level_as_a_single_solve_does(ex, prec):
     f[16, 16, 16] = float("nan")
     arr2, f2, g12, g22 = _inputs(3, 32, 2)
     u_single = torch.empty_like(f)
-    rc1, st1 = ex.solve_ex(32, 4, 1, f, g1, g2, 1e-8, u_single, precision=p, refine=ex.RESTART)
+    rc1, st1 = ex.solve_ex(32, 4, 1, f, g1, g2, 1e-8, u_single, precision=p, refine=ex.RESTART,
+                           inner_tol=1e-5)
     assert rc1 == (ex.EBREAKDOWN if prec == "fp64" else ex.ENOCONV)
     ub, ub2 = torch.empty_like(f), torch.empty_like(f2)
     probs = [dict(n_finest=32, n_levels=4, bc_kind=1, f=f, g1=g1, g2=g2, u_out=ub),

@@ -337,7 +337,7 @@ def test_batch_mixed_large_grids_meet_tolerance_and_accuracy(ex, persistent):
         # in restarted refinement: the single solve with the same split, bit for bit
         single = torch.empty_like(f)
         rc1, st1 = ex.solve_ex(N, nl, bc, f, g1, g2, 1e-9, single, precision=ex.MIXED,
-                               refine=ex.RESTART, fp32_min_unknowns=1 << 18)
+                               refine=ex.RESTART, fp32_min_unknowns=1 << 18, inner_tol=1e-5)
         assert rc1 == ex.OK
         assert [l["iterations"] for l in st.levels()] == [l["iterations"] for l in st1.levels()]
         assert [l["runs"] for l in st.levels()] == [l["runs"] for l in st1.levels()]
@@ -372,7 +372,7 @@ def test_batch_autotuned_shapes_keep_results(ex):
     for (N, nl, bc, arr, f, g1, g2), p in zip(data, probs):
         u1 = torch.empty_like(f)
         assert ex.solve_ex(N, nl, bc, f, g1, g2, 1e-9, u1, precision=ex.MIXED, refine=ex.RESTART,
-                           fp32_min_unknowns=1 << 18)[0] == ex.OK
+                           fp32_min_unknowns=1 << 18, inner_tol=1e-5)[0] == ex.OK
         np.testing.assert_array_equal(host(p["u_out"]), host(u1))
 
 
@@ -402,7 +402,7 @@ def test_batch_mixed_meets_tolerance_and_accuracy(ex, fp32_min):
         else:
             # the batch path refines by restarted FP32 solves
             rc1, st1 = ex.solve_ex(N, nl, bc, f, g1, g2, 1e-8, single, precision=ex.MIXED,
-                                   refine=ex.RESTART)
+                                   refine=ex.RESTART, inner_tol=1e-5)
         assert rc1 == ex.OK
         assert [l["iterations"] for l in st.levels()] == [l["iterations"] for l in st1.levels()]
         np.testing.assert_array_equal(u.ravel(), host(single).ravel())
