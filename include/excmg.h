@@ -89,14 +89,13 @@ typedef struct excmg_opts {
     int max_iters;      /* Bi-CG iterations per run (0: 100000)                             */
     int max_runs;       /* Bi-CG runs per level in Algorithm 1's while loop (0: 5)          */
     double inner_tol;   /* mixed precision: residual reduction per refinement step        */
-                        /* (0: 0.1 with EXCMG_RELIABLE, 1e-4 with EXCMG_RESTART, 1e-5 in    */
-                        /* excmg_solve_batch)                                               */
+                        /* (0: 0.1 with EXCMG_RELIABLE, 1e-4 with EXCMG_RESTART, 1e-5 with  */
+                        /* EXCMG_RESTART in excmg_solve_batch)                              */
     int max_outer;      /* mixed precision: refinement steps per level (0: 60)             */
     int batch_mode;     /* excmg_solve_batch: 0 = four graph-captured phase launches per    */
                         /* Bi-CG step, 1 = one persistent work-queue launch per step        */
     int method;         /* EXCMG_BICG (default) or EXCMG_CG (excmg_solve_ex only)           */
-    int refine;         /* mixed precision: EXCMG_RELIABLE (default) or EXCMG_RESTART;     */
-                        /* excmg_solve_batch always restarts (its FP32 levels)              */
+    int refine;         /* mixed precision: EXCMG_RELIABLE (default) or EXCMG_RESTART      */
     int precond;        /* EXCMG_PRECOND_NONE (default) or EXCMG_PRECOND_JACOBI (solve_ex) */
     int fp32_min_unknowns; /* mixed precision: levels with fewer unknowns run FP64 Bi-CG    */
                         /* (launch-latency bound, so FP32 vectors gain nothing there);       */
@@ -331,10 +330,13 @@ typedef struct excmg_problem {
  * (batch_mode 1), replayed in windows from captured hipGraphs, while each problem follows
  * its own cascade, tolerances and stopping decisions exactly as excmg_solve_ex would.
  * Mixed precision: levels of at least opts.fp32_min_unknowns unknowns (0: 2^18) run FP32
- * Bi-CG inside restarted FP64 refinement (excmg_solve_ex with EXCMG_RESTART and the same
- * fp32_min_unknowns and inner_tol; the batch's default inner_tol is 1e-5); smaller levels
- * run FP64 Bi-CG, as in an FP64 solve (systems of the two kinds advance in separate
- * launches on two streams); opts.refine is not used.  opts supplies tol,
+ * Bi-CG inside FP64 refinement; smaller levels run FP64 Bi-CG, as in an FP64 solve (systems
+ * of the two kinds advance in separate launches on two streams).  opts.refine: with
+ * EXCMG_RELIABLE (default) a run stops when its recurrence residual has fallen by
+ * inner_tol (0: 0.1) or below half the level's target, the FP64 residual replaces r and r*
+ * and the run goes on with its search directions; with EXCMG_RESTART each refinement step
+ * is a fresh run to inner_tol (0: 1e-5), bit for bit as excmg_solve_ex with EXCMG_RESTART
+ * and the same fp32_min_unknowns and inner_tol.  opts supplies tol,
  * precision and the iteration limits (its n_finest, n_levels and bc_kind are ignored).
  * stats, if not NULL, is an array of nprob records.  Runs on a stream of its own, ordered
  * after the library stream's earlier work.  Tile shapes of the batched sweep A: those

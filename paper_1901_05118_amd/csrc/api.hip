@@ -242,10 +242,10 @@ Geom choose_shape(int N, int bc, int kind) {
     // whole depth (511 planes) on 64x16 tiles, one per CU, and the FP64 pair on 64x8.
     static const int kTuned[6][3][2] = {
         {{4, 2}, {4, 2}, {4, 2}},          // N < 48
-        {{4, 4}, {8, 2}, {8, 2}},          // 48 <= N < 96
+        {{8, 2}, {8, 2}, {8, 2}},          // 48 <= N < 96
         {{4, 8}, {8, 16}, {4, 8}},         // 96 <= N < 128
-        {{8, 8}, {8, 16}, {8, 16}},        // 128 <= N < 256
-        {{16, 64}, {8, 128}, {8, 128}},    // 256 <= N < 512
+        {{8, 16}, {8, 16}, {8, 16}},       // 128 <= N < 256
+        {{8, 64}, {8, 128}, {8, 128}},     // 256 <= N < 512
         {{16, 512}, {8, 512}, {16, 512}},  // N >= 512
     };
     const int band = N < 48 ? 0 : N < 96 ? 1 : N < 128 ? 2 : N < 256 ? 3 : N < 512 ? 4 : 5;
@@ -1271,6 +1271,7 @@ struct BProb {
     int level = 0, phase = kPhaseCheck;
     bool f32 = false;           // the current level runs FP32 Bi-CG inside FP64 refinement
     int runs = 0, iters = 0, outer = 0, worst = EXCMG_OK;
+    int iter_base = 0;          // the run's iteration count when it was last (re)started
     int broke = 0;              // the last run broke down (Algorithm 2's denominators)
     double eps = 0.0, prev = INFINITY, last_bb = 0.0;
     double level_bb[EXCMG_MAX_LEVELS] = {};   // b.b of each finished level
@@ -1311,6 +1312,7 @@ struct StepSet {
 
 struct BatchSolver {
     bool mixed = false;
+    bool reliable = true;     // FP32 levels: residual replacement (else restarted refinement)
     long long fp32_min = 1LL << 18;  // mixed: levels with fewer unknowns run FP64 Bi-CG
     bool persistent = false;  // one persistent launch per step instead of four phase launches
     int ty = kBatchTY;        // tile height of the batched sweep A
@@ -1351,6 +1353,7 @@ struct BatchSolver {
 
     int init(int nprob, const excmg_problem *probs, const excmg_opts &o) {
         mixed = (o.precision == EXCMG_MIXED);
+        reliable = (o.refine == EXCMG_RELIABLE);
         fp32_min = o.fp32_min_unknowns > 0 ? o.fp32_min_unknowns : (1LL << 18);
         persistent = (o.batch_mode == 1);
         ty = g_batch_ty;
@@ -1358,7 +1361,7 @@ struct BatchSolver {
         maxit = o.max_iters > 0 ? o.max_iters : 100000;
         max_runs = o.max_runs > 0 ? o.max_runs : 5;
         max_outer = o.max_outer > 0 ? o.max_outer : 60;
-        inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-5;
+        inner_tol = o.inner_tol > 0 ? o.inner_tol : (reliable ? 0.1 : 1e-5);
         CKR(states.ensure((size_t)nprob * sizeof(BicgState)));
         CKR(runs.ensure((size_t)nprob * sizeof(BatchRun)));
         CKR(scal.ensure((size_t)nprob * 4 * sizeof(double)));
@@ -1541,16 +1544,35 @@ struct BatchSolver {
             if (b.runs >= max_runs) return finish_level(j, EXCMG_ENOCONV, rr, bb);
             CKH((copy_convert<double, double>(Lv.nu, b.r.as<double>(), b.rs.as<double>(), st)));
             CKH(bicg_start(Sj, b.part_a.as<Pair>(), stencil_blocks(Lv.g1), b.eps, maxit, st));
+            b.iter_base = 0;
         } else {
             if (b.outer >= max_outer || !(rr < b.prev)) return finish_level(j, EXCMG_ENOCONV, rr, bb);
+            // a run of this level stopped at its threshold: with residual replacement it goes
+            // on from the new residual with its search directions
+            const bool resume = reliable && b.outer > 0 && h_states[j].status == kConverged;
             b.prev = rr;
             b.last_bb = bb;
-            double it = std::max(inner_tol, 0.3 * b.eps * std::sqrt(bb / rr));
-            if (it > 0.5) it = 0.5;
             const int nvb = vec_blocks(Lv.nu);
             CKH(dot_partials<float>(Lv.nu, b.r.as<float>(), b.r.as<float>(), b.part_b.as<Pair>(), nvb, st));
-            CKH(reduce_to((double *)&Sj->bb, b.part_b.as<Pair>(), nvb, 0, st));
-            CKH(bicg_start(Sj, b.part_b.as<Pair>(), nvb, it, maxit, st));
+            if (reliable) {
+                // the run stops when its recurrence residual has fallen by inner_tol since the
+                // replacement, or below half the level's target residual
+                const double rthr = std::max((inner_tol * inner_tol) * rr, 0.25 * thr);
+                if (resume) {
+                    CKH(batch_resume(Sj, b.part_b.as<Pair>(), nvb, rthr, st));
+                    b.iter_base = h_states[j].iter;
+                } else {
+                    CKH(reduce_to((double *)&Sj->bb, b.part_b.as<Pair>(), nvb, 0, st));
+                    CKH(bicg_start(Sj, b.part_b.as<Pair>(), nvb, std::sqrt(rthr / rr), maxit, st));
+                    b.iter_base = 0;
+                }
+            } else {
+                double it = std::max(inner_tol, 0.3 * b.eps * std::sqrt(bb / rr));
+                if (it > 0.5) it = 0.5;
+                CKH(reduce_to((double *)&Sj->bb, b.part_b.as<Pair>(), nvb, 0, st));
+                CKH(bicg_start(Sj, b.part_b.as<Pair>(), nvb, it, maxit, st));
+                b.iter_base = 0;
+            }
             b.outer++;
         }
         b.phase = kPhaseRun;
@@ -1690,7 +1712,7 @@ struct BatchSolver {
                 for (int j = 0; j < np; j++) {
                     BProb &b = *pb[j];
                     if (b.phase != kPhaseRun || h_states[j].status == kRunning) continue;
-                    b.iters += h_states[j].iter;
+                    b.iters += h_states[j].iter - b.iter_base;
                     b.runs++;
                     changed = true;
                     b.phase = kPhaseCheck;
@@ -2392,6 +2414,8 @@ int excmg_solve_batch(int nprob, const excmg_problem *probs, const excmg_opts *o
     if (opts->precision != EXCMG_FP64 && opts->precision != EXCMG_MIXED)
         return fail(EXCMG_EINVAL, "precision %d not supported", opts->precision);
     if (opts->fp32_min_unknowns < 0) return fail(EXCMG_EINVAL, "fp32_min_unknowns must be >= 0");
+    if (opts->refine != EXCMG_RELIABLE && opts->refine != EXCMG_RESTART)
+        return fail(EXCMG_EINVAL, "refine %d not supported", opts->refine);
     for (int j = 0; j < nprob; j++) CKR(check_sizes(probs[j].n_finest, probs[j].n_levels, probs[j].bc_kind));
     // every failure below is recorded in rc and the stream, events and library stream are
     // restored and released on the way out

@@ -168,6 +168,7 @@ __device__ void sweep_b_item(const BatchRun &R, int run, int chunk, BatchCtl *ct
             const double rho_new = pair_value(m[0]);
             S->rr = pair_value(m[1]);
             S->beta = rho_new / S->rho;
+            S->rho_slot[1] = S->rho;   // rho of the previous iteration (residual replacement)
             S->rho = rho_new;
             S->iter = S->iter + 1;
             if (S->rr <= S->thr) S->status = kConverged;
@@ -334,6 +335,7 @@ __global__ void __launch_bounds__(kReduceThreads)
             const double rho_new = pair_value(v[0]);
             S->rr = pair_value(v[1]);
             S->beta = rho_new / S->rho;
+            S->rho_slot[1] = S->rho;   // rho of the previous iteration (residual replacement)
             S->rho = rho_new;
             S->iter = S->iter + 1;
             if (S->rr <= S->thr) S->status = kConverged;
@@ -341,6 +343,35 @@ __global__ void __launch_bounds__(kReduceThreads)
             else if (S->rho == 0.0 || !isfinite(S->rho)) S->status = kBreakdown;
         }
     }
+}
+
+// Residual replacement of a stopped FP32 run: r and r* already hold the FP64 residual of the
+// iterate (rounded to FP32); rho = r*.r from their partials, beta = rho / rho of the
+// previous iteration (so the next direction is formed from the new residual with the old
+// search direction), a new stopping threshold, and the run goes on from its iteration count
+// (which keeps the direction buffers' parity).
+__global__ void __launch_bounds__(kReduceThreads)
+    k_batch_resume(BicgState *s, const Pair *part, int count, double thr) {
+    __shared__ Pair sh[kReduceThreads / kWave];
+    Pair v[1] = {{0.0, 0.0}};
+    for (int i = threadIdx.x; i < count; i += blockDim.x) v[0] = pair_merge(v[0], part[i]);
+    block_merge<1>(v, sh);
+    if (threadIdx.x == 0) {
+        const double rho = pair_value(v[0]);
+        s->beta = rho / s->rho_slot[1];
+        s->rho = rho;
+        s->rr = rho;
+        s->thr = thr;
+        if (s->iter >= s->maxit) s->status = kNoConv;
+        else if (rho == 0.0 || !isfinite(rho) || !isfinite(s->beta)) s->status = kBreakdown;
+        else s->status = kRunning;
+        s->poll_status = s->status;
+    }
+}
+
+hipError_t batch_resume(BicgState *s, const Pair *part, int count, double thr, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_resume, dim3(1), dim3(kReduceThreads), 0, st, s, part, count, thr);
+    return hipGetLastError();
 }
 
 template <typename T, int TY>

@@ -272,6 +272,10 @@ hipError_t batch_step(int ty, int grid, const BatchRun *runs, const int2 *items,
                       hipStream_t st);
 template <typename T>
 hipError_t batch_step_grid(int ty, int *grid);
+// Residual replacement of a stopped batched FP32 run (r, r* already replaced): rho from the
+// `count` partials of r.r, beta = rho / rho of the previous iteration, threshold thr, and
+// the run resumes with its search directions.
+hipError_t batch_resume(BicgState *s, const Pair *part, int count, double thr, hipStream_t st);
 
 // The same iteration as four phase launches (sweep A, alpha, sweep B, beta) over the work
 // list in ctl; grid-stride, no inter-workgroup communication inside a launch.

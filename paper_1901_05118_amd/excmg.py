@@ -332,7 +332,7 @@ def profile_sweep(which: int, precision: int = FP64, reps: int = 20):
 
 def solve_batch(problems, tol: float, precision: int = FP64, max_iters: int = 0,
                 max_runs: int = 0, inner_tol: float = 0.0, max_outer: int = 0,
-                persistent: bool = False, fp32_min_unknowns: int = 0):
+                persistent: bool = False, fp32_min_unknowns: int = 0, refine: int = RELIABLE):
     """Solve independent problems together.  ``problems`` is a list of dicts with keys
     n_finest, n_levels, bc_kind, f, g1, g2, u_out and optionally ut_out.  Returns
     (code, list of Stats)."""
@@ -343,7 +343,7 @@ def solve_batch(problems, tol: float, precision: int = FP64, max_iters: int = 0,
                          _ptr(p["f"], name="f"), _ptr(p["g1"], name="g1"), _ptr(p["g2"], name="g2"),
                          _ptr(p["u_out"], name="u_out"), _ptr(p.get("ut_out"), name="ut_out"))
     o = Opts(0, 0, 0, precision, tol, max_iters, max_runs, inner_tol, max_outer,
-             1 if persistent else 0, BICG, RESTART, PRECOND_NONE, fp32_min_unknowns)
+             1 if persistent else 0, BICG, refine, PRECOND_NONE, fp32_min_unknowns)
     st = (Stats * n)()
     rc = load().excmg_solve_batch(n, arr, ctypes.byref(o), st)
     if rc not in (OK, ENOCONV, EBREAKDOWN):

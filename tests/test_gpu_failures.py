@@ -57,7 +57,7 @@ def test_batched_breakdown_ends_the_level_as_a_single_solve_does(ex, prec):
     ub, ub2 = torch.empty_like(f), torch.empty_like(f2)
     probs = [dict(n_finest=32, n_levels=4, bc_kind=1, f=f, g1=g1, g2=g2, u_out=ub),
              dict(n_finest=32, n_levels=4, bc_kind=2, f=f2, g1=g12, g2=g22, u_out=ub2)]
-    rc, sts = ex.solve_batch(probs, 1e-8, precision=p, fp32_min_unknowns=1)
+    rc, sts = ex.solve_batch(probs, 1e-8, precision=p, fp32_min_unknowns=1, refine=ex.RESTART)
     assert rc == rc1
     single = st1.levels()
     batched = sts[0].levels()

@@ -317,12 +317,20 @@ def test_batch_fp64_large_grids_match_single_solves_and_oracle(ex, persistent):
         assert rel_l2(host(p["ut_out"]), ref.ut) <= 1e-10
 
 
+@pytest.mark.parametrize("refine", ["reliable", "restart"])
 @pytest.mark.parametrize("persistent", [False, True])
-def test_batch_mixed_large_grids_meet_tolerance_and_accuracy(ex, persistent):
+def test_batch_mixed_large_grids_meet_tolerance_and_accuracy(ex, persistent, refine):
+    """Levels under 2^18 unknowns run FP64 Bi-CG, the larger ones (95^3, 127^3) FP32 Bi-CG in
+    FP64 refinement.  Both refinement forms meet the tolerance in the oracle's FP64 residual
+    with the FP64 discretisation error; restarted refinement equals the single solve with the
+    same split bit for bit, and residual replacement leaves the all-FP64 problem (64^3) equal
+    to the FP64 solve."""
+    mode = ex.RELIABLE if refine == "reliable" else ex.RESTART
     data = _batch_inputs([(N, nl, bc, config_problem(c)) for (N, nl, bc, c) in BATCH_LARGE])
     probs = [dict(n_finest=N, n_levels=nl, bc_kind=bc, f=f, g1=g1, g2=g2,
                   u_out=torch.empty_like(f)) for (N, nl, bc, arr, f, g1, g2) in data]
-    rc, stats = ex.solve_batch(probs, 1e-9, precision=ex.MIXED, persistent=persistent)
+    rc, stats = ex.solve_batch(probs, 1e-9, precision=ex.MIXED, persistent=persistent,
+                               refine=mode)
     assert rc == ex.OK, ex.last_error()
     for (N, nl, bc, arr, f, g1, g2), item, p, st in zip(data, BATCH_LARGE, probs, stats):
         u = host(p["u_out"]).reshape((N + 1,) * 3)
@@ -332,9 +340,14 @@ def test_batch_mixed_large_grids_meet_tolerance_and_accuracy(ex, persistent):
         ref = _large_ref(N, nl, bc, item[3], arr)
         e_fp64 = O.norm2(ref.u - arr.u)
         assert abs(O.norm2(u - arr.u) - e_fp64) <= 0.01 * e_fp64
-        print(f"batch mixed N={N}: max |u - u_oracle| = {np.abs(u - ref.u).max():.3e}", flush=True)
-        # levels under 2^18 unknowns run FP64 Bi-CG, the larger ones (95^3, 127^3) FP32 Bi-CG
-        # in restarted refinement: the single solve with the same split, bit for bit
+        print(f"batch mixed ({refine}) N={N}: iterations {[l['iterations'] for l in st.levels()]}, "
+              f"max |u - u_oracle| = {np.abs(u - ref.u).max():.3e}", flush=True)
+        if mode == ex.RELIABLE:
+            if (N - 1) ** 3 < (1 << 18):
+                single = torch.empty_like(f)
+                assert ex.solve_ex(N, nl, bc, f, g1, g2, 1e-9, single)[0] == ex.OK
+                np.testing.assert_array_equal(u.ravel(), host(single).ravel())
+            continue
         single = torch.empty_like(f)
         rc1, st1 = ex.solve_ex(N, nl, bc, f, g1, g2, 1e-9, single, precision=ex.MIXED,
                                refine=ex.RESTART, fp32_min_unknowns=1 << 18, inner_tol=1e-5)
@@ -367,7 +380,7 @@ def test_batch_autotuned_shapes_keep_results(ex):
     ty, ms = ex.autotune_batch(probs, precision=ex.MIXED, reps=2)
     print("mixed batch: ty", ty, "96^3 FP32 shape", ex.get_batch_shape(96, ex.MIXED),
           f"{ms:.3f} ms per step (sizes alone, summed)", flush=True)
-    rc, stats = ex.solve_batch(probs, 1e-9, precision=ex.MIXED)
+    rc, stats = ex.solve_batch(probs, 1e-9, precision=ex.MIXED, refine=ex.RESTART)
     assert rc == ex.OK, ex.last_error()
     for (N, nl, bc, arr, f, g1, g2), p in zip(data, probs):
         u1 = torch.empty_like(f)
@@ -384,7 +397,8 @@ def test_batch_mixed_meets_tolerance_and_accuracy(ex, fp32_min):
     data = _batch_problems()
     probs = [dict(n_finest=N, n_levels=nl, bc_kind=bc, f=f, g1=g1, g2=g2,
                   u_out=torch.empty_like(f)) for (N, nl, bc, arr, f, g1, g2) in data]
-    rc, stats = ex.solve_batch(probs, 1e-8, precision=ex.MIXED, fp32_min_unknowns=fp32_min)
+    rc, stats = ex.solve_batch(probs, 1e-8, precision=ex.MIXED, fp32_min_unknowns=fp32_min,
+                               refine=ex.RESTART)
     assert rc == ex.OK, ex.last_error()
     for (N, nl, bc, arr, f, g1, g2), p, st in zip(data, probs, stats):
         u = host(p["u_out"]).reshape((N + 1,) * 3)
