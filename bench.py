@@ -57,8 +57,9 @@ def update_blocks(nu):
 def sweep_launch(N, ty, zc, form):
     """Name (as the profiler shows it) and launch size in threads of a Bi-CG sweep on the
     grid of N cells with stencil tiles of 64 x ty columns and zc planes.  form: "sigma" /
-    "update" (the two sweeps of the recomputing form, FP32 vectors), "sigma64" / "update64"
-    (the same with FP64 vectors), "fp64" / "stored32" (sweep A of the stored form), "deferred"
+    "update" (the two sweeps of the recomputing form, FP32 vectors; "update_keep" /
+    "update_pair" its sweep B leaving x or applying two iterations' updates), "sigma64" /
+    "update64" / "update_keep64" / "update_pair64" (the same with FP64 vectors), "fp64" / "stored32" (sweep A of the stored form), "deferred"
     (FP32 sweep A that also applies the previous iteration's x update), "update_stored64" /
     "update32" (the stored form's streaming sweep B)."""
     n = N - 1
@@ -73,9 +74,13 @@ def sweep_launch(N, ty, zc, form):
             "stored32": "zmarch<2, {ty}, float, InDirection<float>, OutPairApply<float>, 2>",
             "deferred": "zmarch<2, {ty}, float, InDirection<float>, OutPairApplyX<float>, 2>",
             "sigma": "zmarch<1, {ty}, float, InDirection<float>, OutDirSigma<float>, 3>",
-            "update": "zmarch<2, {ty}, float, InPlainAlpha<float>, OutPairUpdate<float>, {d}>",
+            "update": "zmarch<2, {ty}, float, InPlainAlpha<float>, OutPairUpdate<float, 0>, {d}>",
+            "update_keep": "zmarch<2, {ty}, float, InPlainAlpha<float>, OutPairUpdate<float, 1>, {d}>",
+            "update_pair": "zmarch<2, {ty}, float, InPlainAlpha<float>, OutPairUpdate2<float>, {d}>",
             "sigma64": "zmarch<1, {ty}, double, InDirection<double>, OutDirSigma<double>, 3>",
-            "update64": "zmarch<2, {ty}, double, InPlainAlpha<double>, OutPairUpdate<double>, {d}>"}[form]
+            "update64": "zmarch<2, {ty}, double, InPlainAlpha<double>, OutPairUpdate<double, 0>, {d}>",
+            "update_keep64": "zmarch<2, {ty}, double, InPlainAlpha<double>, OutPairUpdate<double, 1>, {d}>",
+            "update_pair64": "zmarch<2, {ty}, double, InPlainAlpha<double>, OutPairUpdate2<double>, {d}>"}[form]
     return name.format(ty=ty, d=d), tiles * 64 * ty
 
 
@@ -86,11 +91,14 @@ class _Forms(dict):
 def sweep_forms(N, mixed):
     """The Bi-CG sweeps a solve runs on the level of N cells, as {timing kind: (kernel form,
     algorithmic bytes per unknown, label)}; timing kinds as excmg_get_timing's (0 sweep A,
-    1 sweep B, 2 sweep A applying the deferred iterate update).  Mixed solves run FP32
-    vectors from 2^18 unknowns up (smaller levels FP64); both precisions take the
-    recomputing form from 2^22 unknowns up.  Bytes: recomputing form, sweep A reads r, p,
-    r*, p* and writes p, p* (FP32 24, FP64 48), sweep B reads p, p*, r, r* and the FP64
-    iterate and writes r, r*, x (FP32 40, FP64 64); stored form, FP64: sweep A reads r, r*,
+    1 sweep B, 2 sweep A applying the deferred iterate update, 3 and 4 the recomputing
+    form's sweeps B of odd and even iterations).  Mixed solves run FP32 vectors from 2^18
+    unknowns up (smaller levels FP64); both precisions take the recomputing form from 2^22
+    unknowns up.  Bytes: recomputing form, sweep A reads r, p, r*, p* and writes p, p* (FP32
+    24, FP64 48), sweep B reads p, p*, r, r* and writes r, r* (FP32 24, FP64 48) and updates
+    the FP64 iterate once per two iterations: an odd iteration's sweep B leaves it, an even
+    one's reads x and the previous p and writes x (FP32 44, FP64 72); the first sweep B of a
+    run at an even iteration updates x once (FP32 40, FP64 64); stored form, FP64: sweep A reads r, r*,
     p, p* and writes p, p*, q, q* (64), sweep B reads x, p, r, q, r*, q* and writes x, r, r*
     (72); stored form with FP32 vectors: sweep A 32 (48 when it also applies the previous
     iteration's x += alpha p), sweep B streams r, q, r*, q* and writes r, r* (24)."""
@@ -99,9 +107,12 @@ def sweep_forms(N, mixed):
     f.fp32 = mixed and nu >= FP32_MIN
     if nu >= RECOMPUTE_MIN:
         if f.fp32:
-            f.update({0: ("sigma", 24.0, "A"), 1: ("update", 40.0, "B")})
+            f.update({0: ("sigma", 24.0, "A"), 1: ("update", 40.0, "B"),
+                      3: ("update_keep", 24.0, "B, x left"), 4: ("update_pair", 44.0, "B, x twice")})
         else:
-            f.update({0: ("sigma64", 48.0, "A"), 1: ("update64", 64.0, "B")})
+            f.update({0: ("sigma64", 48.0, "A"), 1: ("update64", 64.0, "B"),
+                      3: ("update_keep64", 48.0, "B, x left"),
+                      4: ("update_pair64", 72.0, "B, x twice")})
     elif f.fp32:
         f.update({0: ("stored32", 32.0, "A"), 2: ("deferred", 48.0, "A+x"),
                   1: ("update32", 24.0, "B")})

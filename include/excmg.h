@@ -289,8 +289,12 @@ int excmg_solve_ex(const excmg_opts *opts, const double *f, const double *g1, co
  *                                                               FP64 48 B, mixed 24 B
  *         8: its sweep B: A p, A^T p* formed again, x, r, r* update + rho, r.r
  *                                                               FP64 64 B, mixed 40 B
+ *         9: the same sweep B leaving x alone (an odd iteration of the paired updates that
+ *            solves run in this form)                            FP64 48 B, mixed 24 B
+ *        10: the same sweep B applying the updates of two iterations to x (reads the
+ *            previous direction too)                             FP64 72 B, mixed 44 B
  * (bytes per unknown).  precision selects EXCMG_FP64 or EXCMG_MIXED (sweeps 5 and 6: mixed
- * only; 5 to 8: 3D contexts only). */
+ * only; 5 to 10: 3D contexts only; 9 and 10: not with row_pad 2). */
 int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launch,
                         double *bytes_per_launch);
 
@@ -298,9 +302,11 @@ int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launc
  * device events on the library stream and its duration is added to a per-level total
  * (sweep 0 = sweep A: direction update, A p, A^T p*, sigma; sweep 1 = sweep B: x, r, r*
  * updates, rho, r.r; sweep 2 = sweep A that also applies the previous iteration's x update,
- * in the stored form with the deferred update, its sweep B then leaving x alone).  Only
- * launches that did work are counted.  Turning it on resets the totals;
- * excmg_get_timing reads them. */
+ * in the stored form with the deferred update, its sweep B then leaving x alone; in the
+ * recomputing form, whose sweeps B update x once per two iterations: sweep 3 = sweep B of
+ * an odd iteration, which leaves x to the next one, sweep 4 = sweep B of an even iteration,
+ * which applies both iterations' updates).  Only launches that did work are counted.
+ * Turning it on resets the totals; excmg_get_timing reads them. */
 int excmg_set_timing(int on);
 int excmg_get_timing(int level, int sweep, double *ms_total, long long *launches);
 

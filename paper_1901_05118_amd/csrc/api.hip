@@ -204,8 +204,10 @@ Ctx g_ctx;
 // Optional per-launch timing of the two Bi-CG sweeps (device events on the library stream),
 // accumulated per level: [level][0] sweep A, [level][1] sweep B.
 bool g_timing = false;
-double g_time_ms[EXCMG_MAX_LEVELS][3];   // [0] sweep A, [1] sweep B, [2] sweep A with the
-long long g_time_n[EXCMG_MAX_LEVELS][3];  // deferred update of the iterate
+// [0] sweep A, [1] sweep B, [2] sweep A with the deferred update of the iterate, [3] sweep B
+// leaving the iterate to the next one, [4] sweep B applying two iterations' updates
+double g_time_ms[EXCMG_MAX_LEVELS][5];
+long long g_time_n[EXCMG_MAX_LEVELS][5];
 std::vector<hipEvent_t> g_events;
 
 int ensure_events(size_t count) {
@@ -544,6 +546,12 @@ void release_graphs() {
 // (deferred), this sweep A has none pending (first launch of a run or of a resumed run);
 // 2 = deferred, and this sweep A applies the pending update of iteration j-1.  Deferral:
 // FP32 vectors, FP64 iterate, Bi-CG with folded finalisations and no options.
+// defer (recomputing form, single-point sweeps): paired updates of x.  Sweep B of an odd
+// iteration leaves x alone and sweep B of the next (even) one applies both updates, so x
+// streams once per two iterations (plus the previous direction); a sweep A of an even
+// iteration that stops the run applies the update owed.  0 = x += alpha p in every sweep B;
+// 1 = the first launch of a run or of a resumed run (at even j: x += alpha p, nothing owed
+// before it); 2 = steady state.
 template <typename TX, typename T>
 int launch_iteration(const Level &L, TX *x, long long j, int ev, hipStream_t st, int defer = 0) {
     Ctx &c = g_ctx;
@@ -565,13 +573,19 @@ int launch_iteration(const Level &L, TX *x, long long j, int ev, hipStream_t st,
     if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev], st));
     if constexpr (sizeof(TX) == 8) {
         if (recompute_q<TX, T>(L)) {
+            const int xm = defer == 0 ? 0 : ((j & 1) ? 1 : (defer == 2 ? 2 : 0));
+            la.defer = xm == 2 ? 1 : 0;
+            lb.defer = xm == 2 ? 1 : 0;
             CKH(stencil_dir_sigma<T>(G, G.ty, r, rs, c.p[cur].as<T>(), c.ps[cur].as<T>(),
                                      &S->beta, j == 0 ? 1 : 0, pn, psn, c.part_a.as<Pair>(),
-                                     &S->status, st, la));
+                                     &S->status, st, la, xm == 2 ? x : nullptr,
+                                     xm == 2 ? &S->alpha : nullptr));
             if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev + 1], st));
             if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev + 2], st));
             CKH(stencil_pair_update<T>(G, G.ty, pn, psn, x, r, rs, c.part_b.as<Pair>(),
-                                       &S->status, &S->alpha, st, lb));
+                                       &S->status, &S->alpha, st, lb, xm,
+                                       xm == 2 ? c.p[cur].as<T>() : nullptr,
+                                       xm == 2 ? &S->alpha_slot[cur ^ 1] : nullptr));
             if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev + 3], st));
             return EXCMG_OK;
         }
@@ -634,7 +648,10 @@ int close_window(const Level &L, long long j_next, hipStream_t st, int defer = 0
     return EXCMG_OK;
 }
 
-// Graph of iterations j = 1..K (K even, so the p / p* buffer parity repeats).
+// Graph of iterations j = 1..K (K even, so the p / p* buffer parity repeats).  defer: 0
+// none, 1 the stored form's deferred update, 2 the recomputing form's paired updates (a
+// window ends at an even iteration, where x owes nothing, so its closing check stops the
+// run itself).
 template <typename TX, typename T>
 int window_graph(const Level &L, TX *x, int K, hipGraphExec_t *out, int defer = 0) {
     for (GraphEntry &e : g_graph_cache)
@@ -651,7 +668,7 @@ int window_graph(const Level &L, TX *x, int K, hipGraphExec_t *out, int defer = 
     int rc = EXCMG_OK;
     for (int t = 0; t < K && rc == EXCMG_OK; t++)
         rc = launch_iteration<TX, T>(L, x, 1 + t, -1, g_capture, defer ? 2 : 0);
-    if (rc == EXCMG_OK) rc = close_window<T>(L, K + 1, g_capture, defer);
+    if (rc == EXCMG_OK) rc = close_window<T>(L, K + 1, g_capture, defer == 1 ? 1 : 0);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(g_capture, &graph);
     if (rc != EXCMG_OK) {
@@ -678,15 +695,19 @@ template <typename TX, typename T>
 int bicg_iterate(const Level &L, TX *x, BicgState &hs, long long &j) {
     int K = poll_interval(L.nu);
     K += K & 1;
-    if (g_timing) CKR(ensure_events(4 * (size_t)K));
+    if (g_timing) CKR(ensure_events(4 * (size_t)(K + 1)));
     const bool graphs = g_graphs && !g_timing;
     // x += alpha p deferred to the next sweep A (large grids, FP32 vectors, plain Bi-CG):
     // sweep B then streams r, q, r*, q* only
     const int defer = (!recompute_q<TX, T>(L) && (graphs || g_timing) && K <= 16 && sizeof(T) == 4 &&
                        sizeof(TX) == 8 && !g_cg && !g_var.d && !g_var.xs &&
                        g_ctx.dim == 3) ? 1 : 0;
+    // the recomputing form's paired updates of x (single-point sweeps); windows of
+    // iterations start at odd j, so each ends at an even one with x up to date
+    const int paired = (recompute_q<TX, T>(L) && (graphs || g_timing) &&
+                        (sizeof(T) == 8 || !L.wide)) ? 1 : 0;
     hipGraphExec_t exec = nullptr;
-    if (graphs) CKR((window_graph<TX, T>(L, x, K, &exec, defer)));
+    if (graphs) CKR((window_graph<TX, T>(L, x, K, &exec, defer ? 1 : (paired ? 2 : 0))));
     if (graphs && K <= 16 && hs.status == kRunning) {
         // Short windows (large grids): queue window w+1 before reading the state of window
         // w, so the device never waits for the host.  The window after the one that stopped
@@ -736,11 +757,16 @@ int bicg_iterate(const Level &L, TX *x, BicgState &hs, long long &j) {
             j += K;
         }
         int plain_first = 0;   // timed window starting with a sweep A that owes no update
+        int Kw = K;            // iterations in this window
+        const long long j0 = j;
         if (!graphs) {
-            plain_first = (defer && seg_first) ? 1 : 0;
-            for (int t = 0; t < K; t++, j++) {
+            plain_first = ((defer || paired) && seg_first) ? 1 : 0;
+            // paired updates: a window that starts at an even iteration takes one more, so
+            // that it ends at an even one
+            if (paired && (j & 1) == 0) Kw = K + 1;
+            for (int t = 0; t < Kw; t++, j++) {
                 // with a deferred update, the first sweep A of the call has none pending
-                const int dm = defer ? (seg_first ? 1 : 2) : 0;
+                const int dm = (defer || paired) ? (seg_first ? 1 : 2) : 0;
                 seg_first = false;
                 CKR((launch_iteration<TX, T>(L, x, j, g_timing ? t : -1, g_stream, dm)));
             }
@@ -755,16 +781,19 @@ int bicg_iterate(const Level &L, TX *x, BicgState &hs, long long &j) {
         }
         if (hs.status == kStopping) hs.status = hs.poll_status;
         if (g_timing && L.index < EXCMG_MAX_LEVELS) {
-            const int active = std::min(K, hs.iter - it0);  // launches that did work
+            const int active = std::min(Kw, hs.iter - it0);  // launches that did work
             for (int t = 0; t < active; t++) {
                 float a = 0.f, b2 = 0.f;
                 CKH(hipEventElapsedTime(&a, g_events[4 * t], g_events[4 * t + 1]));
                 CKH(hipEventElapsedTime(&b2, g_events[4 * t + 2], g_events[4 * t + 3]));
-                const int ka = (defer && !(t == 0 && plain_first)) ? 2 : 0;
+                const bool lead = (t == 0 && plain_first);
+                const int ka = (defer && !lead) ? 2 : 0;
+                // paired updates: odd iterations leave x, even ones (but a leading one) apply two
+                const int kb = !paired ? 1 : (((j0 + t) & 1) ? 3 : (lead ? 1 : 4));
                 g_time_ms[L.index][ka] += a;
-                g_time_ms[L.index][1] += b2;
+                g_time_ms[L.index][kb] += b2;
                 g_time_n[L.index][ka]++;
-                g_time_n[L.index][1]++;
+                g_time_n[L.index][kb]++;
             }
         }
     }
@@ -2295,10 +2324,12 @@ int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launc
                         double *bytes_per_launch) {
     g_err[0] = 0;
     if (!g_ctx.ready) return fail(EXCMG_ENOCTX, "no context: call excmg_setup first");
-    if (which < 0 || which > 8 || reps < 1) return fail(EXCMG_EINVAL, "bad sweep or reps");
+    if (which < 0 || which > 10 || reps < 1) return fail(EXCMG_EINVAL, "bad sweep or reps");
     if (precision != EXCMG_FP64 && precision != EXCMG_MIXED)
         return fail(EXCMG_EINVAL, "bad precision");
-    if (which >= 5 && g_ctx.dim != 3) return fail(EXCMG_EINVAL, "sweeps 5 to 8 are 3D ones");
+    if (which >= 5 && g_ctx.dim != 3) return fail(EXCMG_EINVAL, "sweeps 5 to 10 are 3D ones");
+    if (which >= 9 && precision == EXCMG_MIXED && g_ctx.lv.back().wide)
+        return fail(EXCMG_EINVAL, "sweeps 9 and 10 take single-point tiles (row_pad 2 is set)");
     if ((which == 5 || which == 6) && precision != EXCMG_MIXED)
         return fail(EXCMG_EINVAL, "sweeps 5 and 6 are mixed-precision ones");
     Ctx &c = g_ctx;
@@ -2323,8 +2354,8 @@ int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launc
     CKH(hipMemcpyAsync(c.state.p, &hs, sizeof(hs), hipMemcpyHostToDevice, g_stream));
     BicgState *S = c.state.as<BicgState>();
     // algorithmic bytes per unknown of each sweep
-    const double fp64_bytes[9] = {16, 24, 64, 72, 16, 0, 0, 48, 64};
-    const double mixed_bytes[9] = {8, 24, 32, 44, 8, 48, 24, 24, 40};
+    const double fp64_bytes[11] = {16, 24, 64, 72, 16, 0, 0, 48, 64, 48, 72};
+    const double mixed_bytes[11] = {8, 24, 32, 44, 8, 48, 24, 24, 40, 24, 44};
     auto launch_once = [&]() -> hipError_t {
         if (precision == EXCMG_FP64) {
             double *r = c.r.as<double>(), *rs = c.rs.as<double>();
@@ -2345,10 +2376,12 @@ int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launc
                             L.g2, L.g2.ty, r, rs, c.p[0].as<double>(), c.ps[0].as<double>(),
                             &S->beta, 0, c.p[1].as<double>(), c.ps[1].as<double>(),
                             c.part_a.as<Pair>(), &S->status, g_stream, StepLink{});
-                case 8: return stencil_pair_update<double>(
+                case 8:
+                case 9:
+                case 10: return stencil_pair_update<double>(
                             L.g2, L.g2.ty, c.p[1].as<double>(), c.ps[1].as<double>(),
                             L.x.as<double>(), r, rs, c.part_b.as<Pair>(), &S->status, &S->alpha,
-                            g_stream, StepLink{});
+                            g_stream, StepLink{}, which - 8, c.p[0].as<double>(), &S->alpha);
                 default: return copy_convert<double, double>(L.nu, r, c.q.as<double>(), g_stream);
             }
         }
@@ -2379,10 +2412,13 @@ int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launc
                                              c.p[1].as<float>(), c.ps[1].as<float>(),
                                              c.part_a.as<Pair>(), &S->status, g_stream,
                                              StepLink{});
-            case 8: return stencil_pair_update<float>(rq_geom_f32(L), rq_geom_f32(L).ty, c.p[1].as<float>(),
+            case 8:
+            case 9:
+            case 10: return stencil_pair_update<float>(rq_geom_f32(L), rq_geom_f32(L).ty, c.p[1].as<float>(),
                                                c.ps[1].as<float>(), xv, r, rs,
                                                c.part_b.as<Pair>(), &S->status, &S->alpha,
-                                               g_stream, StepLink{});
+                                               g_stream, StepLink{}, which - 8, c.p[0].as<float>(),
+                                               &S->alpha);
             default: return copy_convert<float, float>(L.nu, r, c.q.as<float>(), g_stream);
         }
     };
@@ -2630,7 +2666,7 @@ int excmg_set_timing(int on) {
 }
 
 int excmg_get_timing(int level, int sweep, double *ms_total, long long *launches) {
-    if (level < 0 || level >= EXCMG_MAX_LEVELS || sweep < 0 || sweep > 2)
+    if (level < 0 || level >= EXCMG_MAX_LEVELS || sweep < 0 || sweep > 4)
         return fail(EXCMG_EINVAL, "bad level or sweep");
     if (ms_total) *ms_total = g_time_ms[level][sweep];
     if (launches) *launches = g_time_n[level][sweep];

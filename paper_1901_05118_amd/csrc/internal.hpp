@@ -57,6 +57,8 @@ struct BicgState {
     int poll_status; // the status as the host polls it: a window's closing check writes only
                      // this one when the run's last update is still pending (see step.hpp)
     double rho_slot[2];  // rho_j in slot j & 1 (steps with folded finalisations)
+    double alpha_slot[2];  // alpha_j in slot j & 1 (update sweeps that apply the updates of
+                           // two iterations to the iterate read alpha_{j-1} from it)
 };
 
 // A sweep that folds in the finalisation of the preceding sweep (see step.hpp).  state ==
@@ -68,7 +70,11 @@ struct StepLink {
     int nv = 1;                  // values: 2 = (r*.r, r.r), 1 = r.r (CG) or sigma
     int par = 0;                 // parity of the iteration
     int poll_only = 0;           // end-of-window check: publish the decision for the host only
-    int defer = 0;               // sweep A owing the iterate's update of the previous iteration
+    int defer = 0;               // the sweep owes the iterate's update of the previous
+                                 // iteration: a sweep A that stops the run publishes kStopping;
+                                 // a sweep B that breaks down publishes its breakdown in
+                                 // poll_status only, so that its workgroups that start later
+                                 // still apply the update (the next check takes it from there)
 };
 
 // kStopping: the sweep A that stops a run while owing the iterate's update publishes this
@@ -110,15 +116,22 @@ hipError_t stencil_pair_direction_x(const Geom &g, int ty, const float *r, const
 // (p_new, p*_new, partial of sigma = p*_new . A p_new); sweep B marches the stored p_new,
 // p*_new again for q, q* and applies x += alpha p, r -= alpha q, r* -= alpha q* with the
 // partials of r*.r and r.r (two values per workgroup, the layout of bicg_update's).
+// Paired updates of the iterate (single-point sweeps): sweep B of an odd iteration leaves
+// x untouched (xmode 1), sweep B of the next, even one applies both updates, x += alpha' p'
+// then x += alpha p (xmode 2: p' = p_prev, alpha' from alpha_prev), and a sweep A that stops
+// the run while x owes an update applies it on its own (owe_x: x += alpha p_old, alpha from
+// alpha_owed).  xmode 0: x += alpha p in every sweep B.
 template <typename T>
 hipError_t stencil_dir_sigma(const Geom &g, int ty, const T *r, const T *rs, const T *p_old,
                              const T *ps_old, const double *beta_dev, int first, T *p_new,
                              T *ps_new, Pair *partials, const int *status, hipStream_t st,
-                             StepLink link);
+                             StepLink link, double *owe_x = nullptr,
+                             const double *alpha_owed = nullptr);
 template <typename T>
 hipError_t stencil_pair_update(const Geom &g, int ty, const T *p, const T *ps, double *x, T *r,
                                T *rs, Pair *partials, const int *status, const double *alpha_dev,
-                               hipStream_t st, StepLink link);
+                               hipStream_t st, StepLink link, int xmode = 0,
+                               const T *p_prev = nullptr, const double *alpha_prev = nullptr);
 hipError_t stencil_pair_direction_m(const Geom &g, int ty, const double *r, const double *rs,
                                    const double *p_old, const double *ps_old, const double *d,
                                    const double *beta_dev, int first, double *p_new,

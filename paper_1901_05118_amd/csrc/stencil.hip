@@ -217,9 +217,10 @@ template <typename T>
 hipError_t stencil_dir_sigma(const Geom &g, int ty, const T *r, const T *rs, const T *p_old,
                              const T *ps_old, const double *beta_dev, int first, T *p_new,
                              T *ps_new, Pair *partials, const int *status, hipStream_t st,
-                             StepLink link) {
+                             StepLink link, double *owe_x, const double *alpha_owed) {
     if (g.dim != 3) return hipErrorInvalidValue;
     if (g.tw != kWave) {
+        if (owe_x) return hipErrorInvalidValue;   // paired updates: single-point sweeps only
         if constexpr (sizeof(T) == 4) {
             if (g.tw != 2 * kWave) return hipErrorInvalidValue;
             WideDirection in;
@@ -265,6 +266,18 @@ hipError_t stencil_dir_sigma(const Geom &g, int ty, const T *r, const T *rs, con
     out.beta = 0.0;
     out.first = first;
     out.acc = Pair{0.0, 0.0};
+    if (owe_x) {
+        if (!alpha_owed || first) return hipErrorInvalidValue;
+        OutDirSigmaX<T> ox;
+        static_cast<OutDirSigma<T> &>(ox) = out;
+        ox.x = owe_x;
+        ox.pold = p_old;
+        ox.alpha_dev = alpha_owed;
+        ox.alpha_owed = 0.0;
+        EXCMG_DISPATCH_TY(ty, return (launch3d<TY, T, InDirection<T>, OutDirSigmaX<T>, 1,
+                                               kSigmaDepth<T>>(g, in, ox, st)));
+        return hipSuccess;
+    }
     EXCMG_DISPATCH_TY(ty, return (launch3d<TY, T, InDirection<T>, OutDirSigma<T>, 1, kSigmaDepth<T>>(
                               g, in, out, st)));
     return hipSuccess;
@@ -273,8 +286,14 @@ hipError_t stencil_dir_sigma(const Geom &g, int ty, const T *r, const T *rs, con
 template <typename T>
 hipError_t stencil_pair_update(const Geom &g, int ty, const T *p, const T *ps, double *x, T *r,
                                T *rs, Pair *partials, const int *status, const double *alpha_dev,
-                               hipStream_t st, StepLink link) {
-    if (g.dim != 3) return hipErrorInvalidValue;
+                               hipStream_t st, StepLink link, int xmode, const T *p_prev,
+                               const double *alpha_prev) {
+    if (g.dim != 3 || xmode < 0 || xmode > 2) return hipErrorInvalidValue;
+    // paired updates: single-point tiles; with folded finalisations, mode 2 owes the update
+    // (alpha_j in its slot, the breakdown rule of link_alpha)
+    if (xmode != 0 && g.tw != kWave) return hipErrorInvalidValue;
+    if (xmode == 2 && (!p_prev || !alpha_prev || (link.state && !link.defer)))
+        return hipErrorInvalidValue;
     if (g.tw != kWave) {
         if constexpr (sizeof(T) == 4) {
             if (g.tw != 2 * kWave) return hipErrorInvalidValue;
@@ -306,15 +325,36 @@ hipError_t stencil_pair_update(const Geom &g, int ty, const T *p, const T *ps, d
     in.alpha_dev = alpha_dev;
     in.link = link;
     in.alpha = 0.0;
+    auto fill = [&](auto &out) {
+        out.x = x;
+        out.r = r;
+        out.rs = rs;
+        out.partials = partials;
+        out.status = status;
+        out.alpha = 0.0;
+        out.acc[0] = Pair{0.0, 0.0};
+        out.acc[1] = Pair{0.0, 0.0};
+        out.p_prev = p_prev;
+        out.alpha_prev = 0.0;
+    };
+    if (xmode == 1) {
+        OutPairUpdate<T, 1> out;
+        fill(out);
+        EXCMG_DISPATCH_TY(ty, return (launch3d<TY, T, InPlainAlpha<T>, OutPairUpdate<T, 1>, 2,
+                                               update_depth(TY)>(g, in, out, st)));
+        return hipSuccess;
+    }
+    if (xmode == 2) {
+        OutPairUpdate2<T> out;
+        fill(out);
+        out.state = link.state;
+        out.alpha_prev_dev = alpha_prev;
+        EXCMG_DISPATCH_TY(ty, return (launch3d<TY, T, InPlainAlpha<T>, OutPairUpdate2<T>, 2,
+                                               update_depth(TY)>(g, in, out, st)));
+        return hipSuccess;
+    }
     OutPairUpdate<T> out;
-    out.x = x;
-    out.r = r;
-    out.rs = rs;
-    out.partials = partials;
-    out.status = status;
-    out.alpha = 0.0;
-    out.acc[0] = Pair{0.0, 0.0};
-    out.acc[1] = Pair{0.0, 0.0};
+    fill(out);
     EXCMG_DISPATCH_TY(ty, return (launch3d<TY, T, InPlainAlpha<T>, OutPairUpdate<T>, 2,
                                            update_depth(TY)>(g, in, out, st)));
     return hipSuccess;
@@ -322,18 +362,19 @@ hipError_t stencil_pair_update(const Geom &g, int ty, const T *p, const T *ps, d
 template hipError_t stencil_dir_sigma<float>(const Geom &, int, const float *, const float *,
                                              const float *, const float *, const double *, int,
                                              float *, float *, Pair *, const int *, hipStream_t,
-                                             StepLink);
+                                             StepLink, double *, const double *);
 template hipError_t stencil_dir_sigma<double>(const Geom &, int, const double *, const double *,
                                               const double *, const double *, const double *,
                                               int, double *, double *, Pair *, const int *,
-                                              hipStream_t, StepLink);
+                                              hipStream_t, StepLink, double *, const double *);
 template hipError_t stencil_pair_update<float>(const Geom &, int, const float *, const float *,
                                                double *, float *, float *, Pair *, const int *,
-                                               const double *, hipStream_t, StepLink);
+                                               const double *, hipStream_t, StepLink, int,
+                                               const float *, const double *);
 template hipError_t stencil_pair_update<double>(const Geom &, int, const double *,
                                                 const double *, double *, double *, double *,
                                                 Pair *, const int *, const double *, hipStream_t,
-                                                StepLink);
+                                                StepLink, int, const double *, const double *);
 
 hipError_t stencil_pair_direction_m(const Geom &g, int ty, const double *r, const double *rs,
                                    const double *p_old, const double *ps_old, const double *d,

@@ -68,7 +68,7 @@ __device__ __forceinline__ bool link_step(const StepLink &L, double &beta, Pair 
     BicgState *s = L.state;
     // state fields of the previous launches, requested before the merge waits on memory
     const double thr = s->thr, rho_old = s->rho_slot[L.par ^ 1];
-    const int iter = s->iter, maxit = s->maxit;
+    const int iter = s->iter, maxit = s->maxit, prev_st = s->poll_status;
     Pair v[2];
     if (L.nv == 2) {
         merge_fixed<2>(L.part, L.count, v, sh);
@@ -81,7 +81,9 @@ __device__ __forceinline__ bool link_step(const StepLink &L, double &beta, Pair 
     const double rho_new = pair_value(v[0]);
     const double rr = pair_value(v[1]);
     int st;
-    if (rr <= thr) st = kConverged;
+    // a breakdown of the preceding sweep B that owed the iterate's update comes first
+    if (prev_st == kBreakdown) st = kBreakdown;
+    else if (rr <= thr) st = kConverged;
     else if (iter >= maxit) st = kNoConv;
     else if (rho_new == 0.0 || !isfinite(rho_new)) st = kBreakdown;
     else st = kRunning;
@@ -112,10 +114,13 @@ __device__ __forceinline__ bool link_alpha(const StepLink &L, double &alpha, Pai
     if (blockIdx.x == 0 && block_tid() == 0) {
         s->sigma = sigma;
         if (bad) {
-            s->status = kBreakdown;
+            // with an update owed, the status stays running until the next check, so the
+            // workgroups that start later take the same decision and apply their part
+            if (!L.defer) s->status = kBreakdown;
             s->poll_status = kBreakdown;
         } else {
             s->alpha = alpha;
+            s->alpha_slot[L.par] = alpha;
             s->iter = s->iter + 1;
         }
     }

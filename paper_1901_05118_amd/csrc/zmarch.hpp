@@ -636,10 +636,35 @@ struct OutDirSigma {
     }
 };
 
+// Sweep A of the recomputing form that owes the iterate the update of the previous
+// iteration (paired updates, see OutPairUpdate): while the run goes on the next sweep B
+// applies it; when the run stops at the start of this launch, x += alpha p_old is applied
+// here on its own, with the update sweep's arithmetic.
+template <typename T>
+struct OutDirSigmaX : OutDirSigma<T> {
+    double *x;
+    const T *pold;               // p of iteration j-1 (the direction this sweep reads)
+    const double *alpha_dev;     // alpha of iteration j-1
+    double alpha_owed;
+    __device__ void prepare() { alpha_owed = wave_uniform(*alpha_dev); }
+    // 0: running; 2: the run stops in this launch (a workgroup already decided it); 1: stopped
+    // before this launch (nothing owed)
+    __device__ int gate() const {
+        const int s = *this->status;
+        return s == kRunning ? 0 : (s == kStopping ? 2 : 1);
+    }
+    __device__ void finish_output(i64 idx) { x[idx] = x[idx] + alpha_owed * (double)pold[idx]; }
+};
+
 // Sweep B: p and p* (stored by sweep A) are marched for q = A p and q* = A^T p*, then
 // x += alpha p, r -= alpha q, r* -= alpha q*, and the partials of r*.r and r.r: the
 // arithmetic of the update sweep, element by element, with q and q* rounded as if stored.
-template <typename T>
+// XM selects the iterate's update, so that two iterations can share one pass over x:
+//   0  x += alpha p;
+//   1  none (the next sweep B applies it);
+//   2  x += alpha' p' and then x += alpha p, alpha' and p' those of the previous iteration,
+//      each rounded as its own sweep of mode 0 would round it.
+template <typename T, int XM = 0>
 struct OutPairUpdate {
     double *x;
     T *r;
@@ -648,18 +673,31 @@ struct OutPairUpdate {
     const int *status;
     double alpha;
     Pair acc[2];
+    const T *p_prev;             // XM 2: p of the previous iteration
+    double alpha_prev;           // XM 2: its alpha
     struct Pre {
         double x;
-        T r, rs;
+        T r, rs, p;
     };
     template <class In>
     __device__ void bind(const In &in) { alpha = in.alpha; }
     __device__ bool skip() const { return *status != 0; }
     __device__ void centre(i64, const double *) {}
-    __device__ Pre pre(i64 idx) const { return Pre{x[idx], r[idx], rs[idx]}; }
+    __device__ Pre pre(i64 idx) const {
+        Pre v{};
+        if constexpr (XM != 1) v.x = x[idx];
+        if constexpr (XM == 2) v.p = p_prev[idx];
+        v.r = r[idx];
+        v.rs = rs[idx];
+        return v;
+    }
     __device__ void emit(i64 idx, const double *v, const double *c, const Pre &pr) {
         const T q0 = (T)v[0], q1 = (T)v[1];
-        x[idx] = pr.x + alpha * c[0];
+        if constexpr (XM == 0) x[idx] = pr.x + alpha * c[0];
+        if constexpr (XM == 2) {
+            const double xp = pr.x + alpha_prev * (double)pr.p;
+            x[idx] = xp + alpha * c[0];
+        }
         const double ri = (double)pr.r - alpha * (double)q0;
         const double si = (double)pr.rs - alpha * (double)q1;
         const T rt = (T)ri, st = (T)si;
@@ -674,6 +712,27 @@ struct OutPairUpdate {
             partials[block] = acc[0];
             partials[gridDim.x + block] = acc[1];
         }
+    }
+};
+
+// Sweep B of mode 2 with its gate: the previous iteration's update is owed, so a breakdown
+// found at the start of this launch (alpha undefined) still applies x += alpha' p' (the
+// breakdown is published in poll_status only, see link_alpha); after a sweep A that stopped
+// the run (and applied the update itself) the final status replaces kStopping.
+template <typename T>
+struct OutPairUpdate2 : OutPairUpdate<T, 2> {
+    BicgState *state;            // the run's state (NULL without folded finalisations)
+    const double *alpha_prev_dev;
+    __device__ void prepare() { this->alpha_prev = wave_uniform(*alpha_prev_dev); }
+    __device__ int gate() const {
+        const int s = *this->status;
+        if (s == kRunning) return 0;
+        if (s == kStopping && state && blockIdx.x == 0) state->status = state->poll_status;
+        return 1;
+    }
+    __device__ void finish_output(i64 idx) {
+        double *x = this->x;
+        x[idx] = x[idx] + this->alpha_prev * (double)this->p_prev[idx];
     }
 };
 

@@ -395,8 +395,9 @@ def set_timing(on: bool):
 
 
 def get_timing(level: int, sweep: int):
-    """(total ms, launches) of sweep 0 (A), 1 (B) or 2 (A with the deferred x update) on a
-    level since set_timing(True)."""
+    """(total ms, launches) of sweep 0 (A), 1 (B), 2 (A with the deferred x update), 3 (B
+    leaving x to the next iteration) or 4 (B applying two iterations' x updates) on a level
+    since set_timing(True)."""
     ms = ctypes.c_double(0.0)
     n = ctypes.c_longlong(0)
     _check("excmg_get_timing", load().excmg_get_timing(level, sweep, ctypes.byref(ms),

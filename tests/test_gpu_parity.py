@@ -596,10 +596,12 @@ def test_deferred_update_keeps_bicg_equal_to_cg(ex):
 
 def test_recomputing_form_keeps_the_mixed_solve(ex):
     """On large 3D grids the mixed Bi-CG forms q = A p and q* = A^T p* again in its update
-    sweep instead of storing them (same roundings, same update arithmetic).  Forced on every
-    level at 128^3 (recompute_min_unknowns = 1) it gives the stored form's iterates and
-    counts bit for bit, and the CG form's; launch by launch (event timing) too, one sweep A
-    and one sweep B per iteration; a negative threshold is refused."""
+    sweep instead of storing them (same roundings, same update arithmetic), and its sweeps B
+    update the FP64 iterate once per two iterations (x += alpha' p' + alpha p, rounded as two
+    updates).  Forced on every level at 128^3 (recompute_min_unknowns = 1) it gives the stored
+    form's iterates and counts bit for bit, and the CG form's; launch by launch (event timing)
+    too, one sweep A and one sweep B per iteration, the sweeps B of odd and even iterations
+    counted apart; a negative threshold is refused."""
     N, nl, bc = 128, 6, 2
     arr = make_arrays(config_problem(2), N, bc)
     f, g1, g2 = dev(arr.f), dev(arr.g1), dev(arr.g2)
@@ -623,9 +625,15 @@ def test_recomputing_form_keeps_the_mixed_solve(ex):
     _, n_a = ex.get_timing(nl - 1, 0)
     _, n_b = ex.get_timing(nl - 1, 1)
     _, n_x = ex.get_timing(nl - 1, 2)
+    _, n_keep = ex.get_timing(nl - 1, 3)   # odd iterations: x left to the next sweep B
+    _, n_pair = ex.get_timing(nl - 1, 4)   # even iterations: both updates
     ex.set_timing(False)
     assert rc == ex.OK
-    assert n_x == 0 and n_a == n_b == its[1][-1][0]
+    assert n_x == 0 and n_a == n_b + n_keep + n_pair == its[1][-1][0]
+    assert n_keep > 0 and n_pair > 0
+    # per run or resumed run, the odd and even sweeps alternate (one leading sweep B may
+    # update x once)
+    assert abs(n_keep - n_pair) <= its[1][-1][1] + 1 and n_b <= its[1][-1][1] + 1
     np.testing.assert_array_equal(host(u), outs[1])
     with pytest.raises(ex.ExcmgError):
         ex.solve_ex(N, nl, bc, f, g1, g2, 1e-9, torch.empty_like(f), precision=ex.MIXED,
