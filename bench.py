@@ -107,10 +107,12 @@ def sweep_forms(N, mixed):
     f.fp32 = mixed and nu >= FP32_MIN
     if nu >= RECOMPUTE_MIN:
         if f.fp32:
-            f.update({0: ("sigma", 24.0, "A"), 1: ("update", 40.0, "B"),
+            f.update({0: ("sigma", 24.0, "A; even iterations launch its OutDirSigmaX variant"),
+                      1: ("update", 40.0, "B"),
                       3: ("update_keep", 24.0, "B, x left"), 4: ("update_pair", 44.0, "B, x twice")})
         else:
-            f.update({0: ("sigma64", 48.0, "A"), 1: ("update64", 64.0, "B"),
+            f.update({0: ("sigma64", 48.0, "A; even iterations launch its OutDirSigmaX variant"),
+                      1: ("update64", 64.0, "B"),
                       3: ("update_keep64", 48.0, "B, x left"),
                       4: ("update_pair64", 72.0, "B, x twice")})
     elif f.fp32:

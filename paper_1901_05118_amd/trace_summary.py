@@ -46,7 +46,7 @@ def _grid_rows(durations):
     return len(durations), len(act), sum(act) / len(act), med
 
 
-def trace(db_path: str, cmd: str, top: int = 16, sweeps: int = 4) -> str:
+def trace(db_path: str, cmd: str, top: int = 24, sweeps: int = 8) -> str:
     db = sqlite3.connect(db_path)
     cur = db.cursor()
     rows = cur.execute(
