@@ -41,6 +41,7 @@ def log(msg):
 # vectors (the library's defaults)
 RECOMPUTE_MIN = 1 << 22
 FP32_MIN = 1 << 18
+DOWN_MAX = 1 << 26
 
 
 def update_depth(ty):
@@ -69,6 +70,9 @@ def sweep_launch(N, ty, zc, form):
     tiles = -(-n // 64) * -(-n // ty) * -(-n // zc)
     tiles = -(-tiles // 8) * 8  # the grid is padded to whole XCD shares
     d = update_depth(ty)
+    # FP64 sweeps B below 2^26 unknowns march downwards (the library's choice)
+    kern = "zmarch_down" if form in ("update64", "update_keep64", "update_pair64") and \
+        n ** 3 < DOWN_MAX else "zmarch"
     # the last template argument: planes in flight
     name = {"fp64": "zmarch<2, {ty}, double, InDirection<double>, OutPairApply<double>, 2>",
             "stored32": "zmarch<2, {ty}, float, InDirection<float>, OutPairApply<float>, 2>",
@@ -81,7 +85,7 @@ def sweep_launch(N, ty, zc, form):
             "update64": "zmarch<2, {ty}, double, InPlainAlpha<double>, OutPairUpdate<double, 0>, {d}>",
             "update_keep64": "zmarch<2, {ty}, double, InPlainAlpha<double>, OutPairUpdate<double, 1>, {d}>",
             "update_pair64": "zmarch<2, {ty}, double, InPlainAlpha<double>, OutPairUpdate2<double>, {d}>"}[form]
-    return name.format(ty=ty, d=d), tiles * 64 * ty
+    return kern + name.format(ty=ty, d=d)[len("zmarch"):], tiles * 64 * ty
 
 
 class _Forms(dict):

@@ -585,7 +585,8 @@ int launch_iteration(const Level &L, TX *x, long long j, int ev, hipStream_t st,
             CKH(stencil_pair_update<T>(G, G.ty, pn, psn, x, r, rs, c.part_b.as<Pair>(),
                                        &S->status, &S->alpha, st, lb, xm,
                                        xm == 2 ? c.p[cur].as<T>() : nullptr,
-                                       xm == 2 ? &S->alpha_slot[cur ^ 1] : nullptr));
+                                       xm == 2 ? &S->alpha_slot[cur ^ 1] : nullptr,
+                                       sizeof(T) == 8 && L.nu < kDownMaxUnknowns));
             if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev + 3], st));
             return EXCMG_OK;
         }
@@ -2381,7 +2382,8 @@ int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launc
                 case 10: return stencil_pair_update<double>(
                             L.g2, L.g2.ty, c.p[1].as<double>(), c.ps[1].as<double>(),
                             L.x.as<double>(), r, rs, c.part_b.as<Pair>(), &S->status, &S->alpha,
-                            g_stream, StepLink{}, which - 8, c.p[0].as<double>(), &S->alpha);
+                            g_stream, StepLink{}, which - 8, c.p[0].as<double>(), &S->alpha,
+                            L.nu < kDownMaxUnknowns);
                 default: return copy_convert<double, double>(L.nu, r, c.q.as<double>(), g_stream);
             }
         }
@@ -2583,6 +2585,7 @@ int excmg_autotune(int n, int kind, int precision, int reps, int *ty_out, int *z
     CKH(hipEventCreate(&e0));
     CKH(hipEventCreate(&e1));
     int rc = EXCMG_OK;
+    int pair_calls = 0;
     for (int ty : tys) {
         // chunks of 2, 4, ... planes and, last, the whole depth in one march
         for (int zp = 2;; zp *= 2) {
@@ -2596,8 +2599,10 @@ int excmg_autotune(int n, int kind, int precision, int reps, int *ty_out, int *z
                     return stencil_apply<float>(g, ty, v[0].as<float>(), v[1].as<float>(), g_stream);
                 }
                 if (rq) {
-                    // r, r*, p, p* -> p_new, p*_new (sigma); then p_new, p*_new -> x, r, r*
+                    // r, r*, p, p* -> p_new, p*_new (sigma); then p_new, p*_new -> x, r, r*,
+                    // the sweeps B alternating as the solver's paired updates do
                     const StepLink nl{};
+                    const int xm = 1 + (pair_calls++ & 1);
                     hipError_t e;
                     if (es == 8) {
                         e = stencil_dir_sigma<double>(g, ty, v[0].as<double>(), v[1].as<double>(),
@@ -2608,7 +2613,9 @@ int excmg_autotune(int n, int kind, int precision, int reps, int *ty_out, int *z
                         return stencil_pair_update<double>(g, ty, v[4].as<double>(), v[5].as<double>(),
                                                            xd.as<double>(), v[0].as<double>(),
                                                            v[1].as<double>(), part.as<Pair>(), &S->status,
-                                                           &S->alpha, g_stream, nl);
+                                                           &S->alpha, g_stream, nl, xm, v[2].as<double>(),
+                                                           &S->alpha,
+                                                           (long long)nn * nn * nn < kDownMaxUnknowns);
                     }
                     e = stencil_dir_sigma<float>(g, ty, v[0].as<float>(), v[1].as<float>(), v[2].as<float>(),
                                                  v[3].as<float>(), &S->beta, 0, v[4].as<float>(),
@@ -2616,7 +2623,8 @@ int excmg_autotune(int n, int kind, int precision, int reps, int *ty_out, int *z
                     if (e != hipSuccess) return e;
                     return stencil_pair_update<float>(g, ty, v[4].as<float>(), v[5].as<float>(), xd.as<double>(),
                                                       v[0].as<float>(), v[1].as<float>(), part.as<Pair>(),
-                                                      &S->status, &S->alpha, g_stream, nl);
+                                                      &S->status, &S->alpha, g_stream, nl, xm,
+                                                      v[2].as<float>(), &S->alpha);
                 }
                 if (es == 8)
                     return stencil_pair_direction<double>(g, ty, v[0].as<double>(), v[1].as<double>(),

@@ -62,6 +62,13 @@ static hipError_t launch3d(const Geom &g, const In &in, const Out &out, hipStrea
                        0, st, g, in, out);
     return hipGetLastError();
 }
+// The same launch marching every chunk from its top plane down (zmarch_down).
+template <int TY, typename T, class In, class Out, int NA, int D>
+static hipError_t launch3d_down(const Geom &g, const In &in, const Out &out, hipStream_t st) {
+    hipLaunchKernelGGL((zmarch_down<NA, TY, T, In, Out, D>), dim3(xcd_grid(g.ntiles)),
+                       dim3(kWave, TY), 0, st, g, in, out);
+    return hipGetLastError();
+}
 
 // Planes in flight of the recomputing form's sweep A (one marched array, registers to spare):
 // three (measured, FP32 at 512^3: 752 us with two, 733 us with three, four spill; FP64 at
@@ -287,8 +294,9 @@ template <typename T>
 hipError_t stencil_pair_update(const Geom &g, int ty, const T *p, const T *ps, double *x, T *r,
                                T *rs, Pair *partials, const int *status, const double *alpha_dev,
                                hipStream_t st, StepLink link, int xmode, const T *p_prev,
-                               const double *alpha_prev) {
+                               const double *alpha_prev, bool down) {
     if (g.dim != 3 || xmode < 0 || xmode > 2) return hipErrorInvalidValue;
+    if (down && g.tw != kWave) return hipErrorInvalidValue;
     // paired updates: single-point tiles; with folded finalisations, mode 2 owes the update
     // (alpha_j in its slot, the breakdown rule of link_alpha)
     if (xmode != 0 && g.tw != kWave) return hipErrorInvalidValue;
@@ -340,6 +348,9 @@ hipError_t stencil_pair_update(const Geom &g, int ty, const T *p, const T *ps, d
     if (xmode == 1) {
         OutPairUpdate<T, 1> out;
         fill(out);
+        if (down)
+            EXCMG_DISPATCH_TY(ty, return (launch3d_down<TY, T, InPlainAlpha<T>, OutPairUpdate<T, 1>,
+                                                        2, update_depth(TY)>(g, in, out, st)));
         EXCMG_DISPATCH_TY(ty, return (launch3d<TY, T, InPlainAlpha<T>, OutPairUpdate<T, 1>, 2,
                                                update_depth(TY)>(g, in, out, st)));
         return hipSuccess;
@@ -349,12 +360,18 @@ hipError_t stencil_pair_update(const Geom &g, int ty, const T *p, const T *ps, d
         fill(out);
         out.state = link.state;
         out.alpha_prev_dev = alpha_prev;
+        if (down)
+            EXCMG_DISPATCH_TY(ty, return (launch3d_down<TY, T, InPlainAlpha<T>, OutPairUpdate2<T>,
+                                                        2, update_depth(TY)>(g, in, out, st)));
         EXCMG_DISPATCH_TY(ty, return (launch3d<TY, T, InPlainAlpha<T>, OutPairUpdate2<T>, 2,
                                                update_depth(TY)>(g, in, out, st)));
         return hipSuccess;
     }
     OutPairUpdate<T> out;
     fill(out);
+    if (down)
+        EXCMG_DISPATCH_TY(ty, return (launch3d_down<TY, T, InPlainAlpha<T>, OutPairUpdate<T>, 2,
+                                                    update_depth(TY)>(g, in, out, st)));
     EXCMG_DISPATCH_TY(ty, return (launch3d<TY, T, InPlainAlpha<T>, OutPairUpdate<T>, 2,
                                            update_depth(TY)>(g, in, out, st)));
     return hipSuccess;
@@ -370,11 +387,11 @@ template hipError_t stencil_dir_sigma<double>(const Geom &, int, const double *,
 template hipError_t stencil_pair_update<float>(const Geom &, int, const float *, const float *,
                                                double *, float *, float *, Pair *, const int *,
                                                const double *, hipStream_t, StepLink, int,
-                                               const float *, const double *);
+                                               const float *, const double *, bool);
 template hipError_t stencil_pair_update<double>(const Geom &, int, const double *,
                                                 const double *, double *, double *, double *,
                                                 Pair *, const int *, const double *, hipStream_t,
-                                                StepLink, int, const double *, const double *);
+                                                StepLink, int, const double *, const double *, bool);
 
 hipError_t stencil_pair_direction_m(const Geom &g, int ty, const double *r, const double *rs,
                                    const double *p_old, const double *ps_old, const double *d,

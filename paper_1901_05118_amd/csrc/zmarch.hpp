@@ -112,6 +112,53 @@ __device__ __forceinline__ double column_step(Column &s, const TL *B, double &c0
     return y;
 }
 
+// The same pipeline for a march towards decreasing z (planes m+2, m+1, m, ... arrive in that
+// order).  Every output is summed with the association of the upward pipeline, term by term
+// (the z-2 centre still joins S2 first and the z+2 one last), so both directions give the
+// same value bit for bit; the down pipeline holds one plane more of history for that.
+struct ColumnDown {
+    double c1, c2, c3, c4;       // centre values of planes m+1 .. m+4
+    double a1, a2;               // x- + x+ + y- + y+ of planes m+1, m+2
+    double d1;                   // the diagonal group of plane m+1
+    double b1, b2;               // the distance-2 group of planes m+1, m+2
+    double s1, e;                // S1 and S3 of output m+2 (complete)
+};
+
+__device__ __forceinline__ void column_init(ColumnDown &s) {
+    s.c1 = s.c2 = s.c3 = s.c4 = 0.0;
+    s.a1 = s.a2 = s.d1 = s.b1 = s.b2 = s.s1 = s.e = 0.0;
+}
+
+// Consume plane m and return the completed output of plane m+2.
+template <int LS, typename TL>
+__device__ __forceinline__ double column_step(ColumnDown &s, const TL *B, double &c0) {
+    const double c = B[0];
+    const double n0 = B[-1], n1 = B[1], n2 = B[-LS], n3 = B[LS];
+    const double f0 = B[-2], f1 = B[2], f2 = B[-2 * LS], f3 = B[2 * LS];
+    const double d0 = B[-1 - LS], d1 = B[-1 + LS], d2 = B[1 - LS], d3 = B[1 + LS];
+    const double a0 = n0 + n1 + n2 + n3;
+    const double b0 = f0 + f1 + f2 + f3;
+    const double dg = d0 + d1 + d2 + d3;
+    // output m+2: S2 = (its distance-2 group + this plane's centre) + the centre of m+4
+    const double y = 42.0 * s.c2 - 12.0 * s.s1 + ((s.b2 + c) + s.c4) + 2.0 * s.e;
+    // output m+1: S1 and S3 complete with this plane (its z-1 terms)
+    const double s1 = (s.a1 + c) + s.c2;
+    const double e1 = (s.d1 + a0) + s.a2;
+    s.c4 = s.c3;
+    s.c3 = s.c2;
+    s.c2 = s.c1;
+    s.c1 = c;
+    s.a2 = s.a1;
+    s.a1 = a0;
+    s.d1 = dg;
+    s.b2 = s.b1;
+    s.b1 = b0;
+    s.s1 = s1;
+    s.e = e1;
+    c0 = c;
+    return y;
+}
+
 // Inputs of the marched arrays.  Staging is split in two so that global loads stay in
 // flight while earlier planes are consumed: load() fetches the R raw values of a staged
 // element (into registers, no arithmetic), combine() turns them into the staged value.
@@ -254,7 +301,9 @@ struct NoBegin {
 // partials of the previous sweep); it is called after the first planes have been requested,
 // so that their loads and the scalars' merge overlap.  Returns false (nothing written) when
 // begin() ends the run.
-template <int NA, int TY, typename T, class In, class Out, class Begin = NoBegin, int D = 2>
+// DOWN: march the chunk's planes from its top down (same outputs, same values).
+template <int NA, int TY, typename T, class In, class Out, class Begin = NoBegin, int D = 2,
+          bool DOWN = false>
 __device__ __forceinline__ bool zmarch_tile(const Geom &g, int tile, const In &in, Out &out,
                                             Begin begin = Begin{}) {
     constexpr int TX = kWave;
@@ -303,6 +352,8 @@ __device__ __forceinline__ bool zmarch_tile(const Geom &g, int tile, const In &i
     constexpr bool kPre = HasPre<Out>::value;
     using PreT = typename PreOf<Out>::type;
     const int mbeg = k0 - 2, mend = k1 + 1;     // planes mbeg..mend are staged
+    constexpr int DZ = DOWN ? -1 : 1;           // direction of the march
+    const int mfirst = DOWN ? mend : mbeg;
     // in-plane offset of this lane's column (< 2^31), clamped so that lanes outside the grid
     // request valid addresses
     const int col_off = min(iy, n - 1) * g.ld + min(ix, n - 1);
@@ -316,7 +367,7 @@ __device__ __forceinline__ bool zmarch_tile(const Geom &g, int tile, const In &i
     };
     auto fetch = [&](int p, Stage &st) {
         int sz;
-        st.mz = (float)reflect(min(p, mend), n, g.sgn, sz);
+        st.mz = (float)reflect(DOWN ? max(p, mbeg) : min(p, mend), n, g.sgn, sz);
 #pragma unroll
         for (int q = 0; q < NL; q++) {
             const i64 idx = (i64)sz * plane + soff[q];
@@ -324,7 +375,7 @@ __device__ __forceinline__ bool zmarch_tile(const Geom &g, int tile, const In &i
             for (int a = 0; a < NA; a++) in.load(a, idx, st.raw[q][a]);
         }
         if constexpr (kPre)
-            st.pre = out.pre((i64)min(max(p - 3, k0), k1 - 1) * plane + col_off);
+            st.pre = out.pre((i64)min(max(p - 3 * DZ, k0), k1 - 1) * plane + col_off);
     };
     // the staged value is the input times 0 or +-1, which is exact in the storage type
     auto stash = [&](int b, const Stage &st) {
@@ -342,50 +393,52 @@ __device__ __forceinline__ bool zmarch_tile(const Geom &g, int tile, const In &i
         }
     };
 
-    Column col[NA];
+    using Col = std::conditional_t<DOWN, ColumnDown, Column>;
+    Col col[NA];
 #pragma unroll
     for (int a = 0; a < NA; a++) column_init(col[a]);
 
     Stage stage[D], stage0;
-    fetch(mbeg, stage0);
+    fetch(mfirst, stage0);
 #pragma unroll
-    for (int k = 0; k < D; k++) fetch(mbeg + 1 + k, stage[k]);
+    for (int k = 0; k < D; k++) fetch(mfirst + DZ * (1 + k), stage[k]);
     if (!begin()) return false;
     stash(0, stage0);
     __syncthreads();
     int cur = 0;
     const int centre = (ly + 2) * LS + (lx + 2);
-    // consume plane m from LDS, stage plane m+1 from `st`, refill `st` with plane m+1+D
+    // consume plane m from LDS, stage the next plane (m+1, or m-1 down) from `st`, refill
+    // `st` with the plane D after it
     auto body = [&](int m, Stage &st) {
         double y[NA], c0[NA], cprev[NA];
 #pragma unroll
         for (int a = 0; a < NA; a++) {
-            cprev[a] = col[a].c2;    // centre of plane m-2 before the shift
+            cprev[a] = col[a].c2;    // centre of the output plane m-2 (m+2) before the shift
             y[a] = column_step<LS, T>(col[a], &buf[cur][a][centre], c0[a]);
         }
         if (valid) {
             if (m >= k0 && m < k1) out.centre((i64)m * plane + col_off, c0);
-            const int k = m - 2;
+            const int k = m - 2 * DZ;
             if (k >= k0 && k < k1) {
                 if constexpr (kPre) out.emit((i64)k * plane + col_off, y, cprev, st.pre);
                 else out.emit((i64)k * plane + col_off, y, cprev);
             }
         }
         stash(cur ^ 1, st);
-        fetch(m + 1 + D, st);
+        fetch(m + DZ * (1 + D), st);
         __syncthreads();
         cur ^= 1;
     };
     // Whole groups of D planes with no exit inside a group, then the remaining planes.
     const int groups = (mend - mbeg + 1) / D;
-    int m = mbeg;
-    for (int grp = 0; grp < groups; grp++, m += D) {
+    int m = mfirst;
+    for (int grp = 0; grp < groups; grp++, m += DZ * D) {
 #pragma unroll
-        for (int u = 0; u < D; u++) body(m + u, stage[u]);
+        for (int u = 0; u < D; u++) body(m + DZ * u, stage[u]);
     }
 #pragma unroll
     for (int u = 0; u < D - 1; u++)
-        if (m + u <= mend) body(m + u, stage[u]);
+        if (DOWN ? (m - u >= mbeg) : (m + u <= mend)) body(m + DZ * u, stage[u]);
     return true;
 }
 
@@ -407,8 +460,8 @@ __device__ __forceinline__ void zmarch_tile_outputs(const Geom &g, int tile, Out
 
 // One workgroup per tile (XCD-aware order), then the epilogue's block-level reduction.  D:
 // planes in flight.
-template <int NA, int TY, typename T, class In, class Out, int D = 2>
-__global__ void __launch_bounds__(kWave *TY) zmarch(Geom g, In in_arg, Out out) {
+template <int NA, int TY, typename T, class In, class Out, int D, bool DOWN>
+__device__ __forceinline__ void zmarch_launch(const Geom &g, const In &in_arg, Out &out) {
     __shared__ Pair red[4 * TY];
     __shared__ int s_skip;
     In in = in_arg;
@@ -436,7 +489,8 @@ __global__ void __launch_bounds__(kWave *TY) zmarch(Geom g, In in_arg, Out out) 
     };
     const int tile = xcd_tile(blockIdx.x, g.ntiles);
     const bool go = tile < g.ntiles
-                        ? zmarch_tile<NA, TY, T, In, Out, decltype(start), D>(g, tile, in, out, start)
+                        ? zmarch_tile<NA, TY, T, In, Out, decltype(start), D, DOWN>(g, tile, in,
+                                                                                 out, start)
                         : start();
     if (!go) {
         if constexpr (HasGate<Out>::value) {
@@ -445,6 +499,19 @@ __global__ void __launch_bounds__(kWave *TY) zmarch(Geom g, In in_arg, Out out) 
         return;
     }
     out.finish(blockIdx.x, red);  // padding blocks of the XCD-aware grid contribute zero
+}
+
+template <int NA, int TY, typename T, class In, class Out, int D = 2>
+__global__ void __launch_bounds__(kWave *TY) zmarch(Geom g, In in, Out out) {
+    zmarch_launch<NA, TY, T, In, Out, D, false>(g, in, out);
+}
+
+// The same sweep marching every chunk from its top plane down.  A sweep that follows an
+// upward one starts on the planes that one touched last, which the last-level cache may
+// still hold.
+template <int NA, int TY, typename T, class In, class Out, int D = 2>
+__global__ void __launch_bounds__(kWave *TY) zmarch_down(Geom g, In in, Out out) {
+    zmarch_launch<NA, TY, T, In, Out, D, true>(g, in, out);
 }
 
 // ------------------------------------------------------------------ epilogues

@@ -132,3 +132,39 @@ def test_mixed_bicg_equals_cg_at_full_size(ex, problem):
     np.testing.assert_array_equal(outs[0], outs[1])
     np.testing.assert_array_equal(outs[0], outs[2])
     np.testing.assert_array_equal(outs[0], outs[3])
+
+
+def test_fp64_bicg_equals_cg_at_full_size(ex, problem):
+    """The FP64 Bi-CG of the benchmark takes the recomputing form on the 256^3 and 512^3
+    levels, with the iterate updated once per two iterations and, on the 256^3 level, its
+    update sweep marching each chunk from the top plane down.  The CG form (stored q, one
+    x update per iteration, upward sweeps) must match bit for bit."""
+    print("fp64 bicg vs cg 512^3", flush=True)
+    arr, b = problem
+    f, g1, g2 = dev(arr.f), dev(arr.g1), dev(arr.g2)
+    outs, its = [], []
+    for m in (ex.BICG, ex.CG):
+        u = torch.empty_like(f)
+        rc, st = ex.solve_ex(N, NL, BC, f, g1, g2, 1e-8, u, precision=ex.FP64, method=m)
+        assert rc == ex.OK, ex.last_error()
+        outs.append(host(u))
+        its.append([(l["iterations"], l["runs"]) for l in st.levels()])
+        del u
+    assert its[0] == its[1]
+    np.testing.assert_array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_profiled_sweeps_of_the_recomputing_form(ex, prec):
+    """The launcher of single sweeps (excmg_profile_sweep 7-10: sweep A, and sweep B with one,
+    no and two x updates) runs the solver's sweeps on the 256^3 level and reports their
+    algorithmic bytes per unknown."""
+    p = ex.FP64 if prec == "fp64" else ex.MIXED
+    ex.setup(256, 7, BC)
+    nu = 255 ** 3
+    want = {7: 48, 8: 64, 9: 48, 10: 72} if prec == "fp64" else {7: 24, 8: 40, 9: 24, 10: 44}
+    for which, bpu in want.items():
+        ms, nb = ex.profile_sweep(which, p, reps=2)
+        assert ms > 0 and nb == bpu * nu
+    with pytest.raises(ex.ExcmgError):
+        ex.profile_sweep(11, p, reps=1)
