@@ -70,9 +70,11 @@ def sweep_launch(N, ty, zc, form):
     tiles = -(-n // 64) * -(-n // ty) * -(-n // zc)
     tiles = -(-tiles // 8) * 8  # the grid is padded to whole XCD shares
     d = update_depth(ty)
-    # FP64 sweeps B below 2^26 unknowns march downwards (the library's choice)
-    kern = "zmarch_down" if form in ("update64", "update_keep64", "update_pair64") and \
-        n ** 3 < DOWN_MAX else "zmarch"
+    # FP32 sweeps A, and FP64 sweeps B below 2^26 unknowns, march downwards (the library's
+    # choice)
+    kern = "zmarch_down" if form == "sigma" or (
+        form in ("update64", "update_keep64", "update_pair64") and n ** 3 < DOWN_MAX) \
+        else "zmarch"
     # the last template argument: planes in flight
     name = {"fp64": "zmarch<2, {ty}, double, InDirection<double>, OutPairApply<double>, 2>",
             "stored32": "zmarch<2, {ty}, float, InDirection<float>, OutPairApply<float>, 2>",
@@ -168,8 +170,9 @@ def cpu_model():
     return info.get("Model name"), phys, info.get("Thread(s) per core")
 
 
-# FP64 Bi-CG iteration in the algorithmic-bytes convention of the GPU sweeps (recomputing
-# form: sweep A 48 + sweep B 64 bytes per unknown)
+# FP64 Bi-CG iteration in the algorithmic-bytes convention of the GPU sweeps, with the x update
+# in every iteration as the oracle makes it (recomputing form: sweep A 48 + sweep B 64 bytes
+# per unknown; the GPU's paired updates move 106)
 FP64_ITERATION_BYTES = 112.0
 
 

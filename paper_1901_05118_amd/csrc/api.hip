@@ -579,7 +579,7 @@ int launch_iteration(const Level &L, TX *x, long long j, int ev, hipStream_t st,
             CKH(stencil_dir_sigma<T>(G, G.ty, r, rs, c.p[cur].as<T>(), c.ps[cur].as<T>(),
                                      &S->beta, j == 0 ? 1 : 0, pn, psn, c.part_a.as<Pair>(),
                                      &S->status, st, la, xm == 2 ? x : nullptr,
-                                     xm == 2 ? &S->alpha : nullptr));
+                                     xm == 2 ? &S->alpha : nullptr, sizeof(T) == 4 && !L.wide));
             if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev + 1], st));
             if (ev >= 0) CKH(hipEventRecord(g_events[4 * ev + 2], st));
             CKH(stencil_pair_update<T>(G, G.ty, pn, psn, x, r, rs, c.part_b.as<Pair>(),
@@ -2413,7 +2413,7 @@ int excmg_profile_sweep(int which, int precision, int reps, double *ms_per_launc
                                              c.ps[0].as<float>(), &S->beta, 0,
                                              c.p[1].as<float>(), c.ps[1].as<float>(),
                                              c.part_a.as<Pair>(), &S->status, g_stream,
-                                             StepLink{});
+                                             StepLink{}, nullptr, nullptr, !L.wide);
             case 8:
             case 9:
             case 10: return stencil_pair_update<float>(rq_geom_f32(L), rq_geom_f32(L).ty, c.p[1].as<float>(),
@@ -2619,7 +2619,8 @@ int excmg_autotune(int n, int kind, int precision, int reps, int *ty_out, int *z
                     }
                     e = stencil_dir_sigma<float>(g, ty, v[0].as<float>(), v[1].as<float>(), v[2].as<float>(),
                                                  v[3].as<float>(), &S->beta, 0, v[4].as<float>(),
-                                                 v[5].as<float>(), part.as<Pair>(), &S->status, g_stream, nl);
+                                                 v[5].as<float>(), part.as<Pair>(), &S->status, g_stream, nl,
+                                                 nullptr, nullptr, true);
                     if (e != hipSuccess) return e;
                     return stencil_pair_update<float>(g, ty, v[4].as<float>(), v[5].as<float>(), xd.as<double>(),
                                                       v[0].as<float>(), v[1].as<float>(), part.as<Pair>(),

@@ -120,22 +120,23 @@ hipError_t stencil_pair_direction_x(const Geom &g, int ty, const float *r, const
 // x untouched (xmode 1), sweep B of the next, even one applies both updates, x += alpha' p'
 // then x += alpha p (xmode 2: p' = p_prev, alpha' from alpha_prev), and a sweep A that stops
 // the run while x owes an update applies it on its own (owe_x: x += alpha p_old, alpha from
-// alpha_owed).  xmode 0: x += alpha p in every sweep B.  down: sweep B marches each chunk
+// alpha_owed).  xmode 0: x += alpha p in every sweep B.  down: the sweep marches each chunk
 // from its top plane down (zmarch_down; single-point tiles).
 template <typename T>
 hipError_t stencil_dir_sigma(const Geom &g, int ty, const T *r, const T *rs, const T *p_old,
                              const T *ps_old, const double *beta_dev, int first, T *p_new,
                              T *ps_new, Pair *partials, const int *status, hipStream_t st,
                              StepLink link, double *owe_x = nullptr,
-                             const double *alpha_owed = nullptr);
+                             const double *alpha_owed = nullptr, bool down = false);
 template <typename T>
 hipError_t stencil_pair_update(const Geom &g, int ty, const T *p, const T *ps, double *x, T *r,
                                T *rs, Pair *partials, const int *status, const double *alpha_dev,
                                hipStream_t st, StepLink link, int xmode = 0,
                                const T *p_prev = nullptr, const double *alpha_prev = nullptr,
                                bool down = false);
-// Sweep B marches downwards (same values) on FP64 levels below this many unknowns: it then
-// starts on the planes sweep A touched last, which the last-level cache still holds in part.
+// One sweep of each recomputing-form iteration marches downwards (same values), so that it
+// starts on the planes the other sweep touched last, which the last-level cache still holds
+// in part: sweep A with FP32 vectors, sweep B with FP64 vectors below this many unknowns.
 constexpr long long kDownMaxUnknowns = 1LL << 26;
 hipError_t stencil_pair_direction_m(const Geom &g, int ty, const double *r, const double *rs,
                                    const double *p_old, const double *ps_old, const double *d,

@@ -224,10 +224,11 @@ template <typename T>
 hipError_t stencil_dir_sigma(const Geom &g, int ty, const T *r, const T *rs, const T *p_old,
                              const T *ps_old, const double *beta_dev, int first, T *p_new,
                              T *ps_new, Pair *partials, const int *status, hipStream_t st,
-                             StepLink link, double *owe_x, const double *alpha_owed) {
+                             StepLink link, double *owe_x, const double *alpha_owed, bool down) {
     if (g.dim != 3) return hipErrorInvalidValue;
     if (g.tw != kWave) {
-        if (owe_x) return hipErrorInvalidValue;   // paired updates: single-point sweeps only
+        // paired updates and downward marches: single-point sweeps only
+        if (owe_x || down) return hipErrorInvalidValue;
         if constexpr (sizeof(T) == 4) {
             if (g.tw != 2 * kWave) return hipErrorInvalidValue;
             WideDirection in;
@@ -281,10 +282,16 @@ hipError_t stencil_dir_sigma(const Geom &g, int ty, const T *r, const T *rs, con
         ox.pold = p_old;
         ox.alpha_dev = alpha_owed;
         ox.alpha_owed = 0.0;
+        if (down)
+            EXCMG_DISPATCH_TY(ty, return (launch3d_down<TY, T, InDirection<T>, OutDirSigmaX<T>, 1,
+                                                        kSigmaDepth<T>>(g, in, ox, st)));
         EXCMG_DISPATCH_TY(ty, return (launch3d<TY, T, InDirection<T>, OutDirSigmaX<T>, 1,
                                                kSigmaDepth<T>>(g, in, ox, st)));
         return hipSuccess;
     }
+    if (down)
+        EXCMG_DISPATCH_TY(ty, return (launch3d_down<TY, T, InDirection<T>, OutDirSigma<T>, 1,
+                                                    kSigmaDepth<T>>(g, in, out, st)));
     EXCMG_DISPATCH_TY(ty, return (launch3d<TY, T, InDirection<T>, OutDirSigma<T>, 1, kSigmaDepth<T>>(
                               g, in, out, st)));
     return hipSuccess;
@@ -379,11 +386,11 @@ hipError_t stencil_pair_update(const Geom &g, int ty, const T *p, const T *ps, d
 template hipError_t stencil_dir_sigma<float>(const Geom &, int, const float *, const float *,
                                              const float *, const float *, const double *, int,
                                              float *, float *, Pair *, const int *, hipStream_t,
-                                             StepLink, double *, const double *);
+                                             StepLink, double *, const double *, bool);
 template hipError_t stencil_dir_sigma<double>(const Geom &, int, const double *, const double *,
                                               const double *, const double *, const double *,
                                               int, double *, double *, Pair *, const int *,
-                                              hipStream_t, StepLink, double *, const double *);
+                                              hipStream_t, StepLink, double *, const double *, bool);
 template hipError_t stencil_pair_update<float>(const Geom &, int, const float *, const float *,
                                                double *, float *, float *, Pair *, const int *,
                                                const double *, hipStream_t, StepLink, int,
