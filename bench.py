@@ -39,7 +39,8 @@ def log(msg):
 
 # Grids from which Bi-CG takes the recomputing form, and from which mixed solves use FP32
 # vectors (the library's defaults)
-RECOMPUTE_MIN = 1 << 22
+RECOMPUTE_MIN = 1 << 22      # FP32 vectors
+RECOMPUTE_MIN64 = 1 << 20    # FP64 vectors
 FP32_MIN = 1 << 18
 DOWN_MAX = 1 << 26
 
@@ -99,8 +100,8 @@ def sweep_forms(N, mixed):
     algorithmic bytes per unknown, label)}; timing kinds as excmg_get_timing's (0 sweep A,
     1 sweep B, 2 sweep A applying the deferred iterate update, 3 and 4 the recomputing
     form's sweeps B of odd and even iterations).  Mixed solves run FP32 vectors from 2^18
-    unknowns up (smaller levels FP64); both precisions take the recomputing form from 2^22
-    unknowns up.  Bytes: recomputing form, sweep A reads r, p, r*, p* and writes p, p* (FP32
+    unknowns up (smaller levels FP64); the recomputing form is taken from 2^22 unknowns up
+    with FP32 vectors and from 2^20 with FP64 ones.  Bytes: recomputing form, sweep A reads r, p, r*, p* and writes p, p* (FP32
     24, FP64 48), sweep B reads p, p*, r, r* and writes r, r* (FP32 24, FP64 48) and updates
     the FP64 iterate once per two iterations: an odd iteration's sweep B leaves it, an even
     one's reads x and the previous p and writes x (FP32 44, FP64 72); the first sweep B of a
@@ -111,7 +112,7 @@ def sweep_forms(N, mixed):
     nu = (N - 1) ** 3
     f = _Forms()
     f.fp32 = mixed and nu >= FP32_MIN
-    if nu >= RECOMPUTE_MIN:
+    if nu >= (RECOMPUTE_MIN if f.fp32 else RECOMPUTE_MIN64):
         if f.fp32:
             f.update({0: ("sigma", 24.0, "A; even iterations launch its OutDirSigmaX variant"),
                       1: ("update", 40.0, "B"),

@@ -114,7 +114,8 @@ typedef struct excmg_opts {
                         /* unknowns form q = A p and q* = A^T p* again in the update sweep   */
                         /* instead of storing them (mixed 64 instead of 72 bytes per unknown */
                         /* and iteration, FP64 112 instead of 136; a second stencil pass);  */
-                        /* 0: 4194304 (2^22), 1: every level.  Same results bit for bit      */
+                        /* 0: 2^22 with FP32 vectors, 2^20 with FP64 ones; 1: every level.  */
+                        /* Same results bit for bit                                         */
 } excmg_opts;
 
 /* Why a Bi-CG level stopped (excmg_level_stats.exit).  Algorithm 1 repeats Bi-CG on a level

@@ -499,14 +499,22 @@ RunVariant g_var;
 // FP64 CG 704 -> 807 ms, mixed 480 -> 477 ms).  Smaller grids keep the stored form (mixed: x's update deferred to the
 // next sweep A from 2^17 unknowns up): there a second march per iteration costs more
 // latency than the bytes it saves (measured, mixed: 128^3 level 81.9 ms stored, 88.0 ms
-// recomputing; 256^3: 532.0 and 513.7 ms; FP64 256^3: 874.7 and 843.9 ms).
-constexpr long long kRecomputeMin = 1LL << 22;
-long long g_rq_min = kRecomputeMin;   // opts.recompute_min_unknowns of the solve in progress
+// recomputing; 256^3: 532.0 and 513.7 ms; FP64 256^3: 874.7 and 843.9 ms).  With the paired
+// x updates and the alternating march directions FP64 vectors gain from 2^20 unknowns on
+// (128^3 level of the 512^3 solve: 102.6 ms stored, 89.1 ms recomputing; 64^3: 22.8 and
+// 23.5 ms), FP32 vectors still from 2^22 (128^3: 77.7 and 80.1 ms).
+constexpr long long kRecomputeMin = 1LL << 22;     // FP32 vectors
+constexpr long long kRecomputeMin64 = 1LL << 20;   // FP64 vectors
+long long g_rq_min = 0;   // opts.recompute_min_unknowns of the solve in progress (0: defaults)
+
+inline long long recompute_min(bool fp64) {
+    return g_rq_min > 0 ? g_rq_min : (fp64 ? kRecomputeMin64 : kRecomputeMin);
+}
 
 template <typename TX, typename T>
 bool recompute_q(const Level &L) {
     return sizeof(TX) == 8 && !g_cg && !g_var.d && !g_var.xs && g_ctx.dim == 3 &&
-           L.nu >= g_rq_min;
+           L.nu >= recompute_min(sizeof(T) == 8);
 }
 
 // Partials (per value) that the update sweep of level L leaves for the next sweep A.
@@ -1137,7 +1145,7 @@ int solve_cascade(const excmg_opts &o, const double *f, const double *g1, const 
         for (Level &Lv : c.lv) {
             // row_pad 2: padded rows and two-point sweeps on the levels that take the
             // recomputing form
-            Lv.wide = mixed && o.row_pad == 2 && Lv.nu >= g_rq_min && Lv.g2w.tw != 0;
+            Lv.wide = mixed && o.row_pad == 2 && Lv.nu >= recompute_min(false) && Lv.g2w.tw != 0;
             set_rows(Lv, level_ld(Lv.n, mixed && (o.row_pad == 1 || Lv.wide) ? 1 : 0), c.dim);
             if (Lv.ld != Lv.n) flat = std::max(flat, Lv.nflat);
         }
@@ -2250,11 +2258,11 @@ int solve_ex_dim(const excmg_opts *opts, const double *f, const double *g1, cons
     if (st) memset(st, 0, sizeof(*st));
     g_cg = (o.method == EXCMG_CG);
     g_graphs = true;
-    g_rq_min = o.recompute_min_unknowns > 0 ? o.recompute_min_unknowns : kRecomputeMin;
+    g_rq_min = o.recompute_min_unknowns > 0 ? o.recompute_min_unknowns : 0;
     int rc = solve_cascade(o, af.p<double>(), a1.p<double>(), a2.p<double>(), au.p<double>(),
                         ut_out ? at.p<double>() : nullptr, st);
     g_graphs = false;
-    g_rq_min = kRecomputeMin;
+    g_rq_min = 0;
     if (rc != EXCMG_OK && rc != EXCMG_ENOCONV && rc != EXCMG_EBREAKDOWN) return rc;
     CKR(au.back());
     if (ut_out) CKR(at.back());
@@ -2559,7 +2567,7 @@ int excmg_autotune(int n, int kind, int precision, int reps, int *ty_out, int *z
     const long long nv = (long long)nn * nn * ld;
     // on grids where Bi-CG takes the recomputing form, sweep A is timed with the sweep B it
     // shares its launch shape with (the pair the solver runs; x is FP64 in both precisions)
-    const bool rq = kind == 1 && (long long)nn * nn * nn >= kRecomputeMin && !g_var.d &&
+    const bool rq = kind == 1 && (long long)nn * nn * nn >= recompute_min(es == 8) && !g_var.d &&
                     !g_var.xs;
     DBuf v[8], part, stb, xd;
     for (auto &b : v) {
