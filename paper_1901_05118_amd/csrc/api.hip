@@ -466,10 +466,13 @@ int true_residual(const Level &L, const double *b, const double *x, double *r, i
 
 // ------------------------------------------------------------------ Bi-CG (Algorithm 2)
 
-// Iterations launched between two reads of the device state.
+// Iterations launched between two reads of the device state.  At least 16: each window adds
+// a closing check and a state copy, and on the large grids the no-op launches after a stop
+// cost less than those (512^3 solve, one box: mixed 572 / 567 / 563 ms and FP64 814 / 805 /
+// 803 ms with at least 4 / 8 / 16).
 int poll_interval(long long nu) {
     long long k = (1LL << 21) / (nu > 0 ? nu : 1);
-    if (k < 4) k = 4;
+    if (k < 16) k = 16;
     if (k > 64) k = 64;
     return (int)k;
 }
