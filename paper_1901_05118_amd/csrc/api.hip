@@ -466,13 +466,15 @@ int true_residual(const Level &L, const double *b, const double *x, double *r, i
 
 // ------------------------------------------------------------------ Bi-CG (Algorithm 2)
 
-// Iterations launched between two reads of the device state.  At least 16: each window adds
-// a closing check and a state copy, and on the large grids the no-op launches after a stop
-// cost less than those (512^3 solve, one box: mixed 572 / 567 / 563 ms and FP64 814 / 805 /
-// 803 ms with at least 4 / 8 / 16).
-int poll_interval(long long nu) {
+// Iterations launched between two reads of the device state.  At least 16 on 3D grids below
+// 2^26 unknowns: each window adds a closing check and a state copy, which cost more than the
+// no-op launches queued after a stop (512^3 solve, one box: mixed 572 / 567 / 563 ms and
+// FP64 814 / 805 / 803 ms with at least 4 / 8 / 16).  At least 4 on larger grids and in 2D,
+// whose largest levels run a few iterations each and whose no-op launches cost more (2D
+// 4096^2 solve: 85.6 ms with 4, 89.6 ms with 16).
+int poll_interval(long long nu, int dim) {
     long long k = (1LL << 21) / (nu > 0 ? nu : 1);
-    if (k < 16) k = 16;
+    if (k < 16) k = (dim == 3 && nu < (1LL << 26)) ? 16 : 4;
     if (k > 64) k = 64;
     return (int)k;
 }
@@ -705,7 +707,7 @@ int window_graph(const Level &L, TX *x, int K, hipGraphExec_t *out, int defer = 
 // continues at the j it stopped at, with its search directions).
 template <typename TX, typename T>
 int bicg_iterate(const Level &L, TX *x, BicgState &hs, long long &j) {
-    int K = poll_interval(L.nu);
+    int K = poll_interval(L.nu, g_ctx.dim);
     K += K & 1;
     if (g_timing) CKR(ensure_events(4 * (size_t)(K + 1)));
     const bool graphs = g_graphs && !g_timing;
