@@ -112,10 +112,11 @@ typedef struct excmg_opts {
                         /* 512^3 solve 1 and 2 are 2-4% slower than 0 on MI355X             */
     int recompute_min_unknowns; /* 3D Bi-CG (FP64 and mixed): levels with at least this many */
                         /* unknowns form q = A p and q* = A^T p* again in the update sweep   */
-                        /* instead of storing them (mixed 64 instead of 72 bytes per unknown */
-                        /* and iteration, FP64 112 instead of 136; a second stencil pass);  */
-                        /* 0: 2^22 with FP32 vectors, 2^20 with FP64 ones; 1: every level.  */
-                        /* Same results bit for bit                                         */
+                        /* instead of storing them, and update x once per two iterations    */
+                        /* (mixed 58 instead of 72 bytes per unknown and iteration, FP64    */
+                        /* 106 instead of 136; a second stencil pass); 0: 2^22 with FP32    */
+                        /* vectors, 2^20 with FP64 ones; 1: every level.  Same results bit  */
+                        /* for bit                                                          */
 } excmg_opts;
 
 /* Why a Bi-CG level stopped (excmg_level_stats.exit).  Algorithm 1 repeats Bi-CG on a level

@@ -498,8 +498,8 @@ RunVariant g_var;
 
 // Bi-CG on large 3D grids (plain Algorithm 2, folded finalisations, an FP64 iterate) takes
 // the recomputing form: its update sweep marches p and p* again for q and q* instead of
-// reading them back (mixed: 64 instead of 72 bytes per unknown and iteration; FP64: 112
-// instead of 136).  The CG specialisation keeps the stored form: its streaming update sweep
+// reading them back (mixed: 64 instead of 72 bytes per unknown and iteration, 58 with the
+// paired x updates; FP64: 112 instead of 136, 106 paired).  The CG specialisation keeps the stored form: its streaming update sweep
 // is cheap, and a second march cost more than the 16 bytes it saves (measured at 512^3:
 // FP64 CG 704 -> 807 ms, mixed 480 -> 477 ms).  Smaller grids keep the stored form (mixed: x's update deferred to the
 // next sweep A from 2^17 unknowns up): there a second march per iteration costs more
@@ -1373,7 +1373,10 @@ struct BatchSolver {
     // joined to st by events) and run beside the FP64 systems' steps
     hipStream_t st2 = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
-    int steps_per_graph = 8;
+    // Bi-CG steps per captured graph between two reads of the states (64 problems of
+    // 32^3-128^3, one box: 4 / 8 / 16 steps, FP64 1279 / 1252 / 1237 ms, mixed 1180 / 1128 /
+    // 1112 ms; another: 16 / 32 steps, FP64 1240 / 1233 ms, mixed 1117 / 1102 ms)
+    int steps_per_graph = 32;
     long long launches = 0;
 
     ~BatchSolver() {
