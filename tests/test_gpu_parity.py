@@ -205,8 +205,10 @@ def test_config1_solve(ex):
 @pytest.mark.parametrize("bc", [1, 2])
 def test_recomputing_form_fp64_matches_oracle(ex, bc):
     """FP64 Bi-CG in the recomputing form on every level (recompute_min_unknowns = 1): q and
-    q* formed again in the update sweep, rho and r.r summed per tile.  The cascade equals
-    the stored form's bit for bit and the oracle's counts and solution (1e-10)."""
+    q* formed again in the update sweep, rho and r.r summed per tile, x updated once per two
+    iterations, the update sweeps marching downwards.  The cascade equals the stored form's
+    bit for bit and the oracle's counts and solution (1e-10), with graph windows and launch
+    by launch."""
     N, nl = 48, 5
     arr = make_arrays(config_problem(2), N, bc)
     f, g1, g2 = dev(arr.f), dev(arr.g1), dev(arr.g2)
@@ -221,6 +223,22 @@ def test_recomputing_form_fp64_matches_oracle(ex, bc):
     ref = O.excmg(N, nl, bc, arr.f, arr.g1, arr.g2, 1e-9)
     assert outs[1][1][2:] == [lv.iters for lv in ref.levels]
     assert rel_l2(outs[1][0], ref.u.ravel()) <= 1e-10
+    # launch by launch (event timing, no graphs): the same iterates; per level one sweep A
+    # and one sweep B per iteration, the sweeps B of odd and even iterations apart
+    ex.set_timing(True)
+    try:
+        u = torch.empty_like(f)
+        rc, st = ex.solve_ex(N, nl, bc, f, g1, g2, 1e-9, u, recompute_min_unknowns=1)
+        counts = [[ex.get_timing(li, k)[1] for k in range(5)] for li in range(nl)]
+    finally:
+        ex.set_timing(False)
+    assert rc == ex.OK
+    np.testing.assert_array_equal(host(u), outs[1][0])
+    for li, lv in enumerate(st.levels()):
+        n_a, n_b, n_x, n_keep, n_pair = counts[li]
+        assert n_x == 0 and n_a == n_b + n_keep + n_pair == lv["iterations"]
+        if lv["iterations"] >= 4:
+            assert n_keep > 0 and n_pair > 0 and n_b <= lv["runs"]
 
 
 @pytest.mark.parametrize("k", [2, 3])
